@@ -1,0 +1,518 @@
+"""FP64 CPU oracle of the 3D half-Gaussian tile rasterizer.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or
+execute this module: only ``tests/``, the smoke check and the CPU-baseline leg
+of the benchmark use it.  It shares no code with the HIP library; inputs come
+from ``paper_2406_02720_amd.scenes`` (seeded draws, no rasterizer arithmetic),
+which this module does not import either.
+
+What it computes is a plain definition, written out per kernel and per pixel
+in float64 with plain PyTorch CPU ops (so that gradients are the autograd of
+the very same forward):
+
+* preprocess   -- projection of each half-Gaussian kernel to the image
+                  (Eq. 2, Eq. 3, Eq. 6), its half factor (Eq. 7, Eq. 8 and the
+                  conditional-Gaussian derivation of Supp. A.1), the splitting
+                  ellipse of Alg. 1 (Supp. B.1) and the half-aware valid region
+                  of Sec. 3.4; SH colour; depth.
+* bin_sort     -- (tile, depth, record id) lists of the tile rasterizer
+                  (Sec. 3.1, the tile-based rasterization of 3D-GS).
+* render       -- front-to-back alpha blending with the paired-half opacity
+                  of Eq. 10 (Sec. 3.3), per pixel, over the kernels whose
+                  valid region contains the pixel.
+* the gradient -- torch.autograd of ``render`` in end-to-end FP64 mode.
+
+Readings of points the paper leaves open (all listed in the design notes):
+the sign-safe camera-space form of Eq. 8; the half factor taken on the
+low-pass-dilated screen covariance; sigma_{z|xy} used as a standard deviation;
+Gaussian peak 1 (normaliser folded into opacity); pixel centres at +1/2;
+alpha clamp 0.99, skip below 1/255, stop before the kernel that would take the
+transmittance below 1e-4; 3-sigma extents; the per-direction half box.
+
+Two modes:
+  "e2e"  float64 throughout;
+  "rec"  preprocess in float64, then each stored record field rounded to
+         float32 exactly as the GPU record stores it (centre relative to the
+         rect corner, conic, half-factor vector, alpha2, delta-opacity,
+         colour), then blending in float64 on those values.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+F64 = torch.float64
+
+DEFAULT_OPTIONS = dict(
+    tile=16,            # tile edge in pixels (outputs do not depend on it)
+    lowpass=0.3,        # screen-space dilation added to the 2x2 covariance, px^2
+    kappa=3.0,          # sigma extent of the valid region (3-sigma, Supp. B.1)
+    alpha_min=1.0 / 255.0,
+    alpha_max=0.99,
+    t_min=1e-4,
+    fov_clamp=1.3,
+    bg=(0.0, 0.0, 0.0),
+    full_box=False,     # True: both halves splatted with the full ellipse box
+)
+
+
+def options(**kw) -> dict:
+    o = dict(DEFAULT_OPTIONS)
+    o.update(kw)
+    return o
+
+
+# ---------------------------------------------------------------------------
+# inputs
+# ---------------------------------------------------------------------------
+PARAM_KEYS = ("means", "scales", "quats", "normals", "opac1", "opac2", "sh")
+
+
+def scene_to_torch(scene: dict, requires_grad: bool = False) -> dict:
+    """float32 numpy scene -> float64 torch tensors (leaf tensors)."""
+    out = {}
+    for k in PARAM_KEYS:
+        t = torch.tensor(np.asarray(scene[k], np.float64), dtype=F64)
+        if requires_grad:
+            t.requires_grad_(True)
+        out[k] = t
+    out["sh_degree"] = int(scene["sh_degree"])
+    return out
+
+
+def camera_to_torch(cam: dict) -> dict:
+    c = dict(cam)
+    c["R"] = torch.tensor(np.asarray(cam["R"], np.float64), dtype=F64)
+    c["t"] = torch.tensor(np.asarray(cam["t"], np.float64), dtype=F64)
+    for k in ("fx", "fy", "cx", "cy", "znear"):
+        c[k] = float(np.float32(cam[k]))
+    return c
+
+
+# ---------------------------------------------------------------------------
+# geometry pieces
+# ---------------------------------------------------------------------------
+def quat_to_rotmat(q: torch.Tensor) -> torch.Tensor:
+    """Rotation matrix of the normalised quaternion (w, x, y, z) -- the R of
+    Eq. 2.  A zero quaternion maps to the identity."""
+    nrm = torch.linalg.norm(q, dim=-1, keepdim=True)
+    zero = nrm == 0
+    unit = torch.tensor([1.0, 0.0, 0.0, 0.0], dtype=F64).expand_as(q)
+    q = torch.where(zero, unit, q / torch.where(zero, torch.ones_like(nrm), nrm))
+    w, x, y, z = q.unbind(-1)
+    rows = [
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1),
+    ]
+    return torch.stack(rows, -2)
+
+
+def world_covariance(scales: torch.Tensor, quats: torch.Tensor) -> torch.Tensor:
+    """Eq. 2: Sigma_w = R S S^T R^T with S = diag(scales)."""
+    R = quat_to_rotmat(quats)
+    RS = R * scales.unsqueeze(-2)
+    return RS @ RS.transpose(-1, -2)
+
+
+def sh_basis(d: torch.Tensor, degree: int) -> torch.Tensor:
+    """Real spherical harmonics up to ``degree`` (<= 3) at unit directions d,
+    ordered l = 0..D, m = -l..l, including the Condon-Shortley phase (the
+    colour model the paper inherits from 3D-GS, Sec. 3.1).  Each function is
+    the textbook Cartesian polynomial times its normalisation constant."""
+    x, y, z = d.unbind(-1)
+    pi = math.pi
+    out = [torch.full_like(x, 0.5 / math.sqrt(pi))]
+    if degree >= 1:
+        c1 = math.sqrt(3.0 / (4.0 * pi))
+        out += [-c1 * y, c1 * z, -c1 * x]
+    if degree >= 2:
+        a = 0.5 * math.sqrt(15.0 / pi)
+        b = 0.25 * math.sqrt(5.0 / pi)
+        c = 0.25 * math.sqrt(15.0 / pi)
+        xx, yy, zz = x * x, y * y, z * z
+        out += [a * x * y, -a * y * z, b * (2 * zz - xx - yy), -a * x * z, c * (xx - yy)]
+    if degree >= 3:
+        xx, yy, zz = x * x, y * y, z * z
+        k33 = 0.25 * math.sqrt(35.0 / (2.0 * pi))
+        k32 = 0.5 * math.sqrt(105.0 / pi)
+        k31 = 0.25 * math.sqrt(21.0 / (2.0 * pi))
+        k30 = 0.25 * math.sqrt(7.0 / pi)
+        k22 = 0.25 * math.sqrt(105.0 / pi)
+        out += [
+            -k33 * y * (3 * xx - yy),
+            k32 * x * y * z,
+            -k31 * y * (4 * zz - xx - yy),
+            k30 * z * (2 * zz - 3 * xx - 3 * yy),
+            -k31 * x * (4 * zz - xx - yy),
+            k22 * z * (xx - yy),
+            -k33 * x * (xx - 3 * yy),
+        ]
+    return torch.stack(out, -1)
+
+
+def splitting_covariance(Sigma_w: torch.Tensor, n_hat: torch.Tensor) -> torch.Tensor:
+    """Alg. 1 (Supp. B.1): covariance of the flattened ellipsoid that stands
+    for the splitting plane.  The in-plane block is the Schur complement of
+    the covariance expressed in the plane basis (v1, v2, n), and the normal
+    variance is one hundredth of the smaller in-plane variance."""
+    nx, ny, nz = n_hat.unbind(-1)
+    special = (nx == 0) & (ny == 0)
+    e1 = torch.tensor([1.0, 0.0, 0.0], dtype=F64).expand_as(n_hat)
+    e2 = torch.tensor([0.0, 1.0, 0.0], dtype=F64).expand_as(n_hat)
+    v1 = torch.stack([ny, -nx, torch.zeros_like(nx)], -1)
+    v1n = torch.linalg.norm(v1, dim=-1, keepdim=True)
+    v1 = torch.where(special.unsqueeze(-1), e1, v1 / torch.where(v1n == 0, torch.ones_like(v1n), v1n))
+    v2 = torch.linalg.cross(n_hat, v1)
+    v2n = torch.linalg.norm(v2, dim=-1, keepdim=True)
+    v2 = torch.where(special.unsqueeze(-1), e2, v2 / torch.where(v2n == 0, torch.ones_like(v2n), v2n))
+    B = torch.stack([v1, v2, n_hat], -1)                      # columns
+    C = B.transpose(-1, -2) @ Sigma_w @ B
+    a_ = C[..., 0, 0] - C[..., 0, 2] ** 2 / C[..., 2, 2]
+    b_ = C[..., 0, 1] - C[..., 0, 2] * C[..., 1, 2] / C[..., 2, 2]
+    c_ = C[..., 1, 1] - C[..., 1, 2] ** 2 / C[..., 2, 2]
+    z = torch.zeros_like(a_)
+    S = torch.stack([torch.stack([a_, b_, z], -1),
+                     torch.stack([b_, c_, z], -1),
+                     torch.stack([z, z, torch.minimum(a_, c_) / 100.0], -1)], -2)
+    return B @ S @ B.transpose(-1, -2)
+
+
+def _geometry(sc: dict, cam: dict, o: dict, idx: torch.Tensor) -> dict:
+    """Continuous per-kernel quantities for kernels ``idx`` of one camera."""
+    mu = sc["means"][idx]
+    Rc, tc = cam["R"], cam["t"]
+    W, H = cam["width"], cam["height"]
+    fx, fy, cx, cy = cam["fx"], cam["fy"], cam["cx"], cam["cy"]
+
+    t = mu @ Rc.T + tc                                        # camera space
+    tx, ty, tz = t.unbind(-1)
+
+    Sw = world_covariance(sc["scales"][idx], sc["quats"][idx])  # Eq. 2
+
+    # Eq. 3: local affine approximation of the projection (Jacobian rows for
+    # the two screen coordinates; the third row never enters the result).
+    lx = o["fov_clamp"] * W / (2.0 * fx)
+    ly = o["fov_clamp"] * H / (2.0 * fy)
+    xc = torch.clamp(tx / tz, -lx, lx)
+    yc = torch.clamp(ty / tz, -ly, ly)
+    zero = torch.zeros_like(tz)
+    J = torch.stack([torch.stack([fx / tz, zero, -fx * xc / tz], -1),
+                     torch.stack([zero, fy / tz, -fy * yc / tz], -1)], -2)
+    M = J @ Rc                                                # 2x3 world -> screen
+    lam = o["lowpass"] * torch.eye(2, dtype=F64)
+    Shat = M @ Sw @ M.transpose(-1, -2) + lam                 # Eq. 6 (+ dilation)
+    A, B, C = Shat[..., 0, 0], Shat[..., 0, 1], Shat[..., 1, 1]
+    det = A * C - B * B
+    conic = torch.stack([C / det, -B / det, A / det], -1)     # inverse (a, b, c)
+    mean2d = torch.stack([fx * tx / tz + cx, fy * ty / tz + cy], -1)
+
+    # Eq. 7-8 in camera-space form: (screen offset, plane value) is jointly
+    # Gaussian; the half factor is 2 * P(plane value >= 0 | screen offset).
+    n = sc["normals"][idx]
+    nn = torch.linalg.norm(n, dim=-1, keepdim=True)
+    nzero = (nn == 0).squeeze(-1)
+    n_hat = n / torch.where(nn == 0, torch.ones_like(nn), nn)
+    Sn = (Sw @ n_hat.unsqueeze(-1)).squeeze(-1)
+    g = (M @ Sn.unsqueeze(-1)).squeeze(-1)                    # Cov(offset, plane)
+    v = (n_hat * Sn).sum(-1)                                  # Var(plane)
+    Q = torch.stack([torch.stack([conic[..., 0], conic[..., 1]], -1),
+                     torch.stack([conic[..., 1], conic[..., 2]], -1)], -2)
+    w = (Q @ g.unsqueeze(-1)).squeeze(-1)
+    s2 = torch.maximum(v - (g * w).sum(-1), 1e-12 * v)        # conditional variance
+    s2safe = torch.where(nzero | (s2 <= 0), torch.ones_like(s2), s2)
+    k = w / torch.sqrt(2.0 * s2safe).unsqueeze(-1)
+    k = torch.where(nzero.unsqueeze(-1), torch.zeros_like(k), k)
+
+    # SH colour (Sec. 3.1), view direction from the camera centre.
+    o_cam = -(Rc.T @ tc)
+    dvec = mu - o_cam
+    d = dvec / torch.linalg.norm(dvec, dim=-1, keepdim=True)
+    deg = sc["sh_degree"]
+    Y = sh_basis(d, deg)                                      # [n, K]
+    shc = sc["sh"][idx][:, : (deg + 1) ** 2, :]
+    colour = torch.clamp((Y.unsqueeze(-1) * shc).sum(-2) + 0.5, min=0.0)
+
+    a1 = sc["opac1"][idx]
+    a2 = sc["opac2"][idx]
+    return dict(t=t, tz=tz, Sw=Sw, M=M, Shat=Shat, det=det, conic=conic, mean2d=mean2d,
+                n_hat=n_hat, nzero=nzero, g=g, v=v, k=k, colour=colour,
+                alpha2=a2, d_o=(a1 - a2) / 2.0, a1=a1, a2=a2)
+
+
+def _half_box(geo: dict, o: dict):
+    """Sec. 3.4 + Supp. B.1: extents (E-x, E+x, E-y, E+y) of the union of the
+    splatted halves, and whether any half is splatted.  +y points down the
+    image."""
+    kap = o["kappa"]
+    Sh = geo["Shat"]
+    ex = kap * torch.sqrt(Sh[..., 0, 0])
+    ey = kap * torch.sqrt(Sh[..., 1, 1])
+    if o["full_box"]:
+        ones = torch.ones_like(ex, dtype=torch.bool)
+        return (ex, ex, ey, ey), ones, (ex, ey, ex, ey)
+    Ss = splitting_covariance(geo["Sw"], geo["n_hat"])
+    lam = o["lowpass"] * torch.eye(2, dtype=F64)
+    Shs = geo["M"] @ Ss @ geo["M"].transpose(-1, -2) + lam
+    cx_ = torch.minimum(kap * torch.sqrt(Shs[..., 0, 0]), ex)
+    cy_ = torch.minimum(kap * torch.sqrt(Shs[..., 1, 1]), ey)
+    nz = geo["nzero"]
+    cx_ = torch.where(nz, ex, cx_)
+    cy_ = torch.where(nz, ey, cy_)
+    gx, gy = geo["g"].unbind(-1)
+    splat1 = geo["a1"] >= o["alpha_min"]
+    splat2 = geo["a2"] >= o["alpha_min"]
+    ext = []
+    for sgn, splat in ((1.0, splat1), (-1.0, splat2)):
+        e_mx = torch.where(sgn * gx <= 0, ex, cx_)
+        e_px = torch.where(sgn * gx >= 0, ex, cx_)
+        e_my = torch.where(sgn * gy <= 0, ey, cy_)
+        e_py = torch.where(sgn * gy >= 0, ey, cy_)
+        neg = torch.full_like(ex, -math.inf)
+        ext.append([torch.where(splat, e, neg) for e in (e_mx, e_px, e_my, e_py)])
+    union = tuple(torch.maximum(ext[0][i], ext[1][i]) for i in range(4))
+    return union, splat1 | splat2, (ex, ey, cx_, cy_)
+
+
+def preprocess(sc: dict, cam: dict, o: dict | None = None) -> dict:
+    """Per-kernel projection for one camera.  Returns a dict with the culling
+    mask ``valid`` [N], integer pixel rect [N,4] = (x0, x1, y0, y1), tile rect,
+    tiles_touched, fp32 depth bits, and the differentiable record fields of
+    the valid kernels (indexed by ``idx``)."""
+    o = options() if o is None else o
+    N = sc["means"].shape[0]
+    W, H, T = cam["width"], cam["height"], o["tile"]
+    all_idx = torch.arange(N)
+    with torch.no_grad():
+        det_sc = {k: (v.detach() if torch.is_tensor(v) else v) for k, v in sc.items()}
+        geo = _geometry(det_sc, cam, o, all_idx)
+        tz = geo["tz"]
+        ok = torch.isfinite(tz) & (tz > cam["znear"])
+        ok &= torch.isfinite(geo["det"]) & (geo["det"] > 0)
+        for key in ("mean2d", "conic", "k", "colour"):
+            ok &= torch.isfinite(geo[key]).all(-1)
+        (e_mx, e_px, e_my, e_py), splat_any, _ = _half_box(geo, o)
+        ok &= splat_any
+        mx, my = geo["mean2d"].unbind(-1)
+        lo_x = mx - e_mx - 0.5
+        hi_x = mx + e_px - 0.5
+        lo_y = my - e_my - 0.5
+        hi_y = my + e_py - 0.5
+        edges = torch.stack([lo_x, hi_x, lo_y, hi_y], -1)
+        ok &= torch.isfinite(edges).all(-1)
+        big = 1e9
+        ce = torch.clamp(edges, -big, big)
+        x0 = torch.clamp(torch.ceil(ce[:, 0]), min=0).to(torch.int64)
+        x1 = torch.clamp(torch.floor(ce[:, 1]), max=W - 1).to(torch.int64)
+        y0 = torch.clamp(torch.ceil(ce[:, 2]), min=0).to(torch.int64)
+        y1 = torch.clamp(torch.floor(ce[:, 3]), max=H - 1).to(torch.int64)
+        ok &= (x0 <= x1) & (y0 <= y1)
+        rect = torch.stack([x0, x1, y0, y1], -1)
+        trect = torch.stack([x0 // T, x1 // T, y0 // T, y1 // T], -1)
+        tiles = ((trect[:, 1] - trect[:, 0] + 1) * (trect[:, 3] - trect[:, 2] + 1))
+        tiles = torch.where(ok, tiles, torch.zeros_like(tiles))
+        depth_bits = np.where(ok.numpy(), tz.numpy(), 1.0).astype(np.float32).view(np.uint32)
+    idx = torch.nonzero(ok).squeeze(-1)
+    rec = _geometry(sc, cam, o, idx)
+    return dict(N=N, valid=ok, idx=idx, rect=rect, trect=trect, tiles_touched=tiles,
+                depth_bits=depth_bits, edges=edges, rec=rec, cam=cam, opts=o,
+                tiles_x=(W + T - 1) // T, tiles_y=(H + T - 1) // T)
+
+
+# ---------------------------------------------------------------------------
+# sort
+# ---------------------------------------------------------------------------
+def bin_sort(pres: list) -> dict:
+    """Key/value lists of the tile rasterizer over all cameras: one entry per
+    (record, covered tile), key = global tile << 32 | fp32 depth bits, value =
+    record id = camera * N + kernel, sorted by (key, value)."""
+    keys, vals = [], []
+    tile_off = 0
+    for c, pre in enumerate(pres):
+        N = pre["N"]
+        idx = pre["idx"].numpy()
+        tr = pre["trect"].numpy()[idx]
+        wdt = tr[:, 1] - tr[:, 0] + 1
+        cnt = wdt * (tr[:, 3] - tr[:, 2] + 1)
+        rec = np.repeat(np.arange(idx.size), cnt)
+        first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        j = np.arange(int(cnt.sum())) - first             # index inside a record's rect
+        tx = tr[rec, 0] + j % wdt[rec]
+        ty = tr[rec, 2] + j // wdt[rec]
+        tiles = (tile_off + ty * pre["tiles_x"] + tx).astype(np.uint64)
+        keys.append((tiles << np.uint64(32)) | pre["depth_bits"][idx][rec].astype(np.uint64))
+        vals.append((c * N + idx[rec]).astype(np.uint64))
+        tile_off += pre["tiles_x"] * pre["tiles_y"]
+    keys = np.concatenate(keys) if keys else np.zeros(0, np.uint64)
+    vals = np.concatenate(vals) if vals else np.zeros(0, np.uint64)
+    order = np.lexsort((vals, keys))
+    keys, vals = keys[order], vals[order].astype(np.uint32)
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    starts = np.searchsorted(tiles, np.arange(tile_off), side="left")
+    ends = np.searchsorted(tiles, np.arange(tile_off), side="right")
+    ranges = np.stack([starts, ends], 1).astype(np.uint32)
+    return dict(keys=keys, vals=vals, ranges=ranges, tiles_total=tile_off)
+
+
+# ---------------------------------------------------------------------------
+# records as the raster reads them
+# ---------------------------------------------------------------------------
+def raster_records(pre: dict, mode: str = "e2e") -> dict:
+    """Record fields of the valid kernels, sorted by (depth bits, id)."""
+    rec, idx = pre["rect"][pre["idx"]], pre["idx"]
+    g = pre["rec"]
+    corner = torch.stack([rec[:, 0], rec[:, 2]], -1).to(F64)
+    fields = dict(mu_rel=g["mean2d"] - corner, conic=g["conic"], k=g["k"],
+                  alpha2=g["alpha2"], d_o=g["d_o"], colour=g["colour"])
+    if mode == "rec":
+        fields = {k: torch.tensor(v.detach().numpy().astype(np.float32).astype(np.float64))
+                  for k, v in fields.items()}
+    elif mode != "e2e":
+        raise ValueError(mode)
+    order = np.lexsort((idx.numpy(), pre["depth_bits"][idx.numpy()]))
+    order_t = torch.from_numpy(order)
+    out = {k: v[order_t] for k, v in fields.items()}
+    out["rect"] = rec[order_t]
+    out["id"] = idx[order_t]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# blending
+# ---------------------------------------------------------------------------
+def _composite(recs: dict, cand: torch.Tensor, px: torch.Tensor, py: torch.Tensor, o: dict):
+    """Blend pixels (px, py) over candidate records ``cand`` (indices into the
+    depth-sorted records).  Returns colour [P,3], T_final [P], count [P],
+    last position [P] (index into cand, -1 if none) and the smallest relative
+    distance of any decision to its threshold [P]."""
+    r = recs["rect"][cand]
+    inside = ((px[:, None] >= r[None, :, 0]) & (px[:, None] <= r[None, :, 1]) &
+              (py[:, None] >= r[None, :, 2]) & (py[:, None] <= r[None, :, 3]))
+    dx = (px[:, None] - r[None, :, 0]).to(F64) + 0.5 - recs["mu_rel"][cand][None, :, 0]
+    dy = (py[:, None] - r[None, :, 2]).to(F64) + 0.5 - recs["mu_rel"][cand][None, :, 1]
+    a_, b_, c_ = recs["conic"][cand].unbind(-1)
+    quad = a_ * dx * dx + c_ * dy * dy
+    cross = b_ * dx * dy
+    power = -0.5 * quad - cross
+    G = torch.exp(torch.where(inside, power, torch.zeros_like(power)))
+    kx, ky = recs["k"][cand].unbind(-1)
+    I = torch.special.erfc(-(kx * dx + ky * dy))
+    HG = (recs["alpha2"][cand] + recs["d_o"][cand] * I) * G           # Eq. 10
+    alpha = torch.minimum(HG, torch.full_like(HG, o["alpha_max"]))
+    with torch.no_grad():
+        live = inside & (power <= 0)
+        contrib = live & (alpha >= o["alpha_min"])
+        a_c = torch.where(contrib, alpha, torch.zeros_like(alpha))
+        T_after = torch.cumprod(1.0 - a_c, dim=1)
+        crossing = contrib & (T_after < o["t_min"])
+        stopped = torch.cumsum(crossing.to(torch.int64), dim=1) > 0
+        blend = contrib & ~stopped
+        # decisions that were taken (up to and including the crossing kernel)
+        before_or_at = ~(torch.cumsum(crossing.to(torch.int64), dim=1) - crossing.to(torch.int64) > 0)
+        evaluated = live & before_or_at
+        inf = torch.full_like(alpha, math.inf)
+        rel_a = torch.where(evaluated, (alpha - o["alpha_min"]).abs() / o["alpha_min"], inf)
+        rel_t = torch.where(contrib & before_or_at, (T_after - o["t_min"]).abs() / o["t_min"], inf)
+        terms = 0.5 * (a_.abs() * dx * dx + c_.abs() * dy * dy) + cross.abs()
+        rel_p = torch.where(inside, power.abs() / torch.clamp(terms, min=1e-300), inf)
+        margin = torch.minimum(torch.minimum(rel_a, rel_t), rel_p).min(dim=1).values \
+            if cand.numel() else torch.full((px.shape[0],), math.inf, dtype=F64)
+        count = blend.sum(1)
+        pos = torch.arange(cand.numel()).expand_as(blend)
+        last = torch.where(blend, pos, torch.full_like(pos, -1)).max(1).values \
+            if cand.numel() else torch.full((px.shape[0],), -1, dtype=torch.int64)
+    a_b = torch.where(blend, alpha, torch.zeros_like(alpha))
+    one_m = 1.0 - a_b
+    T_incl = torch.cumprod(one_m, dim=1)
+    T_before = torch.cat([torch.ones_like(T_incl[:, :1]), T_incl[:, :-1]], 1)
+    w = a_b * T_before
+    colour = w @ recs["colour"][cand] if cand.numel() else torch.zeros(px.shape[0], 3, dtype=F64)
+    T_final = T_incl[:, -1] if cand.numel() else torch.ones(px.shape[0], dtype=F64)
+    bg = torch.tensor(o["bg"], dtype=F64)
+    out = colour + T_final[:, None] * bg
+    return out, T_final, count, last, margin
+
+
+def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64) -> dict:
+    """Blend the pixels of one camera.  ``pixels`` is an int array [P,2] of
+    (px, py), or None for the full frame.  Returns image values [P,3] (or the
+    [3,H,W] image), T_final, n_contrib, the record id of the last blended
+    kernel (-1 if none) and the decision margin per pixel."""
+    cam, o = pre["cam"], pre["opts"]
+    W, H = cam["width"], cam["height"]
+    recs = raster_records(pre, mode)
+    full = pixels is None
+    if full:
+        yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        # group pixels in 16x16 blocks so each chunk has few candidates
+        bx, by = xx // 16, yy // 16
+        order = np.lexsort((xx.ravel(), yy.ravel(), bx.ravel(), by.ravel()))
+        pixels = np.stack([xx.ravel(), yy.ravel()], 1)[order]
+        chunk = 256
+    pixels = torch.as_tensor(np.asarray(pixels), dtype=torch.int64)
+    rect = recs["rect"]
+    outs, Ts, cnts, lasts, margins = [], [], [], [], []
+    for s in range(0, pixels.shape[0], chunk):
+        px, py = pixels[s:s + chunk, 0], pixels[s:s + chunk, 1]
+        hit = ((rect[:, 0] <= px.max()) & (rect[:, 1] >= px.min()) &
+               (rect[:, 2] <= py.max()) & (rect[:, 3] >= py.min()))
+        cand = torch.nonzero(hit).squeeze(-1)
+        if cand.numel() > 4096:  # sparse pixel sets: keep only per-pixel hits
+            r = rect[cand]
+            any_in = ((px[:, None] >= r[None, :, 0]) & (px[:, None] <= r[None, :, 1]) &
+                      (py[:, None] >= r[None, :, 2]) & (py[:, None] <= r[None, :, 3])).any(0)
+            cand = cand[any_in]
+        out, T, cnt, last, mg = _composite(recs, cand, px, py, o)
+        lasts.append(torch.where(last >= 0, recs["id"][cand][last.clamp(min=0)] if cand.numel() else last,
+                                 torch.full_like(last, -1)))
+        outs.append(out)
+        Ts.append(T)
+        cnts.append(cnt)
+        margins.append(mg)
+    out = torch.cat(outs)
+    res = dict(values=out, T_final=torch.cat(Ts), n_contrib=torch.cat(cnts),
+               last_id=torch.cat(lasts), margin=torch.cat(margins), pixels=pixels)
+    if full:
+        inv = np.empty_like(order)
+        inv[order] = np.arange(order.size)
+        inv_t = torch.from_numpy(inv)
+        res["image"] = out[inv_t].T.reshape(3, H, W)
+        for k in ("T_final", "n_contrib", "last_id", "margin"):
+            res[k] = res[k][inv_t].reshape(H, W)
+    return res
+
+
+def render_grad(scene: dict, cams: list, dL_dout: list, o: dict | None = None, pixels=None) -> dict:
+    """Gradient of L = sum_c <dL_dout[c], image_c> with respect to every
+    kernel parameter, as autograd of the end-to-end FP64 forward.  With
+    ``pixels`` (a list of [P,2] arrays, one per camera), dL_dout[c] is [P,3]
+    and only those pixels are rendered."""
+    o = options() if o is None else o
+    sc = scene_to_torch(scene, requires_grad=True)
+    L = torch.zeros((), dtype=F64)
+    for c, cam in enumerate(cams):
+        pre = preprocess(sc, camera_to_torch(cam), o)
+        if pixels is None:
+            img = render(pre, "e2e")["image"]
+            L = L + (img * torch.as_tensor(np.asarray(dL_dout[c], np.float64))).sum()
+        else:
+            vals = render(pre, "e2e", pixels=pixels[c])["values"]
+            L = L + (vals * torch.as_tensor(np.asarray(dL_dout[c], np.float64))).sum()
+    grads = torch.autograd.grad(L, [sc[k] for k in PARAM_KEYS], allow_unused=True)
+    return {k: (g.numpy() if g is not None else np.zeros(sc[k].shape)) for k, g in zip(PARAM_KEYS, grads)}
+
+
+# ---------------------------------------------------------------------------
+# convenience
+# ---------------------------------------------------------------------------
+def forward(scene: dict, cams: list, o: dict | None = None, mode: str = "e2e") -> list:
+    """Full-frame render of every camera; list of ``render`` results."""
+    o = options() if o is None else o
+    sc = scene_to_torch(scene)
+    out = []
+    with torch.no_grad():
+        for cam in cams:
+            out.append(render(preprocess(sc, camera_to_torch(cam), o), mode))
+    return out
