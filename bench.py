@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the half-Gaussian tile rasterizer on one GPU.
+
+One step = one forward + backward pass of the whole rasterizer over the
+workload's views: hgs_preprocess, hgs_bin_sort, hgs_render_fwd, the L1 loss
+gradient against a seeded target, hgs_render_bwd.  Inputs (parameters,
+target) are resident in HBM before timing starts; buffers are allocated once.
+
+Default workload: 1M half-Gaussians, one 1920x1080 camera, SH degree 3,
+FP32 (shell + box mixture, log-scales N(-4, 1)).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector (256 CU x 2.4 GHz)
+
+WORKLOADS = {
+    3: "1M half-Gaussians, 1920x1080, SH deg 3, fwd+bwd (shell+box mixture)",
+    2: "100k half-Gaussians, 1280x720, SH deg 3, fwd+bwd",
+    1: "1k half-Gaussians, 128x128, SH deg 0, fwd+bwd",
+    4: "500k half-Gaussians, 16 views of uneven size, SH deg 3, fwd+bwd",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--cpu-pixels", type=int, default=256, help="pixels of the oracle CPU sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stages", action="store_true", help="print per-stage timings to stderr")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(views would shard across GPUs with one gradient all-reduce; not built).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2406_02720_amd import binding as B
+    from paper_2406_02720_amd import raster as R
+    from paper_2406_02720_amd import scenes
+
+    B.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    scene, cams = scenes.make_config(args.config)
+    n = scene["means"].shape[0]
+    deg = scene["sh_degree"]
+    soa = R.scene_to_soa(scene, dev)
+    ca = B.make_cameras(cams)
+    opts = B.default_options(tile=args.tile, batch=args.batch)
+    targets = scenes.target_image(cams, seed=102)
+    target = torch.cat([torch.as_tensor(t).reshape(-1) for t in targets]).to(dev)
+
+    # sizing pass (not timed): entry count of this fixed scene
+    fr = R.forward_pass(soa, n, deg, ca, opts)
+    torch.cuda.synchronize()
+    n_dup = int(fr.n_dup.item())
+    cap = n_dup
+    n_rec = n * len(cams)
+    tiles_total = B.hgs_tiles_total(ca, opts)
+    npix = B.hgs_pixels_total(ca)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def buf(nbytes):
+        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
+
+    params = B.params_struct(soa, n, n, deg)
+    grads = torch.zeros_like(soa)
+    gstruct = B.grads_struct(grads, n)
+    records = buf(n_rec * 64)
+    tiles = torch.empty(n_rec, dtype=torch.int32, device=dev)
+    offsets = torch.empty(n_rec, dtype=torch.int64, device=dev)
+    ndup = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws_pre = buf(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, ca, opts))
+    keys = torch.empty(cap, dtype=torch.int64, device=dev)
+    values = torch.empty(cap, dtype=torch.int32, device=dev)
+    ranges = torch.empty(2 * tiles_total, dtype=torch.int32, device=dev)
+    overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws_sort = buf(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, ca, opts, cap))
+    images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+    T_final = torch.empty(npix, dtype=torch.float32, device=dev)
+    last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
+    n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+    ws_r = buf(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts))
+    rgrad = torch.empty(n_rec * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
+    dL = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+    inv_numel = 1.0 / float(3 * npix)
+
+    stage_names = ["preprocess", "bin_sort", "render_fwd", "loss_grad", "render_bwd"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        B.hgs_preprocess(params, ca, opts, records, tiles, offsets, ndup, ws_pre, stream)
+        mark(1)
+        B.hgs_bin_sort(records, tiles, offsets, ndup, n_rec, ca, opts, keys, values, cap, ranges, overflow,
+                       ws_sort, stream)
+        mark(2)
+        B.hgs_render_fwd(records, values, ranges, ca, opts, images, T_final, last_idx, n_contrib, ws_r, stream)
+        mark(3)
+        torch.sub(images, target, out=dL)
+        torch.sign(dL, out=dL)
+        dL.mul_(inv_numel)
+        mark(4)
+        B.hgs_render_bwd(params, ca, opts, records, values, ranges, T_final, last_idx, dL, rgrad, gstruct,
+                         ws_r, stream)
+        mark(5)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert int(overflow.item()) == 0
+
+    # whole-step timing, nothing else in the stream
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+
+    # per-stage timing (separate run, events between the stage calls)
+    stage_ms = np.zeros(5)
+    for _ in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        step(ev)
+        torch.cuda.synchronize()
+        for i in range(5):
+            stage_ms[i] += ev[i].elapsed_time(ev[i + 1])
+    stage_ms /= args.steps
+
+    fwd_ms = stage_ms[0] + stage_ms[1] + stage_ms[2]
+    bwd_ms = stage_ms[4]
+    W = sum(c["width"] * c["height"] for c in cams)
+    value = W / (ms_step * 1e-3) / 1e6
+
+    # algorithmic bytes per stage (what the method must move)
+    sh_floats = 3 * (deg + 1) ** 2
+    param_bytes = 4 * (15 + sh_floats)
+    passes = (32 + max(0, math.ceil(math.log2(max(tiles_total, 1)))) + 7) // 8
+    bytes_pre = n * param_bytes + n_rec * (64 + 4) + n_rec * (4 + 4 + 8)
+    bytes_sort = (n_rec * (8 + 4 + 12) + n_dup * 12 + n_dup * 8 + passes * n_dup * 24 + n_dup * 8
+                  + tiles_total * 8)
+    stage_bytes = {"preprocess": bytes_pre, "bin_sort": bytes_sort}
+    roof = {}
+    for i, name in enumerate(stage_names):
+        if name in stage_bytes:
+            gbs = stage_bytes[name] / (stage_ms[i] * 1e-3) / 1e9
+            roof[name] = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(gbs / HBM_PEAK_GBS, 4), bytes=int(stage_bytes[name]),
+                              ms=round(float(stage_ms[i]), 4))
+    dominant = "bin_sort"
+    roofline = dict(roof[dominant])
+    roofline["kernel"] = dominant
+    roofline["traffic"] = None
+    roofline.pop("ms", None)
+    roofline.pop("bytes", None)
+
+    if args.stages:
+        for i, name in enumerate(stage_names):
+            print(f"{name:12s} {stage_ms[i]:8.3f} ms", file=sys.stderr)
+        print(f"n_dup {n_dup}  passes {passes}  step {ms_step:.3f} ms", file=sys.stderr)
+        print(json.dumps(roof), file=sys.stderr)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cams, args.cpu_pixels)
+
+    out = {
+        "metric": "fwd+bwd Mpixel/s at 1M half-Gaussians 1080p; bwd/fwd time ratio; % HBM roof",
+        "value": round(value, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS.get(args.config, str(args.config)), "n_kernels": n,
+                   "views": len(cams), "pixels": W, "tile": args.tile, "batch": args.batch,
+                   "entries": n_dup},
+        "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
+        "fwd_bwd_over_fwd": round((fwd_ms + bwd_ms) / fwd_ms, 3),
+        "stage_ms": {k: round(float(v), 4) for k, v in zip(stage_names, stage_ms)},
+        "roofline": roofline,
+        "roofline_stages": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(scene, cams, n_pix):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    workload: full preprocess of every kernel plus forward and backward of
+    ``n_pix`` seeded pixels; the rate is extrapolated to a full frame
+    (per-pixel work is independent)."""
+    import numpy as np
+    import torch
+
+    from oracle import hgs_oracle as O
+    from paper_2406_02720_amd import scenes
+
+    o = O.options()
+    cam = cams[0]
+    pix = scenes.sample_pixels(cam, n_pix, seed=5)
+    rng = np.random.default_rng(1)
+    w = rng.normal(size=(n_pix, 3))
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        O.preprocess(O.scene_to_torch(scene), O.camera_to_torch(cam), o)
+    t_pre = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.render_grad(scene, [cam], [w], o, pixels=[pix])
+    t_all = time.perf_counter() - t0
+    per_pix = max(t_all - t_pre, 1e-9) / n_pix
+    full = t_pre + per_pix * cam["width"] * cam["height"]
+    return {"value": round(cam["width"] * cam["height"] / full / 1e6, 9), "unit": "Mpixel/s",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{n_pix} seeded pixels of view 0, fwd+bwd with all kernels preprocessed; "
+                      f"{t_all:.1f} s measured, full frame extrapolated ({full:.0f} s)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * hgs.h -- C ABI of the MI355X tile rasterizer for 3D half-Gaussian splatting.
+ *
+ * The library renders scenes of half-Gaussian kernels (3D-HGS): every kernel
+ * is a 3-D Gaussian (centre, scales, rotation; Eq. 1-2 of the paper) split by
+ * a plane through its centre with unit normal n, the half on the +n side
+ * carrying opacity alpha1 and the other half alpha2 (Sec. 3.2).  A pixel
+ * blends the kernels that cover it front to back with the paired-half
+ * opacity of Eq. 10 (Sec. 3.3).  The valid screen region of each kernel is
+ * the half-aware box of Sec. 3.4, built from the splitting ellipse of Alg. 1
+ * (Supp. B.1).
+ *
+ * Pipeline (each call only enqueues work on `stream`; nothing blocks):
+ *   hgs_preprocess  projection, half factor, valid region, SH colour, depth,
+ *                   tiles touched and their exclusive scan
+ *   hgs_bin_sort    one (tile | depth, record) entry per covered tile, a
+ *                   stable radix sort of the 64-bit keys, per-tile ranges
+ *   hgs_render_fwd  per-pixel front-to-back blending
+ *   hgs_render_bwd  per-pixel back-to-front replay, per-record gradients,
+ *                   chain rule to every kernel parameter
+ *
+ * Conventions (the paper leaves them open):
+ *   - camera axes x right, y down, z forward; pixel (i, j) has its centre at
+ *     (i + 1/2, j + 1/2); records are sorted by camera-space z, ties by
+ *     record id;
+ *   - record id = camera * n + kernel; records of all cameras are stored
+ *     camera-major, [n_cams][n] records of HGS_RECORD_BYTES each;
+ *   - the low-pass `lowpass` (px^2) is added to the 2x2 screen covariance and
+ *     the half factor is taken on that dilated covariance;
+ *   - alpha = min(alpha_max, HG); a kernel with alpha < alpha_min is skipped;
+ *     blending stops before the kernel that would take the transmittance
+ *     below t_min.
+ *
+ * Memory: every pointer named "device" is device memory owned by the caller.
+ * The library never allocates device memory, never synchronises the stream
+ * and keeps no state between calls, so calls may be captured in a HIP graph.
+ * Host pointers (cameras, options, parameter structs) are read during the
+ * call only.
+ *
+ * Errors: every entry point returns HGS_OK (0) or a positive HGS_E* code,
+ * never throws, and leaves a message for hgs_last_error() (thread local).
+ */
+#ifndef HGS_H
+#define HGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HGS_OK 0
+#define HGS_EINVAL 1     /* an argument is out of range or a pointer is null */
+#define HGS_ECAPACITY 2  /* a caller buffer is smaller than the call needs   */
+#define HGS_EHIP 3       /* the HIP runtime reported an error                */
+
+#define HGS_MAX_CAMERAS 32       /* cameras per call                           */
+#define HGS_MAX_IMAGE_SIDE 16384 /* width and height limit                     */
+#define HGS_RECORD_BYTES 64      /* one projected record                       */
+#define HGS_RECORD_GRAD_FLOATS 12 /* per-record gradient accumulators          */
+
+/* options.flags */
+#define HGS_FLAG_FULL_BOX 1u     /* splat both halves with the full ellipse box,
+                                    no half-aware region and no opacity cull  */
+
+/* Pinhole camera.  R is the world->camera rotation (row-major 3x3), t the
+ * translation (x_cam = R x_world + t).  fx, fy, cx, cy in pixels.  Kernels
+ * with camera z <= znear are culled. */
+typedef struct hgs_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float znear;
+  int32_t reserved;
+} hgs_camera;
+
+/* Kernel parameters, structure of arrays, device pointers.  Plane p of a
+ * field is at ptr + p * stride, kernel i at element i (stride >= n):
+ *   means   3 planes  world centre
+ *   scales  3 planes  activated axis lengths (> 0)
+ *   quats   4 planes  rotation (w, x, y, z), any non-zero length; zero means
+ *                     the identity
+ *   normals 3 planes  splitting-plane normal, any length; zero means I = 1
+ *   opac1   1 plane   opacity of the +normal half, activated, in [0, 1]
+ *   opac2   1 plane   opacity of the -normal half
+ *   sh      3 (D+1)^2 planes, plane (k * 3 + channel) holds coefficient k of
+ *                     the real spherical harmonics of degree <= D (0..3)
+ * Non-finite inputs cull the kernel. */
+typedef struct hgs_params {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* normals;
+  const float* opac1;
+  const float* opac2;
+  const float* sh;
+  int64_t n;
+  int64_t stride;
+  int32_t sh_degree;
+  int32_t reserved;
+} hgs_params;
+
+/* Gradients of the scalar loss with respect to every field of hgs_params,
+ * same layout (device pointers, overwritten, not accumulated). */
+typedef struct hgs_param_grads {
+  float* means;
+  float* scales;
+  float* quats;
+  float* normals;
+  float* opac1;
+  float* opac2;
+  float* sh;
+} hgs_param_grads;
+
+/* Rasterizer options; hgs_default_options() fills the defaults given in
+ * brackets.  tile: tile edge in pixels, 8, 16 or 32 [16].  batch: records
+ * staged in on-chip memory per round, 128, 256 or 512 [256].  Outputs do not
+ * depend on tile or batch. */
+typedef struct hgs_options {
+  int32_t tile;
+  int32_t batch;
+  float lowpass;    /* [0.3]  px^2 added to the screen covariance            */
+  float kappa;      /* [3]    sigma extent of the valid region               */
+  float alpha_min;  /* [1/255]                                               */
+  float alpha_max;  /* [0.99]                                                */
+  float t_min;      /* [1e-4]                                                */
+  float fov_clamp;  /* [1.3]  clamp of x/z, y/z in the Jacobian, in units of
+                               the half field of view                        */
+  float bg[3];      /* [0]    background colour                              */
+  uint32_t flags;   /* [0]    HGS_FLAG_*                                     */
+} hgs_options;
+
+void hgs_default_options(hgs_options* opts);
+
+/* Workspace sizes (bytes) of the calls that take one.  `which` is one of the
+ * HGS_WS_* values; n_rec = n_cams * n; capacity = key capacity of
+ * hgs_bin_sort.  Returns 0 for invalid arguments. */
+#define HGS_WS_PREPROCESS 0
+#define HGS_WS_BIN_SORT 1
+#define HGS_WS_RENDER 2
+size_t hgs_workspace_bytes(int32_t which, int64_t n_rec, const hgs_camera* cams, int32_t n_cams,
+                           const hgs_options* opts, int64_t capacity);
+
+/* Number of tiles over all cameras (tile ids are global: the tiles of
+ * camera c follow those of cameras 0..c-1, row-major inside a camera). */
+int64_t hgs_tiles_total(const hgs_camera* cams, int32_t n_cams, const hgs_options* opts);
+
+/* Pixels over all cameras; camera c's per-pixel outputs start at the sum of
+ * width * height of cameras 0..c-1. */
+int64_t hgs_pixels_total(const hgs_camera* cams, int32_t n_cams);
+
+/* Projection of every (camera, kernel) pair -- Eq. 2, Eq. 3, Eq. 6 (+ the
+ * low-pass), the half factor of Eq. 7-8 in camera-space form, Alg. 1 and the
+ * half-aware region of Sec. 3.4, SH colour and depth.  Geometry is computed
+ * in FP64 and stored in FP32.
+ *   records        device, [n_cams * n] records of HGS_RECORD_BYTES (out)
+ *   tiles_touched  device, uint32 [n_cams * n], 0 for culled records (out)
+ *   offsets        device, uint64 [n_cams * n], exclusive prefix sum of
+ *                  tiles_touched (out)
+ *   n_dup          device, uint64 [1], sum of tiles_touched (out)
+ *   workspace      device, hgs_workspace_bytes(HGS_WS_PREPROCESS, ...) bytes
+ * Errors: HGS_EINVAL for null pointers, n < 0, stride < n, sh_degree not in
+ * 0..3, n_cams not in 1..HGS_MAX_CAMERAS, image sides not in
+ * 1..HGS_MAX_IMAGE_SIDE, invalid tile or batch; HGS_ECAPACITY if
+ * workspace_bytes is too small; HGS_EHIP on a launch failure. */
+int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
+                   const hgs_options* opts, void* records, uint32_t* tiles_touched,
+                   uint64_t* offsets, uint64_t* n_dup, void* workspace, size_t workspace_bytes,
+                   hipStream_t stream);
+
+/* Duplicate every record once per tile of its tile rectangle with key
+ * (global tile << 32 | fp32 depth bits) and value record id, sort the
+ * entries by key with a stable LSD radix sort (so equal keys stay in record
+ * order), and write the [start, end) range of every tile.
+ *   records, tiles_touched, offsets, n_dup   from hgs_preprocess (device)
+ *   n_rec          n_cams * n
+ *   keys, values   device, `capacity` entries each (out: sorted entries in
+ *                  the first *n_dup positions)
+ *   ranges         device, uint32 [tiles_total][2] (out)
+ *   overflow       device, int32 [1] (out): 0, or 1 when *n_dup > capacity;
+ *                  then no entry is written and every range is empty
+ *   workspace      device, hgs_workspace_bytes(HGS_WS_BIN_SORT, ...) bytes
+ * capacity must be below 2^32.  The device-side *n_dup decides how much work
+ * is done; capacity only bounds it (so a graph can be captured once with a
+ * generous capacity). */
+int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint64_t* offsets,
+                 const uint64_t* n_dup, int64_t n_rec, const hgs_camera* cams, int32_t n_cams,
+                 const hgs_options* opts, uint64_t* keys, uint32_t* values, int64_t capacity,
+                 uint32_t* ranges, int32_t* overflow, void* workspace, size_t workspace_bytes,
+                 hipStream_t stream);
+
+/* Front-to-back blending of every pixel of every camera (Sec. 3.3, Eq. 10).
+ *   images     device, float [3][H][W] per camera, camera c at 3 * pixel
+ *              offset c (out): blended colour + final transmittance * bg
+ *   T_final    device, float per pixel (out)
+ *   last_idx   device, int32 per pixel (out): position in `values` of the
+ *              last blended entry, -1 if none
+ *   n_contrib  device, int32 per pixel (out): number of blended kernels
+ *   workspace  device, hgs_workspace_bytes(HGS_WS_RENDER, ...) bytes */
+int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* ranges,
+                   const hgs_camera* cams, int32_t n_cams, const hgs_options* opts, float* images,
+                   float* T_final, int32_t* last_idx, int32_t* n_contrib, void* workspace,
+                   size_t workspace_bytes, hipStream_t stream);
+
+/* Gradient of a scalar loss L given dL/d(image) (same layout as `images`).
+ * Replays every pixel back to front from last_idx using T_final (no blend
+ * history is stored), accumulates the gradients of each record's screen
+ * centre (2), conic (3), half-factor vector (2), alpha2, (alpha1-alpha2)/2
+ * and colour (3) in `record_grads`, then applies the chain rule through the
+ * projection to every kernel parameter, summed over cameras.
+ *   record_grads  device, float [n_cams * n][HGS_RECORD_GRAD_FLOATS] scratch
+ *                 (cleared by the call; holds the per-record gradients on
+ *                 return)
+ *   grads         device pointers, overwritten
+ *   workspace     device, hgs_workspace_bytes(HGS_WS_RENDER, ...) bytes
+ * params, cams and opts must be those given to hgs_preprocess. */
+int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
+                   const hgs_options* opts, const void* records, const uint32_t* values,
+                   const uint32_t* ranges, const float* T_final, const int32_t* last_idx,
+                   const float* dL_dimages, float* record_grads, const hgs_param_grads* grads,
+                   void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+const char* hgs_strerror(int code);
+const char* hgs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HGS_H */

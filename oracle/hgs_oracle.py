@@ -45,22 +45,31 @@ import torch
 
 F64 = torch.float64
 
+def _f32(x: float) -> float:
+    """Nearest float32 value: thresholds travel as float32, so both sides of
+    a comparison use the same constant."""
+    return float(np.float32(x))
+
+
 DEFAULT_OPTIONS = dict(
-    tile=16,            # tile edge in pixels (outputs do not depend on it)
-    lowpass=0.3,        # screen-space dilation added to the 2x2 covariance, px^2
-    kappa=3.0,          # sigma extent of the valid region (3-sigma, Supp. B.1)
-    alpha_min=1.0 / 255.0,
-    alpha_max=0.99,
-    t_min=1e-4,
-    fov_clamp=1.3,
+    tile=16,                    # tile edge in pixels (outputs do not depend on it)
+    lowpass=_f32(0.3),          # screen-space dilation added to the 2x2 covariance, px^2
+    kappa=3.0,                  # sigma extent of the valid region (3-sigma, Supp. B.1)
+    alpha_min=_f32(1.0 / 255.0),
+    alpha_max=_f32(0.99),
+    t_min=_f32(1e-4),
+    fov_clamp=_f32(1.3),
     bg=(0.0, 0.0, 0.0),
-    full_box=False,     # True: both halves splatted with the full ellipse box
+    full_box=False,             # True: both halves splatted with the full ellipse box
 )
 
 
 def options(**kw) -> dict:
     o = dict(DEFAULT_OPTIONS)
     o.update(kw)
+    for k in ("lowpass", "kappa", "alpha_min", "alpha_max", "t_min", "fov_clamp"):
+        o[k] = _f32(o[k])
+    o["bg"] = tuple(_f32(b) for b in o["bg"])
     return o
 
 
@@ -222,9 +231,11 @@ def _geometry(sc: dict, cam: dict, o: dict, idx: torch.Tensor) -> dict:
                      torch.stack([conic[..., 1], conic[..., 2]], -1)], -2)
     w = (Q @ g.unsqueeze(-1)).squeeze(-1)
     s2 = torch.maximum(v - (g * w).sum(-1), 1e-12 * v)        # conditional variance
-    s2safe = torch.where(nzero | (s2 <= 0), torch.ones_like(s2), s2)
+    # a zero normal (or a plane of zero variance) has no preferred side: I = 1
+    flat = nzero | ~(s2 > 0)
+    s2safe = torch.where(flat, torch.ones_like(s2), s2)
     k = w / torch.sqrt(2.0 * s2safe).unsqueeze(-1)
-    k = torch.where(nzero.unsqueeze(-1), torch.zeros_like(k), k)
+    k = torch.where(flat.unsqueeze(-1), torch.zeros_like(k), k)
 
     # SH colour (Sec. 3.1), view direction from the camera centre.
     o_cam = -(Rc.T @ tc)
@@ -385,8 +396,9 @@ def raster_records(pre: dict, mode: str = "e2e") -> dict:
 def _composite(recs: dict, cand: torch.Tensor, px: torch.Tensor, py: torch.Tensor, o: dict):
     """Blend pixels (px, py) over candidate records ``cand`` (indices into the
     depth-sorted records).  Returns colour [P,3], T_final [P], count [P],
-    last position [P] (index into cand, -1 if none) and the smallest relative
-    distance of any decision to its threshold [P]."""
+    last position [P] (index into cand, -1 if none) and, per pixel, the
+    smallest relative distance of each kind of decision to its threshold
+    [P,3]: alpha vs alpha_min, transmittance vs t_min, power vs 0."""
     r = recs["rect"][cand]
     inside = ((px[:, None] >= r[None, :, 0]) & (px[:, None] <= r[None, :, 1]) &
               (py[:, None] >= r[None, :, 2]) & (py[:, None] <= r[None, :, 3]))
@@ -417,8 +429,10 @@ def _composite(recs: dict, cand: torch.Tensor, px: torch.Tensor, py: torch.Tenso
         rel_t = torch.where(contrib & before_or_at, (T_after - o["t_min"]).abs() / o["t_min"], inf)
         terms = 0.5 * (a_.abs() * dx * dx + c_.abs() * dy * dy) + cross.abs()
         rel_p = torch.where(inside, power.abs() / torch.clamp(terms, min=1e-300), inf)
-        margin = torch.minimum(torch.minimum(rel_a, rel_t), rel_p).min(dim=1).values \
-            if cand.numel() else torch.full((px.shape[0],), math.inf, dtype=F64)
+        if cand.numel():
+            margin = torch.stack([rel_a.min(1).values, rel_t.min(1).values, rel_p.min(1).values], 1)
+        else:
+            margin = torch.full((px.shape[0], 3), math.inf, dtype=F64)
         count = blend.sum(1)
         pos = torch.arange(cand.numel()).expand_as(blend)
         last = torch.where(blend, pos, torch.full_like(pos, -1)).max(1).values \
@@ -480,7 +494,7 @@ def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64) -> dict:
         inv_t = torch.from_numpy(inv)
         res["image"] = out[inv_t].T.reshape(3, H, W)
         for k in ("T_final", "n_contrib", "last_id", "margin"):
-            res[k] = res[k][inv_t].reshape(H, W)
+            res[k] = res[k][inv_t].reshape((H, W) + tuple(res[k].shape[1:]))
     return res
 
 

@@ -1,0 +1,272 @@
+// C ABI of libhgs: argument validation, camera packing, workspace sizing and
+// the launch sequence of each entry point.  No entry point allocates device
+// memory or synchronises the stream.
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "hgs_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(HGS_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+int ilog2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+int check_opts(const hgs_options* o) {
+  if (!o) return fail(HGS_EINVAL, "options is null");
+  if (o->tile != 8 && o->tile != 16 && o->tile != 32)
+    return fail(HGS_EINVAL, "tile must be 8, 16 or 32 (got %d)", o->tile);
+  if (o->batch != 128 && o->batch != 256 && o->batch != 512)
+    return fail(HGS_EINVAL, "batch must be 128, 256 or 512 (got %d)", o->batch);
+  if (!(o->kappa > 0.0f) || !(o->lowpass >= 0.0f) || !(o->alpha_max > 0.0f) ||
+      !(o->alpha_max < 1.0f) || !(o->alpha_min >= 0.0f) || !(o->t_min > 0.0f) ||
+      !(o->t_min < 1.0f) || !(o->fov_clamp > 0.0f))
+    return fail(HGS_EINVAL, "option value out of range");
+  return HGS_OK;
+}
+
+// Builds the kernel-side camera pack; returns an error code.
+int make_pack(const hgs_camera* cams, int32_t n_cams, const hgs_options* o, hgs::CamPack* cp) {
+  if (!cams) return fail(HGS_EINVAL, "cameras is null");
+  if (n_cams < 1 || n_cams > HGS_MAX_CAMERAS)
+    return fail(HGS_EINVAL, "n_cams must be in 1..%d (got %d)", HGS_MAX_CAMERAS, n_cams);
+  memset(cp, 0, sizeof(*cp));
+  cp->n_cams = n_cams;
+  cp->tile = o->tile;
+  cp->tile_shift = ilog2(o->tile);
+  uint64_t toff = 0, poff = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    const hgs_camera& s = cams[c];
+    if (s.width < 1 || s.height < 1 || s.width > HGS_MAX_IMAGE_SIDE || s.height > HGS_MAX_IMAGE_SIDE)
+      return fail(HGS_EINVAL, "camera %d: image size %dx%d out of range", c, s.width, s.height);
+    if (!(s.fx > 0.0f) || !(s.fy > 0.0f))
+      return fail(HGS_EINVAL, "camera %d: focal lengths must be positive", c);
+    hgs::CamDev& d = cp->cam[c];
+    memcpy(d.R, s.R, sizeof(d.R));
+    memcpy(d.t, s.t, sizeof(d.t));
+    d.fx = s.fx;
+    d.fy = s.fy;
+    d.cx = s.cx;
+    d.cy = s.cy;
+    d.znear = s.znear;
+    d.width = s.width;
+    d.height = s.height;
+    d.tiles_x = (s.width + o->tile - 1) / o->tile;
+    d.tiles_y = (s.height + o->tile - 1) / o->tile;
+    d.tile_off = (uint32_t)toff;
+    d.pix_off = poff;
+    toff += (uint64_t)d.tiles_x * d.tiles_y;
+    poff += (uint64_t)s.width * s.height;
+  }
+  if (toff >= (1ull << 31)) return fail(HGS_EINVAL, "too many tiles");
+  cp->tiles_total = (uint32_t)toff;
+  return HGS_OK;
+}
+
+int key_passes(uint32_t tiles_total) {
+  int tb = 0;
+  while ((1ull << tb) < tiles_total) ++tb;
+  return (32 + tb + 7) / 8;
+}
+
+int make_params(const hgs_params* p, hgs::Params* out) {
+  if (!p) return fail(HGS_EINVAL, "params is null");
+  if (p->n < 0) return fail(HGS_EINVAL, "n must be >= 0");
+  if (p->stride < p->n) return fail(HGS_EINVAL, "stride must be >= n");
+  if (p->sh_degree < 0 || p->sh_degree > 3) return fail(HGS_EINVAL, "sh_degree must be 0..3");
+  if (p->n > 0 && (!p->means || !p->scales || !p->quats || !p->normals || !p->opac1 || !p->opac2 ||
+                   !p->sh))
+    return fail(HGS_EINVAL, "a parameter pointer is null");
+  if (p->n > (int64_t)UINT32_MAX / HGS_MAX_CAMERAS) return fail(HGS_EINVAL, "n too large");
+  out->means = p->means;
+  out->scales = p->scales;
+  out->quats = p->quats;
+  out->normals = p->normals;
+  out->opac1 = p->opac1;
+  out->opac2 = p->opac2;
+  out->sh = p->sh;
+  out->n = p->n;
+  out->stride = p->stride;
+  out->sh_degree = p->sh_degree;
+  return HGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hgs_default_options(hgs_options* o) {
+  if (!o) return;
+  o->tile = 16;
+  o->batch = 256;
+  o->lowpass = 0.3f;
+  o->kappa = 3.0f;
+  o->alpha_min = 1.0f / 255.0f;
+  o->alpha_max = 0.99f;
+  o->t_min = 1e-4f;
+  o->fov_clamp = 1.3f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+  o->flags = 0u;
+}
+
+int64_t hgs_tiles_total(const hgs_camera* cams, int32_t n_cams, const hgs_options* opts) {
+  if (check_opts(opts) != HGS_OK) return -1;
+  hgs::CamPack cp;
+  if (make_pack(cams, n_cams, opts, &cp) != HGS_OK) return -1;
+  return (int64_t)cp.tiles_total;
+}
+
+int64_t hgs_pixels_total(const hgs_camera* cams, int32_t n_cams) {
+  if (!cams || n_cams < 1) return -1;
+  int64_t t = 0;
+  for (int c = 0; c < n_cams; ++c) t += (int64_t)cams[c].width * cams[c].height;
+  return t;
+}
+
+size_t hgs_workspace_bytes(int32_t which, int64_t n_rec, const hgs_camera* cams, int32_t n_cams,
+                           const hgs_options* opts, int64_t capacity) {
+  if (n_rec < 0) return 0;
+  switch (which) {
+    case HGS_WS_PREPROCESS:
+      return hgs::scan_workspace_bytes(n_rec);
+    case HGS_WS_BIN_SORT: {
+      if (check_opts(opts) != HGS_OK || capacity < 0) return 0;
+      hgs::CamPack cp;
+      if (make_pack(cams, n_cams, opts, &cp) != HGS_OK) return 0;
+      return hgs::sort_workspace_bytes(capacity, key_passes(cp.tiles_total));
+    }
+    case HGS_WS_RENDER:
+      return hgs::render_workspace_bytes();
+    default:
+      return 0;
+  }
+}
+
+int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
+                   const hgs_options* opts, void* records, uint32_t* tiles_touched,
+                   uint64_t* offsets, uint64_t* n_dup, void* workspace, size_t workspace_bytes,
+                   hipStream_t stream) {
+  int e;
+  if ((e = check_opts(opts)) != HGS_OK) return e;
+  hgs::Params p;
+  if ((e = make_params(params, &p)) != HGS_OK) return e;
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
+  const int64_t n_rec = p.n * n_cams;
+  if (!n_dup || (n_rec > 0 && (!records || !tiles_touched || !offsets)))
+    return fail(HGS_EINVAL, "an output pointer is null");
+  if (!workspace || workspace_bytes < hgs::scan_workspace_bytes(n_rec))
+    return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", hgs::scan_workspace_bytes(n_rec));
+  const hgs::Opts o = hgs::to_opts(*opts);
+  hipError_t h = hgs::launch_preprocess(p, cp, o, (hgs::Record*)records, tiles_touched, stream);
+  if (h != hipSuccess) return hip_fail(h, "preprocess launch");
+  h = hgs::launch_scan(tiles_touched, n_rec, offsets, n_dup, workspace, stream);
+  if (h != hipSuccess) return hip_fail(h, "scan launch");
+  return HGS_OK;
+}
+
+int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint64_t* offsets,
+                 const uint64_t* n_dup, int64_t n_rec, const hgs_camera* cams, int32_t n_cams,
+                 const hgs_options* opts, uint64_t* keys, uint32_t* values, int64_t capacity,
+                 uint32_t* ranges, int32_t* overflow, void* workspace, size_t workspace_bytes,
+                 hipStream_t stream) {
+  int e;
+  if ((e = check_opts(opts)) != HGS_OK) return e;
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
+  if (n_rec < 0 || n_rec % n_cams != 0) return fail(HGS_EINVAL, "n_rec must be n_cams * n");
+  if (capacity < 0 || capacity >= (int64_t)UINT32_MAX) return fail(HGS_EINVAL, "capacity out of range");
+  if (!n_dup || !ranges || !overflow || (n_rec > 0 && (!records || !tiles_touched || !offsets)) ||
+      (capacity > 0 && (!keys || !values)))
+    return fail(HGS_EINVAL, "a pointer is null");
+  const int passes = key_passes(cp.tiles_total);
+  const size_t need = hgs::sort_workspace_bytes(capacity, passes);
+  if (!workspace || workspace_bytes < need)
+    return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", need);
+  hipError_t h = hgs::launch_bin_sort((const hgs::Record*)records, tiles_touched, offsets, n_dup,
+                                      n_rec, n_rec / n_cams, cp, keys, values, capacity, ranges,
+                                      overflow, workspace, passes, stream);
+  if (h != hipSuccess) return hip_fail(h, "bin_sort launch");
+  return HGS_OK;
+}
+
+int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* ranges,
+                   const hgs_camera* cams, int32_t n_cams, const hgs_options* opts, float* images,
+                   float* T_final, int32_t* last_idx, int32_t* n_contrib, void* workspace,
+                   size_t workspace_bytes, hipStream_t stream) {
+  int e;
+  if ((e = check_opts(opts)) != HGS_OK) return e;
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
+  if (!ranges || !images || !T_final || !last_idx || !n_contrib)
+    return fail(HGS_EINVAL, "a pointer is null");
+  if (!workspace || workspace_bytes < hgs::render_workspace_bytes())
+    return fail(HGS_ECAPACITY, "workspace too small");
+  const hgs::Opts o = hgs::to_opts(*opts);
+  hipError_t h = hgs::launch_render_fwd((const hgs::Record*)records, values, ranges, cp, o, images,
+                                        T_final, last_idx, n_contrib, workspace, stream);
+  if (h != hipSuccess) return hip_fail(h, "render_fwd launch");
+  return HGS_OK;
+}
+
+int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
+                   const hgs_options* opts, const void* records, const uint32_t* values,
+                   const uint32_t* ranges, const float* T_final, const int32_t* last_idx,
+                   const float* dL_dimages, float* record_grads, const hgs_param_grads* grads,
+                   void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  int e;
+  if ((e = check_opts(opts)) != HGS_OK) return e;
+  hgs::Params p;
+  if ((e = make_params(params, &p)) != HGS_OK) return e;
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
+  if (!ranges || !T_final || !last_idx || !dL_dimages || !grads)
+    return fail(HGS_EINVAL, "a pointer is null");
+  const int64_t n_rec = p.n * n_cams;
+  if (n_rec > 0 && (!records || !record_grads || !grads->means || !grads->scales || !grads->quats ||
+                    !grads->normals || !grads->opac1 || !grads->opac2 || !grads->sh))
+    return fail(HGS_EINVAL, "a pointer is null");
+  if (!workspace || workspace_bytes < hgs::render_workspace_bytes())
+    return fail(HGS_ECAPACITY, "workspace too small");
+  const hgs::Opts o = hgs::to_opts(*opts);
+  hipError_t h = hgs::launch_render_bwd((const hgs::Record*)records, values, ranges, cp, o, T_final,
+                                        last_idx, dL_dimages, record_grads, n_rec, workspace, stream);
+  if (h != hipSuccess) return hip_fail(h, "render_bwd launch");
+  hgs::Grads g{grads->means, grads->scales, grads->quats, grads->normals,
+               grads->opac1, grads->opac2,  grads->sh};
+  h = hgs::launch_preprocess_bwd(p, cp, o, (const hgs::Record*)records, record_grads, g, stream);
+  if (h != hipSuccess) return hip_fail(h, "preprocess_bwd launch");
+  return HGS_OK;
+}
+
+const char* hgs_strerror(int code) {
+  switch (code) {
+    case HGS_OK: return "ok";
+    case HGS_EINVAL: return "invalid argument";
+    case HGS_ECAPACITY: return "buffer too small";
+    case HGS_EHIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+const char* hgs_last_error(void) { return g_err; }
+
+}  // extern "C"

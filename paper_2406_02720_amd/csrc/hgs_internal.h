@@ -1,0 +1,130 @@
+// Internal definitions shared by the HIP translation units of libhgs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hgs.h"
+
+namespace hgs {
+
+// Camera as the kernels see it: the public camera plus the derived tile grid
+// and the offsets of its tiles and pixels in the global numbering.
+struct CamDev {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float znear;
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  uint32_t tile_off;
+  uint32_t pad0;
+  uint64_t pix_off;
+};
+
+// Passed by value as a kernel argument (well under the 4 KiB limit), so a
+// launch captures the cameras without any host->device copy.
+struct CamPack {
+  int32_t n_cams;
+  int32_t tile;       // tile edge (8, 16 or 32)
+  int32_t tile_shift; // log2(tile)
+  uint32_t tiles_total;
+  CamDev cam[HGS_MAX_CAMERAS];
+};
+
+// Projected record, 64 bytes = 4 x 16 bytes so that one record moves with
+// four dwordx4 loads and stages in LDS as four 16-byte slots.
+//   q0: centre relative to the pixel-rect corner (x0, y0), half-factor vector
+//   q1: conic (a, b, c) of the dilated screen covariance, alpha2
+//   q2: colour, (alpha1 - alpha2) / 2
+//   q3: rect x0 | x1 << 16, rect y0 | y1 << 16, fp32 depth bits, tiles
+struct alignas(16) Record {
+  float mx, my, kx, ky;
+  float qa, qb, qc, alpha2;
+  float r, g, b, d_o;
+  uint32_t xr, yr, depth, tiles;
+};
+static_assert(sizeof(Record) == HGS_RECORD_BYTES, "record layout");
+
+struct Opts {
+  float lowpass, kappa, alpha_min, alpha_max, t_min, fov_clamp;
+  float bg[3];
+  uint32_t flags;
+  int32_t tile, batch;
+};
+
+inline Opts to_opts(const hgs_options& o) {
+  Opts r;
+  r.lowpass = o.lowpass;
+  r.kappa = o.kappa;
+  r.alpha_min = o.alpha_min;
+  r.alpha_max = o.alpha_max;
+  r.t_min = o.t_min;
+  r.fov_clamp = o.fov_clamp;
+  r.bg[0] = o.bg[0];
+  r.bg[1] = o.bg[1];
+  r.bg[2] = o.bg[2];
+  r.flags = o.flags;
+  r.tile = o.tile;
+  r.batch = o.batch;
+  return r;
+}
+
+struct Params {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* normals;
+  const float* opac1;
+  const float* opac2;
+  const float* sh;
+  int64_t n;
+  int64_t stride;
+  int32_t sh_degree;
+};
+
+struct Grads {
+  float* means;
+  float* scales;
+  float* quats;
+  float* normals;
+  float* opac1;
+  float* opac2;
+  float* sh;
+};
+
+// Camera of a global tile id (cameras are few: linear scan).
+__device__ inline int cam_of_tile(const CamPack& cp, uint32_t tile) {
+  int c = 0;
+  for (int i = 1; i < cp.n_cams; ++i)
+    if (tile >= cp.cam[i].tile_off) c = i;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, Record* rec,
+                             uint32_t* tiles, hipStream_t s);
+size_t scan_workspace_bytes(int64_t n);
+hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint64_t* total,
+                       void* ws, hipStream_t s);
+size_t sort_workspace_bytes(int64_t capacity, int passes);
+hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint64_t* offsets,
+                           const uint64_t* n_dup, int64_t n_rec, int64_t n_per_cam,
+                           const CamPack& cp, uint64_t* keys, uint32_t* vals, int64_t capacity,
+                           uint32_t* ranges, int32_t* overflow, void* ws, int passes,
+                           hipStream_t s);
+size_t render_workspace_bytes();
+hipError_t launch_render_fwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
+                             const CamPack& cp, const Opts& o, float* img, float* T_final,
+                             int32_t* last_idx, int32_t* n_contrib, void* ws, hipStream_t s);
+hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
+                             const CamPack& cp, const Opts& o, const float* T_final,
+                             const int32_t* last_idx, const float* dL_dimg, float* rec_grads,
+                             int64_t n_rec, void* ws, hipStream_t s);
+hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o,
+                                 const Record* rec, const float* rec_grads, const Grads& g,
+                                 hipStream_t s);
+
+}  // namespace hgs

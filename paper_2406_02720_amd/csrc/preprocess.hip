@@ -1,0 +1,540 @@
+// Preprocess: per-(camera, kernel) projection to a 64-byte record, the
+// exclusive scan of tiles touched, and the chain-rule backward of the
+// projection.
+//
+// One thread owns one kernel and loops over the cameras, so the 63 floats of
+// parameters are read from HBM once per kernel (coalesced structure-of-arrays
+// planes) whatever the number of views.  Geometry runs in FP64 (full rate on
+// CDNA4) so that integer decisions -- pixel rects, tiles, fp32 depth keys --
+// agree with an FP64 evaluation of the same formulas.
+
+#include "hgs_internal.h"
+#include "geometry.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kPreBlock = 256;
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// Extents (E-x, E+x, E-y, E+y) of the union of the splatted halves (Sec. 3.4):
+// per direction, a half reaches the full-ellipse tangent extent when the
+// tangent point lies on its side of the plane (sign of g on that axis),
+// otherwise the projected splitting ellipse bounds it.
+struct Box {
+  double emx, epx, emy, epy;
+  bool any;
+};
+
+__device__ __forceinline__ Box half_box(const KernelGeo& k, const ViewGeo& vg, const double* Ss,
+                                        float a1, float a2, const Opts& o) {
+  Box b;
+  const double kap = o.kappa;
+  const double ex = kap * sqrt(vg.A);
+  const double ey = kap * sqrt(vg.C);
+  if (o.flags & HGS_FLAG_FULL_BOX) {
+    b.emx = b.epx = ex;
+    b.emy = b.epy = ey;
+    b.any = true;
+    return b;
+  }
+  double cx = ex, cy = ey;
+  if (!k.nzero) {
+    const double* M = vg.M;
+    double sxx = 0.0, syy = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        sxx += M[r] * Ss[r * 3 + c] * M[c];
+        syy += M[3 + r] * Ss[r * 3 + c] * M[3 + c];
+      }
+    cx = fmin(kap * sqrt(sxx + (double)o.lowpass), ex);
+    cy = fmin(kap * sqrt(syy + (double)o.lowpass), ey);
+  }
+  const bool s1 = a1 >= o.alpha_min;
+  const bool s2 = a2 >= o.alpha_min;
+  const double gx = vg.g[0], gy = vg.g[1];
+  const double ninf = -INFINITY;
+  // half +1 (alpha1 side)
+  const double m1x = s1 ? (gx <= 0.0 ? ex : cx) : ninf;
+  const double p1x = s1 ? (gx >= 0.0 ? ex : cx) : ninf;
+  const double m1y = s1 ? (gy <= 0.0 ? ey : cy) : ninf;
+  const double p1y = s1 ? (gy >= 0.0 ? ey : cy) : ninf;
+  // half -1 (alpha2 side)
+  const double m2x = s2 ? (-gx <= 0.0 ? ex : cx) : ninf;
+  const double p2x = s2 ? (-gx >= 0.0 ? ex : cx) : ninf;
+  const double m2y = s2 ? (-gy <= 0.0 ? ey : cy) : ninf;
+  const double p2y = s2 ? (-gy >= 0.0 ? ey : cy) : ninf;
+  b.emx = fmax(m1x, m2x);
+  b.epx = fmax(p1x, p2x);
+  b.emy = fmax(m1y, m2y);
+  b.epy = fmax(p1y, p2y);
+  b.any = s1 || s2;
+  return b;
+}
+
+__device__ __forceinline__ int clamp_ceil(double x, int lo) {
+  x = fmin(fmax(x, -1e9), 1e9);
+  const int v = (int)ceil(x);
+  return v < lo ? lo : v;
+}
+__device__ __forceinline__ int clamp_floor(double x, int hi) {
+  x = fmin(fmax(x, -1e9), 1e9);
+  const int v = (int)floor(x);
+  return v > hi ? hi : v;
+}
+
+__global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack cp, Opts o,
+                                                               Record* __restrict__ rec,
+                                                               uint32_t* __restrict__ tiles_out) {
+  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  if (i >= p.n) return;
+  const int64_t S = p.stride;
+  float mu[3], s[3], q[4], nrm[3];
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = p.means[c * S + i];
+    s[c] = p.scales[c * S + i];
+    nrm[c] = p.normals[c * S + i];
+  }
+  for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
+  const float a1 = p.opac1[i];
+  const float a2 = p.opac2[i];
+  const int deg = p.sh_degree;
+  const int K = (deg + 1) * (deg + 1);
+  float sh[48];
+#pragma unroll
+  for (int j = 0; j < 48; ++j) sh[j] = (j < 3 * K) ? p.sh[j * S + i] : 0.0f;
+
+  KernelGeo kg;
+  kernel_geo(mu, s, q, nrm, kg);
+  double Ss[9];
+  const bool need_split = !(o.flags & HGS_FLAG_FULL_BOX) && !kg.nzero;
+  if (need_split) splitting_cov(kg, Ss);
+  bool params_ok = finite(kg.mu[0]) && finite(kg.mu[1]) && finite(kg.mu[2]) && finite(kg.Sw[0]) &&
+                   finite(kg.Sw[4]) && finite(kg.Sw[8]) && finite(kg.Sw[1]) && finite(kg.Sw[2]) &&
+                   finite(kg.Sw[5]) && finite(kg.v) && finite((double)a1) && finite((double)a2);
+  const int T = cp.tile;
+  const int tsh = cp.tile_shift;
+
+  for (int c = 0; c < cp.n_cams; ++c) {
+    const CamDev& cam = cp.cam[c];
+    Record r;
+    uint32_t tiles = 0;
+    r.mx = r.my = r.kx = r.ky = 0.0f;
+    r.qa = r.qb = r.qc = r.alpha2 = 0.0f;
+    r.r = r.g = r.b = r.d_o = 0.0f;
+    r.xr = r.yr = r.depth = 0u;
+    ViewGeo vg;
+    view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
+    bool ok = params_ok && finite(vg.t[2]) && vg.t[2] > (double)cam.znear;
+    ok = ok && finite(vg.det) && vg.det > 0.0 && finite(vg.qa) && finite(vg.qb) &&
+         finite(vg.qc) && finite(vg.mx) && finite(vg.my) && finite(vg.k[0]) && finite(vg.k[1]);
+    double col[3] = {0.0, 0.0, 0.0};
+    if (ok) {
+      // SH colour from the camera centre o = -R^T t towards the kernel.
+      const float* R = cam.R;
+      double oc[3];
+      for (int a = 0; a < 3; ++a)
+        oc[a] = -((double)R[0 * 3 + a] * cam.t[0] + (double)R[1 * 3 + a] * cam.t[1] +
+                  (double)R[2 * 3 + a] * cam.t[2]);
+      double dx = kg.mu[0] - oc[0], dy = kg.mu[1] - oc[1], dz = kg.mu[2] - oc[2];
+      const double dl = sqrt(dx * dx + dy * dy + dz * dz);
+      dx /= dl; dy /= dl; dz /= dl;
+      double Y[16];
+      sh_eval(deg, dx, dy, dz, Y);
+      for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+        for (int kk = 0; kk < K; ++kk) acc += Y[kk] * (double)sh[kk * 3 + ch];
+        col[ch] = fmax(acc + 0.5, 0.0);
+      }
+      ok = finite(col[0]) && finite(col[1]) && finite(col[2]);
+    }
+    Box bx;
+    if (ok) {
+      bx = half_box(kg, vg, Ss, a1, a2, o);
+      ok = bx.any;
+    }
+    if (ok) {
+      const double lo_x = vg.mx - bx.emx - 0.5, hi_x = vg.mx + bx.epx - 0.5;
+      const double lo_y = vg.my - bx.emy - 0.5, hi_y = vg.my + bx.epy - 0.5;
+      ok = finite(lo_x) && finite(hi_x) && finite(lo_y) && finite(hi_y);
+      if (ok) {
+        const int x0 = clamp_ceil(lo_x, 0), x1 = clamp_floor(hi_x, cam.width - 1);
+        const int y0 = clamp_ceil(lo_y, 0), y1 = clamp_floor(hi_y, cam.height - 1);
+        ok = x0 <= x1 && y0 <= y1;
+        if (ok) {
+          const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
+          tiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+          r.mx = (float)(vg.mx - (double)x0);
+          r.my = (float)(vg.my - (double)y0);
+          r.kx = (float)vg.k[0];
+          r.ky = (float)vg.k[1];
+          r.qa = (float)vg.qa;
+          r.qb = (float)vg.qb;
+          r.qc = (float)vg.qc;
+          r.alpha2 = a2;
+          r.r = (float)col[0];
+          r.g = (float)col[1];
+          r.b = (float)col[2];
+          r.d_o = (float)(((double)a1 - (double)a2) / 2.0);
+          r.xr = (uint32_t)x0 | ((uint32_t)x1 << 16);
+          r.yr = (uint32_t)y0 | ((uint32_t)y1 << 16);
+          r.depth = __float_as_uint((float)vg.t[2]);
+        }
+      }
+    }
+    (void)T;
+    r.tiles = tiles;
+    const int64_t ri = (int64_t)c * p.n + i;
+    rec[ri] = r;
+    tiles_out[ri] = tiles;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of tiles touched (uint32 -> uint64), reduce-then-scan
+// ---------------------------------------------------------------------------
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Exclusive block scan over kScanBlock threads; returns the block total too.
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t* total, uint64_t* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t inc = wave_incl_scan(x);
+  if (lane == 63) lds[wave] = inc;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanBlock / 64; ++w) {
+    const uint64_t v = lds[w];
+    if (w < wave) pre += v;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - x;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(const uint32_t* __restrict__ in,
+                                                                 int64_t n,
+                                                                 uint64_t* __restrict__ partial) {
+  __shared__ uint64_t lds[kScanBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t idx = base + j * kScanBlock + threadIdx.x;
+    if (idx < n) acc += in[idx];
+  }
+  uint64_t tot;
+  block_excl_scan(acc, &tot, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_partials_kernel(uint64_t* __restrict__ partial,
+                                                                   int64_t m,
+                                                                   uint64_t* __restrict__ total) {
+  __shared__ uint64_t lds[kScanBlock / 64];
+  uint64_t run = 0;
+  for (int64_t base = 0; base < m; base += kScanBlock) {
+    const int64_t idx = base + threadIdx.x;
+    const uint64_t x = idx < m ? partial[idx] : 0;
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan(x, &tot, lds);
+    if (idx < m) partial[idx] = run + ex;
+    run += tot;
+  }
+  if (threadIdx.x == 0) *total = run;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const uint32_t* __restrict__ in,
+                                                                int64_t n,
+                                                                const uint64_t* __restrict__ partial,
+                                                                uint64_t* __restrict__ out) {
+  __shared__ uint64_t lds[kScanBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint64_t run = partial[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t idx = base + j * kScanBlock + threadIdx.x;
+    const uint64_t x = idx < n ? in[idx] : 0;
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan(x, &tot, lds);
+    if (idx < n) out[idx] = run + ex;
+    run += tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward of the projection (chain rule to every kernel parameter)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
+    Params p, CamPack cp, Opts o, const Record* __restrict__ rec,
+    const float* __restrict__ rgrad, Grads G) {
+  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  if (i >= p.n) return;
+  const int64_t S = p.stride;
+  float mu[3], s[3], q[4], nrm[3];
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = p.means[c * S + i];
+    s[c] = p.scales[c * S + i];
+    nrm[c] = p.normals[c * S + i];
+  }
+  for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
+  const int deg = p.sh_degree;
+  const int K = (deg + 1) * (deg + 1);
+
+  KernelGeo kg;
+  kernel_geo(mu, s, q, nrm, kg);
+
+  double g_mu[3] = {0, 0, 0};
+  double g_Sw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double g_nh[3] = {0, 0, 0};
+  double g_a1 = 0.0, g_a2 = 0.0;
+  double g_sh[48];
+#pragma unroll
+  for (int j = 0; j < 48; ++j) g_sh[j] = 0.0;
+
+  for (int c = 0; c < cp.n_cams; ++c) {
+    const int64_t ri = (int64_t)c * p.n + i;
+    if (rec[ri].tiles == 0) continue;  // culled: no gradient
+    const float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS;
+    const double gmx = gr[0], gmy = gr[1];
+    const double gqa = gr[2], gqb = gr[3], gqc = gr[4];
+    const double gkx = gr[5], gky = gr[6];
+    const double galpha2 = gr[7], gdo = gr[8];
+    const double gcol[3] = {gr[9], gr[10], gr[11]};
+
+    g_a2 += galpha2 - 0.5 * gdo;
+    g_a1 += 0.5 * gdo;
+
+    const CamDev& cam = cp.cam[c];
+    ViewGeo vg;
+    view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
+
+    // ---- colour: c = max(0, sum f Y(d) + 0.5), d = (mu - o) / |mu - o|
+    {
+      const float* R = cam.R;
+      double oc[3];
+      for (int a = 0; a < 3; ++a)
+        oc[a] = -((double)R[0 * 3 + a] * cam.t[0] + (double)R[1 * 3 + a] * cam.t[1] +
+                  (double)R[2 * 3 + a] * cam.t[2]);
+      double dv[3] = {kg.mu[0] - oc[0], kg.mu[1] - oc[1], kg.mu[2] - oc[2]};
+      const double dl = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      const double d[3] = {dv[0] / dl, dv[1] / dl, dv[2] / dl};
+      double Y[16];
+      sh_eval(deg, d[0], d[1], d[2], Y);
+      double wk[16];
+      for (int kk = 0; kk < 16; ++kk) wk[kk] = 0.0;
+      for (int ch = 0; ch < 3; ++ch) {
+        double raw = 0.5;
+        for (int kk = 0; kk < K; ++kk) raw += Y[kk] * (double)p.sh[(kk * 3 + ch) * S + i];
+        const double gc = raw > 0.0 ? gcol[ch] : 0.0;
+        for (int kk = 0; kk < K; ++kk) {
+          g_sh[kk * 3 + ch] += gc * Y[kk];
+          wk[kk] += gc * (double)p.sh[(kk * 3 + ch) * S + i];
+        }
+      }
+      double gd[3];
+      sh_grad(deg, d[0], d[1], d[2], wk, &gd[0], &gd[1], &gd[2]);
+      const double dot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+      for (int a = 0; a < 3; ++a) g_mu[a] += (gd[a] - d[a] * dot) / dl;
+    }
+
+    // ---- k = w r, r = (2 s2)^-1/2, w = Q g, s2 = v - g.w (or 1e-12 v)
+    double gw0 = 0.0, gw1 = 0.0, gg0 = 0.0, gg1 = 0.0, gv = 0.0;
+    double gQa = gqa, gQb = gqb, gQc = gqc;
+    if (!kg.nzero && vg.s2 > 0.0) {
+      gw0 = gkx * vg.r;
+      gw1 = gky * vg.r;
+      const double grr = gkx * vg.w[0] + gky * vg.w[1];
+      const double gs2 = -grr * vg.r * vg.r * vg.r;
+      if (!vg.s2clamp) {
+        gv += gs2;
+        gg0 -= gs2 * vg.w[0];
+        gg1 -= gs2 * vg.w[1];
+        gw0 -= gs2 * vg.g[0];
+        gw1 -= gs2 * vg.g[1];
+      } else {
+        gv += 1e-12 * gs2;
+      }
+      gQa += gw0 * vg.g[0];
+      gQb += gw0 * vg.g[1] + gw1 * vg.g[0];
+      gQc += gw1 * vg.g[1];
+      gg0 += vg.qa * gw0 + vg.qb * gw1;
+      gg1 += vg.qb * gw0 + vg.qc * gw1;
+    }
+    // ---- conic = inverse of (A, B; B, C)
+    const double A = vg.A, B = vg.B, C = vg.C;
+    const double id2 = 1.0 / (vg.det * vg.det);
+    const double gA = (-C * C * gQa + B * C * gQb - B * B * gQc) * id2;
+    const double gB = (2.0 * B * C * gQa - (A * C + B * B) * gQb + 2.0 * A * B * gQc) * id2;
+    const double gC = (-B * B * gQa + A * B * gQb - A * A * gQc) * id2;
+    // G_S = [[gA, gB/2], [gB/2, gC]]; Shat = M Sw M^T  =>  dM += 2 G_S M Sw,
+    // dSw += M^T G_S M.  g = M Sn  =>  dM += gg Sn^T, dSn = M^T gg.
+    const double* M = vg.M;
+    const double GS[4] = {gA, 0.5 * gB, 0.5 * gB, gC};
+    double MS[6];
+    for (int r = 0; r < 2; ++r)
+      for (int cc = 0; cc < 3; ++cc)
+        MS[r * 3 + cc] = M[r * 3 + 0] * kg.Sw[0 * 3 + cc] + M[r * 3 + 1] * kg.Sw[1 * 3 + cc] +
+                         M[r * 3 + 2] * kg.Sw[2 * 3 + cc];
+    double gM[6];
+    for (int r = 0; r < 2; ++r)
+      for (int cc = 0; cc < 3; ++cc)
+        gM[r * 3 + cc] = 2.0 * (GS[r * 2 + 0] * MS[0 * 3 + cc] + GS[r * 2 + 1] * MS[1 * 3 + cc]);
+    gM[0] += gg0 * kg.Sn[0]; gM[1] += gg0 * kg.Sn[1]; gM[2] += gg0 * kg.Sn[2];
+    gM[3] += gg1 * kg.Sn[0]; gM[4] += gg1 * kg.Sn[1]; gM[5] += gg1 * kg.Sn[2];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) {
+        double acc = 0.0;
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) acc += M[a * 3 + r] * GS[a * 2 + b] * M[b * 3 + cc];
+        g_Sw[r * 3 + cc] += acc;
+      }
+    double gSn[3];
+    for (int r = 0; r < 3; ++r) gSn[r] = M[r] * gg0 + M[3 + r] * gg1 + gv * kg.nh[r];
+    for (int r = 0; r < 3; ++r) g_nh[r] += gv * kg.Sn[r];
+    // Sn = Sw n  =>  dSw += dSn n^T, dn += Sw dSn
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) g_Sw[r * 3 + cc] += gSn[r] * kg.nh[cc];
+    for (int r = 0; r < 3; ++r)
+      g_nh[r] += kg.Sw[r * 3 + 0] * gSn[0] + kg.Sw[r * 3 + 1] * gSn[1] + kg.Sw[r * 3 + 2] * gSn[2];
+
+    // ---- M = J R_c  =>  dJ = dM R_c^T
+    const float* Rc = cam.R;
+    double gJ00 = 0.0, gJ02 = 0.0, gJ11 = 0.0, gJ12 = 0.0;
+    for (int cc = 0; cc < 3; ++cc) {
+      gJ00 += gM[cc] * (double)Rc[0 * 3 + cc];
+      gJ02 += gM[cc] * (double)Rc[2 * 3 + cc];
+      gJ11 += gM[3 + cc] * (double)Rc[1 * 3 + cc];
+      gJ12 += gM[3 + cc] * (double)Rc[2 * 3 + cc];
+    }
+    const double tx = vg.t[0], ty = vg.t[1], tz = vg.t[2];
+    const double fx = cam.fx, fy = cam.fy;
+    const double tz2 = tz * tz, tz3 = tz2 * tz;
+    double gt[3] = {0.0, 0.0, 0.0};
+    gt[2] += -fx / tz2 * gJ00 - fy / tz2 * gJ11;
+    if (!vg.clx) {
+      gt[0] += -fx / tz2 * gJ02;
+      gt[2] += 2.0 * fx * tx / tz3 * gJ02;
+    } else {
+      gt[2] += fx * vg.xc / tz2 * gJ02;
+    }
+    if (!vg.cly) {
+      gt[1] += -fy / tz2 * gJ12;
+      gt[2] += 2.0 * fy * ty / tz3 * gJ12;
+    } else {
+      gt[2] += fy * vg.yc / tz2 * gJ12;
+    }
+    // screen centre
+    gt[0] += gmx * fx / tz;
+    gt[1] += gmy * fy / tz;
+    gt[2] += -gmx * fx * tx / tz2 - gmy * fy * ty / tz2;
+    // t = R_c mu + t_c
+    for (int a = 0; a < 3; ++a)
+      g_mu[a] += (double)Rc[0 * 3 + a] * gt[0] + (double)Rc[1 * 3 + a] * gt[1] +
+                 (double)Rc[2 * 3 + a] * gt[2];
+  }
+
+  // ---- Sigma_w = Rq diag(s^2) Rq^T
+  double Gs[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Gs[r * 3 + c] = 0.5 * (g_Sw[r * 3 + c] + g_Sw[c * 3 + r]);
+  const double* Rq = kg.Rq;
+  const double dd[3] = {kg.s[0] * kg.s[0], kg.s[1] * kg.s[1], kg.s[2] * kg.s[2]};
+  double GR[9];  // dL/dRq = 2 Gs Rq D
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      GR[r * 3 + c] = 2.0 * (Gs[r * 3 + 0] * Rq[0 * 3 + c] + Gs[r * 3 + 1] * Rq[1 * 3 + c] +
+                             Gs[r * 3 + 2] * Rq[2 * 3 + c]) * dd[c];
+  double g_s[3];
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0;  // (Rq^T Gs Rq)_cc
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) acc += Rq[a * 3 + c] * Gs[a * 3 + b] * Rq[b * 3 + c];
+    g_s[c] = 2.0 * kg.s[c] * acc;
+  }
+  const double qw = kg.qh[0], qx = kg.qh[1], qy = kg.qh[2], qz = kg.qh[3];
+  const double* g = GR;
+  double gq[4];
+  gq[0] = 2.0 * (-qz * g[1] + qy * g[2] + qz * g[3] - qx * g[5] - qy * g[6] + qx * g[7]);
+  gq[1] = 2.0 * (qy * g[1] + qz * g[2] + qy * g[3] - 2.0 * qx * g[4] - qw * g[5] + qz * g[6] +
+                 qw * g[7] - 2.0 * qx * g[8]);
+  gq[2] = 2.0 * (-2.0 * qy * g[0] + qx * g[1] + qw * g[2] + qx * g[3] + qz * g[5] - qw * g[6] +
+                 qz * g[7] - 2.0 * qy * g[8]);
+  gq[3] = 2.0 * (-2.0 * qz * g[0] - qw * g[1] + qx * g[2] + qw * g[3] - 2.0 * qz * g[4] +
+                 qy * g[5] + qx * g[6] + qy * g[7]);
+  double gq_raw[4] = {0, 0, 0, 0};
+  if (kg.qn > 0.0) {
+    const double dot = gq[0] * qw + gq[1] * qx + gq[2] * qy + gq[3] * qz;
+    for (int a = 0; a < 4; ++a) gq_raw[a] = (gq[a] - kg.qh[a] * dot) / kg.qn;
+  }
+  double gn_raw[3] = {0, 0, 0};
+  if (!kg.nzero) {
+    const double dot = g_nh[0] * kg.nh[0] + g_nh[1] * kg.nh[1] + g_nh[2] * kg.nh[2];
+    for (int a = 0; a < 3; ++a) gn_raw[a] = (g_nh[a] - kg.nh[a] * dot) / kg.nn;
+  }
+  for (int c = 0; c < 3; ++c) {
+    G.means[c * S + i] = (float)g_mu[c];
+    G.scales[c * S + i] = (float)g_s[c];
+    G.normals[c * S + i] = (float)gn_raw[c];
+  }
+  for (int c = 0; c < 4; ++c) G.quats[c * S + i] = (float)gq_raw[c];
+  G.opac1[i] = (float)g_a1;
+  G.opac2[i] = (float)g_a2;
+  for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = (float)g_sh[j];
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, Record* rec,
+                             uint32_t* tiles, hipStream_t s) {
+  if (p.n == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
+  hipLaunchKernelGGL(preprocess_kernel, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles);
+  return hipGetLastError();
+}
+
+size_t scan_workspace_bytes(int64_t n) {
+  const int64_t blocks = (n + kScanTile - 1) / kScanTile;
+  return (size_t)(blocks > 0 ? blocks : 1) * sizeof(uint64_t);
+}
+
+hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint64_t* total,
+                       void* ws, hipStream_t s) {
+  const int64_t blocks = (n + kScanTile - 1) / kScanTile;
+  uint64_t* partial = (uint64_t*)ws;
+  if (blocks > 0)
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)blocks), dim3(kScanBlock), 0, s, tiles,
+                       n, partial);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, partial, blocks, total);
+  if (blocks > 0)
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)blocks), dim3(kScanBlock), 0, s, tiles, n,
+                       partial, offsets);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o,
+                                 const Record* rec, const float* rec_grads, const Grads& g,
+                                 hipStream_t s) {
+  if (p.n == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
+  hipLaunchKernelGGL(preprocess_bwd_kernel, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec,
+                     rec_grads, g);
+  return hipGetLastError();
+}
+
+}  // namespace hgs

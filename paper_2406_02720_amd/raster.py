@@ -1,0 +1,186 @@
+"""Rasterizer pipeline over libhgs with torch-owned device memory, and its
+``torch.autograd.Function``.
+
+Forward: hgs_preprocess -> (read the entry count) -> hgs_bin_sort ->
+hgs_render_fwd.  The state kept for backward is the records, the sorted
+values, the tile ranges, and per pixel the final transmittance and the
+position of the last blended entry -- no per-pair blend history.
+Backward: hgs_render_bwd.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+BASE_PLANES = 15  # means 3, scales 3, quats 4, normals 3, opac1, opac2
+
+
+def sh_planes(sh_degree: int) -> int:
+    return 3 * (sh_degree + 1) ** 2
+
+
+def soa_from_natural(means, scales, quats, normals, opac1, opac2, sh) -> torch.Tensor:
+    """Pack natural-layout tensors ([N,3], [N,4], [N], [N,K,3]) into one
+    float32 structure-of-arrays tensor of planes, stride N."""
+    n = means.shape[0]
+    planes = [means.T, scales.T, quats.T, normals.T, opac1.reshape(1, n), opac2.reshape(1, n),
+              sh.reshape(n, -1).T]
+    return torch.cat(planes, 0).to(torch.float32).contiguous()
+
+
+def natural_from_soa(soa: torch.Tensor, K: int):
+    n = soa.shape[1]
+    return (soa[0:3].T, soa[3:6].T, soa[6:10].T, soa[10:13].T, soa[13], soa[14],
+            soa[15:15 + 3 * K].T.reshape(n, K, 3))
+
+
+def scene_to_soa(scene: dict, device="cuda") -> torch.Tensor:
+    t = {k: torch.as_tensor(np.asarray(scene[k], np.float32)) for k in
+         ("means", "scales", "quats", "normals", "opac1", "opac2", "sh")}
+    return soa_from_natural(t["means"], t["scales"], t["quats"], t["normals"], t["opac1"], t["opac2"],
+                            t["sh"]).to(device)
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class Frame:
+    """Device buffers of one forward pass (all views)."""
+    soa: torch.Tensor
+    n: int
+    sh_degree: int
+    cams: object
+    opts: object
+    records: torch.Tensor
+    tiles: torch.Tensor
+    offsets: torch.Tensor
+    n_dup: torch.Tensor
+    keys: torch.Tensor
+    values: torch.Tensor
+    ranges: torch.Tensor
+    overflow: torch.Tensor
+    images: torch.Tensor
+    T_final: torch.Tensor
+    last_idx: torch.Tensor
+    n_contrib: torch.Tensor
+    capacity: int
+    ws_render: torch.Tensor
+
+    def image(self, c: int) -> torch.Tensor:
+        """[3,H,W] view of camera c's image."""
+        off = 0
+        for i in range(c):
+            off += self.cams[i].width * self.cams[i].height
+        w, h = self.cams[c].width, self.cams[c].height
+        return self.images[3 * off:3 * off + 3 * w * h].view(3, h, w)
+
+    def per_pixel(self, t: torch.Tensor, c: int) -> torch.Tensor:
+        off = 0
+        for i in range(c):
+            off += self.cams[i].width * self.cams[i].height
+        w, h = self.cams[c].width, self.cams[c].height
+        return t[off:off + w * h].view(h, w)
+
+
+def _bytes(n: int, device) -> torch.Tensor:
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity: int | None = None) -> Frame:
+    """Run the forward rasterizer.  ``cams`` is a C camera array from
+    ``binding.make_cameras``; ``opts`` an ``hgs_options``.  With
+    ``capacity`` None the entry count is read back (one synchronisation) and
+    the key buffers are sized exactly; otherwise they have ``capacity``
+    entries and an overflow is reported in ``frame.overflow``."""
+    dev = soa.device
+    nc = len(cams)
+    n_rec = n * nc
+    stream = _stream()
+    params = B.params_struct(soa, n, soa.shape[1], sh_degree)
+    records = _bytes(n_rec * B.HGS_RECORD_BYTES, dev)
+    tiles = torch.empty(max(n_rec, 1), dtype=torch.int32, device=dev)
+    offsets = torch.empty(max(n_rec, 1), dtype=torch.int64, device=dev)
+    n_dup = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = _bytes(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, cams, opts), dev)
+    B.hgs_preprocess(params, cams, opts, records, tiles, offsets, n_dup, ws, stream)
+    if capacity is None:
+        capacity = int(n_dup.item())
+    tiles_total = B.hgs_tiles_total(cams, opts)
+    keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+    values = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    ranges = torch.empty(max(2 * tiles_total, 1), dtype=torch.int32, device=dev)
+    overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws_sort = _bytes(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, cams, opts, capacity), dev)
+    B.hgs_bin_sort(records, tiles, offsets, n_dup, n_rec, cams, opts, keys, values, capacity, ranges,
+                   overflow, ws_sort, stream)
+    npix = B.hgs_pixels_total(cams)
+    images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+    T_final = torch.empty(npix, dtype=torch.float32, device=dev)
+    last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
+    n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+    ws_r = _bytes(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), dev)
+    B.hgs_render_fwd(records, values, ranges, cams, opts, images, T_final, last_idx, n_contrib, ws_r, stream)
+    return Frame(soa, n, sh_degree, cams, opts, records, tiles, offsets, n_dup, keys, values, ranges,
+                 overflow, images, T_final, last_idx, n_contrib, capacity, ws_r)
+
+
+def backward_pass(fr: Frame, dL_dimages: torch.Tensor, record_grads: torch.Tensor | None = None,
+                  grads: torch.Tensor | None = None):
+    """Gradients of every parameter plane (same SoA layout as ``fr.soa``) and
+    the per-record gradients."""
+    dev = fr.soa.device
+    n_rec = fr.n * len(fr.cams)
+    if record_grads is None:
+        record_grads = torch.empty(max(n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
+    if grads is None:
+        grads = torch.zeros_like(fr.soa)
+    params = B.params_struct(fr.soa, fr.n, fr.soa.shape[1], fr.sh_degree)
+    gs = B.grads_struct(grads, fr.soa.shape[1])
+    B.hgs_render_bwd(params, fr.cams, fr.opts, fr.records, fr.values, fr.ranges, fr.T_final, fr.last_idx,
+                     dL_dimages, record_grads, gs, fr.ws_render, _stream())
+    return grads, record_grads
+
+
+class HGSRasterize(torch.autograd.Function):
+    """Differentiable half-Gaussian rasterization of one or more views.
+
+    Inputs are natural-layout CUDA tensors (activated values); returns the
+    packed images of all cameras (camera c's [3,H,W] image follows those of
+    cameras 0..c-1)."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, normals, opac1, opac2, sh, cams, opts):
+        K = sh.shape[1]
+        deg = int(round(K ** 0.5)) - 1
+        soa = soa_from_natural(means.detach(), scales.detach(), quats.detach(), normals.detach(),
+                               opac1.detach(), opac2.detach(), sh.detach())
+        fr = forward_pass(soa, means.shape[0], deg, cams, opts)
+        ctx.fr = fr
+        ctx.K = K
+        return fr.images
+
+    @staticmethod
+    def backward(ctx, d_images):
+        grads, _ = backward_pass(ctx.fr, d_images.contiguous().to(torch.float32))
+        m, s, q, nrm, o1, o2, sh = natural_from_soa(grads, ctx.K)
+        return m, s, q, nrm, o1, o2, sh, None, None
+
+
+def rasterize(means, scales, quats, normals, opac1, opac2, sh, cameras, **options):
+    """Render ``cameras`` (list of camera dicts); returns a list of [3,H,W]
+    images, differentiable with respect to every parameter."""
+    cams = B.make_cameras(cameras)
+    opts = B.default_options(**options)
+    packed = HGSRasterize.apply(means, scales, quats, normals, opac1, opac2, sh, cams, opts)
+    out, off = [], 0
+    for c in cameras:
+        w, h = int(c["width"]), int(c["height"])
+        out.append(packed[3 * off:3 * off + 3 * w * h].view(3, h, w))
+        off += w * h
+    return out

@@ -1,0 +1,350 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Bars: records' integer fields (pixel rect, tiles touched, fp32 depth bits),
+sort keys, values and tile ranges bit-exact; record floats to float32
+rounding; per-pixel contributor counts and last contributors exact and images
+within 1e-4 on pixels with no decision within a relative 2e-4 of its
+threshold (REC mode: the oracle blends the float32 record values in FP64);
+gradients within 1e-3 relative (per-tensor L2 and elementwise with a floor)
+against FP64 autograd of the end-to-end oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hgs_oracle as O
+from paper_2406_02720_amd import binding as B
+from paper_2406_02720_amd import raster as R
+from paper_2406_02720_amd import scenes
+
+from hgs_testlib import ambiguous, gpu_forward, oracle_pre, records_np, sorted_entries, split_opts, u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    s1, c1 = scenes.make_config(1)
+    s2, c2 = scenes.make_config(2, n=20000, width=320, height=180)
+    s4, c4 = scenes.make_config(4, n=6000, n_cams=3)
+    c4 = [scenes.pinhole(w, h, c["R"], c["t"]) for c, (w, h) in zip(c4, ((200, 150), (129, 84), (160, 106)))]
+    s3, c3 = scenes.make_config(3, n=30000, width=330, height=190)
+    return {
+        "cfg1": (s1, c1),
+        "cfg2_small": (s2, c2),
+        "cfg2_halfclear": (scenes.with_transparent_halves(s2), c2),
+        "cfg4_three_views": (s4, c4),
+        "cfg3_small": (s3, c3),
+    }
+
+
+CASES = _cases()
+
+
+def _check_records(scene, cams, fr, pres):
+    f, u = records_np(fr)
+    n = scene["means"].shape[0]
+    for c, pre in enumerate(pres):
+        fs, us = f[c * n:(c + 1) * n], u[c * n:(c + 1) * n]
+        valid = pre["valid"].numpy()
+        # integer decisions: an FP64 edge within 1e-9 of an integer could round
+        # either way on the two sides; none is expected
+        e = pre["edges"].numpy()[valid]
+        amb = (np.abs(e - np.round(e)) < 1e-9).any(1)
+        assert amb.sum() == 0
+        np.testing.assert_array_equal(us[:, 15] > 0, valid)
+        np.testing.assert_array_equal(us[:, 15], pre["tiles_touched"].numpy().astype(np.uint32))
+        r = pre["rect"].numpy()[valid]
+        np.testing.assert_array_equal(us[valid, 12] & 0xffff, r[:, 0])
+        np.testing.assert_array_equal(us[valid, 12] >> 16, r[:, 1])
+        np.testing.assert_array_equal(us[valid, 13] & 0xffff, r[:, 2])
+        np.testing.assert_array_equal(us[valid, 13] >> 16, r[:, 3])
+        np.testing.assert_array_equal(us[valid, 14], pre["depth_bits"][valid])
+        g = pre["rec"]
+        corner = np.stack([r[:, 0], r[:, 2]], 1)
+        ref = np.concatenate([g["mean2d"].numpy() - corner, g["k"].numpy(), g["conic"].numpy(),
+                              g["alpha2"].numpy()[:, None], g["colour"].numpy(), g["d_o"].numpy()[:, None]], 1)
+        got = fs[valid][:, [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11]]
+        # fields: mx my kx ky qa qb qc alpha2 r g b d_o
+        scale = np.maximum(np.abs(ref), 1e-30)
+        rel = np.abs(got - ref.astype(np.float32).astype(np.float64)) / scale
+        assert rel.max() < 1e-6, rel.max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("tile", [16, 8, 32])
+def test_preprocess_and_sort_match_oracle(name, tile):
+    scene, cams = CASES[name]
+    print(f"[case] preprocess+sort {name} tile={tile}", flush=True)
+    fr = gpu_forward(scene, cams, tile=tile)
+    pres = oracle_pre(scene, cams, tile=tile)
+    _check_records(scene, cams, fr, pres)
+    bs = O.bin_sort(pres)
+    keys, vals, ranges = sorted_entries(fr)
+    assert int(fr.overflow.item()) == 0
+    assert keys.size == bs["keys"].size
+    np.testing.assert_array_equal(keys, bs["keys"])
+    np.testing.assert_array_equal(vals, bs["vals"])
+    np.testing.assert_array_equal(ranges, bs["ranges"])
+
+
+def _check_render(scene, cams, fr, pres, mode="rec"):
+    n = scene["means"].shape[0]
+    vals = u32(fr.values)
+    flagged_total = pix_total = 0
+    for c, pre in enumerate(pres):
+        ref = O.render(pre, mode)
+        img = fr.image(c).cpu().numpy()
+        T = fr.per_pixel(fr.T_final, c).cpu().numpy()
+        cnt = fr.per_pixel(fr.n_contrib, c).cpu().numpy()
+        last = fr.per_pixel(fr.last_idx, c).cpu().numpy()
+        ok = ~ambiguous(ref["margin"])
+        flagged_total += int((~ok).sum())
+        pix_total += ok.size
+        ref_img = ref["image"].numpy()
+        err = np.abs(img - ref_img).max(0)
+        assert err[ok].max() <= 1e-4, err[ok].max()
+        np.testing.assert_array_equal(cnt[ok], ref["n_contrib"].numpy()[ok])
+        assert np.abs(T - ref["T_final"].numpy())[ok].max() <= 1e-4
+        last_id = np.where(last >= 0, vals[np.maximum(last, 0)].astype(np.int64) - c * n, -1)
+        np.testing.assert_array_equal(last_id[ok], ref["last_id"].numpy()[ok])
+    assert flagged_total <= 0.02 * pix_total, (flagged_total, pix_total)
+    return flagged_total, pix_total
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_render_fwd_matches_oracle(name):
+    scene, cams = CASES[name]
+    print(f"[case] render_fwd {name}", flush=True)
+    fr = gpu_forward(scene, cams)
+    pres = oracle_pre(scene, cams)
+    flagged, total = _check_render(scene, cams, fr, pres)
+    print(f"flagged {flagged}/{total}", flush=True)
+
+
+def test_render_fwd_end_to_end_fp64():
+    scene, cams = CASES["cfg2_small"]
+    fr = gpu_forward(scene, cams)
+    _check_render(scene, cams, fr, oracle_pre(scene, cams), mode="e2e")
+
+
+def test_outputs_identical_across_tile_batch_and_runs():
+    scene, cams = CASES["cfg4_three_views"]
+    ref = gpu_forward(scene, cams)
+    base = ref.images.cpu()
+    for tile in (8, 16, 32):
+        for batch in (128, 256, 512):
+            fr = gpu_forward(scene, cams, tile=tile, batch=batch)
+            assert torch.equal(fr.images.cpu(), base), (tile, batch)
+            assert torch.equal(fr.n_contrib.cpu(), ref.n_contrib.cpu())
+            assert torch.equal(fr.T_final.cpu(), ref.T_final.cpu())
+    again = gpu_forward(scene, cams)
+    assert torch.equal(again.images.cpu(), base)
+    # the batched multi-view call equals one call per view
+    for c, cam in enumerate(cams):
+        single = gpu_forward(scene, [cam])
+        assert torch.equal(single.image(0).cpu(), ref.image(c).cpu())
+
+
+def test_flipped_normals_swap_halves():
+    scene, cams = CASES["cfg2_halfclear"]
+    flipped = dict(scene, normals=-scene["normals"], opac1=scene["opac2"], opac2=scene["opac1"])
+    a = gpu_forward(scene, cams)
+    b = gpu_forward(flipped, cams)
+    ka, va, ra = sorted_entries(a)
+    kb, vb, rb = sorted_entries(b)
+    np.testing.assert_array_equal(ka, kb)
+    np.testing.assert_array_equal(va, vb)
+    assert (a.images - b.images).abs().max().item() < 1e-5
+
+
+def test_equal_opacities_take_the_standard_gaussian_path():
+    scene, cams = CASES["cfg2_small"]
+    eq = scenes.with_equal_opacities(scene)
+    fr = gpu_forward(eq, cams)
+    f, _ = records_np(fr)
+    assert np.all(f[:, 11] == 0.0)   # delta opacity exactly zero -> no half factor
+    _check_render(eq, cams, fr, oracle_pre(eq, cams))
+
+
+def test_full_box_mode_matches_oracle():
+    scene, cams = CASES["cfg2_halfclear"]
+    fr = gpu_forward(scene, cams, full_box=True)
+    pres = oracle_pre(scene, cams, full_box=True)
+    _check_records(scene, cams, fr, pres)
+    _check_render(scene, cams, fr, pres)
+    half = gpu_forward(scene, cams)
+    assert int(half.n_dup.item()) < int(fr.n_dup.item())
+
+
+# ---------------------------------------------------------------------------
+# gradients
+# ---------------------------------------------------------------------------
+def _grad_case(scene, cams, seed=5, **kw):
+    fr = gpu_forward(scene, cams, **kw)
+    pres = oracle_pre(scene, cams, **kw)
+    rng = np.random.default_rng(seed)
+    dls = []
+    for c, (cam, pre) in enumerate(zip(cams, pres)):
+        ref = O.render(pre, "e2e")
+        w = rng.normal(size=(3, cam["height"], cam["width"]))
+        w[:, ambiguous(ref["margin"])] = 0.0        # no gradient through ambiguous pixels
+        dls.append(w)
+    packed = torch.cat([torch.as_tensor(w, dtype=torch.float32).reshape(-1) for w in dls]).cuda()
+    grads, _ = R.backward_pass(fr, packed)
+    torch.cuda.synchronize()
+    _, o = split_opts(kw)
+    ref = O.render_grad(scene, cams, dls, o)
+    K = scene["sh"].shape[1]
+    got = dict(zip(O.PARAM_KEYS, [t.cpu().numpy() for t in R.natural_from_soa(grads, K)]))
+    for k in O.PARAM_KEYS:
+        g, r = got[k].astype(np.float64).reshape(ref[k].shape), ref[k]
+        rel_l2 = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
+        assert rel_l2 <= 1e-3, (k, rel_l2)
+        tol = 1e-3 * np.abs(r) + 1e-5 * np.abs(r).max()
+        bad = np.abs(g - r) > tol
+        assert bad.mean() <= 1e-3, (k, bad.sum(), np.abs(g - r).max())
+
+
+def test_gradients_match_oracle_small():
+    scene, _ = scenes.make_config(2, n=64)
+    cams = [scenes.axis_camera(32, 32, distance=2.5)]
+    _grad_case(scene, cams)
+
+
+def test_gradients_match_oracle_degree3_ragged():
+    scene, _ = scenes.make_config(2, n=1500)
+    cams = [scenes.axis_camera(150, 110, distance=3.0)]
+    _grad_case(scene, cams)
+
+
+def test_gradients_match_oracle_half_clear_multiview():
+    scene, cams = scenes.make_config(4, n=1200, n_cams=2)
+    cams = [scenes.pinhole(96, 72, c["R"], c["t"]) for c in cams]
+    scene = scenes.with_transparent_halves(scene)
+    _grad_case(scene, cams, seed=9, tile=8, batch=128)
+
+
+def test_autograd_function_matches_backward_pass():
+    scene, _ = scenes.make_config(2, n=500)
+    cams = [scenes.axis_camera(64, 48, distance=3.0)]
+    t = {k: torch.tensor(scene[k], device="cuda", requires_grad=True)
+         for k in ("means", "scales", "quats", "normals", "opac1", "opac2", "sh")}
+    imgs = R.rasterize(t["means"], t["scales"], t["quats"], t["normals"], t["opac1"], t["opac2"], t["sh"], cams)
+    target = torch.rand_like(imgs[0])
+    loss = (imgs[0] - target).abs().mean()
+    loss.backward()
+    fr = gpu_forward(scene, cams)
+    dl = (torch.sign(fr.image(0) - target) / target.numel()).reshape(-1)
+    grads, _ = R.backward_pass(fr, dl.contiguous())
+    ref = R.natural_from_soa(grads, scene["sh"].shape[1])
+    for k, r in zip(("means", "scales", "quats", "normals", "opac1", "opac2", "sh"), ref):
+        assert torch.allclose(t[k].grad, r.reshape(t[k].shape), rtol=1e-5, atol=1e-9), k
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_empty_scene_and_all_culled():
+    scene, cams = scenes.make_config(1, n=0)
+    fr = gpu_forward(scene, cams)
+    assert int(fr.n_dup.item()) == 0
+    assert fr.images.abs().max().item() == 0.0 and fr.T_final.min().item() == 1.0
+    scene, cams = scenes.make_config(1, n=200)
+    behind = dict(scene, means=(scene["means"] - np.float32([0, 0, 10])).astype(np.float32))
+    fr = gpu_forward(behind, cams)
+    assert int(fr.n_dup.item()) == 0 and (fr.n_contrib.cpu() == 0).all()
+
+
+def test_one_pixel_and_ragged_images():
+    scene, _ = scenes.make_config(1, n=300)
+    for w, h in ((1, 1), (17, 5), (33, 47)):
+        cams = [scenes.axis_camera(w, h, distance=1.5)]
+        fr = gpu_forward(scene, cams, tile=16)
+        pres = oracle_pre(scene, cams)
+        keys, vals, ranges = sorted_entries(fr)
+        bs = O.bin_sort(pres)
+        np.testing.assert_array_equal(keys, bs["keys"])
+        _check_render(scene, cams, fr, pres)
+
+
+def test_capacity_overflow_is_flagged_and_safe():
+    scene, cams = CASES["cfg1"]
+    fr = gpu_forward(scene, cams, capacity=100)
+    assert int(fr.n_dup.item()) > 100
+    assert int(fr.overflow.item()) == 1
+    ranges = u32(fr.ranges)
+    assert (ranges == 0).all()
+    assert fr.images.abs().max().item() == 0.0
+
+
+def test_non_finite_and_degenerate_parameters_are_culled_or_defined():
+    scene, cams = scenes.make_config(1, n=50)
+    bad = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in scene.items()}
+    bad["means"][0, 0] = np.nan
+    bad["scales"][1, 2] = np.inf
+    bad["quats"][2] = 0.0            # identity rotation
+    bad["normals"][3] = 0.0          # no preferred side: half factor 1
+    bad["opac1"][4] = np.nan
+    fr = gpu_forward(bad, cams)
+    _, u = records_np(fr)
+    assert u[0, 15] == 0 and u[1, 15] == 0 and u[4, 15] == 0
+    pres = oracle_pre(bad, cams)
+    valid = pres[0]["valid"].numpy()
+    np.testing.assert_array_equal(u[:, 15] > 0, valid)
+    f, _ = records_np(fr)
+    assert f[3, 2] == 0.0 and f[3, 3] == 0.0
+
+
+def test_invalid_arguments_return_einval():
+    scene, cams = scenes.make_config(1, n=10)
+    with pytest.raises(B.HGSError) as e:
+        gpu_forward(scene, cams, tile=12)
+    assert e.value.code == B.HGS_EINVAL
+    with pytest.raises(B.HGSError):
+        gpu_forward(scene, cams, batch=64)
+
+
+# ---------------------------------------------------------------------------
+# full-size workload, sampled
+# ---------------------------------------------------------------------------
+@pytest.mark.slow
+def test_full_size_1080p_one_million_sampled():
+    """1M half-Gaussians at 1920x1080 (the benchmark workload): every
+    record's integer fields, the sorted lists of 64 sampled tiles and 1024
+    sampled pixels against the oracle."""
+    scene, cams = scenes.make_config(3)
+    print("[case] full-size 1080p 1M", flush=True)
+    fr = gpu_forward(scene, cams)
+    pres = oracle_pre(scene, cams)
+    pre = pres[0]
+    f, u = records_np(fr)
+    valid = pre["valid"].numpy()
+    np.testing.assert_array_equal(u[:, 15], pre["tiles_touched"].numpy().astype(np.uint32))
+    np.testing.assert_array_equal(u[valid, 14], pre["depth_bits"][valid])
+    r = pre["rect"].numpy()[valid]
+    np.testing.assert_array_equal(u[valid, 12], (r[:, 0] | (r[:, 1] << 16)).astype(np.uint32))
+    np.testing.assert_array_equal(u[valid, 13], (r[:, 2] | (r[:, 3] << 16)).astype(np.uint32))
+    keys, vals, ranges = sorted_entries(fr)
+    assert keys.size == int(pre["tiles_touched"].sum())
+    assert np.all(keys[:-1] <= keys[1:])
+    # sampled tiles: list = records covering the tile, by (depth, id)
+    tr = pre["trect"].numpy()
+    rng = np.random.default_rng(0)
+    tx_n = pre["tiles_x"]
+    for t in rng.choice(ranges.shape[0], 64, replace=False):
+        ty, tx = divmod(int(t), tx_n)
+        cover = np.nonzero(valid & (tr[:, 0] <= tx) & (tr[:, 1] >= tx) & (tr[:, 2] <= ty) & (tr[:, 3] >= ty))[0]
+        order = np.lexsort((cover, pre["depth_bits"][cover]))
+        s, e = ranges[t]
+        np.testing.assert_array_equal(vals[s:e], cover[order].astype(np.uint32))
+    # sampled pixels in REC mode
+    pix = scenes.sample_pixels(cams[0], 1024, seed=3)
+    ref = O.render(pre, "rec", pixels=pix)
+    img = fr.image(0).cpu().numpy()[:, pix[:, 1], pix[:, 0]].T
+    cnt = fr.per_pixel(fr.n_contrib, 0).cpu().numpy()[pix[:, 1], pix[:, 0]]
+    ok = ~ambiguous(ref["margin"])
+    assert ok.mean() > 0.9
+    assert np.abs(img - ref["values"].numpy())[ok].max() <= 1e-4
+    np.testing.assert_array_equal(cnt[ok], ref["n_contrib"].numpy()[ok])

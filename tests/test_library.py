@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI (no GPU needed): the shared library loads,
+exports every function the public header declares, and its host-only entry
+points validate arguments."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2406_02720_amd import binding as B
+from paper_2406_02720_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hgs.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hgs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_stages():
+    names = _declared_functions()
+    for stage in ("hgs_preprocess", "hgs_bin_sort", "hgs_render_fwd", "hgs_render_bwd"):
+        assert stage in names
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libhgs.so not built")
+    lib = C.CDLL(B.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header():
+    assert C.sizeof(B.hgs_camera) == 80
+    assert C.sizeof(B.hgs_options) == 48
+    assert C.sizeof(B.hgs_params) == 7 * 8 + 8 + 8 + 8
+    assert C.sizeof(B.hgs_param_grads) == 7 * 8
+
+
+@pytest.mark.skipif(not os.path.exists(B.LIB_PATH), reason="libhgs.so not built")
+def test_host_side_validation_and_sizes():
+    o = B.default_options()
+    assert (o.tile, o.batch) == (16, 256)
+    assert o.alpha_min == float(np.float32(1 / 255)) and o.t_min == float(np.float32(1e-4))
+    _, cams = scenes.make_config(3, n=10)
+    ca = B.make_cameras(cams)
+    assert B.hgs_tiles_total(ca, o) == 120 * 68
+    assert B.hgs_pixels_total(ca) == 1920 * 1080
+    for tile, tiles in ((8, 240 * 135), (32, 60 * 34)):
+        assert B.hgs_tiles_total(ca, B.default_options(tile=tile)) == tiles
+    assert B.hgs_tiles_total(ca, B.default_options(tile=12)) == -1
+    assert B.hgs_tiles_total(ca, B.default_options(batch=100)) == -1
+    assert B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, 100, ca, o, 1000) > 12 * 1000
+    assert B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, 100, ca, B.default_options(tile=12), 1000) == 0
+    # calls with invalid arguments fail before touching the GPU
+    lib = B.load()
+    rc = lib.hgs_preprocess(None, ca, 1, C.byref(o), None, None, None, None, None, 0, None)
+    assert rc == B.HGS_EINVAL and b"params" in lib.hgs_last_error()
+    p = B.hgs_params()
+    p.n, p.stride, p.sh_degree = 10, 10, 4
+    rc = lib.hgs_preprocess(C.byref(p), ca, 1, C.byref(o), None, None, None, None, None, 0, None)
+    assert rc == B.HGS_EINVAL and b"sh_degree" in lib.hgs_last_error()
+    p.sh_degree = 0
+    rc = lib.hgs_preprocess(C.byref(p), ca, 0, C.byref(o), None, None, None, None, None, 0, None)
+    assert rc == B.HGS_EINVAL
+    big = (B.hgs_camera * 1)()
+    big[0].width, big[0].height, big[0].fx, big[0].fy = 70000, 10, 1.0, 1.0
+    assert B.hgs_tiles_total(big, o) == -1
+    assert lib.hgs_strerror(B.HGS_ECAPACITY) == b"buffer too small"
