@@ -89,7 +89,8 @@ typedef struct hgs_camera {
  *   opac2   1 plane   opacity of the -normal half
  *   sh      3 (D+1)^2 planes, plane (k * 3 + channel) holds coefficient k of
  *                     the real spherical harmonics of degree <= D (0..3)
- * Non-finite inputs cull the kernel. */
+ * A non-finite value in any of the fields above culls the kernel (as does a
+ * non-finite colour). */
 typedef struct hgs_params {
   const float* means;
   const float* scales;
@@ -180,7 +181,8 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
  *   n_rec          n_cams * n
  *   keys, values   device, `capacity` entries each (out: sorted entries in
  *                  the first *n_dup positions)
- *   ranges         device, uint32 [tiles_total][2] (out)
+ *   ranges         device, uint32 [tiles_total][2] (out); a tile without
+ *                  entries gets [0, 0)
  *   overflow       device, int32 [1] (out): 0, or 1 when *n_dup > capacity;
  *                  then no entry is written and every range is empty
  *   workspace      device, hgs_workspace_bytes(HGS_WS_BIN_SORT, ...) bytes

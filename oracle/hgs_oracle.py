@@ -301,6 +301,9 @@ def preprocess(sc: dict, cam: dict, o: dict | None = None) -> dict:
         geo = _geometry(det_sc, cam, o, all_idx)
         tz = geo["tz"]
         ok = torch.isfinite(tz) & (tz > cam["znear"])
+        for key in ("means", "scales", "quats", "normals"):        # a non-finite parameter
+            ok &= torch.isfinite(det_sc[key]).all(-1)               # culls the kernel
+        ok &= torch.isfinite(det_sc["opac1"]) & torch.isfinite(det_sc["opac2"])
         ok &= torch.isfinite(geo["det"]) & (geo["det"] > 0)
         for key in ("mean2d", "conic", "k", "colour"):
             ok &= torch.isfinite(geo[key]).all(-1)
@@ -363,6 +366,9 @@ def bin_sort(pres: list) -> dict:
     tiles = (keys >> np.uint64(32)).astype(np.int64)
     starts = np.searchsorted(tiles, np.arange(tile_off), side="left")
     ends = np.searchsorted(tiles, np.arange(tile_off), side="right")
+    empty = starts == ends
+    starts[empty] = 0                                   # an empty tile is [0, 0)
+    ends[empty] = 0
     ranges = np.stack([starts, ends], 1).astype(np.uint32)
     return dict(keys=keys, vals=vals, ranges=ranges, tiles_total=tile_off)
 

@@ -15,7 +15,8 @@
 //   k       = Q g / sqrt(2 (v - g^T Q g))          half factor
 //             I(delta) = erfc(-k . delta)          Eq. 7-8 (camera-space,
 //                                                  sign-safe form)
-// The conditional variance is clamped to >= 1e-12 v.
+// The conditional variance is clamped to >= 1e-12 v.  All array indices are
+// compile-time constants so that everything stays in registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,133 +26,129 @@
 
 namespace hgs {
 
-// Real spherical harmonics up to degree 3 with the Condon-Shortley phase,
-// ordered l = 0..3, m = -l..l; the normalisations are the textbook ones.
-struct SHConst {
-  static constexpr double PI = 3.14159265358979323846;
+// Symmetric 3x3.
+struct Sym3 {
+  double xx, xy, xz, yy, yz, zz;
 };
-__device__ __forceinline__ void sh_eval(int deg, double x, double y, double z, double* Y) {
-  const double c0 = 0.28209479177387814347;   // 1/(2 sqrt(pi))
-  const double c1 = 0.48860251190291992159;   // sqrt(3/(4 pi))
-  const double a2 = 1.09254843059207907054;   // sqrt(15/pi)/2
-  const double b2 = 0.31539156525252000603;   // sqrt(5/pi)/4
-  const double c2 = 0.54627421529603953527;   // sqrt(15/pi)/4
-  const double k33 = 0.59004358992664351035;  // sqrt(35/(2 pi))/4
-  const double k32 = 2.89061144264055405538;  // sqrt(105/pi)/2
-  const double k31 = 0.45704579946446573616;  // sqrt(21/(2 pi))/4
-  const double k30 = 0.37317633259011539141;  // sqrt(7/pi)/4
-  const double k22 = 1.44530572132027702769;  // sqrt(105/pi)/4
-  Y[0] = c0;
-  if (deg < 1) return;
-  Y[1] = -c1 * y;
-  Y[2] = c1 * z;
-  Y[3] = -c1 * x;
-  if (deg < 2) return;
-  const double xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = a2 * x * y;
-  Y[5] = -a2 * y * z;
-  Y[6] = b2 * (2.0 * zz - xx - yy);
-  Y[7] = -a2 * x * z;
-  Y[8] = c2 * (xx - yy);
-  if (deg < 3) return;
-  Y[9] = -k33 * y * (3.0 * xx - yy);
-  Y[10] = k32 * x * y * z;
-  Y[11] = -k31 * y * (4.0 * zz - xx - yy);
-  Y[12] = k30 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-  Y[13] = -k31 * x * (4.0 * zz - xx - yy);
-  Y[14] = k22 * z * (xx - yy);
-  Y[15] = -k33 * x * (xx - 3.0 * yy);
+
+__device__ __forceinline__ void sym_mul_vec(const Sym3& S, const double* v, double* out) {
+  out[0] = S.xx * v[0] + S.xy * v[1] + S.xz * v[2];
+  out[1] = S.xy * v[0] + S.yy * v[1] + S.yz * v[2];
+  out[2] = S.xz * v[0] + S.yz * v[1] + S.zz * v[2];
 }
 
-// Gradient of sum_k wk * Y_k(x, y, z) with respect to (x, y, z), treating
-// the three components as independent variables.
-__device__ __forceinline__ void sh_grad(int deg, double x, double y, double z, const double* wk,
-                                        double* gx, double* gy, double* gz) {
-  const double c1 = 0.48860251190291992159;
-  const double a2 = 1.09254843059207907054;
-  const double b2 = 0.31539156525252000603;
-  const double c2 = 0.54627421529603953527;
-  const double k33 = 0.59004358992664351035;
-  const double k32 = 2.89061144264055405538;
-  const double k31 = 0.45704579946446573616;
-  const double k30 = 0.37317633259011539141;
-  const double k22 = 1.44530572132027702769;
-  double X = 0.0, Yv = 0.0, Z = 0.0;
-  if (deg >= 1) {
-    Yv += -c1 * wk[1];
-    Z += c1 * wk[2];
-    X += -c1 * wk[3];
+// u^T S w
+__device__ __forceinline__ double sym_form(const Sym3& S, const double* u, const double* w) {
+  double Sw[3];
+  sym_mul_vec(S, w, Sw);
+  return u[0] * Sw[0] + u[1] * Sw[1] + u[2] * Sw[2];
+}
+
+// Real spherical harmonics up to degree D with the Condon-Shortley phase,
+// ordered l = 0..D, m = -l..l; the normalisations are the textbook ones.
+namespace shc {
+constexpr double c0 = 0.28209479177387814347;   // 1/(2 sqrt(pi))
+constexpr double c1 = 0.48860251190291992159;   // sqrt(3/(4 pi))
+constexpr double a2 = 1.09254843059207907054;   // sqrt(15/pi)/2
+constexpr double b2 = 0.31539156525252000603;   // sqrt(5/pi)/4
+constexpr double c2 = 0.54627421529603953527;   // sqrt(15/pi)/4
+constexpr double k33 = 0.59004358992664351035;  // sqrt(35/(2 pi))/4
+constexpr double k32 = 2.89061144264055405538;  // sqrt(105/pi)/2
+constexpr double k31 = 0.45704579946446573616;  // sqrt(21/(2 pi))/4
+constexpr double k30 = 0.37317633259011539141;  // sqrt(7/pi)/4
+constexpr double k22 = 1.44530572132027702769;  // sqrt(105/pi)/4
+}  // namespace shc
+
+template <int D, typename F>
+__device__ __forceinline__ void sh_eval(F x, F y, F z, F* Y) {
+  using namespace shc;
+  Y[0] = (F)c0;
+  if constexpr (D >= 1) {
+    Y[1] = (F)(-c1) * y;
+    Y[2] = (F)c1 * z;
+    Y[3] = (F)(-c1) * x;
   }
-  if (deg >= 2) {
-    X += a2 * y * wk[4];
-    Yv += a2 * x * wk[4];
-    Yv += -a2 * z * wk[5];
-    Z += -a2 * y * wk[5];
-    X += -2.0 * b2 * x * wk[6];
-    Yv += -2.0 * b2 * y * wk[6];
-    Z += 4.0 * b2 * z * wk[6];
-    X += -a2 * z * wk[7];
-    Z += -a2 * x * wk[7];
-    X += 2.0 * c2 * x * wk[8];
-    Yv += -2.0 * c2 * y * wk[8];
+  if constexpr (D >= 2) {
+    const F xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = (F)a2 * x * y;
+    Y[5] = (F)(-a2) * y * z;
+    Y[6] = (F)b2 * ((F)2 * zz - xx - yy);
+    Y[7] = (F)(-a2) * x * z;
+    Y[8] = (F)c2 * (xx - yy);
   }
-  if (deg >= 3) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    X += -6.0 * k33 * x * y * wk[9];
-    Yv += -k33 * (3.0 * xx - 3.0 * yy) * wk[9];
-    X += k32 * y * z * wk[10];
-    Yv += k32 * x * z * wk[10];
-    Z += k32 * x * y * wk[10];
-    X += 2.0 * k31 * x * y * wk[11];
-    Yv += -k31 * (4.0 * zz - xx - 3.0 * yy) * wk[11];
-    Z += -8.0 * k31 * y * z * wk[11];
-    X += -6.0 * k30 * x * z * wk[12];
-    Yv += -6.0 * k30 * y * z * wk[12];
-    Z += k30 * (6.0 * zz - 3.0 * xx - 3.0 * yy) * wk[12];
-    X += -k31 * (4.0 * zz - 3.0 * xx - yy) * wk[13];
-    Yv += 2.0 * k31 * x * y * wk[13];
-    Z += -8.0 * k31 * x * z * wk[13];
-    X += 2.0 * k22 * x * z * wk[14];
-    Yv += -2.0 * k22 * y * z * wk[14];
-    Z += k22 * (xx - yy) * wk[14];
-    X += -k33 * (3.0 * xx - 3.0 * yy) * wk[15];
-    Yv += 6.0 * k33 * x * y * wk[15];
+  if constexpr (D >= 3) {
+    const F xx = x * x, yy = y * y, zz = z * z;
+    Y[9] = (F)(-k33) * y * ((F)3 * xx - yy);
+    Y[10] = (F)k32 * x * y * z;
+    Y[11] = (F)(-k31) * y * ((F)4 * zz - xx - yy);
+    Y[12] = (F)k30 * z * ((F)2 * zz - (F)3 * xx - (F)3 * yy);
+    Y[13] = (F)(-k31) * x * ((F)4 * zz - xx - yy);
+    Y[14] = (F)k22 * z * (xx - yy);
+    Y[15] = (F)(-k33) * x * (xx - (F)3 * yy);
+  }
+}
+
+// Gradient of sum_k wk * Y_k(x, y, z) with respect to (x, y, z), the three
+// components taken as independent variables.
+template <int D, typename F>
+__device__ __forceinline__ void sh_grad(F x, F y, F z, const F* wk, F* gx, F* gy, F* gz) {
+  using namespace shc;
+  F X = 0, Yv = 0, Z = 0;
+  if constexpr (D >= 1) {
+    Yv += (F)(-c1) * wk[1];
+    Z += (F)c1 * wk[2];
+    X += (F)(-c1) * wk[3];
+  }
+  if constexpr (D >= 2) {
+    X += (F)a2 * y * wk[4];
+    Yv += (F)a2 * x * wk[4];
+    Yv += (F)(-a2) * z * wk[5];
+    Z += (F)(-a2) * y * wk[5];
+    X += (F)(-2.0 * b2) * x * wk[6];
+    Yv += (F)(-2.0 * b2) * y * wk[6];
+    Z += (F)(4.0 * b2) * z * wk[6];
+    X += (F)(-a2) * z * wk[7];
+    Z += (F)(-a2) * x * wk[7];
+    X += (F)(2.0 * c2) * x * wk[8];
+    Yv += (F)(-2.0 * c2) * y * wk[8];
+  }
+  if constexpr (D >= 3) {
+    const F xx = x * x, yy = y * y, zz = z * z;
+    X += (F)(-6.0 * k33) * x * y * wk[9];
+    Yv += (F)(-k33) * ((F)3 * xx - (F)3 * yy) * wk[9];
+    X += (F)k32 * y * z * wk[10];
+    Yv += (F)k32 * x * z * wk[10];
+    Z += (F)k32 * x * y * wk[10];
+    X += (F)(2.0 * k31) * x * y * wk[11];
+    Yv += (F)(-k31) * ((F)4 * zz - xx - (F)3 * yy) * wk[11];
+    Z += (F)(-8.0 * k31) * y * z * wk[11];
+    X += (F)(-6.0 * k30) * x * z * wk[12];
+    Yv += (F)(-6.0 * k30) * y * z * wk[12];
+    Z += (F)k30 * ((F)6 * zz - (F)3 * xx - (F)3 * yy) * wk[12];
+    X += (F)(-k31) * ((F)4 * zz - (F)3 * xx - yy) * wk[13];
+    Yv += (F)(2.0 * k31) * x * y * wk[13];
+    Z += (F)(-8.0 * k31) * x * z * wk[13];
+    X += (F)(2.0 * k22) * x * z * wk[14];
+    Yv += (F)(-2.0 * k22) * y * z * wk[14];
+    Z += (F)k22 * (xx - yy) * wk[14];
+    X += (F)(-k33) * ((F)3 * xx - (F)3 * yy) * wk[15];
+    Yv += (F)(6.0 * k33) * x * y * wk[15];
   }
   *gx = X;
   *gy = Yv;
   *gz = Z;
 }
 
-// Camera-independent part of a kernel.
-struct KernelGeo {
-  double mu[3];
-  double s[3];
-  double qn;        // |q|
-  double qh[4];     // normalised quaternion (identity if q == 0)
-  double Rq[9];     // rotation, row-major
-  double Sw[9];     // world covariance, row-major (symmetric)
-  double nn;        // |n|
-  double nh[3];     // unit normal (0 if n == 0)
-  double Sn[3];     // Sigma_w n
-  double v;         // n^T Sigma_w n
-  bool nzero;
-};
-
-__device__ __forceinline__ void kernel_geo(const float* mu, const float* s, const float* q,
-                                           const float* n, KernelGeo& k) {
-  for (int i = 0; i < 3; ++i) {
-    k.mu[i] = (double)mu[i];
-    k.s[i] = (double)s[i];
-  }
+// Normalised quaternion (identity for q == 0) and its rotation matrix.
+__device__ __forceinline__ void quat_rot(const float* q, double* qh, double& qn, double* R) {
   double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
-  k.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  if (k.qn == 0.0) {
+  qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  if (qn == 0.0) {
     qw = 1.0; qx = qy = qz = 0.0;
   } else {
-    qw /= k.qn; qx /= k.qn; qy /= k.qn; qz /= k.qn;
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
   }
-  k.qh[0] = qw; k.qh[1] = qx; k.qh[2] = qy; k.qh[3] = qz;
-  double* R = k.Rq;
+  qh[0] = qw; qh[1] = qx; qh[2] = qy; qh[3] = qz;
   R[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
   R[1] = 2.0 * (qx * qy - qw * qz);
   R[2] = 2.0 * (qx * qz + qw * qy);
@@ -161,29 +158,45 @@ __device__ __forceinline__ void kernel_geo(const float* mu, const float* s, cons
   R[6] = 2.0 * (qx * qz - qw * qy);
   R[7] = 2.0 * (qy * qz + qw * qx);
   R[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
-  const double d0 = k.s[0] * k.s[0], d1 = k.s[1] * k.s[1], d2 = k.s[2] * k.s[2];
-  for (int r = 0; r < 3; ++r)
-    for (int c = r; c < 3; ++c) {
-      const double val = R[r * 3 + 0] * d0 * R[c * 3 + 0] + R[r * 3 + 1] * d1 * R[c * 3 + 1] +
-                         R[r * 3 + 2] * d2 * R[c * 3 + 2];
-      k.Sw[r * 3 + c] = val;
-      k.Sw[c * 3 + r] = val;
-    }
+}
+
+// Camera-independent part of a kernel.
+struct KernelGeo {
+  double mu[3];
+  Sym3 Sw;        // world covariance
+  double nn;      // |n|
+  double nh[3];   // unit normal (0 if n == 0)
+  double Sn[3];   // Sigma_w n
+  double v;       // n^T Sigma_w n
+  bool nzero;
+};
+
+__device__ __forceinline__ void kernel_geo(const float* mu, const float* s, const float* q,
+                                           const float* n, KernelGeo& k) {
+  for (int i = 0; i < 3; ++i) k.mu[i] = (double)mu[i];
+  double qh[4], qn, R[9];
+  quat_rot(q, qh, qn, R);
+  const double d0 = (double)s[0] * s[0], d1 = (double)s[1] * s[1], d2 = (double)s[2] * s[2];
+  k.Sw.xx = R[0] * d0 * R[0] + R[1] * d1 * R[1] + R[2] * d2 * R[2];
+  k.Sw.xy = R[0] * d0 * R[3] + R[1] * d1 * R[4] + R[2] * d2 * R[5];
+  k.Sw.xz = R[0] * d0 * R[6] + R[1] * d1 * R[7] + R[2] * d2 * R[8];
+  k.Sw.yy = R[3] * d0 * R[3] + R[4] * d1 * R[4] + R[5] * d2 * R[5];
+  k.Sw.yz = R[3] * d0 * R[6] + R[4] * d1 * R[7] + R[5] * d2 * R[8];
+  k.Sw.zz = R[6] * d0 * R[6] + R[7] * d1 * R[7] + R[8] * d2 * R[8];
   const double nx = n[0], ny = n[1], nz = n[2];
   k.nn = sqrt(nx * nx + ny * ny + nz * nz);
   k.nzero = !(k.nn > 0.0);
   const double inv = k.nzero ? 0.0 : 1.0 / k.nn;
   k.nh[0] = nx * inv; k.nh[1] = ny * inv; k.nh[2] = nz * inv;
-  for (int r = 0; r < 3; ++r)
-    k.Sn[r] = k.Sw[r * 3 + 0] * k.nh[0] + k.Sw[r * 3 + 1] * k.nh[1] + k.Sw[r * 3 + 2] * k.nh[2];
+  sym_mul_vec(k.Sw, k.nh, k.Sn);
   k.v = k.nh[0] * k.Sn[0] + k.nh[1] * k.Sn[1] + k.nh[2] * k.Sn[2];
 }
 
 // Alg. 1 (Supp. B.1): covariance of the flattened ellipsoid standing for the
 // splitting plane.  Plane basis (v1, v2, n); the in-plane block is the Schur
 // complement of the covariance in that basis; the normal variance is
-// min(a', c') / 100.  Output row-major symmetric 3x3.
-__device__ __forceinline__ void splitting_cov(const KernelGeo& k, double* S) {
+// min(a', c') / 100.
+__device__ __forceinline__ Sym3 splitting_cov(const KernelGeo& k) {
   const double nx = k.nh[0], ny = k.nh[1], nz = k.nh[2];
   double v1[3], v2[3];
   if (nx == 0.0 && ny == 0.0) {
@@ -192,37 +205,33 @@ __device__ __forceinline__ void splitting_cov(const KernelGeo& k, double* S) {
   } else {
     const double l1 = sqrt(ny * ny + nx * nx);
     v1[0] = ny / l1; v1[1] = -nx / l1; v1[2] = 0.0;
-    double c0 = ny * v1[2] - nz * v1[1];
-    double c1 = nz * v1[0] - nx * v1[2];
-    double c2 = nx * v1[1] - ny * v1[0];
+    const double c0 = ny * v1[2] - nz * v1[1];
+    const double c1 = nz * v1[0] - nx * v1[2];
+    const double c2 = nx * v1[1] - ny * v1[0];
     const double l2 = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
     v2[0] = c0 / l2; v2[1] = c1 / l2; v2[2] = c2 / l2;
   }
-  const double B[9] = {v1[0], v2[0], nx, v1[1], v2[1], ny, v1[2], v2[2], nz};  // columns v1 v2 n
-  double SB[9];  // Sw * B
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      SB[r * 3 + c] = k.Sw[r * 3 + 0] * B[0 * 3 + c] + k.Sw[r * 3 + 1] * B[1 * 3 + c] +
-                      k.Sw[r * 3 + 2] * B[2 * 3 + c];
-  double C[9];  // B^T Sw B
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      C[r * 3 + c] = B[0 * 3 + r] * SB[0 * 3 + c] + B[1 * 3 + r] * SB[1 * 3 + c] +
-                     B[2 * 3 + r] * SB[2 * 3 + c];
-  const double ap = C[0] - C[2] * C[2] / C[8];
-  const double bp = C[1] - C[2] * C[5] / C[8];
-  const double cp = C[4] - C[5] * C[5] / C[8];
+  // covariance in the basis (v1, v2, n)
+  const double C00 = sym_form(k.Sw, v1, v1), C01 = sym_form(k.Sw, v1, v2);
+  const double C02 = sym_form(k.Sw, v1, k.nh), C11 = sym_form(k.Sw, v2, v2);
+  const double C12 = sym_form(k.Sw, v2, k.nh), C22 = sym_form(k.Sw, k.nh, k.nh);
+  const double ap = C00 - C02 * C02 / C22;
+  const double bp = C01 - C02 * C12 / C22;
+  const double cp = C11 - C12 * C12 / C22;
   const double dp = fmin(ap, cp) / 100.0;
-  const double Sd[9] = {ap, bp, 0.0, bp, cp, 0.0, 0.0, 0.0, dp};
-  double T[9];  // B * Sd
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      T[r * 3 + c] = B[r * 3 + 0] * Sd[0 * 3 + c] + B[r * 3 + 1] * Sd[1 * 3 + c] +
-                     B[r * 3 + 2] * Sd[2 * 3 + c];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      S[r * 3 + c] = T[r * 3 + 0] * B[c * 3 + 0] + T[r * 3 + 1] * B[c * 3 + 1] +
-                     T[r * 3 + 2] * B[c * 3 + 2];
+  // back to world: S = ap v1 v1^T + bp (v1 v2^T + v2 v1^T) + cp v2 v2^T + dp n n^T
+  Sym3 S;
+  const double* nh = k.nh;
+#define HGS_SPLIT_ENTRY(i, j) \
+  (ap * v1[i] * v1[j] + bp * (v1[i] * v2[j] + v2[i] * v1[j]) + cp * v2[i] * v2[j] + dp * nh[i] * nh[j])
+  S.xx = HGS_SPLIT_ENTRY(0, 0);
+  S.xy = HGS_SPLIT_ENTRY(0, 1);
+  S.xz = HGS_SPLIT_ENTRY(0, 2);
+  S.yy = HGS_SPLIT_ENTRY(1, 1);
+  S.yz = HGS_SPLIT_ENTRY(1, 2);
+  S.zz = HGS_SPLIT_ENTRY(2, 2);
+#undef HGS_SPLIT_ENTRY
+  return S;
 }
 
 // Per-camera part.
@@ -263,14 +272,12 @@ __device__ __forceinline__ void view_geo(const KernelGeo& k, const CamDev& cam, 
     vg.M[c] = J00 * (double)R[0 * 3 + c] + J02 * (double)R[2 * 3 + c];
     vg.M[3 + c] = J11 * (double)R[1 * 3 + c] + J12 * (double)R[2 * 3 + c];
   }
-  double MS[6];  // M * Sw
-  for (int r = 0; r < 2; ++r)
-    for (int c = 0; c < 3; ++c)
-      MS[r * 3 + c] = vg.M[r * 3 + 0] * k.Sw[0 * 3 + c] + vg.M[r * 3 + 1] * k.Sw[1 * 3 + c] +
-                      vg.M[r * 3 + 2] * k.Sw[2 * 3 + c];
-  vg.A = MS[0] * vg.M[0] + MS[1] * vg.M[1] + MS[2] * vg.M[2] + lowpass;
-  vg.B = MS[0] * vg.M[3] + MS[1] * vg.M[4] + MS[2] * vg.M[5];
-  vg.C = MS[3] * vg.M[3] + MS[4] * vg.M[4] + MS[5] * vg.M[5] + lowpass;
+  double S0[3], S1[3];  // Sigma_w M^T columns
+  sym_mul_vec(k.Sw, vg.M, S0);
+  sym_mul_vec(k.Sw, vg.M + 3, S1);
+  vg.A = vg.M[0] * S0[0] + vg.M[1] * S0[1] + vg.M[2] * S0[2] + lowpass;
+  vg.B = vg.M[3] * S0[0] + vg.M[4] * S0[1] + vg.M[5] * S0[2];
+  vg.C = vg.M[3] * S1[0] + vg.M[4] * S1[1] + vg.M[5] * S1[2] + lowpass;
   vg.det = vg.A * vg.C - vg.B * vg.B;
   vg.qa = vg.C / vg.det;
   vg.qb = -vg.B / vg.det;
@@ -293,6 +300,14 @@ __device__ __forceinline__ void view_geo(const KernelGeo& k, const CamDev& cam, 
     vg.k[0] = vg.w[0] * vg.r;
     vg.k[1] = vg.w[1] * vg.r;
   }
+}
+
+// Camera centre o = -R^T t in world space.
+__device__ __forceinline__ void camera_centre(const CamDev& cam, double* oc) {
+  const float* R = cam.R;
+  for (int a = 0; a < 3; ++a)
+    oc[a] = -((double)R[0 * 3 + a] * cam.t[0] + (double)R[1 * 3 + a] * cam.t[1] +
+              (double)R[2 * 3 + a] * cam.t[2]);
 }
 
 }  // namespace hgs

@@ -28,7 +28,7 @@ struct Box {
   bool any;
 };
 
-__device__ __forceinline__ Box half_box(const KernelGeo& k, const ViewGeo& vg, const double* Ss,
+__device__ __forceinline__ Box half_box(const KernelGeo& k, const ViewGeo& vg, const Sym3& Ss,
                                         float a1, float a2, const Opts& o) {
   Box b;
   const double kap = o.kappa;
@@ -42,13 +42,8 @@ __device__ __forceinline__ Box half_box(const KernelGeo& k, const ViewGeo& vg, c
   }
   double cx = ex, cy = ey;
   if (!k.nzero) {
-    const double* M = vg.M;
-    double sxx = 0.0, syy = 0.0;
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) {
-        sxx += M[r] * Ss[r * 3 + c] * M[c];
-        syy += M[3 + r] * Ss[r * 3 + c] * M[3 + c];
-      }
+    const double sxx = sym_form(Ss, vg.M, vg.M);
+    const double syy = sym_form(Ss, vg.M + 3, vg.M + 3);
     cx = fmin(kap * sqrt(sxx + (double)o.lowpass), ex);
     cy = fmin(kap * sqrt(syy + (double)o.lowpass), ey);
   }
@@ -85,9 +80,11 @@ __device__ __forceinline__ int clamp_floor(double x, int hi) {
   return v > hi ? hi : v;
 }
 
+template <int D>
 __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack cp, Opts o,
                                                                Record* __restrict__ rec,
                                                                uint32_t* __restrict__ tiles_out) {
+  constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   if (i >= p.n) return;
   const int64_t S = p.stride;
@@ -100,21 +97,16 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
   for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
   const float a1 = p.opac1[i];
   const float a2 = p.opac2[i];
-  const int deg = p.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
-  float sh[48];
-#pragma unroll
-  for (int j = 0; j < 48; ++j) sh[j] = (j < 3 * K) ? p.sh[j * S + i] : 0.0f;
+  // any non-finite parameter culls the kernel
+  bool params_ok = finite((double)a1) && finite((double)a2);
+  for (int c = 0; c < 3; ++c)
+    params_ok = params_ok && finite((double)mu[c]) && finite((double)s[c]) && finite((double)nrm[c]);
+  for (int c = 0; c < 4; ++c) params_ok = params_ok && finite((double)q[c]);
 
   KernelGeo kg;
   kernel_geo(mu, s, q, nrm, kg);
-  double Ss[9];
-  const bool need_split = !(o.flags & HGS_FLAG_FULL_BOX) && !kg.nzero;
-  if (need_split) splitting_cov(kg, Ss);
-  bool params_ok = finite(kg.mu[0]) && finite(kg.mu[1]) && finite(kg.mu[2]) && finite(kg.Sw[0]) &&
-                   finite(kg.Sw[4]) && finite(kg.Sw[8]) && finite(kg.Sw[1]) && finite(kg.Sw[2]) &&
-                   finite(kg.Sw[5]) && finite(kg.v) && finite((double)a1) && finite((double)a2);
-  const int T = cp.tile;
+  Sym3 Ss = kg.Sw;
+  if (!(o.flags & HGS_FLAG_FULL_BOX) && !kg.nzero) Ss = splitting_cov(kg);
   const int tsh = cp.tile_shift;
 
   for (int c = 0; c < cp.n_cams; ++c) {
@@ -130,25 +122,26 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
     bool ok = params_ok && finite(vg.t[2]) && vg.t[2] > (double)cam.znear;
     ok = ok && finite(vg.det) && vg.det > 0.0 && finite(vg.qa) && finite(vg.qb) &&
          finite(vg.qc) && finite(vg.mx) && finite(vg.my) && finite(vg.k[0]) && finite(vg.k[1]);
-    double col[3] = {0.0, 0.0, 0.0};
+    double col0 = 0.0, col1 = 0.0, col2 = 0.0;
     if (ok) {
-      // SH colour from the camera centre o = -R^T t towards the kernel.
-      const float* R = cam.R;
+      // SH colour from the camera centre towards the kernel
       double oc[3];
-      for (int a = 0; a < 3; ++a)
-        oc[a] = -((double)R[0 * 3 + a] * cam.t[0] + (double)R[1 * 3 + a] * cam.t[1] +
-                  (double)R[2 * 3 + a] * cam.t[2]);
+      camera_centre(cam, oc);
       double dx = kg.mu[0] - oc[0], dy = kg.mu[1] - oc[1], dz = kg.mu[2] - oc[2];
       const double dl = sqrt(dx * dx + dy * dy + dz * dz);
       dx /= dl; dy /= dl; dz /= dl;
-      double Y[16];
-      sh_eval(deg, dx, dy, dz, Y);
-      for (int ch = 0; ch < 3; ++ch) {
-        double acc = 0.0;
-        for (int kk = 0; kk < K; ++kk) acc += Y[kk] * (double)sh[kk * 3 + ch];
-        col[ch] = fmax(acc + 0.5, 0.0);
+      double Y[K];
+      sh_eval<D>(dx, dy, dz, Y);
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) {
+        col0 += Y[kk] * (double)p.sh[(kk * 3 + 0) * S + i];
+        col1 += Y[kk] * (double)p.sh[(kk * 3 + 1) * S + i];
+        col2 += Y[kk] * (double)p.sh[(kk * 3 + 2) * S + i];
       }
-      ok = finite(col[0]) && finite(col[1]) && finite(col[2]);
+      col0 = fmax(col0 + 0.5, 0.0);
+      col1 = fmax(col1 + 0.5, 0.0);
+      col2 = fmax(col2 + 0.5, 0.0);
+      ok = finite(col0) && finite(col1) && finite(col2);
     }
     Box bx;
     if (ok) {
@@ -174,9 +167,9 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
           r.qb = (float)vg.qb;
           r.qc = (float)vg.qc;
           r.alpha2 = a2;
-          r.r = (float)col[0];
-          r.g = (float)col[1];
-          r.b = (float)col[2];
+          r.r = (float)col0;
+          r.g = (float)col1;
+          r.b = (float)col2;
           r.d_o = (float)(((double)a1 - (double)a2) / 2.0);
           r.xr = (uint32_t)x0 | ((uint32_t)x1 << 16);
           r.yr = (uint32_t)y0 | ((uint32_t)y1 << 16);
@@ -184,7 +177,6 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
         }
       }
     }
-    (void)T;
     r.tiles = tiles;
     const int64_t ri = (int64_t)c * p.n + i;
     rec[ri] = r;
@@ -280,9 +272,21 @@ __global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const uint32_t* 
 // ---------------------------------------------------------------------------
 // backward of the projection (chain rule to every kernel parameter)
 // ---------------------------------------------------------------------------
+// symmetric part of u v^T, added to S
+__device__ __forceinline__ void add_sym_outer(Sym3& S, const double* u, const double* v, double w) {
+  S.xx += w * u[0] * v[0];
+  S.yy += w * u[1] * v[1];
+  S.zz += w * u[2] * v[2];
+  S.xy += w * 0.5 * (u[0] * v[1] + u[1] * v[0]);
+  S.xz += w * 0.5 * (u[0] * v[2] + u[2] * v[0]);
+  S.yz += w * 0.5 * (u[1] * v[2] + u[2] * v[1]);
+}
+
+template <int D>
 __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     Params p, CamPack cp, Opts o, const Record* __restrict__ rec,
     const float* __restrict__ rgrad, Grads G) {
+  constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   if (i >= p.n) return;
   const int64_t S = p.stride;
@@ -293,19 +297,17 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     nrm[c] = p.normals[c * S + i];
   }
   for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
-  const int deg = p.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
 
   KernelGeo kg;
   kernel_geo(mu, s, q, nrm, kg);
 
-  double g_mu[3] = {0, 0, 0};
-  double g_Sw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  double g_nh[3] = {0, 0, 0};
+  double g_mu[3] = {0.0, 0.0, 0.0};
+  Sym3 g_Sw = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double g_nh[3] = {0.0, 0.0, 0.0};
   double g_a1 = 0.0, g_a2 = 0.0;
-  double g_sh[48];
+  float g_sh[3 * K];
 #pragma unroll
-  for (int j = 0; j < 48; ++j) g_sh[j] = 0.0;
+  for (int j = 0; j < 3 * K; ++j) g_sh[j] = 0.0f;
 
   for (int c = 0; c < cp.n_cams; ++c) {
     const int64_t ri = (int64_t)c * p.n + i;
@@ -317,6 +319,7 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     const double galpha2 = gr[7], gdo = gr[8];
     const double gcol[3] = {gr[9], gr[10], gr[11]};
 
+    // alpha2 and (alpha1 - alpha2) / 2
     g_a2 += galpha2 - 0.5 * gdo;
     g_a1 += 0.5 * gdo;
 
@@ -324,41 +327,47 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     ViewGeo vg;
     view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
 
-    // ---- colour: c = max(0, sum f Y(d) + 0.5), d = (mu - o) / |mu - o|
+    // ---- colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - o) / |mu - o|
     {
-      const float* R = cam.R;
       double oc[3];
-      for (int a = 0; a < 3; ++a)
-        oc[a] = -((double)R[0 * 3 + a] * cam.t[0] + (double)R[1 * 3 + a] * cam.t[1] +
-                  (double)R[2 * 3 + a] * cam.t[2]);
-      double dv[3] = {kg.mu[0] - oc[0], kg.mu[1] - oc[1], kg.mu[2] - oc[2]};
-      const double dl = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-      const double d[3] = {dv[0] / dl, dv[1] / dl, dv[2] / dl};
-      double Y[16];
-      sh_eval(deg, d[0], d[1], d[2], Y);
-      double wk[16];
-      for (int kk = 0; kk < 16; ++kk) wk[kk] = 0.0;
-      for (int ch = 0; ch < 3; ++ch) {
-        double raw = 0.5;
-        for (int kk = 0; kk < K; ++kk) raw += Y[kk] * (double)p.sh[(kk * 3 + ch) * S + i];
-        const double gc = raw > 0.0 ? gcol[ch] : 0.0;
-        for (int kk = 0; kk < K; ++kk) {
-          g_sh[kk * 3 + ch] += gc * Y[kk];
-          wk[kk] += gc * (double)p.sh[(kk * 3 + ch) * S + i];
+      camera_centre(cam, oc);
+      const double dv0 = kg.mu[0] - oc[0], dv1 = kg.mu[1] - oc[1], dv2 = kg.mu[2] - oc[2];
+      const double dl = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
+      const double d0 = dv0 / dl, d1 = dv1 / dl, d2 = dv2 / dl;
+      double Y[K];
+      sh_eval<D>(d0, d1, d2, Y);
+      double raw[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[kk] * (double)p.sh[(kk * 3 + ch) * S + i];
+      double gc[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) gc[ch] = (raw[ch] + 0.5 > 0.0) ? gcol[ch] : 0.0;
+      double wk[K];
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) {
+        double acc = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          g_sh[kk * 3 + ch] += (float)(gc[ch] * Y[kk]);
+          acc += gc[ch] * (double)p.sh[(kk * 3 + ch) * S + i];
         }
+        wk[kk] = acc;
       }
-      double gd[3];
-      sh_grad(deg, d[0], d[1], d[2], wk, &gd[0], &gd[1], &gd[2]);
-      const double dot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
-      for (int a = 0; a < 3; ++a) g_mu[a] += (gd[a] - d[a] * dot) / dl;
+      double gd0, gd1, gd2;
+      sh_grad<D>(d0, d1, d2, wk, &gd0, &gd1, &gd2);
+      const double dot = gd0 * d0 + gd1 * d1 + gd2 * d2;
+      g_mu[0] += (gd0 - d0 * dot) / dl;
+      g_mu[1] += (gd1 - d1 * dot) / dl;
+      g_mu[2] += (gd2 - d2 * dot) / dl;
     }
 
     // ---- k = w r, r = (2 s2)^-1/2, w = Q g, s2 = v - g.w (or 1e-12 v)
-    double gw0 = 0.0, gw1 = 0.0, gg0 = 0.0, gg1 = 0.0, gv = 0.0;
+    double gg0 = 0.0, gg1 = 0.0, gv = 0.0;
     double gQa = gqa, gQb = gqb, gQc = gqc;
     if (!kg.nzero && vg.s2 > 0.0) {
-      gw0 = gkx * vg.r;
-      gw1 = gky * vg.r;
+      double gw0 = gkx * vg.r, gw1 = gky * vg.r;
       const double grr = gkx * vg.w[0] + gky * vg.w[1];
       const double gs2 = -grr * vg.r * vg.r * vg.r;
       if (!vg.s2clamp) {
@@ -382,40 +391,41 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     const double gA = (-C * C * gQa + B * C * gQb - B * B * gQc) * id2;
     const double gB = (2.0 * B * C * gQa - (A * C + B * B) * gQb + 2.0 * A * B * gQc) * id2;
     const double gC = (-B * B * gQa + A * B * gQb - A * A * gQc) * id2;
-    // G_S = [[gA, gB/2], [gB/2, gC]]; Shat = M Sw M^T  =>  dM += 2 G_S M Sw,
-    // dSw += M^T G_S M.  g = M Sn  =>  dM += gg Sn^T, dSn = M^T gg.
+    // G_S = [[gA, gB/2], [gB/2, gC]].  Shat = M Sw M^T: dM += 2 G_S M Sw,
+    // dSw += M^T G_S M.  g = M Sn: dM += gg Sn^T, dSn = M^T gg.
     const double* M = vg.M;
-    const double GS[4] = {gA, 0.5 * gB, 0.5 * gB, gC};
-    double MS[6];
-    for (int r = 0; r < 2; ++r)
-      for (int cc = 0; cc < 3; ++cc)
-        MS[r * 3 + cc] = M[r * 3 + 0] * kg.Sw[0 * 3 + cc] + M[r * 3 + 1] * kg.Sw[1 * 3 + cc] +
-                         M[r * 3 + 2] * kg.Sw[2 * 3 + cc];
+    const double GS00 = gA, GS01 = 0.5 * gB, GS11 = gC;
+    double MS0[3], MS1[3];  // rows of M Sw
+    sym_mul_vec(kg.Sw, M, MS0);
+    sym_mul_vec(kg.Sw, M + 3, MS1);
     double gM[6];
-    for (int r = 0; r < 2; ++r)
-      for (int cc = 0; cc < 3; ++cc)
-        gM[r * 3 + cc] = 2.0 * (GS[r * 2 + 0] * MS[0 * 3 + cc] + GS[r * 2 + 1] * MS[1 * 3 + cc]);
-    gM[0] += gg0 * kg.Sn[0]; gM[1] += gg0 * kg.Sn[1]; gM[2] += gg0 * kg.Sn[2];
-    gM[3] += gg1 * kg.Sn[0]; gM[4] += gg1 * kg.Sn[1]; gM[5] += gg1 * kg.Sn[2];
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc) {
-        double acc = 0.0;
-        for (int a = 0; a < 2; ++a)
-          for (int b = 0; b < 2; ++b) acc += M[a * 3 + r] * GS[a * 2 + b] * M[b * 3 + cc];
-        g_Sw[r * 3 + cc] += acc;
-      }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      gM[cc] = 2.0 * (GS00 * MS0[cc] + GS01 * MS1[cc]) + gg0 * kg.Sn[cc];
+      gM[3 + cc] = 2.0 * (GS01 * MS0[cc] + GS11 * MS1[cc]) + gg1 * kg.Sn[cc];
+    }
+    // M^T G_S M (symmetric)
+    add_sym_outer(g_Sw, M, M, GS00);
+    add_sym_outer(g_Sw, M + 3, M + 3, GS11);
+    add_sym_outer(g_Sw, M, M + 3, 2.0 * GS01);
     double gSn[3];
-    for (int r = 0; r < 3; ++r) gSn[r] = M[r] * gg0 + M[3 + r] * gg1 + gv * kg.nh[r];
-    for (int r = 0; r < 3; ++r) g_nh[r] += gv * kg.Sn[r];
-    // Sn = Sw n  =>  dSw += dSn n^T, dn += Sw dSn
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc) g_Sw[r * 3 + cc] += gSn[r] * kg.nh[cc];
-    for (int r = 0; r < 3; ++r)
-      g_nh[r] += kg.Sw[r * 3 + 0] * gSn[0] + kg.Sw[r * 3 + 1] * gSn[1] + kg.Sw[r * 3 + 2] * gSn[2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      gSn[r] = M[r] * gg0 + M[3 + r] * gg1 + gv * kg.nh[r];
+      g_nh[r] += gv * kg.Sn[r];
+    }
+    // Sn = Sw n: dSw += sym(dSn n^T), dn += Sw dSn
+    add_sym_outer(g_Sw, gSn, kg.nh, 1.0);
+    double SgSn[3];
+    sym_mul_vec(kg.Sw, gSn, SgSn);
+    g_nh[0] += SgSn[0];
+    g_nh[1] += SgSn[1];
+    g_nh[2] += SgSn[2];
 
-    // ---- M = J R_c  =>  dJ = dM R_c^T
+    // ---- M = J R_c: dJ = dM R_c^T
     const float* Rc = cam.R;
     double gJ00 = 0.0, gJ02 = 0.0, gJ11 = 0.0, gJ12 = 0.0;
+#pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       gJ00 += gM[cc] * (double)Rc[0 * 3 + cc];
       gJ02 += gM[cc] * (double)Rc[2 * 3 + cc];
@@ -425,49 +435,48 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     const double tx = vg.t[0], ty = vg.t[1], tz = vg.t[2];
     const double fx = cam.fx, fy = cam.fy;
     const double tz2 = tz * tz, tz3 = tz2 * tz;
-    double gt[3] = {0.0, 0.0, 0.0};
-    gt[2] += -fx / tz2 * gJ00 - fy / tz2 * gJ11;
+    double gt0 = 0.0, gt1 = 0.0, gt2 = 0.0;
+    gt2 += -fx / tz2 * gJ00 - fy / tz2 * gJ11;
     if (!vg.clx) {
-      gt[0] += -fx / tz2 * gJ02;
-      gt[2] += 2.0 * fx * tx / tz3 * gJ02;
+      gt0 += -fx / tz2 * gJ02;
+      gt2 += 2.0 * fx * tx / tz3 * gJ02;
     } else {
-      gt[2] += fx * vg.xc / tz2 * gJ02;
+      gt2 += fx * vg.xc / tz2 * gJ02;
     }
     if (!vg.cly) {
-      gt[1] += -fy / tz2 * gJ12;
-      gt[2] += 2.0 * fy * ty / tz3 * gJ12;
+      gt1 += -fy / tz2 * gJ12;
+      gt2 += 2.0 * fy * ty / tz3 * gJ12;
     } else {
-      gt[2] += fy * vg.yc / tz2 * gJ12;
+      gt2 += fy * vg.yc / tz2 * gJ12;
     }
     // screen centre
-    gt[0] += gmx * fx / tz;
-    gt[1] += gmy * fy / tz;
-    gt[2] += -gmx * fx * tx / tz2 - gmy * fy * ty / tz2;
+    gt0 += gmx * fx / tz;
+    gt1 += gmy * fy / tz;
+    gt2 += -gmx * fx * tx / tz2 - gmy * fy * ty / tz2;
     // t = R_c mu + t_c
+#pragma unroll
     for (int a = 0; a < 3; ++a)
-      g_mu[a] += (double)Rc[0 * 3 + a] * gt[0] + (double)Rc[1 * 3 + a] * gt[1] +
-                 (double)Rc[2 * 3 + a] * gt[2];
+      g_mu[a] += (double)Rc[0 * 3 + a] * gt0 + (double)Rc[1 * 3 + a] * gt1 + (double)Rc[2 * 3 + a] * gt2;
   }
 
-  // ---- Sigma_w = Rq diag(s^2) Rq^T
-  double Gs[9];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) Gs[r * 3 + c] = 0.5 * (g_Sw[r * 3 + c] + g_Sw[c * 3 + r]);
-  const double* Rq = kg.Rq;
-  const double dd[3] = {kg.s[0] * kg.s[0], kg.s[1] * kg.s[1], kg.s[2] * kg.s[2]};
-  double GR[9];  // dL/dRq = 2 Gs Rq D
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      GR[r * 3 + c] = 2.0 * (Gs[r * 3 + 0] * Rq[0 * 3 + c] + Gs[r * 3 + 1] * Rq[1 * 3 + c] +
-                             Gs[r * 3 + 2] * Rq[2 * 3 + c]) * dd[c];
+  // ---- Sigma_w = Rq diag(s^2) Rq^T:  dRq = 2 Gs Rq D,  ds_c = 2 s_c (Rq^T Gs Rq)_cc
+  double qh[4], qn, Rq[9];
+  quat_rot(q, qh, qn, Rq);
+  const double sc[3] = {(double)s[0], (double)s[1], (double)s[2]};
   double g_s[3];
+  double GR[9];
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double acc = 0.0;  // (Rq^T Gs Rq)_cc
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) acc += Rq[a * 3 + c] * Gs[a * 3 + b] * Rq[b * 3 + c];
-    g_s[c] = 2.0 * kg.s[c] * acc;
+    const double col[3] = {Rq[0 * 3 + c], Rq[1 * 3 + c], Rq[2 * 3 + c]};
+    double Gc[3];
+    sym_mul_vec(g_Sw, col, Gc);
+    g_s[c] = 2.0 * sc[c] * (col[0] * Gc[0] + col[1] * Gc[1] + col[2] * Gc[2]);
+    const double dsq = sc[c] * sc[c];
+    GR[0 * 3 + c] = 2.0 * Gc[0] * dsq;
+    GR[1 * 3 + c] = 2.0 * Gc[1] * dsq;
+    GR[2 * 3 + c] = 2.0 * Gc[2] * dsq;
   }
-  const double qw = kg.qh[0], qx = kg.qh[1], qy = kg.qh[2], qz = kg.qh[3];
+  const double qw = qh[0], qx = qh[1], qy = qh[2], qz = qh[3];
   const double* g = GR;
   double gq[4];
   gq[0] = 2.0 * (-qz * g[1] + qy * g[2] + qz * g[3] - qx * g[5] - qy * g[6] + qx * g[7]);
@@ -477,25 +486,30 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
                  qz * g[7] - 2.0 * qy * g[8]);
   gq[3] = 2.0 * (-2.0 * qz * g[0] - qw * g[1] + qx * g[2] + qw * g[3] - 2.0 * qz * g[4] +
                  qy * g[5] + qx * g[6] + qy * g[7]);
-  double gq_raw[4] = {0, 0, 0, 0};
-  if (kg.qn > 0.0) {
+  double gq_raw[4] = {0.0, 0.0, 0.0, 0.0};
+  if (qn > 0.0) {
     const double dot = gq[0] * qw + gq[1] * qx + gq[2] * qy + gq[3] * qz;
-    for (int a = 0; a < 4; ++a) gq_raw[a] = (gq[a] - kg.qh[a] * dot) / kg.qn;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gq_raw[a] = (gq[a] - qh[a] * dot) / qn;
   }
-  double gn_raw[3] = {0, 0, 0};
+  double gn_raw[3] = {0.0, 0.0, 0.0};
   if (!kg.nzero) {
     const double dot = g_nh[0] * kg.nh[0] + g_nh[1] * kg.nh[1] + g_nh[2] * kg.nh[2];
+#pragma unroll
     for (int a = 0; a < 3; ++a) gn_raw[a] = (g_nh[a] - kg.nh[a] * dot) / kg.nn;
   }
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
     G.means[c * S + i] = (float)g_mu[c];
     G.scales[c * S + i] = (float)g_s[c];
     G.normals[c * S + i] = (float)gn_raw[c];
   }
+#pragma unroll
   for (int c = 0; c < 4; ++c) G.quats[c * S + i] = (float)gq_raw[c];
   G.opac1[i] = (float)g_a1;
   G.opac2[i] = (float)g_a2;
-  for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = (float)g_sh[j];
+#pragma unroll
+  for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = g_sh[j];
 }
 
 }  // namespace
@@ -504,7 +518,12 @@ hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, 
                              uint32_t* tiles, hipStream_t s) {
   if (p.n == 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
-  hipLaunchKernelGGL(preprocess_kernel, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles);
+  switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
+    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
+    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
+    default: hipLaunchKernelGGL(preprocess_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
+  }
   return hipGetLastError();
 }
 
@@ -532,8 +551,12 @@ hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts&
                                  hipStream_t s) {
   if (p.n == 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
-  hipLaunchKernelGGL(preprocess_bwd_kernel, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec,
-                     rec_grads, g);
+  switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(preprocess_bwd_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+    case 1: hipLaunchKernelGGL(preprocess_bwd_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+    case 2: hipLaunchKernelGGL(preprocess_bwd_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+    default: hipLaunchKernelGGL(preprocess_bwd_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+  }
   return hipGetLastError();
 }
 

@@ -1,16 +1,22 @@
 // Tile rasterizer: per-pixel front-to-back blending with the paired-half
 // opacity of Eq. 10, and its back-to-front replay for gradients.
 //
-// One workgroup owns one tile (T x T pixels, one thread per pixel: 1, 4 or 16
-// wavefronts).  The tile's sorted list is consumed in batches of BATCH
-// records that the workgroup stages in LDS (64 bytes each, four 16-byte
-// slots), so every record is read from HBM once per tile and then broadcast
-// to all pixels from LDS.  Blending stops per pixel before the kernel that
-// would take the transmittance below t_min, and the tile stops when all its
-// pixels have.  For each pixel the forward pass keeps only the final
-// transmittance, the position of the last blended entry and the count; the
-// backward pass recomputes each pair from the records and walks the list
-// backwards, dividing the transmittance back out.
+// Work decomposition (CDNA, wave64): a wavefront owns a 16x16 block of
+// pixels (8x8 for 8-pixel tiles) and each lane owns 4 pixels of it (1 for
+// 8-pixel tiles) -- pixel rows ly, ly+4, ly+8, ly+12 of column lx.  A 32-pixel
+// tile is four such wavefronts walking the same list.  Every lane of a
+// wavefront needs the same record at the same time, so the list is walked
+// with wave-uniform indices: a round fetches `batch` entry ids with one
+// vector load per lane, then each id is broadcast with v_readlane and its
+// 64-byte record is loaded as uniform (scalar) data, one entry ahead of its
+// use.  No LDS staging and no workgroup barriers: each wavefront stops as
+// soon as all of its pixels are done.
+//
+// Backward: each lane replays its pixels back to front from the last blended
+// entry, dividing the transmittance back out, and sums its pixels'
+// gradients for the entry; the 12 sums are then reduced across the 64 lanes
+// with DPP row operations and one lane issues the float atomics, so there is
+// one reduction and one set of atomics per (entry, 256 pixels).
 
 #include "hgs_internal.h"
 
@@ -18,229 +24,290 @@ namespace hgs {
 
 namespace {
 
+constexpr float kTwoOverSqrtPi = 1.12837916709551257390f;
+
 struct Pair {
   bool live;   // in rect and power <= 0
   float dx, dy, G, I, HG, a;
 };
 
-__device__ __forceinline__ bool in_rect(uint32_t xr, uint32_t yr, int px, int py) {
-  const int x0 = (int)(xr & 0xffffu), x1 = (int)(xr >> 16);
-  const int y0 = (int)(yr & 0xffffu), y1 = (int)(yr >> 16);
-  return px >= x0 && px <= x1 && py >= y0 && py <= y1;
-}
-
-__device__ __forceinline__ void eval_pair(const float4& q0, const float4& q1, const float4& q3,
-                                          float d_o, int px, int py, float alpha_max, Pair& P) {
-  const uint32_t xr = __float_as_uint(q3.x), yr = __float_as_uint(q3.y);
-  P.live = in_rect(xr, yr, px, py);
+// One pixel against one record.  Pure function of its inputs, so the forward
+// and backward passes take identical decisions.
+__device__ __forceinline__ void eval_pair(const Record& r, int px, int py, float alpha_max,
+                                          Pair& P) {
+  const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
+  const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
+  P.live = px >= x0 && px <= x1 && py >= y0 && py <= y1;
   if (!P.live) return;
-  P.dx = (float)(px - (int)(xr & 0xffffu)) + 0.5f - q0.x;
-  P.dy = (float)(py - (int)(yr & 0xffffu)) + 0.5f - q0.y;
-  const float power = -0.5f * (q1.x * P.dx * P.dx + q1.z * P.dy * P.dy) - q1.y * P.dx * P.dy;
+  P.dx = (float)(px - x0) + 0.5f - r.mx;
+  P.dy = (float)(py - y0) + 0.5f - r.my;
+  const float power = -0.5f * (r.qa * P.dx * P.dx + r.qc * P.dy * P.dy) - r.qb * P.dx * P.dy;
   P.live = !(power > 0.0f);
   if (!P.live) return;
   P.G = __expf(power);
-  if (d_o != 0.0f) {
-    P.I = erfcf(-(q0.z * P.dx + q0.w * P.dy));
-    P.HG = (q1.w + d_o * P.I) * P.G;
+  if (r.d_o != 0.0f) {
+    P.I = erfcf(-(r.kx * P.dx + r.ky * P.dy));
+    P.HG = (r.alpha2 + r.d_o * P.I) * P.G;
   } else {
     P.I = 1.0f;
-    P.HG = q1.w * P.G;
+    P.HG = r.alpha2 * P.G;
   }
   P.a = fminf(alpha_max, P.HG);
 }
 
-template <int T, int BATCH>
-__global__ __launch_bounds__(T* T) void render_fwd_kernel(
+template <int T>
+struct Geometry {
+  static constexpr int SUB = (T == 8) ? 8 : 16;       // pixels per wavefront side
+  static constexpr int PPL = SUB * SUB / 64;          // pixels per lane
+  static constexpr int WAVES = (T / SUB) * (T / SUB); // wavefronts per tile
+  static constexpr int ROWSTEP = 64 / SUB;            // rows between a lane's pixels
+};
+
+__device__ __forceinline__ Record load_record(const Record* __restrict__ rec, uint32_t id) {
+  return rec[id];
+}
+
+// Sum over the 64 lanes; the total lands in lane 63.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+__device__ __forceinline__ float wave_sum_last(float v) {
+  v += dpp<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x124, 0xf>(v);  // row_ror:4
+  v += dpp<0x128, 0xf>(v);  // row_ror:8   (every lane holds its row's sum)
+  v += dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int o = __shfl_xor(v, m, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+template <int T, int IPL>
+__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, CamPack cp, Opts o, float* __restrict__ img,
     float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib) {
-  constexpr int NT = T * T;
-  __shared__ float4 s_q[4][BATCH];
+  using Gm = Geometry<T>;
+  constexpr int PPL = Gm::PPL;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t tile = blockIdx.x;
   const int c = cam_of_tile(cp, tile);
   const CamDev& cam = cp.cam[c];
   const uint32_t lt = tile - cam.tile_off;
   const int ty = (int)(lt / (uint32_t)cam.tiles_x);
   const int tx = (int)(lt - (uint32_t)ty * (uint32_t)cam.tiles_x);
-  const int px = tx * T + (int)(threadIdx.x % T);
-  const int py = ty * T + (int)(threadIdx.x / T);
-  const bool inside = px < cam.width && py < cam.height;
+  const int ox = tx * T + (wave % (T / Gm::SUB)) * Gm::SUB;
+  const int oy = ty * T + (wave / (T / Gm::SUB)) * Gm::SUB;
+  const int px = ox + lane % Gm::SUB;
+  int py[PPL];
+  bool inside[PPL];
+  float Tr[PPL], C0[PPL], C1[PPL], C2[PPL];
+  int32_t cnt[PPL], last[PPL];
+  bool done[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    py[j] = oy + lane / Gm::SUB + j * Gm::ROWSTEP;
+    inside[j] = px < cam.width && py[j] < cam.height;
+    Tr[j] = 1.0f;
+    C0[j] = C1[j] = C2[j] = 0.0f;
+    cnt[j] = 0;
+    last[j] = -1;
+    done[j] = !inside[j];
+  }
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-
-  float Tr = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  int32_t count = 0, last = -1;
-  bool done = !inside;
   const float amin = o.alpha_min, amax = o.alpha_max, tmin = o.t_min;
 
-  for (uint32_t b = start; b < end; b += BATCH) {
-    if (__syncthreads_count(done) == NT) break;
-    const uint32_t nb = (end - b) < (uint32_t)BATCH ? (end - b) : (uint32_t)BATCH;
-    for (uint32_t j = threadIdx.x; j < nb; j += NT) {
-      const float4* rp = reinterpret_cast<const float4*>(rec + vals[b + j]);
-      s_q[0][j] = rp[0];
-      s_q[1][j] = rp[1];
-      s_q[2][j] = rp[2];
-      s_q[3][j] = rp[3];
+  for (uint32_t base = start; base < end; base += 64 * IPL) {
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) any |= !done[j];
+    if (__ballot(any) == 0ull) break;
+    uint32_t ids[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+      const uint32_t p = base + k * 64 + lane;
+      ids[k] = p < end ? vals[p] : 0u;
     }
-    __syncthreads();
-    if (!done) {
-      for (uint32_t j = 0; j < nb; ++j) {
-        const float4 q2 = s_q[2][j];
-        Pair P;
-        eval_pair(s_q[0][j], s_q[1][j], s_q[3][j], q2.w, px, py, amax, P);
-        if (!P.live || P.a < amin) continue;
-        const float Tn = Tr * (1.0f - P.a);
-        if (Tn < tmin) {
-          done = true;
-          break;
+    const uint32_t nb = (end - base) < (uint32_t)(64 * IPL) ? (end - base) : (uint32_t)(64 * IPL);
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+      const int lim = (int)nb - k * 64;
+      if (lim <= 0) break;
+      const int cntk = lim < 64 ? lim : 64;
+      for (int l = 0; l < cntk; ++l) {
+        const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
+        const Record r = load_record(rec, id);
+        const int32_t pos = (int32_t)(base + k * 64 + l);
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          if (done[j]) continue;
+          Pair P;
+          eval_pair(r, px, py[j], amax, P);
+          if (!P.live || P.a < amin) continue;
+          const float Tn = Tr[j] * (1.0f - P.a);
+          if (Tn < tmin) {
+            done[j] = true;
+            continue;
+          }
+          const float w = P.a * Tr[j];
+          C0[j] += r.r * w;
+          C1[j] += r.g * w;
+          C2[j] += r.b * w;
+          Tr[j] = Tn;
+          ++cnt[j];
+          last[j] = pos;
         }
-        const float w = P.a * Tr;
-        C0 += q2.x * w;
-        C1 += q2.y * w;
-        C2 += q2.z * w;
-        Tr = Tn;
-        ++count;
-        last = (int32_t)(b + j);
       }
     }
   }
-  if (inside) {
-    const uint64_t plane = (uint64_t)cam.width * cam.height;
-    const uint64_t pix = (uint64_t)py * cam.width + px;
-    float* im = img + 3 * cam.pix_off;
-    im[pix] = C0 + Tr * o.bg[0];
-    im[plane + pix] = C1 + Tr * o.bg[1];
-    im[2 * plane + pix] = C2 + Tr * o.bg[2];
-    T_final[cam.pix_off + pix] = Tr;
-    last_idx[cam.pix_off + pix] = last;
-    n_contrib[cam.pix_off + pix] = count;
+  const uint64_t plane = (uint64_t)cam.width * cam.height;
+  float* im = img + 3 * cam.pix_off;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    if (!inside[j]) continue;
+    const uint64_t pix = (uint64_t)py[j] * cam.width + px;
+    im[pix] = C0[j] + Tr[j] * o.bg[0];
+    im[plane + pix] = C1[j] + Tr[j] * o.bg[1];
+    im[2 * plane + pix] = C2[j] + Tr[j] * o.bg[2];
+    T_final[cam.pix_off + pix] = Tr[j];
+    last_idx[cam.pix_off + pix] = last[j];
+    n_contrib[cam.pix_off + pix] = cnt[j];
   }
 }
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-  return x;
-}
-
-template <int T, int BATCH>
-__global__ __launch_bounds__(T* T) void render_bwd_kernel(
+template <int T, int IPL>
+__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, CamPack cp, Opts o, const float* __restrict__ T_final,
     const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimg,
     float* __restrict__ rgrad) {
-  constexpr int NT = T * T;
-  __shared__ float4 s_q[4][BATCH];
-  __shared__ uint32_t s_id[BATCH];
-  __shared__ int32_t s_max;
+  using Gm = Geometry<T>;
+  constexpr int PPL = Gm::PPL;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t tile = blockIdx.x;
   const int c = cam_of_tile(cp, tile);
   const CamDev& cam = cp.cam[c];
   const uint32_t lt = tile - cam.tile_off;
   const int ty = (int)(lt / (uint32_t)cam.tiles_x);
   const int tx = (int)(lt - (uint32_t)ty * (uint32_t)cam.tiles_x);
-  const int px = tx * T + (int)(threadIdx.x % T);
-  const int py = ty * T + (int)(threadIdx.x / T);
-  const bool inside = px < cam.width && py < cam.height;
-  const uint32_t start = ranges[2 * tile];
+  const int ox = tx * T + (wave % (T / Gm::SUB)) * Gm::SUB;
+  const int oy = ty * T + (wave / (T / Gm::SUB)) * Gm::SUB;
+  const int px = ox + lane % Gm::SUB;
+  const uint64_t plane = (uint64_t)cam.width * cam.height;
+  const float* g = dL_dimg + 3 * cam.pix_off;
 
-  float Tf = 1.0f, dL0 = 0.0f, dL1 = 0.0f, dL2 = 0.0f;
-  int32_t last = -1;
-  if (inside) {
-    const uint64_t plane = (uint64_t)cam.width * cam.height;
-    const uint64_t pix = (uint64_t)py * cam.width + px;
-    Tf = T_final[cam.pix_off + pix];
-    last = last_idx[cam.pix_off + pix];
-    const float* g = dL_dimg + 3 * cam.pix_off;
-    dL0 = g[pix];
-    dL1 = g[plane + pix];
-    dL2 = g[2 * plane + pix];
-  }
-  if (threadIdx.x == 0) s_max = -1;
-  __syncthreads();
-  if (last >= 0) atomicMax(&s_max, last);
-  __syncthreads();
-  const int32_t top = s_max;
-  if (top < 0) return;
-
-  const float amin = o.alpha_min, amax = o.alpha_max;
-  const float bgdot = o.bg[0] * dL0 + o.bg[1] * dL1 + o.bg[2] * dL2;
-  float Tr = Tf;
-  float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-  float la = 0.0f, lc0 = 0.0f, lc1 = 0.0f, lc2 = 0.0f;
-  const float kTwoOverSqrtPi = 1.12837916709551257390f;
-
-  for (int64_t bend = (int64_t)top + 1; bend > (int64_t)start; bend -= BATCH) {
-    const int64_t bbeg = bend - BATCH > (int64_t)start ? bend - BATCH : (int64_t)start;
-    const uint32_t nb = (uint32_t)(bend - bbeg);
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < nb; j += NT) {
-      const uint32_t id = vals[bbeg + j];
-      const float4* rp = reinterpret_cast<const float4*>(rec + id);
-      s_id[j] = id;
-      s_q[0][j] = rp[0];
-      s_q[1][j] = rp[1];
-      s_q[2][j] = rp[2];
-      s_q[3][j] = rp[3];
+  int py[PPL];
+  int32_t last[PPL];
+  float Tf[PPL], Tr[PPL], dL0[PPL], dL1[PPL], dL2[PPL];
+  float acc0[PPL], acc1[PPL], acc2[PPL], la[PPL], lc0[PPL], lc1[PPL], lc2[PPL], bgdot[PPL];
+  int top = -1;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    py[j] = oy + lane / Gm::SUB + j * Gm::ROWSTEP;
+    const bool inside = px < cam.width && py[j] < cam.height;
+    last[j] = -1;
+    Tf[j] = 1.0f;
+    dL0[j] = dL1[j] = dL2[j] = 0.0f;
+    if (inside) {
+      const uint64_t pix = (uint64_t)py[j] * cam.width + px;
+      Tf[j] = T_final[cam.pix_off + pix];
+      last[j] = last_idx[cam.pix_off + pix];
+      dL0[j] = g[pix];
+      dL1[j] = g[plane + pix];
+      dL2[j] = g[2 * plane + pix];
     }
-    __syncthreads();
-    for (int j = (int)nb - 1; j >= 0; --j) {
-      const int64_t pos = bbeg + j;
-      const float4 q0 = s_q[0][j], q1 = s_q[1][j], q2 = s_q[2][j];
-      Pair P;
-      bool contrib = false;
-      if (pos <= last) {
-        eval_pair(q0, q1, s_q[3][j], q2.w, px, py, amax, P);
-        contrib = P.live && P.a >= amin;
-      }
-      if (__ballot(contrib) == 0ull) continue;
-      float g[HGS_RECORD_GRAD_FLOATS];
+    Tr[j] = Tf[j];
+    acc0[j] = acc1[j] = acc2[j] = 0.0f;
+    la[j] = lc0[j] = lc1[j] = lc2[j] = 0.0f;
+    bgdot[j] = o.bg[0] * dL0[j] + o.bg[1] * dL1[j] + o.bg[2] * dL2[j];
+    top = last[j] > top ? last[j] : top;
+  }
+  top = wave_max(top);
+  const int32_t start = (int32_t)ranges[2 * tile];
+  if (top < start) return;
+  const float amin = o.alpha_min, amax = o.alpha_max;
+
+  // entries top, top-1, ..., start in rounds of 64 * IPL
+  for (int32_t hi = top; hi >= start; hi -= 64 * IPL) {
+    uint32_t ids[IPL];
 #pragma unroll
-      for (int k = 0; k < HGS_RECORD_GRAD_FLOATS; ++k) g[k] = 0.0f;
-      if (contrib) {
-        const float a = P.a;
-        const float Tb = Tr / (1.0f - a);
-        const float wcol = a * Tb;
-        g[9] = wcol * dL0;
-        g[10] = wcol * dL1;
-        g[11] = wcol * dL2;
-        acc0 = la * lc0 + (1.0f - la) * acc0;
-        acc1 = la * lc1 + (1.0f - la) * acc1;
-        acc2 = la * lc2 + (1.0f - la) * acc2;
-        la = a;
-        lc0 = q2.x;
-        lc1 = q2.y;
-        lc2 = q2.z;
-        float dLda = ((q2.x - acc0) * dL0 + (q2.y - acc1) * dL1 + (q2.z - acc2) * dL2) * Tb;
-        dLda += -Tf / (1.0f - a) * bgdot;
-        Tr = Tb;
-        const float dHG = (P.HG > amax) ? 0.0f : dLda;
-        const float d_o = q2.w;
-        const float dG = dHG * (q1.w + d_o * P.I);
-        g[7] = dHG * P.G;
-        g[8] = dHG * P.I * P.G;
-        float du = 0.0f;
-        if (d_o != 0.0f) {
-          const float u = q0.z * P.dx + q0.w * P.dy;
-          du = dHG * d_o * P.G * kTwoOverSqrtPi * __expf(-u * u);
+    for (int k = 0; k < IPL; ++k) {
+      const int32_t p = hi - (k * 64 + lane);
+      ids[k] = p >= start ? vals[p] : 0u;
+    }
+    const int32_t nb = (hi - start + 1) < 64 * IPL ? (hi - start + 1) : 64 * IPL;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+      const int lim = nb - k * 64;
+      if (lim <= 0) break;
+      const int cntk = lim < 64 ? lim : 64;
+      for (int l = 0; l < cntk; ++l) {
+        const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
+        const Record r = load_record(rec, id);
+        const int32_t pos = hi - (k * 64 + l);
+        float gs[HGS_RECORD_GRAD_FLOATS];
+#pragma unroll
+        for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q) gs[q] = 0.0f;
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          if (pos > last[j]) continue;
+          Pair P;
+          eval_pair(r, px, py[j], amax, P);
+          if (!P.live || P.a < amin) continue;
+          any = true;
+          const float a = P.a;
+          const float Tb = Tr[j] / (1.0f - a);
+          const float wcol = a * Tb;
+          gs[9] += wcol * dL0[j];
+          gs[10] += wcol * dL1[j];
+          gs[11] += wcol * dL2[j];
+          acc0[j] = la[j] * lc0[j] + (1.0f - la[j]) * acc0[j];
+          acc1[j] = la[j] * lc1[j] + (1.0f - la[j]) * acc1[j];
+          acc2[j] = la[j] * lc2[j] + (1.0f - la[j]) * acc2[j];
+          la[j] = a;
+          lc0[j] = r.r;
+          lc1[j] = r.g;
+          lc2[j] = r.b;
+          float dLda = ((r.r - acc0[j]) * dL0[j] + (r.g - acc1[j]) * dL1[j] + (r.b - acc2[j]) * dL2[j]) * Tb;
+          dLda += -Tf[j] / (1.0f - a) * bgdot[j];
+          Tr[j] = Tb;
+          const float dHG = (P.HG > amax) ? 0.0f : dLda;
+          const float dG = dHG * (r.alpha2 + r.d_o * P.I);
+          gs[7] += dHG * P.G;
+          gs[8] += dHG * P.I * P.G;
+          float du = 0.0f;
+          if (r.d_o != 0.0f) {
+            const float u = r.kx * P.dx + r.ky * P.dy;
+            du = dHG * r.d_o * P.G * kTwoOverSqrtPi * __expf(-u * u);
+          }
+          gs[5] += du * P.dx;
+          gs[6] += du * P.dy;
+          const float GG = dG * P.G;
+          gs[0] += GG * (r.qa * P.dx + r.qb * P.dy) - du * r.kx;
+          gs[1] += GG * (r.qb * P.dx + r.qc * P.dy) - du * r.ky;
+          gs[2] += -0.5f * GG * P.dx * P.dx;
+          gs[3] += -GG * P.dx * P.dy;
+          gs[4] += -0.5f * GG * P.dy * P.dy;
         }
-        g[5] = du * P.dx;
-        g[6] = du * P.dy;
-        const float GG = dG * P.G;
-        g[0] = GG * (q1.x * P.dx + q1.y * P.dy) - du * q0.z;
-        g[1] = GG * (q1.y * P.dx + q1.z * P.dy) - du * q0.w;
-        g[2] = -0.5f * GG * P.dx * P.dx;
-        g[3] = -GG * P.dx * P.dy;
-        g[4] = -0.5f * GG * P.dy * P.dy;
-      }
+        if (__ballot(any) == 0ull) continue;
 #pragma unroll
-      for (int k = 0; k < HGS_RECORD_GRAD_FLOATS; ++k) g[k] = wave_sum(g[k]);
-      if ((threadIdx.x & 63) == 0) {
-        float* dst = rgrad + (uint64_t)s_id[j] * HGS_RECORD_GRAD_FLOATS;
+        for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q) gs[q] = wave_sum_last(gs[q]);
+        if (lane == 63) {
+          float* dst = rgrad + (uint64_t)id * HGS_RECORD_GRAD_FLOATS;
 #pragma unroll
-        for (int k = 0; k < HGS_RECORD_GRAD_FLOATS; ++k)
-          if (g[k] != 0.0f) atomicAdd(dst + k, g[k]);
+          for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q)
+            if (gs[q] != 0.0f) atomicAdd(dst + q, gs[q]);
+        }
       }
     }
   }
@@ -256,8 +323,8 @@ template <int T, int B>
 hipError_t fwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                       const CamPack& cp, const Opts& o, float* img, float* Tf, int32_t* li,
                       int32_t* nc, hipStream_t s) {
-  hipLaunchKernelGGL((render_fwd_kernel<T, B>), dim3(cp.tiles_total), dim3(T * T), 0, s, rec, vals,
-                     ranges, cp, o, img, Tf, li, nc);
+  hipLaunchKernelGGL((render_fwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
+                     0, s, rec, vals, ranges, cp, o, img, Tf, li, nc);
   return hipGetLastError();
 }
 
@@ -265,12 +332,12 @@ template <int T, int B>
 hipError_t bwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                       const CamPack& cp, const Opts& o, const float* Tf, const int32_t* li,
                       const float* dL, float* rg, hipStream_t s) {
-  hipLaunchKernelGGL((render_bwd_kernel<T, B>), dim3(cp.tiles_total), dim3(T * T), 0, s, rec, vals,
-                     ranges, cp, o, Tf, li, dL, rg);
+  hipLaunchKernelGGL((render_bwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
+                     0, s, rec, vals, ranges, cp, o, Tf, li, dL, rg);
   return hipGetLastError();
 }
 
-#define HGS_DISPATCH(T_, B_, CALL)        \
+#define HGS_DISPATCH(T_, B_, CALL) \
   if (o.tile == T_ && o.batch == B_) return CALL<T_, B_>
 
 }  // namespace

@@ -28,7 +28,7 @@ def soa_from_natural(means, scales, quats, normals, opac1, opac2, sh) -> torch.T
     float32 structure-of-arrays tensor of planes, stride N."""
     n = means.shape[0]
     planes = [means.T, scales.T, quats.T, normals.T, opac1.reshape(1, n), opac2.reshape(1, n),
-              sh.reshape(n, -1).T]
+              sh.reshape(n, sh.shape[1] * sh.shape[2]).T]
     return torch.cat(planes, 0).to(torch.float32).contiguous()
 
 
