@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=256, help="pixels of the oracle CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage timings to stderr")
+    ap.add_argument("--full-keys", action="store_true", help="sort the 64-bit keys over all bits")
     return ap.parse_args()
 
 
@@ -67,7 +68,7 @@ def main():
     deg = scene["sh_degree"]
     soa = R.scene_to_soa(scene, dev)
     ca = B.make_cameras(cams)
-    opts = B.default_options(tile=args.tile, batch=args.batch)
+    opts = B.default_options(tile=args.tile, batch=args.batch, sort_full_keys=args.full_keys)
     targets = scenes.target_image(cams, seed=102)
     target = torch.cat([torch.as_tensor(t).reshape(-1) for t in targets]).to(dev)
 
@@ -92,7 +93,7 @@ def main():
     offsets = torch.empty(n_rec, dtype=torch.int64, device=dev)
     ndup = torch.zeros(1, dtype=torch.int64, device=dev)
     ws_pre = buf(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, ca, opts))
-    keys = torch.empty(cap, dtype=torch.int64, device=dev)
+    keys = torch.empty(cap, dtype=torch.int64, device=dev) if args.full_keys else None
     values = torch.empty(cap, dtype=torch.int32, device=dev)
     ranges = torch.empty(2 * tiles_total, dtype=torch.int32, device=dev)
     overflow = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -102,11 +103,11 @@ def main():
     last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
     n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
     ws_r = buf(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts))
-    rgrad = torch.empty(n_rec * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
+    rgrad = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
     dL = torch.empty(3 * npix, dtype=torch.float32, device=dev)
     inv_numel = 1.0 / float(3 * npix)
 
-    stage_names = ["preprocess", "bin_sort", "render_fwd", "loss_grad", "render_bwd"]
+    stage_names = ["preprocess", "bin_sort", "render_fwd", "loss_grad", "raster_bwd", "preprocess_bwd"]
 
     def step(ev=None):
         def mark(i):
@@ -124,10 +125,13 @@ def main():
         torch.sign(dL, out=dL)
         dL.mul_(inv_numel)
         mark(4)
-        B.hgs_render_bwd(params, ca, opts, records, values, ranges, T_final, last_idx, dL, rgrad, gstruct,
-                         ws_r, stream)
+        # record gradients start cleared (hgs_preprocess_bwd clears them after use)
+        B.hgs_raster_bwd(records, values, ranges, ca, opts, T_final, last_idx, dL, rgrad, stream)
         mark(5)
+        B.hgs_preprocess_bwd(params, ca, opts, records, rgrad, gstruct, stream)
+        mark(6)
 
+    ns = len(stage_names)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -145,46 +149,75 @@ def main():
     ms_step = t0.elapsed_time(t1) / args.steps
 
     # per-stage timing (separate run, events between the stage calls)
-    stage_ms = np.zeros(5)
+    stage_ms = np.zeros(ns)
     for _ in range(args.steps):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)]
         step(ev)
         torch.cuda.synchronize()
-        for i in range(5):
+        for i in range(ns):
             stage_ms[i] += ev[i].elapsed_time(ev[i + 1])
     stage_ms /= args.steps
+    st = dict(zip(stage_names, stage_ms))
 
-    fwd_ms = stage_ms[0] + stage_ms[1] + stage_ms[2]
-    bwd_ms = stage_ms[4]
+    fwd_ms = st["preprocess"] + st["bin_sort"] + st["render_fwd"]
+    bwd_ms = st["raster_bwd"] + st["preprocess_bwd"]
     W = sum(c["width"] * c["height"] for c in cams)
     value = W / (ms_step * 1e-3) / 1e6
 
-    # algorithmic bytes per stage (what the method must move)
+    # ---- algorithmic work per stage
+    # pairs the raster must evaluate: for every pixel, the entries of its
+    # tile list up to its last blended one; blended pairs: n_contrib
+    starts = ranges.view(-1, 2)[:, 0].to(torch.int64)
+    pix_tile = pixel_tiles(cams, args.tile, dev)
+    last = last_idx.to(torch.int64)
+    pairs = int(torch.clamp(last - starts[pix_tile] + 1, min=0).sum().item())
+    blended = int(n_contrib.to(torch.int64).sum().item())
     sh_floats = 3 * (deg + 1) ** 2
     param_bytes = 4 * (15 + sh_floats)
-    passes = (32 + max(0, math.ceil(math.log2(max(tiles_total, 1)))) + 7) // 8
+    tb = max(0, math.ceil(math.log2(max(tiles_total, 1))))
     bytes_pre = n * param_bytes + n_rec * (64 + 4) + n_rec * (4 + 4 + 8)
-    bytes_sort = (n_rec * (8 + 4 + 12) + n_dup * 12 + n_dup * 8 + passes * n_dup * 24 + n_dup * 8
-                  + tiles_total * 8)
-    stage_bytes = {"preprocess": bytes_pre, "bin_sort": bytes_sort}
+    if args.full_keys:
+        passes = (32 + tb + 7) // 8
+        bytes_sort = (n_rec * 28 + n_dup * 12 + passes * n_dup * 24 + n_dup * 8 + tiles_total * 8)
+    else:
+        passes = (tb + 7) // 8
+        bytes_sort = (n_rec * (12 + 4 * 16 + 12 + 16 + 28) + n_dup * 8 + passes * n_dup * 16
+                      + n_dup * 4 + tiles_total * 8)
+    bytes_pbwd = n * (param_bytes + param_bytes) + n_rec * (48 + 48 + 4)
+    # FP32 operations of one pair, written out (fma = 2): evaluation
+    # (offsets, quadratic form, exp, half factor, Eq. 10 opacity, clamp) and,
+    # for a blended pair, compositing; backward adds the gradient formulas.
+    F_EVAL, F_BLEND, F_GRAD = 42.0, 9.0, 75.0
+    flops_fwd = pairs * F_EVAL + blended * F_BLEND
+    flops_bwd = pairs * F_EVAL + blended * (F_BLEND + F_GRAD)
     roof = {}
-    for i, name in enumerate(stage_names):
-        if name in stage_bytes:
-            gbs = stage_bytes[name] / (stage_ms[i] * 1e-3) / 1e9
-            roof[name] = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                              frac=round(gbs / HBM_PEAK_GBS, 4), bytes=int(stage_bytes[name]),
-                              ms=round(float(stage_ms[i]), 4))
-    dominant = "bin_sort"
-    roofline = dict(roof[dominant])
+
+    def add(name, bound, amount):
+        ms = float(st[name])
+        if bound == "hbm":
+            a = amount / (ms * 1e-3) / 1e9
+            roof[name] = dict(bound="hbm", achieved=round(a, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(a / HBM_PEAK_GBS, 4), bytes=int(amount), ms=round(ms, 4))
+        else:
+            a = amount / (ms * 1e-3) / 1e12
+            roof[name] = dict(bound="alu", achieved=round(a, 2), peak=FP32_VECTOR_PEAK_TF, unit="TFLOP/s",
+                              frac=round(a / FP32_VECTOR_PEAK_TF, 4), flops=float(amount), ms=round(ms, 4))
+    add("preprocess", "hbm", bytes_pre)
+    add("bin_sort", "hbm", bytes_sort)
+    add("render_fwd", "alu", flops_fwd)
+    add("raster_bwd", "alu", flops_bwd)
+    add("preprocess_bwd", "hbm", bytes_pbwd)
+    # the dominant kernel: the longest single-kernel stage
+    dominant = max(("render_fwd", "raster_bwd", "preprocess_bwd"), key=lambda k: st[k])
+    roofline = {k: v for k, v in roof[dominant].items() if k not in ("ms", "bytes", "flops")}
     roofline["kernel"] = dominant
     roofline["traffic"] = None
-    roofline.pop("ms", None)
-    roofline.pop("bytes", None)
 
     if args.stages:
-        for i, name in enumerate(stage_names):
-            print(f"{name:12s} {stage_ms[i]:8.3f} ms", file=sys.stderr)
-        print(f"n_dup {n_dup}  passes {passes}  step {ms_step:.3f} ms", file=sys.stderr)
+        for name in stage_names:
+            print(f"{name:15s} {st[name]:8.3f} ms", file=sys.stderr)
+        print(f"n_dup {n_dup}  tile passes {passes}  pairs {pairs}  blended {blended}  step {ms_step:.3f} ms",
+              file=sys.stderr)
         print(json.dumps(roof), file=sys.stderr)
 
     cpu = None
@@ -206,15 +239,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS.get(args.config, str(args.config)), "n_kernels": n,
                    "views": len(cams), "pixels": W, "tile": args.tile, "batch": args.batch,
-                   "entries": n_dup},
+                   "entries": n_dup, "sort": "full_keys" if args.full_keys else "depth_first"},
         "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
         "fwd_bwd_over_fwd": round((fwd_ms + bwd_ms) / fwd_ms, 3),
-        "stage_ms": {k: round(float(v), 4) for k, v in zip(stage_names, stage_ms)},
+        "stage_ms": {k: round(float(v), 4) for k, v in st.items()},
         "roofline": roofline,
         "roofline_stages": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def pixel_tiles(cams, T, dev):
+    """Global tile id of every pixel (cameras packed), for work accounting."""
+    import torch
+    out, off = [], 0
+    for c in cams:
+        w, h = c["width"], c["height"]
+        tx = (w + T - 1) // T
+        ys = torch.arange(h, device=dev).view(-1, 1) // T
+        xs = torch.arange(w, device=dev).view(1, -1) // T
+        out.append((off + ys * tx + xs).reshape(-1))
+        off += tx * ((h + T - 1) // T)
+    return torch.cat(out)
 
 
 def cpu_baseline(scene, cams, n_pix):

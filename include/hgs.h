@@ -65,6 +65,10 @@ extern "C" {
 /* options.flags */
 #define HGS_FLAG_FULL_BOX 1u     /* splat both halves with the full ellipse box,
                                     no half-aware region and no opacity cull  */
+#define HGS_FLAG_SORT_FULL_KEYS 2u /* hgs_bin_sort: radix-sort the duplicated
+                                    entries over all 32 + tile bits of their
+                                    64-bit keys instead of sorting the records
+                                    by depth first (same result)              */
 
 /* Pinhole camera.  R is the world->camera rotation (row-major 3x3), t the
  * translation (x_cam = R x_world + t).  fx, fy, cx, cy in pixels.  Kernels
@@ -176,11 +180,17 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
 /* Duplicate every record once per tile of its tile rectangle with key
  * (global tile << 32 | fp32 depth bits) and value record id, sort the
  * entries by key with a stable LSD radix sort (so equal keys stay in record
- * order), and write the [start, end) range of every tile.
+ * order), and write the [start, end) range of every tile.  By default the
+ * radix passes over the 32 depth bits run on the records before duplication
+ * (every entry of a record shares its depth) and only the tile bits are
+ * sorted over the entries; HGS_FLAG_SORT_FULL_KEYS sorts the duplicated
+ * 64-bit keys over all bits.  Both give the same order.
  *   records, tiles_touched, offsets, n_dup   from hgs_preprocess (device)
  *   n_rec          n_cams * n
  *   keys, values   device, `capacity` entries each (out: sorted entries in
- *                  the first *n_dup positions)
+ *                  the first *n_dup positions); keys may be NULL unless
+ *                  HGS_FLAG_SORT_FULL_KEYS is set (the raster needs only the
+ *                  values and ranges)
  *   ranges         device, uint32 [tiles_total][2] (out); a tile without
  *                  entries gets [0, 0)
  *   overflow       device, int32 [1] (out): 0, or 1 when *n_dup > capacity;
@@ -215,8 +225,7 @@ int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* 
  * and colour (3) in `record_grads`, then applies the chain rule through the
  * projection to every kernel parameter, summed over cameras.
  *   record_grads  device, float [n_cams * n][HGS_RECORD_GRAD_FLOATS] scratch
- *                 (cleared by the call; holds the per-record gradients on
- *                 return)
+ *                 (any contents on entry; cleared on return)
  *   grads         device pointers, overwritten
  *   workspace     device, hgs_workspace_bytes(HGS_WS_RENDER, ...) bytes
  * params, cams and opts must be those given to hgs_preprocess. */
@@ -225,6 +234,28 @@ int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_c
                    const uint32_t* ranges, const float* T_final, const int32_t* last_idx,
                    const float* dL_dimages, float* record_grads, const hgs_param_grads* grads,
                    void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* The two halves of hgs_render_bwd, for callers that want the per-record
+ * gradients themselves (the screen-space centre gradient drives the
+ * densification heuristics of 3D-GS training) or schedule the halves
+ * separately.
+ *
+ * hgs_raster_bwd: the per-pixel back-to-front replay only; ADDS each
+ * record's 12 gradients to record_grads (device, float
+ * [n_cams * n][HGS_RECORD_GRAD_FLOATS]), which the caller must have cleared
+ * (hgs_preprocess_bwd leaves it cleared).  n is the kernel count given to
+ * hgs_preprocess.
+ *
+ * hgs_preprocess_bwd: the chain rule from record_grads to every kernel
+ * parameter (summed over cameras, grads overwritten); clears record_grads
+ * after reading it. */
+int hgs_raster_bwd(const void* records, const uint32_t* values, const uint32_t* ranges,
+                   const hgs_camera* cams, int32_t n_cams, const hgs_options* opts,
+                   const float* T_final, const int32_t* last_idx, const float* dL_dimages,
+                   float* record_grads, hipStream_t stream);
+int hgs_preprocess_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
+                       const hgs_options* opts, const void* records, float* record_grads,
+                       const hgs_param_grads* grads, hipStream_t stream);
 
 const char* hgs_strerror(int code);
 const char* hgs_last_error(void);

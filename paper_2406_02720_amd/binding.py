@@ -18,11 +18,12 @@ HGS_MAX_CAMERAS = 32
 HGS_RECORD_BYTES = 64
 HGS_RECORD_GRAD_FLOATS = 12
 HGS_FLAG_FULL_BOX = 1
+HGS_FLAG_SORT_FULL_KEYS = 2
 HGS_WS_PREPROCESS, HGS_WS_BIN_SORT, HGS_WS_RENDER = 0, 1, 2
 
 EXPORTS = ("hgs_default_options", "hgs_workspace_bytes", "hgs_tiles_total", "hgs_pixels_total",
            "hgs_preprocess", "hgs_bin_sort", "hgs_render_fwd", "hgs_render_bwd",
-           "hgs_strerror", "hgs_last_error")
+           "hgs_raster_bwd", "hgs_preprocess_bwd", "hgs_strerror", "hgs_last_error")
 
 
 class hgs_camera(C.Structure):
@@ -91,6 +92,11 @@ def load(path: str = LIB_PATH):
     lib.hgs_render_bwd.argtypes = [P(hgs_params), P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp,
                                    vp, vp, vp, P(hgs_param_grads), vp, sz, vp]
     lib.hgs_render_bwd.restype = C.c_int
+    lib.hgs_raster_bwd.argtypes = [vp, vp, vp, P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp, vp]
+    lib.hgs_raster_bwd.restype = C.c_int
+    lib.hgs_preprocess_bwd.argtypes = [P(hgs_params), P(hgs_camera), i32, P(hgs_options), vp, vp,
+                                       P(hgs_param_grads), vp]
+    lib.hgs_preprocess_bwd.restype = C.c_int
     lib.hgs_strerror.argtypes = [C.c_int]
     lib.hgs_strerror.restype = C.c_char_p
     lib.hgs_last_error.argtypes = []
@@ -112,6 +118,8 @@ def default_options(**kw) -> hgs_options:
             o.bg[:] = [float(x) for x in v]
         elif k == "full_box":
             o.flags = (o.flags | HGS_FLAG_FULL_BOX) if v else (o.flags & ~HGS_FLAG_FULL_BOX)
+        elif k == "sort_full_keys":
+            o.flags = (o.flags | HGS_FLAG_SORT_FULL_KEYS) if v else (o.flags & ~HGS_FLAG_SORT_FULL_KEYS)
         else:
             setattr(o, k, v)
     return o
@@ -192,3 +200,13 @@ def hgs_render_bwd(params, cams, opts, records, values, ranges, T_final, last_id
                                 _ptr(ranges), _ptr(T_final), _ptr(last_idx), _ptr(dL_dimages),
                                 _ptr(record_grads), C.byref(grads), _ptr(ws), ws.numel() * ws.element_size(),
                                 stream))
+
+
+def hgs_raster_bwd(records, values, ranges, cams, opts, T_final, last_idx, dL_dimages, record_grads, stream):
+    check(load().hgs_raster_bwd(_ptr(records), _ptr(values), _ptr(ranges), cams, len(cams), C.byref(opts),
+                                _ptr(T_final), _ptr(last_idx), _ptr(dL_dimages), _ptr(record_grads), stream))
+
+
+def hgs_preprocess_bwd(params, cams, opts, records, record_grads, grads, stream):
+    check(load().hgs_preprocess_bwd(C.byref(params), cams, len(cams), C.byref(opts), _ptr(records),
+                                    _ptr(record_grads), C.byref(grads), stream))

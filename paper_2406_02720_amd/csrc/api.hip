@@ -81,12 +81,6 @@ int make_pack(const hgs_camera* cams, int32_t n_cams, const hgs_options* o, hgs:
   return HGS_OK;
 }
 
-int key_passes(uint32_t tiles_total) {
-  int tb = 0;
-  while ((1ull << tb) < tiles_total) ++tb;
-  return (32 + tb + 7) / 8;
-}
-
 int make_params(const hgs_params* p, hgs::Params* out) {
   if (!p) return fail(HGS_EINVAL, "params is null");
   if (p->n < 0) return fail(HGS_EINVAL, "n must be >= 0");
@@ -151,7 +145,7 @@ size_t hgs_workspace_bytes(int32_t which, int64_t n_rec, const hgs_camera* cams,
       if (check_opts(opts) != HGS_OK || capacity < 0) return 0;
       hgs::CamPack cp;
       if (make_pack(cams, n_cams, opts, &cp) != HGS_OK) return 0;
-      return hgs::sort_workspace_bytes(capacity, key_passes(cp.tiles_total));
+      return hgs::sort_workspace_bytes(n_rec, capacity, (opts->flags & HGS_FLAG_SORT_FULL_KEYS) != 0);
     }
     case HGS_WS_RENDER:
       return hgs::render_workspace_bytes();
@@ -194,16 +188,16 @@ int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint6
   if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
   if (n_rec < 0 || n_rec % n_cams != 0) return fail(HGS_EINVAL, "n_rec must be n_cams * n");
   if (capacity < 0 || capacity >= (int64_t)UINT32_MAX) return fail(HGS_EINVAL, "capacity out of range");
+  const bool full_keys = (opts->flags & HGS_FLAG_SORT_FULL_KEYS) != 0;
   if (!n_dup || !ranges || !overflow || (n_rec > 0 && (!records || !tiles_touched || !offsets)) ||
-      (capacity > 0 && (!keys || !values)))
+      (capacity > 0 && (!values || (full_keys && !keys))))
     return fail(HGS_EINVAL, "a pointer is null");
-  const int passes = key_passes(cp.tiles_total);
-  const size_t need = hgs::sort_workspace_bytes(capacity, passes);
+  const size_t need = hgs::sort_workspace_bytes(n_rec, capacity, full_keys);
   if (!workspace || workspace_bytes < need)
     return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", need);
   hipError_t h = hgs::launch_bin_sort((const hgs::Record*)records, tiles_touched, offsets, n_dup,
                                       n_rec, n_rec / n_cams, cp, keys, values, capacity, ranges,
-                                      overflow, workspace, passes, stream);
+                                      overflow, workspace, full_keys, stream);
   if (h != hipSuccess) return hip_fail(h, "bin_sort launch");
   return HGS_OK;
 }
@@ -227,6 +221,44 @@ int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* 
   return HGS_OK;
 }
 
+int hgs_raster_bwd(const void* records, const uint32_t* values, const uint32_t* ranges,
+                   const hgs_camera* cams, int32_t n_cams, const hgs_options* opts,
+                   const float* T_final, const int32_t* last_idx, const float* dL_dimages,
+                   float* record_grads, hipStream_t stream) {
+  int e;
+  if ((e = check_opts(opts)) != HGS_OK) return e;
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
+  if (!ranges || !T_final || !last_idx || !dL_dimages || !record_grads)
+    return fail(HGS_EINVAL, "a pointer is null");
+  const hgs::Opts o = hgs::to_opts(*opts);
+  hipError_t h = hgs::launch_render_bwd((const hgs::Record*)records, values, ranges, cp, o, T_final,
+                                        last_idx, dL_dimages, record_grads, stream);
+  if (h != hipSuccess) return hip_fail(h, "raster_bwd launch");
+  return HGS_OK;
+}
+
+int hgs_preprocess_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
+                       const hgs_options* opts, const void* records, float* record_grads,
+                       const hgs_param_grads* grads, hipStream_t stream) {
+  int e;
+  if ((e = check_opts(opts)) != HGS_OK) return e;
+  hgs::Params p;
+  if ((e = make_params(params, &p)) != HGS_OK) return e;
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
+  if (!grads) return fail(HGS_EINVAL, "grads is null");
+  if (p.n > 0 && (!records || !record_grads || !grads->means || !grads->scales || !grads->quats ||
+                  !grads->normals || !grads->opac1 || !grads->opac2 || !grads->sh))
+    return fail(HGS_EINVAL, "a pointer is null");
+  const hgs::Opts o = hgs::to_opts(*opts);
+  hgs::Grads g{grads->means, grads->scales, grads->quats, grads->normals,
+               grads->opac1, grads->opac2,  grads->sh};
+  hipError_t h = hgs::launch_preprocess_bwd(p, cp, o, (const hgs::Record*)records, record_grads, g, stream);
+  if (h != hipSuccess) return hip_fail(h, "preprocess_bwd launch");
+  return HGS_OK;
+}
+
 int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
                    const hgs_options* opts, const void* records, const uint32_t* values,
                    const uint32_t* ranges, const float* T_final, const int32_t* last_idx,
@@ -238,23 +270,15 @@ int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_c
   if ((e = make_params(params, &p)) != HGS_OK) return e;
   hgs::CamPack cp;
   if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
-  if (!ranges || !T_final || !last_idx || !dL_dimages || !grads)
-    return fail(HGS_EINVAL, "a pointer is null");
-  const int64_t n_rec = p.n * n_cams;
-  if (n_rec > 0 && (!records || !record_grads || !grads->means || !grads->scales || !grads->quats ||
-                    !grads->normals || !grads->opac1 || !grads->opac2 || !grads->sh))
-    return fail(HGS_EINVAL, "a pointer is null");
   if (!workspace || workspace_bytes < hgs::render_workspace_bytes())
     return fail(HGS_ECAPACITY, "workspace too small");
-  const hgs::Opts o = hgs::to_opts(*opts);
-  hipError_t h = hgs::launch_render_bwd((const hgs::Record*)records, values, ranges, cp, o, T_final,
-                                        last_idx, dL_dimages, record_grads, n_rec, workspace, stream);
-  if (h != hipSuccess) return hip_fail(h, "render_bwd launch");
-  hgs::Grads g{grads->means, grads->scales, grads->quats, grads->normals,
-               grads->opac1, grads->opac2,  grads->sh};
-  h = hgs::launch_preprocess_bwd(p, cp, o, (const hgs::Record*)records, record_grads, g, stream);
-  if (h != hipSuccess) return hip_fail(h, "preprocess_bwd launch");
-  return HGS_OK;
+  if (p.n > 0 && !record_grads) return fail(HGS_EINVAL, "record_grads is null");
+  hipError_t h = hgs::launch_zero_f32(record_grads, p.n * n_cams * HGS_RECORD_GRAD_FLOATS, stream);
+  if (h != hipSuccess) return hip_fail(h, "clear launch");
+  if ((e = hgs_raster_bwd(records, values, ranges, cams, n_cams, opts, T_final, last_idx, dL_dimages,
+                          record_grads, stream)) != HGS_OK)
+    return e;
+  return hgs_preprocess_bwd(params, cams, n_cams, opts, records, record_grads, grads, stream);
 }
 
 const char* hgs_strerror(int code) {

@@ -285,7 +285,7 @@ __device__ __forceinline__ void add_sym_outer(Sym3& S, const double* u, const do
 template <int D>
 __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     Params p, CamPack cp, Opts o, const Record* __restrict__ rec,
-    const float* __restrict__ rgrad, Grads G) {
+    float* __restrict__ rgrad, Grads G) {
   constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   if (i >= p.n) return;
@@ -311,13 +311,16 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
 
   for (int c = 0; c < cp.n_cams; ++c) {
     const int64_t ri = (int64_t)c * p.n + i;
-    if (rec[ri].tiles == 0) continue;  // culled: no gradient
-    const float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS;
-    const double gmx = gr[0], gmy = gr[1];
-    const double gqa = gr[2], gqb = gr[3], gqc = gr[4];
-    const double gkx = gr[5], gky = gr[6];
-    const double galpha2 = gr[7], gdo = gr[8];
-    const double gcol[3] = {gr[9], gr[10], gr[11]};
+    if (rec[ri].tiles == 0) continue;  // culled: no gradient, nothing to clear
+    float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS;
+    float4* gr4 = reinterpret_cast<float4*>(gr);
+    const float4 r0 = gr4[0], r1 = gr4[1], r2 = gr4[2];
+    gr4[0] = gr4[1] = gr4[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // leave the buffer cleared
+    const double gmx = r0.x, gmy = r0.y;
+    const double gqa = r0.z, gqb = r0.w, gqc = r1.x;
+    const double gkx = r1.y, gky = r1.z;
+    const double galpha2 = r1.w, gdo = r2.x;
+    const double gcol[3] = {r2.y, r2.z, r2.w};
 
     // alpha2 and (alpha1 - alpha2) / 2
     g_a2 += galpha2 - 0.5 * gdo;
@@ -547,7 +550,7 @@ hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint
 }
 
 hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o,
-                                 const Record* rec, const float* rec_grads, const Grads& g,
+                                 const Record* rec, float* rec_grads, const Grads& g,
                                  hipStream_t s) {
   if (p.n == 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);

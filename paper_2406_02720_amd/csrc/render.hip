@@ -20,6 +20,11 @@
 
 #include "hgs_internal.h"
 
+// Every fused multiply-add below is written out: with contraction left to the
+// compiler, instantiations with different pixels-per-lane fused differently
+// and images depended on the tile size in the last bit.
+#pragma clang fp contract(off)
+
 namespace hgs {
 
 namespace {
@@ -39,15 +44,16 @@ __device__ __forceinline__ void eval_pair(const Record& r, int px, int py, float
   const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
   P.live = px >= x0 && px <= x1 && py >= y0 && py <= y1;
   if (!P.live) return;
-  P.dx = (float)(px - x0) + 0.5f - r.mx;
-  P.dy = (float)(py - y0) + 0.5f - r.my;
-  const float power = -0.5f * (r.qa * P.dx * P.dx + r.qc * P.dy * P.dy) - r.qb * P.dx * P.dy;
+  P.dx = ((float)(px - x0) + 0.5f) - r.mx;
+  P.dy = ((float)(py - y0) + 0.5f) - r.my;
+  const float quad = fmaf(r.qa * P.dx, P.dx, (r.qc * P.dy) * P.dy);
+  const float power = fmaf(-0.5f, quad, -((r.qb * P.dx) * P.dy));
   P.live = !(power > 0.0f);
   if (!P.live) return;
   P.G = __expf(power);
   if (r.d_o != 0.0f) {
-    P.I = erfcf(-(r.kx * P.dx + r.ky * P.dy));
-    P.HG = (r.alpha2 + r.d_o * P.I) * P.G;
+    P.I = erfcf(-fmaf(r.kx, P.dx, r.ky * P.dy));
+    P.HG = fmaf(r.d_o, P.I, r.alpha2) * P.G;
   } else {
     P.I = 1.0f;
     P.HG = r.alpha2 * P.G;
@@ -159,9 +165,9 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
             continue;
           }
           const float w = P.a * Tr[j];
-          C0[j] += r.r * w;
-          C1[j] += r.g * w;
-          C2[j] += r.b * w;
+          C0[j] = fmaf(r.r, w, C0[j]);
+          C1[j] = fmaf(r.g, w, C1[j]);
+          C2[j] = fmaf(r.b, w, C2[j]);
           Tr[j] = Tn;
           ++cnt[j];
           last[j] = pos;
@@ -175,9 +181,9 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
   for (int j = 0; j < PPL; ++j) {
     if (!inside[j]) continue;
     const uint64_t pix = (uint64_t)py[j] * cam.width + px;
-    im[pix] = C0[j] + Tr[j] * o.bg[0];
-    im[plane + pix] = C1[j] + Tr[j] * o.bg[1];
-    im[2 * plane + pix] = C2[j] + Tr[j] * o.bg[2];
+    im[pix] = fmaf(Tr[j], o.bg[0], C0[j]);
+    im[plane + pix] = fmaf(Tr[j], o.bg[1], C1[j]);
+    im[2 * plane + pix] = fmaf(Tr[j], o.bg[2], C2[j]);
     T_final[cam.pix_off + pix] = Tr[j];
     last_idx[cam.pix_off + pix] = last[j];
     n_contrib[cam.pix_off + pix] = cnt[j];
@@ -363,18 +369,19 @@ hipError_t launch_render_fwd(const Record* rec, const uint32_t* vals, const uint
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  g = g < 1 ? 1 : (g > 8192 ? 8192 : g);
+  hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)g), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                              const CamPack& cp, const Opts& o, const float* T_final,
                              const int32_t* last_idx, const float* dL_dimg, float* rec_grads,
-                             int64_t n_rec, void* ws, hipStream_t s) {
-  (void)ws;
-  {
-    const int64_t n = n_rec * HGS_RECORD_GRAD_FLOATS;
-    int64_t g = (n + 255) / 256;
-    g = g < 1 ? 1 : (g > 8192 ? 8192 : g);
-    hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)g), dim3(256), 0, s, rec_grads, n);
-  }
-  if (cp.tiles_total == 0) return hipGetLastError();
+                             hipStream_t s) {
+  if (cp.tiles_total == 0) return hipSuccess;
 #define ARGS (rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rec_grads, s)
   HGS_DISPATCH(8, 128, bwd_launch) ARGS;
   HGS_DISPATCH(8, 256, bwd_launch) ARGS;

@@ -1,25 +1,36 @@
 // Binning and sorting of (tile | depth, record) entries.
 //
-//   duplicate   one entry per tile of each record's tile rectangle, written at
-//               the record's exclusive-scan offset.  A wavefront owns 64
-//               consecutive records, whose entries are contiguous; each lane
-//               finds the record of an output slot by binary search over the
-//               64 offsets, so writes are coalesced and a record covering
-//               thousands of tiles is spread over the whole wavefront.
-//   radix sort  stable LSD sort of the 64-bit keys with 8-bit digits, only
-//               over the bits in use (32 depth bits + enough tile bits).  One
-//               histogram pass computes the digit counts of every pass; each
-//               pass is then a single sweep (Onesweep, Adinets & Merrill
-//               2022): a block takes a partition ticket, ranks its keys with
-//               wave64 ballot match masks, publishes per-digit counts and
-//               resolves its global digit offsets by decoupled look-back over
-//               the preceding partitions (Merrill & Garland 2016), then
-//               scatters through LDS so that global writes are runs of equal
-//               digits.
-//   ranges      [start, end) of every tile in the sorted order.
+// The entries must end up ordered by the 64-bit key tile << 32 | depth bits,
+// ties by record id.  An LSD radix sort does this with 8-bit digits, low
+// digits first.  Every entry of a record carries that record's depth, so the
+// four passes over the depth digits can be applied to the N records before
+// they are duplicated ("depth-first"):
 //
-// The device-side entry count decides all work; the launch grids are sized
-// by the caller's capacity, and surplus blocks exit at once.
+//   1. depth keys of the records (+ their digit histograms), four one-sweep
+//      passes over the N records -> record ids in (depth, id) order;
+//   2. tiles touched in that order, exclusive scan -> entry offsets;
+//   3. duplicate: one (tile, record id) entry per covered tile, written in
+//      record order (+ histograms of the tile digits);
+//   4. one-sweep passes over the ceil(log2 tiles) tile bits of the entries
+//      (32-bit keys) -- stable, so equal tiles keep (depth, id) order;
+//   5. tile ranges.
+//
+// The entries then move through only ceil(tile bits / 8) passes instead of
+// ceil((32 + tile bits) / 8).  With HGS_FLAG_SORT_FULL_KEYS the entries are
+// instead duplicated with full 64-bit keys in record order and sorted over
+// all 32 + tile bits.  Both produce the same entry order.
+//
+// One-sweep pass (Onesweep, Adinets & Merrill 2022): a block takes a
+// partition ticket (forward progress: earlier partitions belong to blocks
+// already running), ranks its keys within each wavefront with wave64 ballot
+// match masks, publishes per-digit counts and resolves its global digit
+// offsets by decoupled look-back over the preceding partitions (Merrill &
+// Garland 2016), then scatters through LDS so that global writes are runs of
+// equal digits.  Histograms use the same ballot match so that a wavefront
+// adds each distinct digit once.
+//
+// The device-side entry count decides all work; launch grids are sized by
+// the caller's capacity and surplus blocks exit at once.
 
 #include "hgs_internal.h"
 
@@ -35,28 +46,56 @@ constexpr int kWaves = kBlock / 64;
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagPrefix = 2ull << 62;
 constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr int kMaxPasses = 8;
 
-__device__ __forceinline__ uint64_t entry_count(const uint64_t* n_dup, int64_t capacity) {
-  const uint64_t n = *n_dup;
+__device__ __forceinline__ uint64_t entry_count(const uint64_t* n_dev, int64_t capacity) {
+  if (!n_dev) return (uint64_t)capacity;
+  const uint64_t n = *n_dev;
   return n > (uint64_t)capacity ? 0ull : n;
 }
 
-__device__ __forceinline__ uint64_t ld_acquire(const uint64_t* p) {
+__device__ __forceinline__ uint64_t ld_flag(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release(uint64_t* p, uint64_t v) {
+__device__ __forceinline__ void st_flag(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Lanes of the wavefront holding the same 8-bit digit as this lane (all 64
+// lanes must call).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d) {
+  uint64_t m = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t bal = __ballot((d >> b) & 1u);
+    m &= ((d >> b) & 1u) ? bal : ~bal;
+  }
+  return m;
+}
+
+// bins[d] += 1 for every valid lane, one LDS atomic per distinct digit.
+__device__ __forceinline__ void wave_hist_add(uint32_t* bins, uint32_t d, bool valid) {
+  const uint64_t m = match_digit(d) & __ballot(valid);
+  if (valid && (int)__lane_id() == __ffsll((unsigned long long)m) - 1)
+    atomicAdd(&bins[d], (uint32_t)__popcll(m));
+}
+
+__device__ __forceinline__ void flush_hist(const uint32_t* s_h, int words, uint32_t* hist) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) {
+    const uint32_t v = s_h[i];
+    if (v) atomicAdd(&hist[i], v);
+  }
+}
+
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void sort_init_kernel(uint32_t* __restrict__ hist, int hist_words,
-                                                           uint32_t* __restrict__ tickets, int passes,
+__global__ __launch_bounds__(kBlock) void sort_init_kernel(uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ tickets,
                                                            uint64_t* __restrict__ lookback0,
                                                            int64_t lookback_words) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = t; i < hist_words; i += stride) hist[i] = 0u;
-  for (int64_t i = t; i < passes; i += stride) tickets[i] = 0u;
+  for (int64_t i = t; i < 2 * kMaxPasses * kRadix; i += stride) hist[i] = 0u;
+  for (int64_t i = t; i < 2 * kMaxPasses; i += stride) tickets[i] = 0u;
   for (int64_t i = t; i < lookback_words; i += stride) lookback0[i] = 0ull;
 }
 
@@ -64,88 +103,6 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* __restrict__
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = t; i < n; i += stride) p[i] = v;
-}
-
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void duplicate_kernel(
-    const Record* __restrict__ rec, const uint32_t* __restrict__ tiles,
-    const uint64_t* __restrict__ offsets, const uint64_t* __restrict__ n_dup, int64_t n_rec,
-    int64_t n_per_cam, CamPack cp, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    int64_t capacity, int32_t* __restrict__ overflow) {
-  __shared__ uint64_t s_off[kWaves][64];
-  __shared__ uint32_t s_base[kWaves][64];   // first global tile of the rect
-  __shared__ uint32_t s_w[kWaves][64];      // rect width in tiles
-  __shared__ uint32_t s_tx[kWaves][64];     // tiles per row of the camera
-  __shared__ uint32_t s_depth[kWaves][64];
-  const uint64_t total = *n_dup;
-  const bool over = total > (uint64_t)capacity;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *overflow = over ? 1 : 0;
-  if (over) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r = ((int64_t)blockIdx.x * kWaves + wave) * 64 + lane;
-  uint32_t cnt = 0;
-  uint64_t off = total;
-  if (r < n_rec) {
-    cnt = tiles[r];
-    off = offsets[r];
-  }
-  if (cnt > 0) {
-    const Record& R = rec[r];
-    const int cam = (int)(r / n_per_cam);
-    const CamDev& C = cp.cam[cam];
-    const int sh = cp.tile_shift;
-    const uint32_t tx0 = (R.xr & 0xffffu) >> sh, tx1 = (R.xr >> 16) >> sh;
-    const uint32_t ty0 = (R.yr & 0xffffu) >> sh;
-    s_base[wave][lane] = C.tile_off + ty0 * (uint32_t)C.tiles_x + tx0;
-    s_w[wave][lane] = tx1 - tx0 + 1;
-    s_tx[wave][lane] = (uint32_t)C.tiles_x;
-    s_depth[wave][lane] = R.depth;
-  }
-  s_off[wave][lane] = off;
-  // wave range [start, end): offsets are non-decreasing in r
-  const uint64_t start = __shfl(off, 0, 64);
-  uint64_t end = off + cnt;
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const uint64_t o = __shfl_xor(end, m, 64);
-    end = o > end ? o : end;
-  }
-  if (r >= n_rec && lane == 0) end = start;  // whole wave past the end
-  __syncthreads();
-  const uint32_t rbase = (uint32_t)(((int64_t)blockIdx.x * kWaves + wave) * 64);
-  for (uint64_t o = start + lane; o < end; o += 64) {
-    int lo = 0;
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1)
-      if (s_off[wave][lo + step] <= o) lo += step;
-    const uint32_t l = (uint32_t)(o - s_off[wave][lo]);
-    const uint32_t w = s_w[wave][lo];
-    const uint32_t row = l / w, col = l - row * w;
-    const uint32_t tile = s_base[wave][lo] + row * s_tx[wave][lo] + col;
-    keys[o] = ((uint64_t)tile << 32) | s_depth[wave][lo];
-    vals[o] = rbase + (uint32_t)lo;
-  }
-}
-
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void hist_kernel(const uint64_t* __restrict__ keys,
-                                                      const uint64_t* __restrict__ n_dup,
-                                                      int64_t capacity, int passes,
-                                                      uint32_t* __restrict__ hist) {
-  __shared__ uint32_t s_h[8][kRadix];
-  for (int i = threadIdx.x; i < 8 * kRadix; i += kBlock) (&s_h[0][0])[i] = 0u;
-  __syncthreads();
-  const uint64_t n = entry_count(n_dup, capacity);
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n; i += stride) {
-    const uint64_t k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 0xffu], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < passes * kRadix; i += kBlock) {
-    const uint32_t v = (&s_h[0][0])[i];
-    if (v) atomicAdd(&hist[i], v);
-  }
 }
 
 // Exclusive scan of each pass's 256 digit counts (one block, thread = digit).
@@ -167,13 +124,160 @@ __global__ __launch_bounds__(kRadix) void hist_scan_kernel(uint32_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// depth-first path
+// ---------------------------------------------------------------------------
+// Depth key of every record (culled records sort last and emit nothing) and
+// the histograms of its four digits.
+__global__ __launch_bounds__(kBlock) void depth_keys_kernel(const Record* __restrict__ rec,
+                                                            const uint32_t* __restrict__ tiles,
+                                                            int64_t n_rec, uint32_t* __restrict__ keys,
+                                                            uint32_t* __restrict__ ids,
+                                                            uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[4 * kRadix];
+  for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) s_h[i] = 0u;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n_rec; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    const bool ok = i < n_rec;
+    uint32_t k = 0xffffffffu;
+    if (ok) {
+      k = tiles[i] ? rec[i].depth : 0xffffffffu;
+      keys[i] = k;
+      ids[i] = (uint32_t)i;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) wave_hist_add(s_h + p * kRadix, (k >> (8 * p)) & 0xffu, ok);
+  }
+  __syncthreads();
+  flush_hist(s_h, 4 * kRadix, hist);
+}
+
+__global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* __restrict__ ids,
+                                                               const uint32_t* __restrict__ tiles,
+                                                               int64_t n, uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = tiles[ids[i]];
+}
+
+// One entry per covered tile.  A wavefront owns 64 consecutive slots of the
+// record order `order` (identity when null), whose entries are contiguous;
+// each lane finds the slot of an output position by binary search over the
+// 64 offsets, so writes are coalesced and a record covering many tiles is
+// spread over the whole wavefront.  KEY64 writes tile << 32 | depth keys,
+// otherwise 32-bit tile keys; `hist` receives the digit histograms of the
+// key bits from `hist_shift` on, `hist_passes` digits.
+template <bool KEY64>
+__global__ __launch_bounds__(kBlock) void duplicate_kernel(
+    const Record* __restrict__ rec, const uint32_t* __restrict__ order,
+    const uint32_t* __restrict__ tiles, const uint64_t* __restrict__ offsets,
+    const uint64_t* __restrict__ n_dup, int64_t n_rec, int64_t n_per_cam, CamPack cp,
+    void* __restrict__ keys_out, uint32_t* __restrict__ vals, int64_t capacity,
+    int32_t* __restrict__ overflow, uint32_t* __restrict__ hist, int hist_shift, int hist_passes) {
+  __shared__ uint64_t s_off[kWaves][64];
+  __shared__ uint32_t s_base[kWaves][64];   // first global tile of the rect
+  __shared__ uint32_t s_w[kWaves][64];      // rect width in tiles
+  __shared__ uint32_t s_tx[kWaves][64];     // tiles per row of the camera
+  __shared__ uint32_t s_depth[kWaves][64];
+  __shared__ uint32_t s_id[kWaves][64];
+  __shared__ uint32_t s_h[kMaxPasses * kRadix];
+  for (int i = threadIdx.x; i < hist_passes * kRadix; i += kBlock) s_h[i] = 0u;
+  const uint64_t total = *n_dup;
+  const bool over = total > (uint64_t)capacity;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *overflow = over ? 1 : 0;
+  if (over) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j = ((int64_t)blockIdx.x * kWaves + wave) * 64 + lane;
+  uint32_t cnt = 0;
+  uint64_t off = total;
+  if (j < n_rec) {
+    const uint32_t r = order ? order[j] : (uint32_t)j;
+    cnt = tiles[r];
+    off = offsets[j];
+    if (cnt > 0) {
+      const Record& R = rec[r];
+      const int cam = (int)(r / n_per_cam);
+      const CamDev& C = cp.cam[cam];
+      const int sh = cp.tile_shift;
+      const uint32_t tx0 = (R.xr & 0xffffu) >> sh, tx1 = (R.xr >> 16) >> sh;
+      const uint32_t ty0 = (R.yr & 0xffffu) >> sh;
+      s_base[wave][lane] = C.tile_off + ty0 * (uint32_t)C.tiles_x + tx0;
+      s_w[wave][lane] = tx1 - tx0 + 1;
+      s_tx[wave][lane] = (uint32_t)C.tiles_x;
+      s_depth[wave][lane] = R.depth;
+      s_id[wave][lane] = r;
+    }
+  }
+  s_off[wave][lane] = off;
+  // slots' entries are contiguous: [start, end)
+  const uint64_t start = __shfl(off, 0, 64);
+  uint64_t end = off + cnt;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const uint64_t o = __shfl_xor(end, m, 64);
+    end = o > end ? o : end;
+  }
+  __syncthreads();
+  for (uint64_t o0 = start; o0 < end; o0 += 64) {
+    const uint64_t o = o0 + lane;
+    const bool ok = o < end;
+    uint32_t tile = 0;
+    if (ok) {
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1)
+        if (s_off[wave][lo + step] <= o) lo += step;
+      const uint32_t l = (uint32_t)(o - s_off[wave][lo]);
+      const uint32_t w = s_w[wave][lo];
+      const uint32_t row = l / w, col = l - row * w;
+      tile = s_base[wave][lo] + row * s_tx[wave][lo] + col;
+      if (KEY64)
+        static_cast<uint64_t*>(keys_out)[o] = ((uint64_t)tile << 32) | s_depth[wave][lo];
+      else
+        static_cast<uint32_t*>(keys_out)[o] = tile;
+      vals[o] = s_id[wave][lo];
+    }
+    for (int p = 0; p < hist_passes; ++p) {
+      const int sh = hist_shift + 8 * p;
+      const uint32_t d = KEY64 ? (uint32_t)((((uint64_t)tile << 32) >> sh) & 0xffu) : ((tile >> sh) & 0xffu);
+      wave_hist_add(s_h + p * kRadix, d, ok);
+    }
+  }
+  __syncthreads();
+  flush_hist(s_h, hist_passes * kRadix, hist);
+}
+
+// Histogram of the depth digits of 64-bit entries (full-key path): every
+// entry of a record has the record's depth, so each record adds its tile
+// count to its depth digits.
+__global__ __launch_bounds__(kBlock) void depth_hist_weighted_kernel(const Record* __restrict__ rec,
+                                                                     const uint32_t* __restrict__ tiles,
+                                                                     int64_t n_rec,
+                                                                     uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[4 * kRadix];
+  for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) s_h[i] = 0u;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_rec; i += stride) {
+    const uint32_t c = tiles[i];
+    if (c) {
+      const uint32_t k = rec[i].depth;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) atomicAdd(&s_h[p * kRadix + ((k >> (8 * p)) & 0xffu)], c);
+    }
+  }
+  __syncthreads();
+  flush_hist(s_h, 4 * kRadix, hist);
+}
+
+// ---------------------------------------------------------------------------
+template <typename K>
 __global__ __launch_bounds__(kBlock) void onesweep_kernel(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint64_t* __restrict__ n_dup,
-    int64_t capacity, int shift, const uint32_t* __restrict__ digit_base,
-    uint64_t* __restrict__ lookback, uint64_t* __restrict__ lookback_next,
-    uint32_t* __restrict__ ticket) {
-  __shared__ uint64_t s_keys[kPart];
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint64_t* __restrict__ n_dev, int64_t capacity, int shift,
+    const uint32_t* __restrict__ digit_base, uint64_t* __restrict__ lookback,
+    uint64_t* __restrict__ lookback_next, uint32_t* __restrict__ ticket) {
+  __shared__ K s_keys[kPart];
   __shared__ uint32_t s_vals[kPart];
   __shared__ uint32_t s_cnt[kWaves][kRadix];
   __shared__ uint32_t s_start[kRadix];
@@ -185,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   if (t == 0) s_part = atomicAdd(ticket, 1u);
   for (int i = t; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0u;
   __syncthreads();
-  const uint64_t n = entry_count(n_dup, capacity);
+  const uint64_t n = entry_count(n_dev, capacity);
   const uint64_t parts = (n + kPart - 1) / kPart;
   const uint32_t part = s_part;
   if (part >= parts) return;
@@ -193,26 +297,21 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
 
   const uint64_t base = (uint64_t)part * kPart;
   const uint64_t wbase = base + (uint64_t)wave * 64 * kItems;
-  uint64_t key[kItems];
+  K key[kItems];
   uint32_t val[kItems];
   uint32_t rank[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
     const bool ok = idx < n;
-    key[i] = ok ? kin[idx] : ~0ull;
+    key[i] = ok ? kin[idx] : (K)~(K)0;
     val[i] = ok ? vin[idx] : 0u;
   }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const uint32_t d = (uint32_t)(key[i] >> shift) & 0xffu;
-    uint64_t match = ~0ull;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bal = __ballot((d >> b) & 1u);
-      match &= ((d >> b) & 1u) ? bal : ~bal;
-    }
+    const uint64_t match = match_digit(d);
     const uint32_t below = __popcll(match & lt_mask);
     const uint32_t same = __popcll(match);
     const uint32_t c = s_cnt[wave][d];
@@ -228,7 +327,6 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     s_cnt[w][t] = tot;
     tot += c;
   }
-  // block-wide exclusive scan of the digit totals
   uint32_t inc = tot;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -238,10 +336,7 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   if (lane == 63) s_scan[wave] = inc;
   // publish this partition's digit count before looking back
   uint64_t* my = lookback + (uint64_t)part * kRadix + t;
-  if (part == 0)
-    st_release(my, kFlagPrefix | (uint64_t)tot);
-  else
-    st_release(my, kFlagAgg | (uint64_t)tot);
+  st_flag(my, (part == 0 ? kFlagPrefix : kFlagAgg) | (uint64_t)tot);
   __syncthreads();
   uint32_t wpre = 0;
 #pragma unroll
@@ -254,14 +349,14 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   if (part > 0) {
     int64_t j = (int64_t)part - 1;
     while (true) {
-      const uint64_t w = ld_acquire(lookback + (uint64_t)j * kRadix + t);
+      const uint64_t w = ld_flag(lookback + (uint64_t)j * kRadix + t);
       const uint64_t flag = w & ~kValueMask;
       if (flag == 0) continue;
       excl += w & kValueMask;
       if (flag == kFlagPrefix) break;
       --j;
     }
-    st_release(my, kFlagPrefix | (excl + tot));
+    st_flag(my, kFlagPrefix | (excl + tot));
   }
   s_glob[t] = (uint64_t)digit_base[t] + excl - start;
   __syncthreads();
@@ -279,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   for (int i = 0; i < kItems; ++i) {
     const uint32_t p = (uint32_t)(i * kBlock + t);
     if (p < nvalid) {
-      const uint64_t k = s_keys[p];
+      const K k = s_keys[p];
       const uint32_t d = (uint32_t)(k >> shift) & 0xffu;
       const uint64_t dst = s_glob[d] + p;
       kout[dst] = k;
@@ -289,109 +384,195 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void ranges_kernel(const uint64_t* __restrict__ keys,
+template <typename K>
+__global__ __launch_bounds__(kBlock) void ranges_kernel(const K* __restrict__ keys, int key_shift,
                                                         const uint64_t* __restrict__ n_dup,
                                                         int64_t capacity,
                                                         uint32_t* __restrict__ ranges) {
   const uint64_t n = entry_count(n_dup, capacity);
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const uint32_t tile = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[2 * (uint64_t)tile] = (uint32_t)i;
-  if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != tile)
+  const uint32_t tile = (uint32_t)(keys[i] >> key_shift);
+  if (i == 0 || (uint32_t)(keys[i - 1] >> key_shift) != tile) ranges[2 * (uint64_t)tile] = (uint32_t)i;
+  if (i == n - 1 || (uint32_t)(keys[i + 1] >> key_shift) != tile)
     ranges[2 * (uint64_t)tile + 1] = (uint32_t)(i + 1);
 }
 
+// 64-bit keys of the depth-first path, when the caller asks for them.
+__global__ __launch_bounds__(kBlock) void compose_keys_kernel(const uint32_t* __restrict__ tile_keys,
+                                                              const uint32_t* __restrict__ vals,
+                                                              const Record* __restrict__ rec,
+                                                              const uint64_t* __restrict__ n_dup,
+                                                              int64_t capacity,
+                                                              uint64_t* __restrict__ keys) {
+  const uint64_t n = entry_count(n_dup, capacity);
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = ((uint64_t)tile_keys[i] << 32) | rec[vals[i]].depth;
+}
+
+// ---------------------------------------------------------------------------
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 struct SortWs {
-  uint64_t* alt_keys;
+  // depth-first path
+  uint32_t* rkeys[2];
+  uint32_t* rids[2];
+  uint32_t* counts;
+  uint64_t* offsets;
+  void* scan_ws;
+  uint32_t* tkeys[2];
+  // both paths
+  uint64_t* alt_keys64;
   uint32_t* alt_vals;
-  uint32_t* hist;
-  uint32_t* tickets;
+  uint32_t* hist;      // [2][kMaxPasses][256]: record passes, entry passes
+  uint32_t* tickets;   // [2][kMaxPasses]
   uint64_t* lookback[2];
   int64_t parts;
   size_t bytes;
 };
 
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-SortWs carve(void* ws, int64_t capacity, int passes) {
-  SortWs w;
-  const int64_t parts = (capacity + kPart - 1) / kPart;
+SortWs carve(void* ws, int64_t n_rec, int64_t capacity, bool full_keys) {
+  SortWs w{};
+  const int64_t m = capacity > n_rec ? capacity : n_rec;
+  const int64_t parts = (m + kPart - 1) / kPart;
   w.parts = parts > 0 ? parts : 1;
+  const size_t nr = (size_t)(n_rec > 0 ? n_rec : 1), cap = (size_t)(capacity > 0 ? capacity : 1);
   char* p = (char*)ws;
   size_t off = 0;
-  w.alt_keys = (uint64_t*)(p + off);
-  off += align256((size_t)(capacity > 0 ? capacity : 1) * 8);
-  w.alt_vals = (uint32_t*)(p + off);
-  off += align256((size_t)(capacity > 0 ? capacity : 1) * 4);
-  w.hist = (uint32_t*)(p + off);
-  off += align256((size_t)8 * kRadix * 4);
-  w.tickets = (uint32_t*)(p + off);
-  off += align256((size_t)8 * 4);
-  for (int b = 0; b < 2; ++b) {
-    w.lookback[b] = (uint64_t*)(p + off);
-    off += align256((size_t)w.parts * kRadix * 8);
+  auto take = [&](size_t bytes) {
+    void* q = p ? (void*)(p + off) : nullptr;
+    off += align256(bytes);
+    return q;
+  };
+  if (full_keys) {
+    w.alt_keys64 = (uint64_t*)take(cap * 8);
+  } else {
+    for (int b = 0; b < 2; ++b) w.rkeys[b] = (uint32_t*)take(nr * 4);
+    for (int b = 0; b < 2; ++b) w.rids[b] = (uint32_t*)take(nr * 4);
+    w.counts = (uint32_t*)take(nr * 4);
+    w.offsets = (uint64_t*)take(nr * 8);
+    w.scan_ws = take(scan_workspace_bytes(n_rec) + 256);
+    for (int b = 0; b < 2; ++b) w.tkeys[b] = (uint32_t*)take(cap * 4);
   }
-  (void)passes;
+  w.alt_vals = (uint32_t*)take(cap * 4);
+  w.hist = (uint32_t*)take((size_t)2 * kMaxPasses * kRadix * 4);
+  w.tickets = (uint32_t*)take((size_t)2 * kMaxPasses * 4);
+  for (int b = 0; b < 2; ++b) w.lookback[b] = (uint64_t*)take((size_t)w.parts * kRadix * 8);
   w.bytes = off;
   return w;
 }
 
+unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+template <typename K>
+void onesweep_passes(K** kb, uint32_t** vb, const uint64_t* n_dev, int64_t cap, int first_shift,
+                     int passes, const uint32_t* bases, SortWs& w, uint32_t* tickets, int& lb,
+                     hipStream_t s) {
+  const unsigned grid = (unsigned)((cap + kPart - 1) / kPart > 0 ? (cap + kPart - 1) / kPart : 1);
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(onesweep_kernel<K>, dim3(grid), dim3(kBlock), 0, s, kb[p & 1], vb[p & 1],
+                       kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, cap, first_shift + 8 * p,
+                       bases + p * kRadix, w.lookback[lb & 1], w.lookback[(lb + 1) & 1], tickets + p);
+    ++lb;
+  }
+}
+
 }  // namespace
 
-size_t sort_workspace_bytes(int64_t capacity, int passes) { return carve(nullptr, capacity, passes).bytes; }
+int tile_bits(uint32_t tiles_total) {
+  int tb = 0;
+  while ((1ull << tb) < tiles_total) ++tb;
+  return tb;
+}
+
+size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, bool full_keys) {
+  return carve(nullptr, n_rec, capacity, full_keys).bytes;
+}
 
 hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint64_t* offsets,
                            const uint64_t* n_dup, int64_t n_rec, int64_t n_per_cam,
                            const CamPack& cp, uint64_t* keys, uint32_t* vals, int64_t capacity,
-                           uint32_t* ranges, int32_t* overflow, void* ws, int passes,
+                           uint32_t* ranges, int32_t* overflow, void* ws, bool full_keys,
                            hipStream_t s) {
-  SortWs w = carve(ws, capacity, passes);
-  // ping-pong so that the last pass lands in the caller's buffers
-  uint64_t* kb[2];
-  uint32_t* vb[2];
-  if (passes % 2 == 0) {
-    kb[0] = keys; vb[0] = vals; kb[1] = w.alt_keys; vb[1] = w.alt_vals;
+  SortWs w = carve(ws, n_rec, capacity, full_keys);
+  const int tb = tile_bits(cp.tiles_total);
+  uint32_t* hist_rec = w.hist;
+  uint32_t* hist_ent = w.hist + kMaxPasses * kRadix;
+  int lb = 0;  // look-back buffer in use
+  hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(w.parts * kRadix, kBlock, 4096)), dim3(kBlock), 0, s,
+                     w.hist, w.tickets, w.lookback[0], w.parts * kRadix);
+  const unsigned dup_grid = grid_for((n_rec + 63) / 64, kWaves, 1 << 30);
+
+  if (full_keys) {
+    const int passes = (32 + tb + 7) / 8;
+    uint64_t* kb[2];
+    uint32_t* vb[2];
+    if (passes % 2 == 0) {
+      kb[0] = keys; vb[0] = vals; kb[1] = w.alt_keys64; vb[1] = w.alt_vals;
+    } else {
+      kb[0] = w.alt_keys64; vb[0] = w.alt_vals; kb[1] = keys; vb[1] = vals;
+    }
+    hipLaunchKernelGGL(depth_hist_weighted_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s,
+                       rec, tiles, n_rec, hist_ent);
+    hipLaunchKernelGGL(duplicate_kernel<true>, dim3(dup_grid), dim3(kBlock), 0, s, rec, nullptr, tiles,
+                       offsets, n_dup, n_rec, n_per_cam, cp, (void*)kb[0], vb[0], capacity, overflow,
+                       hist_ent + 4 * kRadix, 32, passes - 4);
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, passes);
+    onesweep_passes<uint64_t>(kb, vb, n_dup, capacity, 0, passes, hist_ent, w, w.tickets + kMaxPasses,
+                              lb, s);
   } else {
-    kb[0] = w.alt_keys; vb[0] = w.alt_vals; kb[1] = keys; vb[1] = vals;
-  }
-  const int64_t lb_words = w.parts * kRadix;
-  {
-    const int64_t g = (lb_words + kBlock - 1) / kBlock;
-    const unsigned grid = (unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
-    hipLaunchKernelGGL(sort_init_kernel, dim3(grid), dim3(kBlock), 0, s, w.hist, passes * kRadix,
-                       w.tickets, passes, w.lookback[0], lb_words);
-  }
-  {
-    const int64_t waves = (n_rec + 63) / 64;
-    const int64_t blocks = (waves + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, s,
-                       rec, tiles, offsets, n_dup, n_rec, n_per_cam, cp, kb[0], vb[0], capacity,
-                       overflow);
-  }
-  {
-    int64_t g = (capacity + kBlock * 16 - 1) / (kBlock * 16);
-    const unsigned grid = (unsigned)(g < 1 ? 1 : (g > 2048 ? 2048 : g));
-    hipLaunchKernelGGL(hist_kernel, dim3(grid), dim3(kBlock), 0, s, kb[0], n_dup, capacity, passes,
-                       w.hist);
-    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, w.hist, passes);
-  }
-  for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)w.parts), dim3(kBlock), 0, s, kb[p & 1],
-                       vb[p & 1], kb[(p + 1) & 1], vb[(p + 1) & 1], n_dup, capacity, 8 * p,
-                       w.hist + p * kRadix, w.lookback[p & 1], w.lookback[(p + 1) & 1],
-                       w.tickets + p);
-  }
-  {
+    // 1. records in (depth, id) order
+    hipLaunchKernelGGL(depth_keys_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s, rec,
+                       tiles, n_rec, w.rkeys[0], w.rids[0], hist_rec);
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec, 4);
+    if (n_rec > 0)
+      onesweep_passes<uint32_t>(w.rkeys, w.rids, nullptr, n_rec, 0, 4, hist_rec, w, w.tickets, lb, s);
+    const uint32_t* order = w.rids[0];  // four passes: back in buffer 0
+    // 2. entry offsets in that order
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(n_rec, kBlock, 1 << 30)), dim3(kBlock), 0, s,
+                       order, tiles, n_rec, w.counts);
+    hipError_t e = launch_scan(w.counts, n_rec, w.offsets, (uint64_t*)((char*)w.scan_ws),
+                               (char*)w.scan_ws + 256, s);
+    if (e != hipSuccess) return e;
+    // 3-4. entries with 32-bit tile keys, sorted over the tile bits
+    const int passes = (tb + 7) / 8;
+    uint32_t* kb[2] = {w.tkeys[0], w.tkeys[1]};
+    uint32_t* vb[2];
+    if (passes % 2 == 0) {
+      vb[0] = vals; vb[1] = w.alt_vals;
+    } else {
+      vb[0] = w.alt_vals; vb[1] = vals;
+    }
+    hipLaunchKernelGGL(duplicate_kernel<false>, dim3(dup_grid), dim3(kBlock), 0, s, rec, order, tiles,
+                       (const uint64_t*)w.offsets, n_dup, n_rec, n_per_cam, cp, (void*)kb[0], vb[0],
+                       capacity, overflow, hist_ent, 0, passes);
+    if (passes > 0) {
+      hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, passes);
+      onesweep_passes<uint32_t>(kb, vb, n_dup, capacity, 0, passes, hist_ent, w, w.tickets + kMaxPasses,
+                                lb, s);
+    }
+    const uint32_t* tkeys = kb[passes & 1];
+    // 5. ranges (and 64-bit keys if asked for)
     const int64_t nr = 2 * (int64_t)cp.tiles_total;
-    const int64_t g = (nr + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g))), dim3(kBlock),
-                       0, s, ranges, nr, 0u);
-    const int64_t gk = (capacity + kBlock - 1) / kBlock;
-    if (gk > 0)
-      hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)gk), dim3(kBlock), 0, s, keys, n_dup, capacity,
-                         ranges);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nr, kBlock, 4096)), dim3(kBlock), 0, s, ranges, nr, 0u);
+    if (capacity > 0) {
+      hipLaunchKernelGGL(ranges_kernel<uint32_t>, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock),
+                         0, s, tkeys, 0, n_dup, capacity, ranges);
+      if (keys)
+        hipLaunchKernelGGL(compose_keys_kernel, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock),
+                           0, s, tkeys, vals, rec, n_dup, capacity, keys);
+    }
+    return hipGetLastError();
   }
+  const int64_t nr = 2 * (int64_t)cp.tiles_total;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nr, kBlock, 4096)), dim3(kBlock), 0, s, ranges, nr, 0u);
+  if (capacity > 0)
+    hipLaunchKernelGGL(ranges_kernel<uint64_t>, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock), 0,
+                       s, keys, 32, n_dup, capacity, ranges);
   return hipGetLastError();
 }
 

@@ -26,12 +26,12 @@ def ambiguous(margin) -> np.ndarray:
     return (m < BANDS).any(-1)
 
 OPT_KEYS = ("tile", "batch", "lowpass", "kappa", "alpha_min", "alpha_max", "t_min", "fov_clamp", "bg",
-            "full_box")
+            "full_box", "sort_full_keys")
 
 
 def split_opts(kw):
     gpu = {k: v for k, v in kw.items() if k in OPT_KEYS}
-    orc = {k: v for k, v in kw.items() if k in OPT_KEYS and k != "batch"}
+    orc = {k: v for k, v in kw.items() if k in OPT_KEYS and k not in ("batch", "sort_full_keys")}
     return gpu, O.options(**orc)
 
 

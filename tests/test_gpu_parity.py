@@ -73,11 +73,11 @@ def _check_records(scene, cams, fr, pres):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("tile", [16, 8, 32])
-def test_preprocess_and_sort_match_oracle(name, tile):
+@pytest.mark.parametrize("tile,full_keys", [(16, False), (8, False), (32, False), (16, True), (8, True)])
+def test_preprocess_and_sort_match_oracle(name, tile, full_keys):
     scene, cams = CASES[name]
-    print(f"[case] preprocess+sort {name} tile={tile}", flush=True)
-    fr = gpu_forward(scene, cams, tile=tile)
+    print(f"[case] preprocess+sort {name} tile={tile} full_keys={full_keys}", flush=True)
+    fr = gpu_forward(scene, cams, tile=tile, sort_full_keys=full_keys)
     pres = oracle_pre(scene, cams, tile=tile)
     _check_records(scene, cams, fr, pres)
     bs = O.bin_sort(pres)
@@ -224,6 +224,28 @@ def test_gradients_match_oracle_half_clear_multiview():
     cams = [scenes.pinhole(96, 72, c["R"], c["t"]) for c in cams]
     scene = scenes.with_transparent_halves(scene)
     _grad_case(scene, cams, seed=9, tile=8, batch=128)
+
+
+def test_split_backward_equals_render_bwd():
+    """hgs_raster_bwd + hgs_preprocess_bwd == hgs_render_bwd, and the chain
+    rule leaves the per-record gradients cleared."""
+    scene, cams = CASES["cfg4_three_views"]
+    fr = gpu_forward(scene, cams)
+    dl = torch.randn(fr.images.numel(), device="cuda")
+    g_ref, rg_ref = R.backward_pass(fr, dl)
+    rg_ref = rg_ref.clone()
+    n_rec = fr.n * len(cams)
+    rg = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    B.hgs_raster_bwd(fr.records, fr.values, fr.ranges, fr.cams, fr.opts, fr.T_final, fr.last_idx, dl, rg, st)
+    torch.cuda.synchronize()
+    assert torch.allclose(rg, rg_ref, rtol=1e-5, atol=1e-7)
+    grads = torch.zeros_like(fr.soa)
+    params = B.params_struct(fr.soa, fr.n, fr.soa.shape[1], fr.sh_degree)
+    B.hgs_preprocess_bwd(params, fr.cams, fr.opts, fr.records, rg, B.grads_struct(grads, fr.soa.shape[1]), st)
+    torch.cuda.synchronize()
+    assert (rg == 0).all()
+    assert torch.allclose(grads, g_ref, rtol=1e-4, atol=1e-7)
 
 
 def test_autograd_function_matches_backward_pass():
