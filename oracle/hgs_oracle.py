@@ -376,13 +376,21 @@ def bin_sort(pres: list) -> dict:
 # ---------------------------------------------------------------------------
 # records as the raster reads them
 # ---------------------------------------------------------------------------
-def raster_records(pre: dict, mode: str = "e2e") -> dict:
-    """Record fields of the valid kernels, sorted by (depth bits, id)."""
+RECORD_FIELDS = ("mu_rel", "conic", "k", "alpha2", "d_o", "colour")
+
+
+def raster_records(pre: dict, mode: str = "e2e", leaves: dict | None = None) -> dict:
+    """Record fields of the valid kernels, sorted by (depth bits, id).  With
+    ``leaves`` (a dict to fill) the e2e fields are detached leaf tensors that
+    require grad, in the order of ``pre["idx"]``."""
     rec, idx = pre["rect"][pre["idx"]], pre["idx"]
     g = pre["rec"]
     corner = torch.stack([rec[:, 0], rec[:, 2]], -1).to(F64)
     fields = dict(mu_rel=g["mean2d"] - corner, conic=g["conic"], k=g["k"],
                   alpha2=g["alpha2"], d_o=g["d_o"], colour=g["colour"])
+    if leaves is not None:
+        fields = {k: v.detach().clone().requires_grad_(True) for k, v in fields.items()}
+        leaves.update(fields)
     if mode == "rec":
         fields = {k: torch.tensor(v.detach().numpy().astype(np.float32).astype(np.float64))
                   for k, v in fields.items()}
@@ -455,14 +463,14 @@ def _composite(recs: dict, cand: torch.Tensor, px: torch.Tensor, py: torch.Tenso
     return out, T_final, count, last, margin
 
 
-def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64) -> dict:
+def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64, leaves: dict | None = None) -> dict:
     """Blend the pixels of one camera.  ``pixels`` is an int array [P,2] of
     (px, py), or None for the full frame.  Returns image values [P,3] (or the
     [3,H,W] image), T_final, n_contrib, the record id of the last blended
     kernel (-1 if none) and the decision margin per pixel."""
     cam, o = pre["cam"], pre["opts"]
     W, H = cam["width"], cam["height"]
-    recs = raster_records(pre, mode)
+    recs = raster_records(pre, mode, leaves)
     full = pixels is None
     if full:
         yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
@@ -522,6 +530,24 @@ def render_grad(scene: dict, cams: list, dL_dout: list, o: dict | None = None, p
             L = L + (vals * torch.as_tensor(np.asarray(dL_dout[c], np.float64))).sum()
     grads = torch.autograd.grad(L, [sc[k] for k in PARAM_KEYS], allow_unused=True)
     return {k: (g.numpy() if g is not None else np.zeros(sc[k].shape)) for k, g in zip(PARAM_KEYS, grads)}
+
+
+def record_grads(scene: dict, cam: dict, dL_dout, o: dict | None = None) -> dict:
+    """Gradient of L = <dL_dout, image> with respect to each valid record's
+    screen-space fields (centre, conic (a, b, c) with power
+    -(a dx^2 + 2 b dx dy + c dy^2)/2, half-factor vector, alpha2,
+    (alpha1 - alpha2)/2, colour): autograd of the end-to-end FP64 blend with
+    those fields as leaves.  Returns (kernel indices, dict of [n_valid, .])."""
+    o = options() if o is None else o
+    with torch.no_grad():
+        pre = preprocess(scene_to_torch(scene), camera_to_torch(cam), o)
+    leaves = {}
+    img = render(pre, "e2e", leaves=leaves)["image"]
+    L = (img * torch.as_tensor(np.asarray(dL_dout, np.float64))).sum()
+    keys = list(RECORD_FIELDS)
+    gs = torch.autograd.grad(L, [leaves[k] for k in keys], allow_unused=True)
+    return pre["idx"].numpy(), {k: (g.numpy() if g is not None else np.zeros(leaves[k].shape))
+                                for k, g in zip(keys, gs)}
 
 
 # ---------------------------------------------------------------------------

@@ -39,14 +39,24 @@ namespace hgs {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kItems = 16;
-constexpr int kPart = kBlock * kItems;  // keys per partition
 constexpr int kRadix = 256;
+// keys per thread of a one-sweep pass: 32-bit keys use 8192-key partitions,
+// 64-bit keys 4096 (LDS holds a partition's keys and values)
+template <typename K>
+struct SweepItems {
+  static constexpr int value = sizeof(K) == 4 ? 32 : 16;
+};
+constexpr int kPartMin = kBlock * 16;  // smallest partition, sizes the look-back
+// Digit histograms are accumulated in kHistCopies replicas (block b adds to
+// replica b % kHistCopies): thousands of blocks adding to one 256-word
+// histogram serialise on a few cache lines.
+constexpr int kHistCopies = 64;
 constexpr int kWaves = kBlock / 64;
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagPrefix = 2ull << 62;
 constexpr uint64_t kValueMask = (1ull << 62) - 1;
 constexpr int kMaxPasses = 8;
+constexpr int kHistWords = 2 * kMaxPasses * kRadix;  // one replica: record + entry passes
 
 __device__ __forceinline__ uint64_t entry_count(const uint64_t* n_dev, int64_t capacity) {
   if (!n_dev) return (uint64_t)capacity;
@@ -81,9 +91,10 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* bins, uint32_t d, bool v
 }
 
 __device__ __forceinline__ void flush_hist(const uint32_t* s_h, int words, uint32_t* hist) {
+  uint32_t* dst = hist + (blockIdx.x % kHistCopies) * kHistWords;
   for (int i = threadIdx.x; i < words; i += blockDim.x) {
     const uint32_t v = s_h[i];
-    if (v) atomicAdd(&hist[i], v);
+    if (v) atomicAdd(&dst[i], v);
   }
 }
 
@@ -94,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void sort_init_kernel(uint32_t* __restrict_
                                                            int64_t lookback_words) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = t; i < 2 * kMaxPasses * kRadix; i += stride) hist[i] = 0u;
+  for (int64_t i = t; i < (int64_t)kHistCopies * kHistWords; i += stride) hist[i] = 0u;
   for (int64_t i = t; i < 2 * kMaxPasses; i += stride) tickets[i] = 0u;
   for (int64_t i = t; i < lookback_words; i += stride) lookback0[i] = 0ull;
 }
@@ -105,11 +116,15 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* __restrict__
   for (int64_t i = t; i < n; i += stride) p[i] = v;
 }
 
-// Exclusive scan of each pass's 256 digit counts (one block, thread = digit).
-__global__ __launch_bounds__(kRadix) void hist_scan_kernel(uint32_t* __restrict__ hist, int passes) {
+// Sum of the replicas and exclusive scan of each pass's 256 digit counts
+// (one block, thread = digit); `hist` points at the passes of replica 0,
+// `bases` receives the scans.
+__global__ __launch_bounds__(kRadix) void hist_scan_kernel(const uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ bases, int passes) {
   __shared__ uint32_t s[kRadix];
   for (int p = 0; p < passes; ++p) {
-    const uint32_t v = hist[p * kRadix + threadIdx.x];
+    uint32_t v = 0;
+    for (int c = 0; c < kHistCopies; ++c) v += hist[c * kHistWords + p * kRadix + threadIdx.x];
     s[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < kRadix; off <<= 1) {
@@ -118,7 +133,7 @@ __global__ __launch_bounds__(kRadix) void hist_scan_kernel(uint32_t* __restrict_
       s[threadIdx.x] += add;
       __syncthreads();
     }
-    hist[p * kRadix + threadIdx.x] = s[threadIdx.x] - v;
+    bases[p * kRadix + threadIdx.x] = s[threadIdx.x] - v;
     __syncthreads();
   }
 }
@@ -277,8 +292,10 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     uint32_t* __restrict__ vout, const uint64_t* __restrict__ n_dev, int64_t capacity, int shift,
     const uint32_t* __restrict__ digit_base, uint64_t* __restrict__ lookback,
     uint64_t* __restrict__ lookback_next, uint32_t* __restrict__ ticket) {
-  __shared__ K s_keys[kPart];
-  __shared__ uint32_t s_vals[kPart];
+  constexpr int ITEMS = SweepItems<K>::value;
+  constexpr int PART = kBlock * ITEMS;
+  __shared__ K s_keys[PART];
+  __shared__ uint32_t s_vals[PART];
   __shared__ uint32_t s_cnt[kWaves][kRadix];
   __shared__ uint32_t s_start[kRadix];
   __shared__ uint64_t s_glob[kRadix];
@@ -290,26 +307,27 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   for (int i = t; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0u;
   __syncthreads();
   const uint64_t n = entry_count(n_dev, capacity);
-  const uint64_t parts = (n + kPart - 1) / kPart;
+  const uint64_t parts = (n + PART - 1) / PART;
   const uint32_t part = s_part;
   if (part >= parts) return;
   lookback_next[(uint64_t)part * kRadix + t] = 0ull;
 
-  const uint64_t base = (uint64_t)part * kPart;
-  const uint64_t wbase = base + (uint64_t)wave * 64 * kItems;
-  K key[kItems];
-  uint32_t val[kItems];
-  uint32_t rank[kItems];
+  const uint64_t base = (uint64_t)part * PART;
+  const uint64_t wbase = base + (uint64_t)wave * 64 * ITEMS;
+  K key[ITEMS];
+  uint32_t val[ITEMS];
+  uint32_t rank[ITEMS];
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
     const bool ok = idx < n;
     key[i] = ok ? kin[idx] : (K)~(K)0;
     val[i] = ok ? vin[idx] : 0u;
   }
+  // rank within the wavefront, in item-then-lane order (stable)
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const uint32_t d = (uint32_t)(key[i] >> shift) & 0xffu;
     const uint64_t match = match_digit(d);
     const uint32_t below = __popcll(match & lt_mask);
@@ -327,6 +345,9 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     s_cnt[w][t] = tot;
     tot += c;
   }
+  // publish this partition's digit count as early as possible
+  uint64_t* my = lookback + (uint64_t)part * kRadix + t;
+  st_flag(my, (part == 0 ? kFlagPrefix : kFlagAgg) | (uint64_t)tot);
   uint32_t inc = tot;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -334,9 +355,6 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     if (lane >= off) inc += y;
   }
   if (lane == 63) s_scan[wave] = inc;
-  // publish this partition's digit count before looking back
-  uint64_t* my = lookback + (uint64_t)part * kRadix + t;
-  st_flag(my, (part == 0 ? kFlagPrefix : kFlagAgg) | (uint64_t)tot);
   __syncthreads();
   uint32_t wpre = 0;
 #pragma unroll
@@ -344,6 +362,16 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     if (w < wave) wpre += s_scan[w];
   const uint32_t start = wpre + inc - tot;
   s_start[t] = start;
+  __syncthreads();
+  // scatter into LDS in block-sorted order (needs only block-local offsets,
+  // so it runs before the look-back and hides part of its latency)
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t d = (uint32_t)(key[i] >> shift) & 0xffu;
+    const uint32_t pos = s_start[d] + s_cnt[wave][d] + rank[i];
+    s_keys[pos] = key[i];
+    s_vals[pos] = val[i];
+  }
   // decoupled look-back for digit t
   uint64_t excl = 0;
   if (part > 0) {
@@ -351,7 +379,10 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     while (true) {
       const uint64_t w = ld_flag(lookback + (uint64_t)j * kRadix + t);
       const uint64_t flag = w & ~kValueMask;
-      if (flag == 0) continue;
+      if (flag == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
       excl += w & kValueMask;
       if (flag == kFlagPrefix) break;
       --j;
@@ -360,18 +391,9 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   }
   s_glob[t] = (uint64_t)digit_base[t] + excl - start;
   __syncthreads();
-  // scatter into LDS in block-sorted order
+  const uint64_t nvalid = (n - base) < (uint64_t)PART ? (n - base) : (uint64_t)PART;
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const uint32_t d = (uint32_t)(key[i] >> shift) & 0xffu;
-    const uint32_t pos = s_start[d] + s_cnt[wave][d] + rank[i];
-    s_keys[pos] = key[i];
-    s_vals[pos] = val[i];
-  }
-  __syncthreads();
-  const uint64_t nvalid = (n - base) < (uint64_t)kPart ? (n - base) : (uint64_t)kPart;
-#pragma unroll
-  for (int i = 0; i < kItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const uint32_t p = (uint32_t)(i * kBlock + t);
     if (p < nvalid) {
       const K k = s_keys[p];
@@ -425,7 +447,8 @@ struct SortWs {
   // both paths
   uint64_t* alt_keys64;
   uint32_t* alt_vals;
-  uint32_t* hist;      // [2][kMaxPasses][256]: record passes, entry passes
+  uint32_t* hist;      // [kHistCopies][2][kMaxPasses][256]: record passes, entry passes
+  uint32_t* bases;     // [2][kMaxPasses][256] scanned
   uint32_t* tickets;   // [2][kMaxPasses]
   uint64_t* lookback[2];
   int64_t parts;
@@ -435,7 +458,7 @@ struct SortWs {
 SortWs carve(void* ws, int64_t n_rec, int64_t capacity, bool full_keys) {
   SortWs w{};
   const int64_t m = capacity > n_rec ? capacity : n_rec;
-  const int64_t parts = (m + kPart - 1) / kPart;
+  const int64_t parts = (m + kPartMin - 1) / kPartMin;
   w.parts = parts > 0 ? parts : 1;
   const size_t nr = (size_t)(n_rec > 0 ? n_rec : 1), cap = (size_t)(capacity > 0 ? capacity : 1);
   char* p = (char*)ws;
@@ -456,7 +479,8 @@ SortWs carve(void* ws, int64_t n_rec, int64_t capacity, bool full_keys) {
     for (int b = 0; b < 2; ++b) w.tkeys[b] = (uint32_t*)take(cap * 4);
   }
   w.alt_vals = (uint32_t*)take(cap * 4);
-  w.hist = (uint32_t*)take((size_t)2 * kMaxPasses * kRadix * 4);
+  w.hist = (uint32_t*)take((size_t)kHistCopies * kHistWords * 4);
+  w.bases = (uint32_t*)take((size_t)kHistWords * 4);
   w.tickets = (uint32_t*)take((size_t)2 * kMaxPasses * 4);
   for (int b = 0; b < 2; ++b) w.lookback[b] = (uint64_t*)take((size_t)w.parts * kRadix * 8);
   w.bytes = off;
@@ -472,7 +496,8 @@ template <typename K>
 void onesweep_passes(K** kb, uint32_t** vb, const uint64_t* n_dev, int64_t cap, int first_shift,
                      int passes, const uint32_t* bases, SortWs& w, uint32_t* tickets, int& lb,
                      hipStream_t s) {
-  const unsigned grid = (unsigned)((cap + kPart - 1) / kPart > 0 ? (cap + kPart - 1) / kPart : 1);
+  constexpr int PART = kBlock * SweepItems<K>::value;
+  const unsigned grid = (unsigned)((cap + PART - 1) / PART > 0 ? (cap + PART - 1) / PART : 1);
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(onesweep_kernel<K>, dim3(grid), dim3(kBlock), 0, s, kb[p & 1], vb[p & 1],
                        kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, cap, first_shift + 8 * p,
@@ -500,10 +525,13 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                            hipStream_t s) {
   SortWs w = carve(ws, n_rec, capacity, full_keys);
   const int tb = tile_bits(cp.tiles_total);
-  uint32_t* hist_rec = w.hist;
+  uint32_t* hist_rec = w.hist;                       // replica 0; replicas follow
   uint32_t* hist_ent = w.hist + kMaxPasses * kRadix;
+  uint32_t* base_rec = w.bases;
+  uint32_t* base_ent = w.bases + kMaxPasses * kRadix;
   int lb = 0;  // look-back buffer in use
-  hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(w.parts * kRadix, kBlock, 4096)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(w.parts * kRadix + kHistCopies * kHistWords, kBlock, 4096)),
+                     dim3(kBlock), 0, s,
                      w.hist, w.tickets, w.lookback[0], w.parts * kRadix);
   const unsigned dup_grid = grid_for((n_rec + 63) / 64, kWaves, 1 << 30);
 
@@ -521,16 +549,16 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     hipLaunchKernelGGL(duplicate_kernel<true>, dim3(dup_grid), dim3(kBlock), 0, s, rec, nullptr, tiles,
                        offsets, n_dup, n_rec, n_per_cam, cp, (void*)kb[0], vb[0], capacity, overflow,
                        hist_ent + 4 * kRadix, 32, passes - 4);
-    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, passes);
-    onesweep_passes<uint64_t>(kb, vb, n_dup, capacity, 0, passes, hist_ent, w, w.tickets + kMaxPasses,
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
+    onesweep_passes<uint64_t>(kb, vb, n_dup, capacity, 0, passes, base_ent, w, w.tickets + kMaxPasses,
                               lb, s);
   } else {
     // 1. records in (depth, id) order
     hipLaunchKernelGGL(depth_keys_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s, rec,
                        tiles, n_rec, w.rkeys[0], w.rids[0], hist_rec);
-    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec, 4);
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec, base_rec, 4);
     if (n_rec > 0)
-      onesweep_passes<uint32_t>(w.rkeys, w.rids, nullptr, n_rec, 0, 4, hist_rec, w, w.tickets, lb, s);
+      onesweep_passes<uint32_t>(w.rkeys, w.rids, nullptr, n_rec, 0, 4, base_rec, w, w.tickets, lb, s);
     const uint32_t* order = w.rids[0];  // four passes: back in buffer 0
     // 2. entry offsets in that order
     hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(n_rec, kBlock, 1 << 30)), dim3(kBlock), 0, s,
@@ -551,8 +579,8 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        (const uint64_t*)w.offsets, n_dup, n_rec, n_per_cam, cp, (void*)kb[0], vb[0],
                        capacity, overflow, hist_ent, 0, passes);
     if (passes > 0) {
-      hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, passes);
-      onesweep_passes<uint32_t>(kb, vb, n_dup, capacity, 0, passes, hist_ent, w, w.tickets + kMaxPasses,
+      hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
+      onesweep_passes<uint32_t>(kb, vb, n_dup, capacity, 0, passes, base_ent, w, w.tickets + kMaxPasses,
                                 lb, s);
     }
     const uint32_t* tkeys = kb[passes & 1];

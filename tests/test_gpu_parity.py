@@ -226,23 +226,39 @@ def test_gradients_match_oracle_half_clear_multiview():
     _grad_case(scene, cams, seed=9, tile=8, batch=128)
 
 
-def test_split_backward_equals_render_bwd():
-    """hgs_raster_bwd + hgs_preprocess_bwd == hgs_render_bwd, and the chain
-    rule leaves the per-record gradients cleared."""
-    scene, cams = CASES["cfg4_three_views"]
-    fr = gpu_forward(scene, cams)
-    dl = torch.randn(fr.images.numel(), device="cuda")
-    g_ref, rg_ref = R.backward_pass(fr, dl)
-    rg_ref = rg_ref.clone()
-    n_rec = fr.n * len(cams)
+def test_raster_bwd_record_gradients_match_oracle():
+    """hgs_raster_bwd alone: the 12 per-record gradients against FP64
+    autograd of the blend with the record fields as leaves; then
+    hgs_preprocess_bwd on them equals hgs_render_bwd and clears them."""
+    scene, _ = scenes.make_config(2, n=1500)
+    scene = scenes.with_transparent_halves(scene)
+    cam = scenes.axis_camera(150, 110, distance=3.0)
+    fr = gpu_forward(scene, [cam])
+    pre = oracle_pre(scene, [cam])[0]
+    ref_amb = O.render(pre, "e2e")
+    w = np.random.default_rng(4).normal(size=(3, 110, 150))
+    w[:, ambiguous(ref_amb["margin"])] = 0.0
+    dl = torch.as_tensor(w, dtype=torch.float32).reshape(-1).cuda()
+    n_rec = fr.n
     rg = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, device="cuda")
     st = torch.cuda.current_stream().cuda_stream
     B.hgs_raster_bwd(fr.records, fr.values, fr.ranges, fr.cams, fr.opts, fr.T_final, fr.last_idx, dl, rg, st)
     torch.cuda.synchronize()
-    assert torch.allclose(rg, rg_ref, rtol=1e-5, atol=1e-7)
+    got = rg.cpu().numpy().reshape(n_rec, B.HGS_RECORD_GRAD_FLOATS).astype(np.float64)
+    idx, ref = O.record_grads(scene, cam, w)
+    refm = np.concatenate([ref["mu_rel"], ref["conic"], ref["k"], ref["alpha2"][:, None],
+                           ref["d_o"][:, None], ref["colour"]], 1)
+    gotm = got[idx]
+    assert np.all(got[np.setdiff1d(np.arange(n_rec), idx)] == 0)
+    for q in range(B.HGS_RECORD_GRAD_FLOATS):
+        g, r = gotm[:, q], refm[:, q]
+        rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
+        assert rel <= 1e-3, (q, rel)
+    # the chain rule half equals the full call and clears the buffer
     grads = torch.zeros_like(fr.soa)
     params = B.params_struct(fr.soa, fr.n, fr.soa.shape[1], fr.sh_degree)
     B.hgs_preprocess_bwd(params, fr.cams, fr.opts, fr.records, rg, B.grads_struct(grads, fr.soa.shape[1]), st)
+    g_ref, _ = R.backward_pass(fr, dl)
     torch.cuda.synchronize()
     assert (rg == 0).all()
     assert torch.allclose(grads, g_ref, rtol=1e-4, atol=1e-7)
