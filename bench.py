@@ -3,8 +3,10 @@
 
 One step = one forward + backward pass of the whole rasterizer over the
 workload's views: hgs_preprocess, hgs_bin_sort, hgs_render_fwd, the L1 loss
-gradient against a seeded target, hgs_render_bwd.  Inputs (parameters,
-target) are resident in HBM before timing starts; buffers are allocated once.
+gradient against a seeded target, then the two halves of hgs_render_bwd
+(hgs_raster_bwd, hgs_preprocess_bwd) so that each is timed on its own.
+Inputs (parameters, target) are resident in HBM before timing starts;
+buffers are allocated once.
 
 Default workload: 1M half-Gaussians, one 1920x1080 camera, SH degree 3,
 FP32 (shell + box mixture, log-scales N(-4, 1)).  Prints one JSON line.
@@ -44,11 +46,35 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage timings to stderr")
     ap.add_argument("--full-keys", action="store_true", help="sort the 64-bit keys over all bits")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES, 5 times (counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe(nbytes: int):
+    """A plain device-to-device copy of known size: the reference for scaling
+    the HBM byte counters of the rasterizer's kernels."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 5
+    print(json.dumps({"copy_bytes": nbytes, "ms": round(ms, 4),
+                      "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
 
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(views would shard across GPUs with one gradient all-reduce; not built).", file=sys.stderr)

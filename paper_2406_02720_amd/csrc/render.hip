@@ -31,15 +31,41 @@ namespace {
 
 constexpr float kTwoOverSqrtPi = 1.12837916709551257390f;
 
+// erfc(x) from the Chebyshev-fitted form of Numerical Recipes (Press et al.,
+// 2nd ed., Sec. 6.2, "erfcc"): erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2)
+// for z = |x|, fractional error below 1.2e-7 everywhere; erfc(-z) = 2 -
+// erfc(z).  Branch-free (one v_rcp, one exp2, ten fma), so the lanes
+// of a wavefront never diverge on the argument's range.  Result in [0, 2].
+__device__ __forceinline__ float erfc_fast(float x) {
+  const float z = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  const float e = t * __expf(fmaf(-z, z, p));
+  return x >= 0.0f ? e : 2.0f - e;
+}
+
 struct Pair {
   bool live;   // in rect and power <= 0
   float dx, dy, G, I, HG, a;
 };
 
 // One pixel against one record.  Pure function of its inputs, so the forward
-// and backward passes take identical decisions.
-__device__ __forceinline__ void eval_pair(const Record& r, int px, int py, float alpha_max,
-                                          Pair& P) {
+// and backward passes take identical decisions.  `amax_half` is
+// max(alpha2, alpha2 + 2 d_o) rounded as below: since I lies in [0, 2] and
+// every rounding is monotone, HG <= G * amax_half, so a pair whose bound is
+// already below alpha_min is skipped without the half factor -- the same
+// decision the full evaluation takes.
+__device__ __forceinline__ void eval_pair(const Record& r, float amax_half, int px, int py,
+                                          float alpha_min, float alpha_max, Pair& P) {
   const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
   const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
   P.live = px >= x0 && px <= x1 && py >= y0 && py <= y1;
@@ -51,14 +77,24 @@ __device__ __forceinline__ void eval_pair(const Record& r, int px, int py, float
   P.live = !(power > 0.0f);
   if (!P.live) return;
   P.G = __expf(power);
+  if (P.G * amax_half < alpha_min) {  // cannot reach alpha_min
+    P.a = 0.0f;
+    P.HG = 0.0f;
+    P.I = 1.0f;
+    return;
+  }
   if (r.d_o != 0.0f) {
-    P.I = erfcf(-fmaf(r.kx, P.dx, r.ky * P.dy));
+    P.I = erfc_fast(-fmaf(r.kx, P.dx, r.ky * P.dy));
     P.HG = fmaf(r.d_o, P.I, r.alpha2) * P.G;
   } else {
     P.I = 1.0f;
     P.HG = r.alpha2 * P.G;
   }
   P.a = fminf(alpha_max, P.HG);
+}
+
+__device__ __forceinline__ float half_bound(const Record& r) {
+  return fmaxf(r.alpha2, fmaf(r.d_o, 2.0f, r.alpha2));
 }
 
 template <int T>
@@ -152,12 +188,13 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
       for (int l = 0; l < cntk; ++l) {
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
+        const float hb = half_bound(r);
         const int32_t pos = (int32_t)(base + k * 64 + l);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
           if (done[j]) continue;
           Pair P;
-          eval_pair(r, px, py[j], amax, P);
+          eval_pair(r, hb, px, py[j], amin, amax, P);
           if (!P.live || P.a < amin) continue;
           const float Tn = Tr[j] * (1.0f - P.a);
           if (Tn < tmin) {
@@ -259,6 +296,7 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
       for (int l = 0; l < cntk; ++l) {
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
+        const float hb = half_bound(r);
         const int32_t pos = hi - (k * 64 + l);
         float gs[HGS_RECORD_GRAD_FLOATS];
 #pragma unroll
@@ -268,7 +306,7 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
         for (int j = 0; j < PPL; ++j) {
           if (pos > last[j]) continue;
           Pair P;
-          eval_pair(r, px, py[j], amax, P);
+          eval_pair(r, hb, px, py[j], amin, amax, P);
           if (!P.live || P.a < amin) continue;
           any = true;
           const float a = P.a;

@@ -50,7 +50,7 @@ constexpr int kPartMin = kBlock * 16;  // smallest partition, sizes the look-bac
 // Digit histograms are accumulated in kHistCopies replicas (block b adds to
 // replica b % kHistCopies): thousands of blocks adding to one 256-word
 // histogram serialise on a few cache lines.
-constexpr int kHistCopies = 64;
+constexpr int kHistCopies = 128;
 constexpr int kWaves = kBlock / 64;
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagPrefix = 2ull << 62;
@@ -175,20 +175,46 @@ __global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* _
   if (i < n) out[i] = tiles[ids[i]];
 }
 
-// One entry per covered tile.  A wavefront owns 64 consecutive slots of the
-// record order `order` (identity when null), whose entries are contiguous;
-// each lane finds the slot of an output position by binary search over the
-// 64 offsets, so writes are coalesced and a record covering many tiles is
-// spread over the whole wavefront.  KEY64 writes tile << 32 | depth keys,
-// otherwise 32-bit tile keys; `hist` receives the digit histograms of the
-// key bits from `hist_shift` on, `hist_passes` digits.
+// Output chunks of the duplication: a wavefront writes the entries
+// [c * kChunk, (c + 1) * kChunk).  Balancing by output rather than by record
+// matters because, in depth order, the nearest kernels -- the ones covering
+// the most tiles -- are adjacent.
+constexpr int kChunk = 2048;
+
+// chunk_start[c] = the slot whose entries contain position c * kChunk, for
+// the n_chunks chunks that fit the capacity (entries beyond it are never
+// written: the duplication reports the overflow instead).
+__global__ __launch_bounds__(kBlock) void chunk_start_kernel(const uint32_t* __restrict__ order,
+                                                             const uint32_t* __restrict__ tiles,
+                                                             const uint64_t* __restrict__ offsets,
+                                                             int64_t n_rec, uint64_t n_chunks,
+                                                             uint32_t* __restrict__ chunk_start) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n_rec) return;
+  const uint32_t cnt = tiles[order ? order[j] : (uint32_t)j];
+  if (cnt == 0) return;
+  const uint64_t a = offsets[j], b = a + cnt;
+  for (uint64_t c = (a + kChunk - 1) / kChunk; c * kChunk < b && c < n_chunks; ++c)
+    chunk_start[c] = (uint32_t)j;
+}
+
+// One entry per covered tile, for the record slots in `order` (identity when
+// null) whose entries start at `offsets`.  The wavefront of chunk c loads the
+// descriptors of 64 consecutive slots (from chunk_start[c]) into LDS and
+// emits the chunk's entries that fall in them, 64 at a time; each lane finds
+// the slot of its output position by binary search over the 64 offsets, so
+// writes are coalesced and a kernel covering many tiles is spread over many
+// lanes and wavefronts.  KEY64 writes tile << 32 | depth keys, otherwise
+// 32-bit tile keys; `hist` receives the digit histograms of the key bits
+// from `hist_shift` on, `hist_passes` digits.
 template <bool KEY64>
 __global__ __launch_bounds__(kBlock) void duplicate_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ order,
     const uint32_t* __restrict__ tiles, const uint64_t* __restrict__ offsets,
-    const uint64_t* __restrict__ n_dup, int64_t n_rec, int64_t n_per_cam, CamPack cp,
-    void* __restrict__ keys_out, uint32_t* __restrict__ vals, int64_t capacity,
-    int32_t* __restrict__ overflow, uint32_t* __restrict__ hist, int hist_shift, int hist_passes) {
+    const uint32_t* __restrict__ chunk_start, const uint64_t* __restrict__ n_dup, int64_t n_rec,
+    int64_t n_per_cam, CamPack cp, void* __restrict__ keys_out, uint32_t* __restrict__ vals,
+    int64_t capacity, int32_t* __restrict__ overflow, uint32_t* __restrict__ hist, int hist_shift,
+    int hist_passes) {
   __shared__ uint64_t s_off[kWaves][64];
   __shared__ uint32_t s_base[kWaves][64];   // first global tile of the rect
   __shared__ uint32_t s_w[kWaves][64];      // rect width in tiles
@@ -197,65 +223,78 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(
   __shared__ uint32_t s_id[kWaves][64];
   __shared__ uint32_t s_h[kMaxPasses * kRadix];
   for (int i = threadIdx.x; i < hist_passes * kRadix; i += kBlock) s_h[i] = 0u;
+  __syncthreads();
   const uint64_t total = *n_dup;
   const bool over = total > (uint64_t)capacity;
   if (blockIdx.x == 0 && threadIdx.x == 0) *overflow = over ? 1 : 0;
   if (over) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t j = ((int64_t)blockIdx.x * kWaves + wave) * 64 + lane;
-  uint32_t cnt = 0;
-  uint64_t off = total;
-  if (j < n_rec) {
-    const uint32_t r = order ? order[j] : (uint32_t)j;
-    cnt = tiles[r];
-    off = offsets[j];
-    if (cnt > 0) {
-      const Record& R = rec[r];
-      const int cam = (int)(r / n_per_cam);
-      const CamDev& C = cp.cam[cam];
-      const int sh = cp.tile_shift;
-      const uint32_t tx0 = (R.xr & 0xffffu) >> sh, tx1 = (R.xr >> 16) >> sh;
-      const uint32_t ty0 = (R.yr & 0xffffu) >> sh;
-      s_base[wave][lane] = C.tile_off + ty0 * (uint32_t)C.tiles_x + tx0;
-      s_w[wave][lane] = tx1 - tx0 + 1;
-      s_tx[wave][lane] = (uint32_t)C.tiles_x;
-      s_depth[wave][lane] = R.depth;
-      s_id[wave][lane] = r;
-    }
-  }
-  s_off[wave][lane] = off;
-  // slots' entries are contiguous: [start, end)
-  const uint64_t start = __shfl(off, 0, 64);
-  uint64_t end = off + cnt;
+  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
+  const uint64_t o_begin = c * kChunk;
+  const uint64_t o_end = o_begin + kChunk < total ? o_begin + kChunk : total;
+  if (o_begin < total) {
+    int64_t j0 = chunk_start[c];
+    while (true) {
+      // descriptors of slots j0 .. j0 + 63
+      const int64_t j = j0 + lane;
+      uint32_t cnt = 0;
+      uint64_t off = total;
+      if (j < n_rec) {
+        const uint32_t r = order ? order[j] : (uint32_t)j;
+        cnt = tiles[r];
+        off = offsets[j];
+        if (cnt > 0) {
+          const Record& R = rec[r];
+          const int cam = (int)(r / n_per_cam);
+          const CamDev& C = cp.cam[cam];
+          const int sh = cp.tile_shift;
+          const uint32_t tx0 = (R.xr & 0xffffu) >> sh, tx1 = (R.xr >> 16) >> sh;
+          const uint32_t ty0 = (R.yr & 0xffffu) >> sh;
+          s_base[wave][lane] = C.tile_off + ty0 * (uint32_t)C.tiles_x + tx0;
+          s_w[wave][lane] = tx1 - tx0 + 1;
+          s_tx[wave][lane] = (uint32_t)C.tiles_x;
+          s_depth[wave][lane] = R.depth;
+          s_id[wave][lane] = r;
+        }
+      }
+      s_off[wave][lane] = off;
+      uint64_t win_end = off + cnt;  // end of the window's entries (max over lanes)
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const uint64_t o = __shfl_xor(end, m, 64);
-    end = o > end ? o : end;
-  }
-  __syncthreads();
-  for (uint64_t o0 = start; o0 < end; o0 += 64) {
-    const uint64_t o = o0 + lane;
-    const bool ok = o < end;
-    uint32_t tile = 0;
-    if (ok) {
-      int lo = 0;
+      for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = __shfl_xor(win_end, m, 64);
+        win_end = o > win_end ? o : win_end;
+      }
+      const uint64_t win_begin = __shfl(off, 0, 64);
+      const uint64_t lo_o = win_begin > o_begin ? win_begin : o_begin;
+      const uint64_t hi_o = win_end < o_end ? win_end : o_end;
+      for (uint64_t o0 = lo_o; o0 < hi_o; o0 += 64) {
+        const uint64_t o = o0 + lane;
+        const bool ok = o < hi_o;
+        uint32_t tile = 0;
+        if (ok) {
+          int lo = 0;
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1)
-        if (s_off[wave][lo + step] <= o) lo += step;
-      const uint32_t l = (uint32_t)(o - s_off[wave][lo]);
-      const uint32_t w = s_w[wave][lo];
-      const uint32_t row = l / w, col = l - row * w;
-      tile = s_base[wave][lo] + row * s_tx[wave][lo] + col;
-      if (KEY64)
-        static_cast<uint64_t*>(keys_out)[o] = ((uint64_t)tile << 32) | s_depth[wave][lo];
-      else
-        static_cast<uint32_t*>(keys_out)[o] = tile;
-      vals[o] = s_id[wave][lo];
-    }
-    for (int p = 0; p < hist_passes; ++p) {
-      const int sh = hist_shift + 8 * p;
-      const uint32_t d = KEY64 ? (uint32_t)((((uint64_t)tile << 32) >> sh) & 0xffu) : ((tile >> sh) & 0xffu);
-      wave_hist_add(s_h + p * kRadix, d, ok);
+          for (int step = 32; step >= 1; step >>= 1)
+            if (s_off[wave][lo + step] <= o) lo += step;
+          const uint32_t l = (uint32_t)(o - s_off[wave][lo]);
+          const uint32_t w = s_w[wave][lo];
+          const uint32_t row = l / w, col = l - row * w;
+          tile = s_base[wave][lo] + row * s_tx[wave][lo] + col;
+          if (KEY64)
+            static_cast<uint64_t*>(keys_out)[o] = ((uint64_t)tile << 32) | s_depth[wave][lo];
+          else
+            static_cast<uint32_t*>(keys_out)[o] = tile;
+          vals[o] = s_id[wave][lo];
+        }
+        for (int p = 0; p < hist_passes; ++p) {
+          const int sh = hist_shift + 8 * p;
+          const uint32_t d = KEY64 ? (uint32_t)((((uint64_t)tile << 32) >> sh) & 0xffu)
+                                   : ((tile >> sh) & 0xffu);
+          wave_hist_add(s_h + p * kRadix, d, ok);
+        }
+      }
+      if (win_end >= o_end || j0 + 64 >= n_rec) break;
+      j0 += 64;
     }
   }
   __syncthreads();
@@ -447,6 +486,7 @@ struct SortWs {
   // both paths
   uint64_t* alt_keys64;
   uint32_t* alt_vals;
+  uint32_t* chunk_start;
   uint32_t* hist;      // [kHistCopies][2][kMaxPasses][256]: record passes, entry passes
   uint32_t* bases;     // [2][kMaxPasses][256] scanned
   uint32_t* tickets;   // [2][kMaxPasses]
@@ -479,6 +519,7 @@ SortWs carve(void* ws, int64_t n_rec, int64_t capacity, bool full_keys) {
     for (int b = 0; b < 2; ++b) w.tkeys[b] = (uint32_t*)take(cap * 4);
   }
   w.alt_vals = (uint32_t*)take(cap * 4);
+  w.chunk_start = (uint32_t*)take((cap + kChunk - 1) / kChunk * 4 + 4);
   w.hist = (uint32_t*)take((size_t)kHistCopies * kHistWords * 4);
   w.bases = (uint32_t*)take((size_t)kHistWords * 4);
   w.tickets = (uint32_t*)take((size_t)2 * kMaxPasses * 4);
@@ -533,7 +574,7 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
   hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(w.parts * kRadix + kHistCopies * kHistWords, kBlock, 4096)),
                      dim3(kBlock), 0, s,
                      w.hist, w.tickets, w.lookback[0], w.parts * kRadix);
-  const unsigned dup_grid = grid_for((n_rec + 63) / 64, kWaves, 1 << 30);
+  const unsigned dup_grid = grid_for((capacity + kChunk - 1) / kChunk, kWaves, 1 << 30);
 
   if (full_keys) {
     const int passes = (32 + tb + 7) / 8;
@@ -546,9 +587,13 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     }
     hipLaunchKernelGGL(depth_hist_weighted_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s,
                        rec, tiles, n_rec, hist_ent);
+    if (n_rec > 0)
+      hipLaunchKernelGGL(chunk_start_kernel, dim3(grid_for(n_rec, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
+                         nullptr, tiles, offsets, n_rec, (uint64_t)((capacity + kChunk - 1) / kChunk),
+                         w.chunk_start);
     hipLaunchKernelGGL(duplicate_kernel<true>, dim3(dup_grid), dim3(kBlock), 0, s, rec, nullptr, tiles,
-                       offsets, n_dup, n_rec, n_per_cam, cp, (void*)kb[0], vb[0], capacity, overflow,
-                       hist_ent + 4 * kRadix, 32, passes - 4);
+                       offsets, (const uint32_t*)w.chunk_start, n_dup, n_rec, n_per_cam, cp, (void*)kb[0],
+                       vb[0], capacity, overflow, hist_ent + 4 * kRadix, 32, passes - 4);
     hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
     onesweep_passes<uint64_t>(kb, vb, n_dup, capacity, 0, passes, base_ent, w, w.tickets + kMaxPasses,
                               lb, s);
@@ -575,9 +620,13 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     } else {
       vb[0] = w.alt_vals; vb[1] = vals;
     }
+    if (n_rec > 0)
+      hipLaunchKernelGGL(chunk_start_kernel, dim3(grid_for(n_rec, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
+                         order, tiles, (const uint64_t*)w.offsets, n_rec,
+                         (uint64_t)((capacity + kChunk - 1) / kChunk), w.chunk_start);
     hipLaunchKernelGGL(duplicate_kernel<false>, dim3(dup_grid), dim3(kBlock), 0, s, rec, order, tiles,
-                       (const uint64_t*)w.offsets, n_dup, n_rec, n_per_cam, cp, (void*)kb[0], vb[0],
-                       capacity, overflow, hist_ent, 0, passes);
+                       (const uint64_t*)w.offsets, (const uint32_t*)w.chunk_start, n_dup, n_rec, n_per_cam,
+                       cp, (void*)kb[0], vb[0], capacity, overflow, hist_ent, 0, passes);
     if (passes > 0) {
       hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
       onesweep_passes<uint32_t>(kb, vb, n_dup, capacity, 0, passes, base_ent, w, w.tickets + kMaxPasses,
