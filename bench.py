@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage timings to stderr")
     ap.add_argument("--full-keys", action="store_true", help="sort the 64-bit keys over all bits")
+    ap.add_argument("--per-tile", action="store_true", help="one raster workgroup per tile (no persistent grid)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES, 5 times (counter calibration)")
     return ap.parse_args()
@@ -122,6 +123,7 @@ def main():
     keys = torch.empty(cap, dtype=torch.int64, device=dev) if args.full_keys else None
     values = torch.empty(cap, dtype=torch.int32, device=dev)
     ranges = torch.empty(2 * tiles_total, dtype=torch.int32, device=dev)
+    order = None if args.per_tile else torch.empty(tiles_total, dtype=torch.int32, device=dev)
     overflow = torch.zeros(1, dtype=torch.int32, device=dev)
     ws_sort = buf(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, ca, opts, cap))
     images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
@@ -142,17 +144,18 @@ def main():
         mark(0)
         B.hgs_preprocess(params, ca, opts, records, tiles, offsets, ndup, ws_pre, stream)
         mark(1)
-        B.hgs_bin_sort(records, tiles, offsets, ndup, n_rec, ca, opts, keys, values, cap, ranges, overflow,
-                       ws_sort, stream)
+        B.hgs_bin_sort(records, tiles, offsets, ndup, n_rec, ca, opts, keys, values, cap, ranges, order,
+                       overflow, ws_sort, stream)
         mark(2)
-        B.hgs_render_fwd(records, values, ranges, ca, opts, images, T_final, last_idx, n_contrib, ws_r, stream)
+        B.hgs_render_fwd(records, values, ranges, order, ca, opts, images, T_final, last_idx, n_contrib, ws_r,
+                         stream)
         mark(3)
         torch.sub(images, target, out=dL)
         torch.sign(dL, out=dL)
         dL.mul_(inv_numel)
         mark(4)
         # record gradients start cleared (hgs_preprocess_bwd clears them after use)
-        B.hgs_raster_bwd(records, values, ranges, ca, opts, T_final, last_idx, dL, rgrad, stream)
+        B.hgs_raster_bwd(records, values, ranges, order, ca, opts, T_final, last_idx, dL, rgrad, ws_r, stream)
         mark(5)
         B.hgs_preprocess_bwd(params, ca, opts, records, rgrad, gstruct, stream)
         mark(6)
@@ -193,10 +196,7 @@ def main():
     # ---- algorithmic work per stage
     # pairs the raster must evaluate: for every pixel, the entries of its
     # tile list up to its last blended one; blended pairs: n_contrib
-    starts = ranges.view(-1, 2)[:, 0].to(torch.int64)
-    pix_tile = pixel_tiles(cams, args.tile, dev)
-    last = last_idx.to(torch.int64)
-    pairs = int(torch.clamp(last - starts[pix_tile] + 1, min=0).sum().item())
+    pairs = int((last_idx.to(torch.int64) + 1).sum().item())
     blended = int(n_contrib.to(torch.int64).sum().item())
     sh_floats = 3 * (deg + 1) ** 2
     param_bytes = 4 * (15 + sh_floats)
@@ -265,7 +265,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS.get(args.config, str(args.config)), "n_kernels": n,
                    "views": len(cams), "pixels": W, "tile": args.tile, "batch": args.batch,
-                   "entries": n_dup, "sort": "full_keys" if args.full_keys else "depth_first"},
+                   "entries": n_dup, "sort": "full_keys" if args.full_keys else "depth_first",
+                   "raster": "per_tile" if args.per_tile else "persistent"},
         "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
         "fwd_bwd_over_fwd": round((fwd_ms + bwd_ms) / fwd_ms, 3),
         "stage_ms": {k: round(float(v), 4) for k, v in st.items()},
@@ -274,20 +275,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-
-
-def pixel_tiles(cams, T, dev):
-    """Global tile id of every pixel (cameras packed), for work accounting."""
-    import torch
-    out, off = [], 0
-    for c in cams:
-        w, h = c["width"], c["height"]
-        tx = (w + T - 1) // T
-        ys = torch.arange(h, device=dev).view(-1, 1) // T
-        xs = torch.arange(w, device=dev).view(1, -1) // T
-        out.append((off + ys * tx + xs).reshape(-1))
-        off += tx * ((h + T - 1) // T)
-    return torch.cat(out)
 
 
 def cpu_baseline(scene, cams, n_pix):

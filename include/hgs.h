@@ -193,6 +193,9 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
  *                  values and ranges)
  *   ranges         device, uint32 [tiles_total][2] (out); a tile without
  *                  entries gets [0, 0)
+ *   tile_order     device, uint32 [tiles_total] (out), may be NULL: the tile
+ *                  ids by decreasing number of entries (ties by id), the
+ *                  order in which the persistent raster takes tiles
  *   overflow       device, int32 [1] (out): 0, or 1 when *n_dup > capacity;
  *                  then no entry is written and every range is empty
  *   workspace      device, hgs_workspace_bytes(HGS_WS_BIN_SORT, ...) bytes
@@ -202,21 +205,27 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
 int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint64_t* offsets,
                  const uint64_t* n_dup, int64_t n_rec, const hgs_camera* cams, int32_t n_cams,
                  const hgs_options* opts, uint64_t* keys, uint32_t* values, int64_t capacity,
-                 uint32_t* ranges, int32_t* overflow, void* workspace, size_t workspace_bytes,
-                 hipStream_t stream);
+                 uint32_t* ranges, uint32_t* tile_order, int32_t* overflow, void* workspace,
+                 size_t workspace_bytes, hipStream_t stream);
 
 /* Front-to-back blending of every pixel of every camera (Sec. 3.3, Eq. 10).
+ * With tile_order (from hgs_bin_sort) the raster runs as a persistent grid
+ * sized to the device whose wavefronts take (tile, pixel block) work items
+ * in that order from a counter in the workspace; with NULL, one workgroup
+ * per tile.  The outputs are identical either way.
  *   images     device, float [3][H][W] per camera, camera c at 3 * pixel
  *              offset c (out): blended colour + final transmittance * bg
  *   T_final    device, float per pixel (out)
- *   last_idx   device, int32 per pixel (out): position in `values` of the
- *              last blended entry, -1 if none
+ *   last_idx   device, int32 per pixel (out): index, within the pixel's
+ *              tile list (values[start .. end) of its tile), of the last
+ *              blended entry; -1 if none
  *   n_contrib  device, int32 per pixel (out): number of blended kernels
  *   workspace  device, hgs_workspace_bytes(HGS_WS_RENDER, ...) bytes */
 int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* ranges,
-                   const hgs_camera* cams, int32_t n_cams, const hgs_options* opts, float* images,
-                   float* T_final, int32_t* last_idx, int32_t* n_contrib, void* workspace,
-                   size_t workspace_bytes, hipStream_t stream);
+                   const uint32_t* tile_order, const hgs_camera* cams, int32_t n_cams,
+                   const hgs_options* opts, float* images, float* T_final, int32_t* last_idx,
+                   int32_t* n_contrib, void* workspace, size_t workspace_bytes,
+                   hipStream_t stream);
 
 /* Gradient of a scalar loss L given dL/d(image) (same layout as `images`).
  * Replays every pixel back to front from last_idx using T_final (no blend
@@ -231,7 +240,8 @@ int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* 
  * params, cams and opts must be those given to hgs_preprocess. */
 int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
                    const hgs_options* opts, const void* records, const uint32_t* values,
-                   const uint32_t* ranges, const float* T_final, const int32_t* last_idx,
+                   const uint32_t* ranges, const uint32_t* tile_order, const float* T_final,
+                   const int32_t* last_idx,
                    const float* dL_dimages, float* record_grads, const hgs_param_grads* grads,
                    void* workspace, size_t workspace_bytes, hipStream_t stream);
 
@@ -250,9 +260,10 @@ int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_c
  * parameter (summed over cameras, grads overwritten); clears record_grads
  * after reading it. */
 int hgs_raster_bwd(const void* records, const uint32_t* values, const uint32_t* ranges,
-                   const hgs_camera* cams, int32_t n_cams, const hgs_options* opts,
-                   const float* T_final, const int32_t* last_idx, const float* dL_dimages,
-                   float* record_grads, hipStream_t stream);
+                   const uint32_t* tile_order, const hgs_camera* cams, int32_t n_cams,
+                   const hgs_options* opts, const float* T_final, const int32_t* last_idx,
+                   const float* dL_dimages, float* record_grads, void* workspace,
+                   size_t workspace_bytes, hipStream_t stream);
 int hgs_preprocess_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
                        const hgs_options* opts, const void* records, float* record_grads,
                        const hgs_param_grads* grads, hipStream_t stream);

@@ -1,0 +1,214 @@
+"""Multi-view training step of the half-Gaussian rasterizer: all views in one
+call per stage, the persistent tile scheduler, HIP-graph capture of the whole
+forward + loss + backward step, and an autotuner for tile size and batch
+depth.
+
+Every view shares one preprocess launch (parameters read once), one sort (one
+global tile numbering) and one raster launch per direction.  A captured step
+replays with no host work at all; the entry capacity is fixed at capture, and
+an overflow (more entries than capacity, reported on the device) is detected
+after replay and answered by re-capturing with more room.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import binding as B
+from . import raster as R
+
+
+def _bytes(n, dev):
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=dev)
+
+
+class BatchedRasterizer:
+    """Forward + backward of one scene over many views with fixed buffers.
+
+    ``soa`` is the structure-of-arrays parameter tensor (see
+    ``raster.soa_from_natural``); ``cameras`` a list of camera dicts (at most
+    HGS_MAX_CAMERAS).  ``capacity`` bounds the number of (tile, kernel)
+    entries; by default it is measured once and given ``headroom``."""
+
+    def __init__(self, soa, n, sh_degree, cameras, tile=16, batch=256, capacity=None, headroom=1.25,
+                 persistent=True, full_keys=False):
+        self.dev = soa.device
+        self.soa, self.n, self.deg = soa, n, sh_degree
+        self.cameras = list(cameras)
+        self.cams = B.make_cameras(self.cameras)
+        self.opts = B.default_options(tile=tile, batch=batch, sort_full_keys=full_keys)
+        self.persistent = persistent
+        nc = len(self.cameras)
+        self.n_rec = n * nc
+        self.tiles_total = B.hgs_tiles_total(self.cams, self.opts)
+        self.npix = B.hgs_pixels_total(self.cams)
+        dev = self.dev
+        self.params = B.params_struct(soa, n, soa.shape[1], sh_degree)
+        self.records = _bytes(self.n_rec * B.HGS_RECORD_BYTES, dev)
+        self.tiles = torch.empty(max(self.n_rec, 1), dtype=torch.int32, device=dev)
+        self.offsets = torch.empty(max(self.n_rec, 1), dtype=torch.int64, device=dev)
+        self.n_dup = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ws_pre = _bytes(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, self.n_rec, self.cams, self.opts), dev)
+        self.ranges = torch.empty(max(2 * self.tiles_total, 1), dtype=torch.int32, device=dev)
+        self.order = torch.empty(max(self.tiles_total, 1), dtype=torch.int32, device=dev) if persistent else None
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.images = torch.empty(3 * self.npix, dtype=torch.float32, device=dev)
+        self.T_final = torch.empty(self.npix, dtype=torch.float32, device=dev)
+        self.last_idx = torch.empty(self.npix, dtype=torch.int32, device=dev)
+        self.n_contrib = torch.empty(self.npix, dtype=torch.int32, device=dev)
+        self.ws_r = _bytes(B.hgs_workspace_bytes(B.HGS_WS_RENDER, self.n_rec, self.cams, self.opts), dev)
+        self.rgrad = torch.zeros(max(self.n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
+        self.grads = torch.zeros_like(soa)
+        self.gstruct = B.grads_struct(self.grads, soa.shape[1])
+        self.dL = torch.zeros(3 * self.npix, dtype=torch.float32, device=dev)
+        self.graph = None
+        if capacity is None:
+            B.hgs_preprocess(self.params, self.cams, self.opts, self.records, self.tiles, self.offsets,
+                             self.n_dup, self.ws_pre, self._stream())
+            capacity = max(1, int(math.ceil(int(self.n_dup.item()) * headroom)))
+        self._alloc_entries(capacity)
+
+    @staticmethod
+    def _stream():
+        return torch.cuda.current_stream().cuda_stream
+
+    def _alloc_entries(self, capacity):
+        self.capacity = int(capacity)
+        full = bool(self.opts.flags & B.HGS_FLAG_SORT_FULL_KEYS)
+        self.keys = torch.empty(self.capacity, dtype=torch.int64, device=self.dev) if full else None
+        self.values = torch.empty(self.capacity, dtype=torch.int32, device=self.dev)
+        self.ws_sort = _bytes(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, self.n_rec, self.cams, self.opts,
+                                                    self.capacity), self.dev)
+
+    # -- stages ------------------------------------------------------------
+    def forward(self):
+        st = self._stream()
+        B.hgs_preprocess(self.params, self.cams, self.opts, self.records, self.tiles, self.offsets, self.n_dup,
+                         self.ws_pre, st)
+        B.hgs_bin_sort(self.records, self.tiles, self.offsets, self.n_dup, self.n_rec, self.cams, self.opts,
+                       self.keys, self.values, self.capacity, self.ranges, self.order, self.overflow,
+                       self.ws_sort, st)
+        B.hgs_render_fwd(self.records, self.values, self.ranges, self.order, self.cams, self.opts, self.images,
+                         self.T_final, self.last_idx, self.n_contrib, self.ws_r, st)
+
+    def backward(self):
+        st = self._stream()
+        B.hgs_raster_bwd(self.records, self.values, self.ranges, self.order, self.cams, self.opts, self.T_final,
+                         self.last_idx, self.dL, self.rgrad, self.ws_r, st)
+        B.hgs_preprocess_bwd(self.params, self.cams, self.opts, self.records, self.rgrad, self.gstruct, st)
+
+    def step(self, loss_grad):
+        """forward; loss_grad(images, dL) writes dL/dimages into dL; backward."""
+        self.forward()
+        loss_grad(self.images, self.dL)
+        self.backward()
+
+    # -- graph ---------------------------------------------------------------
+    def capture(self, loss_grad):
+        """Capture step(loss_grad) in a HIP graph (after two eager warm-ups on
+        a side stream)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                self.step(loss_grad)
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(loss_grad)
+        self.graph = g
+        self._loss_grad = loss_grad
+        return g
+
+    def replay(self, check=True):
+        """Replay the captured step; with ``check``, read the overflow flag and
+        re-capture with twice the capacity when the entries did not fit (the
+        step is then run again)."""
+        self.graph.replay()
+        if check and int(self.overflow.item()) != 0:
+            need = int(self.n_dup.item())
+            self._alloc_entries(max(2 * self.capacity, int(need * 1.25)))
+            self.capture(self._loss_grad)
+            self.graph.replay()
+            return True
+        return False
+
+    # -- views ---------------------------------------------------------------
+    def image(self, c):
+        off = sum(self.cameras[i]["width"] * self.cameras[i]["height"] for i in range(c))
+        w, h = self.cameras[c]["width"], self.cameras[c]["height"]
+        return self.images[3 * off:3 * (off + w * h)].view(3, h, w)
+
+
+def l1_loss_grad(target):
+    """dL/dimages of the mean L1 loss against ``target`` (packed like images)."""
+    inv = 1.0 / float(target.numel())
+
+    def fn(images, dL):
+        torch.sub(images, target, out=dL)
+        torch.sign(dL, out=dL)
+        dL.mul_(inv)
+    return fn
+
+
+def time_steps(run, steps=10, warmup=3):
+    """Average milliseconds of run() over ``steps`` after ``warmup``."""
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        run()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+# ---------------------------------------------------------------------------
+# autotuner
+# ---------------------------------------------------------------------------
+TILES = (8, 16, 32)
+BATCHES = (128, 256, 512)
+
+
+def shape_class(n, cameras):
+    """Cache key: kernel count and pixel count rounded to powers of two, and
+    the number of views (outputs never depend on the choice, only speed)."""
+    pix = sum(c["width"] * c["height"] for c in cameras)
+    return f"n{2 ** round(math.log2(max(n, 1)))}_p{2 ** round(math.log2(max(pix, 1)))}_v{len(cameras)}"
+
+
+def autotune(soa, n, sh_degree, cameras, target, cache_path=None, steps=5, warmup=2, tiles=TILES,
+             batches=BATCHES):
+    """Time the graph-captured step for every (tile, batch) and return the
+    fastest as (tile, batch, {config: ms}); results are cached per shape
+    class in ``cache_path`` (JSON)."""
+    key = shape_class(n, cameras)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            e = cache[key]
+            return e["tile"], e["batch"], e["ms"]
+    loss = l1_loss_grad(target)
+    ms = {}
+    for t in tiles:
+        for b in batches:
+            br = BatchedRasterizer(soa, n, sh_degree, cameras, tile=t, batch=b)
+            br.capture(loss)
+            ms[f"{t}x{b}"] = time_steps(lambda: br.graph.replay(), steps, warmup)
+            del br
+    best = min(ms, key=ms.get)
+    t, b = (int(x) for x in best.split("x"))
+    if cache_path:
+        cache[key] = {"tile": t, "batch": b, "ms": ms}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return t, b, ms

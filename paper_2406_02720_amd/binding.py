@@ -84,15 +84,16 @@ def load(path: str = LIB_PATH):
                                    vp, sz, vp]
     lib.hgs_preprocess.restype = C.c_int
     lib.hgs_bin_sort.argtypes = [vp, vp, vp, vp, i64, P(hgs_camera), i32, P(hgs_options), vp, vp, i64,
-                                 vp, vp, vp, sz, vp]
+                                 vp, vp, vp, vp, sz, vp]
     lib.hgs_bin_sort.restype = C.c_int
-    lib.hgs_render_fwd.argtypes = [vp, vp, vp, P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp, vp,
-                                   sz, vp]
+    lib.hgs_render_fwd.argtypes = [vp, vp, vp, vp, P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp,
+                                   vp, sz, vp]
     lib.hgs_render_fwd.restype = C.c_int
     lib.hgs_render_bwd.argtypes = [P(hgs_params), P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp,
-                                   vp, vp, vp, P(hgs_param_grads), vp, sz, vp]
+                                   vp, vp, vp, vp, P(hgs_param_grads), vp, sz, vp]
     lib.hgs_render_bwd.restype = C.c_int
-    lib.hgs_raster_bwd.argtypes = [vp, vp, vp, P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp, vp]
+    lib.hgs_raster_bwd.argtypes = [vp, vp, vp, vp, P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp,
+                                   vp, sz, vp]
     lib.hgs_raster_bwd.restype = C.c_int
     lib.hgs_preprocess_bwd.argtypes = [P(hgs_params), P(hgs_camera), i32, P(hgs_options), vp, vp,
                                        P(hgs_param_grads), vp]
@@ -182,29 +183,33 @@ def hgs_preprocess(params, cams, opts, records, tiles, offsets, n_dup, ws, strea
 
 
 def hgs_bin_sort(records, tiles, offsets, n_dup, n_rec, cams, opts, keys, values, capacity, ranges,
-                 overflow, ws, stream):
+                 tile_order, overflow, ws, stream):
     check(load().hgs_bin_sort(_ptr(records), _ptr(tiles), _ptr(offsets), _ptr(n_dup), n_rec, cams, len(cams),
-                              C.byref(opts), _ptr(keys), _ptr(values), capacity, _ptr(ranges), _ptr(overflow),
-                              _ptr(ws), ws.numel() * ws.element_size(), stream))
+                              C.byref(opts), _ptr(keys), _ptr(values), capacity, _ptr(ranges), _ptr(tile_order),
+                              _ptr(overflow), _ptr(ws), ws.numel() * ws.element_size(), stream))
 
 
-def hgs_render_fwd(records, values, ranges, cams, opts, images, T_final, last_idx, n_contrib, ws, stream):
-    check(load().hgs_render_fwd(_ptr(records), _ptr(values), _ptr(ranges), cams, len(cams), C.byref(opts),
+def hgs_render_fwd(records, values, ranges, tile_order, cams, opts, images, T_final, last_idx, n_contrib, ws,
+                   stream):
+    check(load().hgs_render_fwd(_ptr(records), _ptr(values), _ptr(ranges), _ptr(tile_order), cams, len(cams),
+                                C.byref(opts),
                                 _ptr(images), _ptr(T_final), _ptr(last_idx), _ptr(n_contrib), _ptr(ws),
                                 ws.numel() * ws.element_size(), stream))
 
 
-def hgs_render_bwd(params, cams, opts, records, values, ranges, T_final, last_idx, dL_dimages,
+def hgs_render_bwd(params, cams, opts, records, values, ranges, tile_order, T_final, last_idx, dL_dimages,
                    record_grads, grads, ws, stream):
     check(load().hgs_render_bwd(C.byref(params), cams, len(cams), C.byref(opts), _ptr(records), _ptr(values),
-                                _ptr(ranges), _ptr(T_final), _ptr(last_idx), _ptr(dL_dimages),
+                                _ptr(ranges), _ptr(tile_order), _ptr(T_final), _ptr(last_idx), _ptr(dL_dimages),
                                 _ptr(record_grads), C.byref(grads), _ptr(ws), ws.numel() * ws.element_size(),
                                 stream))
 
 
-def hgs_raster_bwd(records, values, ranges, cams, opts, T_final, last_idx, dL_dimages, record_grads, stream):
-    check(load().hgs_raster_bwd(_ptr(records), _ptr(values), _ptr(ranges), cams, len(cams), C.byref(opts),
-                                _ptr(T_final), _ptr(last_idx), _ptr(dL_dimages), _ptr(record_grads), stream))
+def hgs_raster_bwd(records, values, ranges, tile_order, cams, opts, T_final, last_idx, dL_dimages, record_grads,
+                   ws, stream):
+    check(load().hgs_raster_bwd(_ptr(records), _ptr(values), _ptr(ranges), _ptr(tile_order), cams, len(cams),
+                                C.byref(opts), _ptr(T_final), _ptr(last_idx), _ptr(dL_dimages),
+                                _ptr(record_grads), _ptr(ws), ws.numel() * ws.element_size(), stream))
 
 
 def hgs_preprocess_bwd(params, cams, opts, records, record_grads, grads, stream):

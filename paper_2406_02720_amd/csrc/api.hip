@@ -89,7 +89,7 @@ int make_params(const hgs_params* p, hgs::Params* out) {
   if (p->n > 0 && (!p->means || !p->scales || !p->quats || !p->normals || !p->opac1 || !p->opac2 ||
                    !p->sh))
     return fail(HGS_EINVAL, "a parameter pointer is null");
-  if (p->n > (int64_t)UINT32_MAX / HGS_MAX_CAMERAS) return fail(HGS_EINVAL, "n too large");
+  if (p->n > (int64_t)INT32_MAX / HGS_MAX_CAMERAS) return fail(HGS_EINVAL, "n too large");
   out->means = p->means;
   out->scales = p->scales;
   out->quats = p->quats;
@@ -145,7 +145,8 @@ size_t hgs_workspace_bytes(int32_t which, int64_t n_rec, const hgs_camera* cams,
       if (check_opts(opts) != HGS_OK || capacity < 0) return 0;
       hgs::CamPack cp;
       if (make_pack(cams, n_cams, opts, &cp) != HGS_OK) return 0;
-      return hgs::sort_workspace_bytes(n_rec, capacity, (opts->flags & HGS_FLAG_SORT_FULL_KEYS) != 0);
+      return hgs::sort_workspace_bytes(n_rec, capacity, (int64_t)cp.tiles_total,
+                                       (opts->flags & HGS_FLAG_SORT_FULL_KEYS) != 0);
     }
     case HGS_WS_RENDER:
       return hgs::render_workspace_bytes();
@@ -180,8 +181,8 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
 int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint64_t* offsets,
                  const uint64_t* n_dup, int64_t n_rec, const hgs_camera* cams, int32_t n_cams,
                  const hgs_options* opts, uint64_t* keys, uint32_t* values, int64_t capacity,
-                 uint32_t* ranges, int32_t* overflow, void* workspace, size_t workspace_bytes,
-                 hipStream_t stream) {
+                 uint32_t* ranges, uint32_t* tile_order, int32_t* overflow, void* workspace,
+                 size_t workspace_bytes, hipStream_t stream) {
   int e;
   if ((e = check_opts(opts)) != HGS_OK) return e;
   hgs::CamPack cp;
@@ -192,18 +193,19 @@ int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint6
   if (!n_dup || !ranges || !overflow || (n_rec > 0 && (!records || !tiles_touched || !offsets)) ||
       (capacity > 0 && (!values || (full_keys && !keys))))
     return fail(HGS_EINVAL, "a pointer is null");
-  const size_t need = hgs::sort_workspace_bytes(n_rec, capacity, full_keys);
+  const size_t need = hgs::sort_workspace_bytes(n_rec, capacity, (int64_t)cp.tiles_total, full_keys);
   if (!workspace || workspace_bytes < need)
     return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", need);
   hipError_t h = hgs::launch_bin_sort((const hgs::Record*)records, tiles_touched, offsets, n_dup,
                                       n_rec, n_rec / n_cams, cp, keys, values, capacity, ranges,
-                                      overflow, workspace, full_keys, stream);
+                                      tile_order, overflow, workspace, full_keys, stream);
   if (h != hipSuccess) return hip_fail(h, "bin_sort launch");
   return HGS_OK;
 }
 
 int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* ranges,
-                   const hgs_camera* cams, int32_t n_cams, const hgs_options* opts, float* images,
+                   const uint32_t* tile_order, const hgs_camera* cams, int32_t n_cams,
+                   const hgs_options* opts, float* images,
                    float* T_final, int32_t* last_idx, int32_t* n_contrib, void* workspace,
                    size_t workspace_bytes, hipStream_t stream) {
   int e;
@@ -215,25 +217,28 @@ int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* 
   if (!workspace || workspace_bytes < hgs::render_workspace_bytes())
     return fail(HGS_ECAPACITY, "workspace too small");
   const hgs::Opts o = hgs::to_opts(*opts);
-  hipError_t h = hgs::launch_render_fwd((const hgs::Record*)records, values, ranges, cp, o, images,
-                                        T_final, last_idx, n_contrib, workspace, stream);
+  hipError_t h = hgs::launch_render_fwd((const hgs::Record*)records, values, ranges, tile_order, cp, o,
+                                        images, T_final, last_idx, n_contrib, workspace, stream);
   if (h != hipSuccess) return hip_fail(h, "render_fwd launch");
   return HGS_OK;
 }
 
 int hgs_raster_bwd(const void* records, const uint32_t* values, const uint32_t* ranges,
-                   const hgs_camera* cams, int32_t n_cams, const hgs_options* opts,
-                   const float* T_final, const int32_t* last_idx, const float* dL_dimages,
-                   float* record_grads, hipStream_t stream) {
+                   const uint32_t* tile_order, const hgs_camera* cams, int32_t n_cams,
+                   const hgs_options* opts, const float* T_final, const int32_t* last_idx,
+                   const float* dL_dimages, float* record_grads, void* workspace,
+                   size_t workspace_bytes, hipStream_t stream) {
   int e;
   if ((e = check_opts(opts)) != HGS_OK) return e;
   hgs::CamPack cp;
   if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
   if (!ranges || !T_final || !last_idx || !dL_dimages || !record_grads)
     return fail(HGS_EINVAL, "a pointer is null");
+  if (!workspace || workspace_bytes < hgs::render_workspace_bytes())
+    return fail(HGS_ECAPACITY, "workspace too small");
   const hgs::Opts o = hgs::to_opts(*opts);
-  hipError_t h = hgs::launch_render_bwd((const hgs::Record*)records, values, ranges, cp, o, T_final,
-                                        last_idx, dL_dimages, record_grads, stream);
+  hipError_t h = hgs::launch_render_bwd((const hgs::Record*)records, values, ranges, tile_order, cp, o,
+                                        T_final, last_idx, dL_dimages, record_grads, workspace, stream);
   if (h != hipSuccess) return hip_fail(h, "raster_bwd launch");
   return HGS_OK;
 }
@@ -261,7 +266,8 @@ int hgs_preprocess_bwd(const hgs_params* params, const hgs_camera* cams, int32_t
 
 int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
                    const hgs_options* opts, const void* records, const uint32_t* values,
-                   const uint32_t* ranges, const float* T_final, const int32_t* last_idx,
+                   const uint32_t* ranges, const uint32_t* tile_order, const float* T_final,
+                   const int32_t* last_idx,
                    const float* dL_dimages, float* record_grads, const hgs_param_grads* grads,
                    void* workspace, size_t workspace_bytes, hipStream_t stream) {
   int e;
@@ -275,8 +281,8 @@ int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_c
   if (p.n > 0 && !record_grads) return fail(HGS_EINVAL, "record_grads is null");
   hipError_t h = hgs::launch_zero_f32(record_grads, p.n * n_cams * HGS_RECORD_GRAD_FLOATS, stream);
   if (h != hipSuccess) return hip_fail(h, "clear launch");
-  if ((e = hgs_raster_bwd(records, values, ranges, cams, n_cams, opts, T_final, last_idx, dL_dimages,
-                          record_grads, stream)) != HGS_OK)
+  if ((e = hgs_raster_bwd(records, values, ranges, tile_order, cams, n_cams, opts, T_final, last_idx,
+                          dL_dimages, record_grads, workspace, workspace_bytes, stream)) != HGS_OK)
     return e;
   return hgs_preprocess_bwd(params, cams, n_cams, opts, records, record_grads, grads, stream);
 }

@@ -110,21 +110,24 @@ size_t scan_workspace_bytes(int64_t n);
 hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint64_t* total,
                        void* ws, hipStream_t s);
 int tile_bits(uint32_t tiles_total);
-size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, bool full_keys);
+size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, int64_t n_tiles, bool full_keys);
 hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint64_t* offsets,
                            const uint64_t* n_dup, int64_t n_rec, int64_t n_per_cam,
                            const CamPack& cp, uint64_t* keys, uint32_t* vals, int64_t capacity,
-                           uint32_t* ranges, int32_t* overflow, void* ws, bool full_keys,
-                           hipStream_t s);
+                           uint32_t* ranges, uint32_t* tile_order, int32_t* overflow, void* ws,
+                           bool full_keys, hipStream_t s);
 size_t render_workspace_bytes();
+// tile_order non-null selects the persistent raster (workspace holds its
+// work counters: [0] forward, [1] backward)
 hipError_t launch_render_fwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
-                             const CamPack& cp, const Opts& o, float* img, float* T_final,
-                             int32_t* last_idx, int32_t* n_contrib, void* ws, hipStream_t s);
+                             const uint32_t* tile_order, const CamPack& cp, const Opts& o,
+                             float* img, float* T_final, int32_t* last_idx, int32_t* n_contrib,
+                             void* ws, hipStream_t s);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t s);
 hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
-                             const CamPack& cp, const Opts& o, const float* T_final,
-                             const int32_t* last_idx, const float* dL_dimg, float* rec_grads,
-                             hipStream_t s);
+                             const uint32_t* tile_order, const CamPack& cp, const Opts& o,
+                             const float* T_final, const int32_t* last_idx, const float* dL_dimg,
+                             float* rec_grads, void* ws, hipStream_t s);
 hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o,
                                  const Record* rec, float* rec_grads, const Grads& g,
                                  hipStream_t s);

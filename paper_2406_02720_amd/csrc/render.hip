@@ -133,15 +133,16 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// One wavefront's block of pixels (sub-block `wave` of `tile`), front to back.
 template <int T, int IPL>
-__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
+__device__ __forceinline__ void fwd_block(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, CamPack cp, Opts o, float* __restrict__ img,
-    float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib) {
+    const uint32_t* __restrict__ ranges, const CamPack& cp, const Opts& o, float* __restrict__ img,
+    float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib,
+    uint32_t tile, int wave, int lane) {
   using Gm = Geometry<T>;
   constexpr int PPL = Gm::PPL;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t tile = blockIdx.x;
+  if (tile >= cp.tiles_total) return;  // never index past the tile arrays
   const int c = cam_of_tile(cp, tile);
   const CamDev& cam = cp.cam[c];
   const uint32_t lt = tile - cam.tile_off;
@@ -165,10 +166,13 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
     last[j] = -1;
     done[j] = !inside[j];
   }
-  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  // the tile's list; positions below are indices into it (fit int32: a
+  // list holds at most one entry per record)
+  const uint32_t* __restrict__ lst = vals + ranges[2 * tile];
+  const int64_t len = (int64_t)ranges[2 * tile + 1] - (int64_t)ranges[2 * tile];
   const float amin = o.alpha_min, amax = o.alpha_max, tmin = o.t_min;
 
-  for (uint32_t base = start; base < end; base += 64 * IPL) {
+  for (int64_t base = 0; base < len; base += 64 * IPL) {
     bool any = false;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) any |= !done[j];
@@ -176,10 +180,10 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
     uint32_t ids[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-      const uint32_t p = base + k * 64 + lane;
-      ids[k] = p < end ? vals[p] : 0u;
+      const int64_t p = base + k * 64 + lane;
+      ids[k] = p < len ? lst[p] : 0u;
     }
-    const uint32_t nb = (end - base) < (uint32_t)(64 * IPL) ? (end - base) : (uint32_t)(64 * IPL);
+    const int64_t nb = (len - base) < (int64_t)(64 * IPL) ? (len - base) : (int64_t)(64 * IPL);
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       const int lim = (int)nb - k * 64;
@@ -227,16 +231,49 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
   }
 }
 
+// Next work item of a persistent wavefront: (tile of rank w in `order`, sub-block).
+__device__ __forceinline__ uint32_t next_work(uint32_t* counter, int lane) {
+  uint32_t w = 0;
+  if (lane == 0) w = atomicAdd(counter, 1u);
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)w);
+}
+
 template <int T, int IPL>
-__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
+__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, CamPack cp, Opts o, const float* __restrict__ T_final,
-    const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimg,
-    float* __restrict__ rgrad) {
+    const uint32_t* __restrict__ ranges, CamPack cp, Opts o, float* __restrict__ img,
+    float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib) {
+  fwd_block<T, IPL>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, blockIdx.x,
+                    threadIdx.x >> 6, threadIdx.x & 63);
+}
+
+// Persistent form: one wavefront per workgroup, a grid sized to the chip;
+// every wavefront takes work items (tile rank, sub-block) from a counter,
+// tiles in `order` (longest list first) so that long tiles do not start last.
+template <int T, int IPL>
+__global__ __launch_bounds__(64) void render_fwd_persistent_kernel(
+    const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
+    float* __restrict__ img, float* __restrict__ T_final, int32_t* __restrict__ last_idx,
+    int32_t* __restrict__ n_contrib, uint32_t* __restrict__ counter) {
+  constexpr uint32_t WAVES = Geometry<T>::WAVES;
+  const uint32_t n_work = cp.tiles_total * WAVES;
+  const int lane = threadIdx.x & 63;
+  for (uint32_t w = next_work(counter, lane); w < n_work; w = next_work(counter, lane))
+    fwd_block<T, IPL>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, order[w / WAVES],
+                      (int)(w % WAVES), lane);
+}
+
+// One wavefront's block of pixels, back to front.
+template <int T, int IPL>
+__device__ __forceinline__ void bwd_block(
+    const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, const CamPack& cp, const Opts& o,
+    const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,
+    const float* __restrict__ dL_dimg, float* __restrict__ rgrad, uint32_t tile, int wave, int lane) {
   using Gm = Geometry<T>;
   constexpr int PPL = Gm::PPL;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t tile = blockIdx.x;
+  if (tile >= cp.tiles_total) return;  // never index past the tile arrays
   const int c = cam_of_tile(cp, tile);
   const CamDev& cam = cp.cam[c];
   const uint32_t lt = tile - cam.tile_off;
@@ -275,19 +312,19 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
     top = last[j] > top ? last[j] : top;
   }
   top = wave_max(top);
-  const int32_t start = (int32_t)ranges[2 * tile];
-  if (top < start) return;
+  if (top < 0) return;
+  const uint32_t* __restrict__ lst = vals + ranges[2 * tile];
   const float amin = o.alpha_min, amax = o.alpha_max;
 
-  // entries top, top-1, ..., start in rounds of 64 * IPL
-  for (int32_t hi = top; hi >= start; hi -= 64 * IPL) {
+  // list indices top, top-1, ..., 0 in rounds of 64 * IPL
+  for (int32_t hi = top; hi >= 0; hi -= 64 * IPL) {
     uint32_t ids[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       const int32_t p = hi - (k * 64 + lane);
-      ids[k] = p >= start ? vals[p] : 0u;
+      ids[k] = p >= 0 ? lst[p] : 0u;
     }
-    const int32_t nb = (hi - start + 1) < 64 * IPL ? (hi - start + 1) : 64 * IPL;
+    const int32_t nb = (hi + 1) < 64 * IPL ? (hi + 1) : 64 * IPL;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       const int lim = nb - k * 64;
@@ -357,27 +394,85 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
   }
 }
 
+template <int T, int IPL>
+__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
+    const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, CamPack cp, Opts o, const float* __restrict__ T_final,
+    const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimg,
+    float* __restrict__ rgrad) {
+  bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, blockIdx.x,
+                    threadIdx.x >> 6, threadIdx.x & 63);
+}
+
+template <int T, int IPL>
+__global__ __launch_bounds__(64) void render_bwd_persistent_kernel(
+    const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
+    const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,
+    const float* __restrict__ dL_dimg, float* __restrict__ rgrad, uint32_t* __restrict__ counter) {
+  constexpr uint32_t WAVES = Geometry<T>::WAVES;
+  const uint32_t n_work = cp.tiles_total * WAVES;
+  const int lane = threadIdx.x & 63;
+  for (uint32_t w = next_work(counter, lane); w < n_work; w = next_work(counter, lane))
+    bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, order[w / WAVES],
+                      (int)(w % WAVES), lane);
+}
+
+__global__ void clear_counter_kernel(uint32_t* __restrict__ p) { *p = 0u; }
+
 __global__ void zero_f32_kernel(float* __restrict__ p, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = t; i < n; i += stride) p[i] = 0.0f;
 }
 
+// Workgroups of the persistent grid: as many one-wavefront workgroups as
+// the chip keeps resident, never more than there are work items.
+template <typename F>
+unsigned persistent_grid(F kernel, uint32_t n_work) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || per_cu < 1)
+    per_cu = 8;
+  const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
+  return (unsigned)(g < n_work ? g : (n_work > 0 ? n_work : 1));
+}
+
 template <int T, int B>
 hipError_t fwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
-                      const CamPack& cp, const Opts& o, float* img, float* Tf, int32_t* li,
-                      int32_t* nc, hipStream_t s) {
-  hipLaunchKernelGGL((render_fwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
-                     0, s, rec, vals, ranges, cp, o, img, Tf, li, nc);
+                      const uint32_t* order, const CamPack& cp, const Opts& o, float* img, float* Tf,
+                      int32_t* li, int32_t* nc, void* ws, hipStream_t s) {
+  if (order) {
+    uint32_t* counter = static_cast<uint32_t*>(ws);
+    hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    const uint32_t n_work = cp.tiles_total * Geometry<T>::WAVES;
+    hipLaunchKernelGGL((render_fwd_persistent_kernel<T, B / 64>),
+                       dim3(persistent_grid(render_fwd_persistent_kernel<T, B / 64>, n_work)), dim3(64), 0,
+                       s, rec, vals, ranges, order, cp, o, img, Tf, li, nc, counter);
+  } else {
+    hipLaunchKernelGGL((render_fwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
+                       0, s, rec, vals, ranges, cp, o, img, Tf, li, nc);
+  }
   return hipGetLastError();
 }
 
 template <int T, int B>
 hipError_t bwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
-                      const CamPack& cp, const Opts& o, const float* Tf, const int32_t* li,
-                      const float* dL, float* rg, hipStream_t s) {
-  hipLaunchKernelGGL((render_bwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
-                     0, s, rec, vals, ranges, cp, o, Tf, li, dL, rg);
+                      const uint32_t* order, const CamPack& cp, const Opts& o, const float* Tf,
+                      const int32_t* li, const float* dL, float* rg, void* ws, hipStream_t s) {
+  if (order) {
+    uint32_t* counter = static_cast<uint32_t*>(ws) + 1;
+    hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    const uint32_t n_work = cp.tiles_total * Geometry<T>::WAVES;
+    hipLaunchKernelGGL((render_bwd_persistent_kernel<T, B / 64>),
+                       dim3(persistent_grid(render_bwd_persistent_kernel<T, B / 64>, n_work)), dim3(64), 0,
+                       s, rec, vals, ranges, order, cp, o, Tf, li, dL, rg, counter);
+  } else {
+    hipLaunchKernelGGL((render_bwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
+                       0, s, rec, vals, ranges, cp, o, Tf, li, dL, rg);
+  }
   return hipGetLastError();
 }
 
@@ -389,11 +484,11 @@ hipError_t bwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* r
 size_t render_workspace_bytes() { return 256; }
 
 hipError_t launch_render_fwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
-                             const CamPack& cp, const Opts& o, float* img, float* T_final,
-                             int32_t* last_idx, int32_t* n_contrib, void* ws, hipStream_t s) {
-  (void)ws;
+                             const uint32_t* tile_order, const CamPack& cp, const Opts& o,
+                             float* img, float* T_final, int32_t* last_idx, int32_t* n_contrib,
+                             void* ws, hipStream_t s) {
   if (cp.tiles_total == 0) return hipSuccess;
-#define ARGS (rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, s)
+#define ARGS (rec, vals, ranges, tile_order, cp, o, img, T_final, last_idx, n_contrib, ws, s)
   HGS_DISPATCH(8, 128, fwd_launch) ARGS;
   HGS_DISPATCH(8, 256, fwd_launch) ARGS;
   HGS_DISPATCH(8, 512, fwd_launch) ARGS;
@@ -416,11 +511,11 @@ hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
-                             const CamPack& cp, const Opts& o, const float* T_final,
-                             const int32_t* last_idx, const float* dL_dimg, float* rec_grads,
-                             hipStream_t s) {
+                             const uint32_t* tile_order, const CamPack& cp, const Opts& o,
+                             const float* T_final, const int32_t* last_idx, const float* dL_dimg,
+                             float* rec_grads, void* ws, hipStream_t s) {
   if (cp.tiles_total == 0) return hipSuccess;
-#define ARGS (rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rec_grads, s)
+#define ARGS (rec, vals, ranges, tile_order, cp, o, T_final, last_idx, dL_dimg, rec_grads, ws, s)
   HGS_DISPATCH(8, 128, bwd_launch) ARGS;
   HGS_DISPATCH(8, 256, bwd_launch) ARGS;
   HGS_DISPATCH(8, 512, bwd_launch) ARGS;

@@ -100,14 +100,17 @@ __device__ __forceinline__ void flush_hist(const uint32_t* s_h, int words, uint3
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void sort_init_kernel(uint32_t* __restrict__ hist,
-                                                           uint32_t* __restrict__ tickets,
-                                                           uint64_t* __restrict__ lookback0,
-                                                           int64_t lookback_words) {
+                                                           uint32_t* __restrict__ tickets) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = t; i < (int64_t)kHistCopies * kHistWords; i += stride) hist[i] = 0u;
   for (int64_t i = t; i < 2 * kMaxPasses; i += stride) tickets[i] = 0u;
-  for (int64_t i = t; i < lookback_words; i += stride) lookback0[i] = 0ull;
+}
+
+__global__ __launch_bounds__(kBlock) void zero_u64_kernel(uint64_t* __restrict__ p, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = t; i < n; i += stride) p[i] = 0ull;
 }
 
 __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -459,6 +462,34 @@ __global__ __launch_bounds__(kBlock) void ranges_kernel(const K* __restrict__ ke
     ranges[2 * (uint64_t)tile + 1] = (uint32_t)(i + 1);
 }
 
+// Processing order of the tiles, longest list first: 16-bit key
+// 0xffff - min(length, 0xffff), value = tile id, and the histograms of its
+// two digits.
+__global__ __launch_bounds__(kBlock) void order_keys_kernel(const uint32_t* __restrict__ ranges,
+                                                            int64_t n_tiles, uint32_t* __restrict__ keys,
+                                                            uint32_t* __restrict__ ids,
+                                                            uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[2 * kRadix];
+  for (int i = threadIdx.x; i < 2 * kRadix; i += kBlock) s_h[i] = 0u;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n_tiles; base += stride) {
+    const int64_t t = base + threadIdx.x;
+    const bool ok = t < n_tiles;
+    uint32_t k = 0;
+    if (ok) {
+      const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+      k = 0xffffu - (len < 0xffffu ? len : 0xffffu);
+      keys[t] = k;
+      ids[t] = (uint32_t)t;
+    }
+    wave_hist_add(s_h, k & 0xffu, ok);
+    wave_hist_add(s_h + kRadix, (k >> 8) & 0xffu, ok);
+  }
+  __syncthreads();
+  flush_hist(s_h, 2 * kRadix, hist);
+}
+
 // 64-bit keys of the depth-first path, when the caller asks for them.
 __global__ __launch_bounds__(kBlock) void compose_keys_kernel(const uint32_t* __restrict__ tile_keys,
                                                               const uint32_t* __restrict__ vals,
@@ -487,6 +518,8 @@ struct SortWs {
   uint64_t* alt_keys64;
   uint32_t* alt_vals;
   uint32_t* chunk_start;
+  uint32_t* okeys[2];  // tile order sort
+  uint32_t* oalt;
   uint32_t* hist;      // [kHistCopies][2][kMaxPasses][256]: record passes, entry passes
   uint32_t* bases;     // [2][kMaxPasses][256] scanned
   uint32_t* tickets;   // [2][kMaxPasses]
@@ -495,9 +528,10 @@ struct SortWs {
   size_t bytes;
 };
 
-SortWs carve(void* ws, int64_t n_rec, int64_t capacity, bool full_keys) {
+SortWs carve(void* ws, int64_t n_rec, int64_t capacity, int64_t n_tiles, bool full_keys) {
   SortWs w{};
-  const int64_t m = capacity > n_rec ? capacity : n_rec;
+  int64_t m = capacity > n_rec ? capacity : n_rec;
+  m = m > n_tiles ? m : n_tiles;
   const int64_t parts = (m + kPartMin - 1) / kPartMin;
   w.parts = parts > 0 ? parts : 1;
   const size_t nr = (size_t)(n_rec > 0 ? n_rec : 1), cap = (size_t)(capacity > 0 ? capacity : 1);
@@ -520,6 +554,9 @@ SortWs carve(void* ws, int64_t n_rec, int64_t capacity, bool full_keys) {
   }
   w.alt_vals = (uint32_t*)take(cap * 4);
   w.chunk_start = (uint32_t*)take((cap + kChunk - 1) / kChunk * 4 + 4);
+  const size_t nt = (size_t)(n_tiles > 0 ? n_tiles : 1);
+  for (int b = 0; b < 2; ++b) w.okeys[b] = (uint32_t*)take(nt * 4);
+  w.oalt = (uint32_t*)take(nt * 4);
   w.hist = (uint32_t*)take((size_t)kHistCopies * kHistWords * 4);
   w.bases = (uint32_t*)take((size_t)kHistWords * 4);
   w.tickets = (uint32_t*)take((size_t)2 * kMaxPasses * 4);
@@ -533,12 +570,21 @@ unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
   return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+// The passes of one sort phase (same key count bound `cap`, so every pass has
+// the same number of partitions).  A pass reads look-back buffer lb and
+// clears the other one over its partitions for the next pass; the first
+// buffer is cleared here over the phase's partition bound, so no state from
+// an earlier phase (with a different partition count) survives.
 template <typename K>
 void onesweep_passes(K** kb, uint32_t** vb, const uint64_t* n_dev, int64_t cap, int first_shift,
                      int passes, const uint32_t* bases, SortWs& w, uint32_t* tickets, int& lb,
                      hipStream_t s) {
   constexpr int PART = kBlock * SweepItems<K>::value;
-  const unsigned grid = (unsigned)((cap + PART - 1) / PART > 0 ? (cap + PART - 1) / PART : 1);
+  const int64_t parts = (cap + PART - 1) / PART > 0 ? (cap + PART - 1) / PART : 1;
+  const unsigned grid = (unsigned)parts;
+  if (passes <= 0) return;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_for(parts * kRadix, kBlock, 4096)), dim3(kBlock), 0, s,
+                     w.lookback[lb & 1], parts * kRadix);
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(onesweep_kernel<K>, dim3(grid), dim3(kBlock), 0, s, kb[p & 1], vb[p & 1],
                        kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, cap, first_shift + 8 * p,
@@ -555,25 +601,24 @@ int tile_bits(uint32_t tiles_total) {
   return tb;
 }
 
-size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, bool full_keys) {
-  return carve(nullptr, n_rec, capacity, full_keys).bytes;
+size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, int64_t n_tiles, bool full_keys) {
+  return carve(nullptr, n_rec, capacity, n_tiles, full_keys).bytes;
 }
 
 hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint64_t* offsets,
                            const uint64_t* n_dup, int64_t n_rec, int64_t n_per_cam,
                            const CamPack& cp, uint64_t* keys, uint32_t* vals, int64_t capacity,
-                           uint32_t* ranges, int32_t* overflow, void* ws, bool full_keys,
-                           hipStream_t s) {
-  SortWs w = carve(ws, n_rec, capacity, full_keys);
+                           uint32_t* ranges, uint32_t* tile_order, int32_t* overflow, void* ws,
+                           bool full_keys, hipStream_t s) {
+  SortWs w = carve(ws, n_rec, capacity, (int64_t)cp.tiles_total, full_keys);
   const int tb = tile_bits(cp.tiles_total);
   uint32_t* hist_rec = w.hist;                       // replica 0; replicas follow
   uint32_t* hist_ent = w.hist + kMaxPasses * kRadix;
   uint32_t* base_rec = w.bases;
   uint32_t* base_ent = w.bases + kMaxPasses * kRadix;
   int lb = 0;  // look-back buffer in use
-  hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(w.parts * kRadix + kHistCopies * kHistWords, kBlock, 4096)),
-                     dim3(kBlock), 0, s,
-                     w.hist, w.tickets, w.lookback[0], w.parts * kRadix);
+  hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(kHistCopies * kHistWords, kBlock, 4096)), dim3(kBlock),
+                     0, s, w.hist, w.tickets);
   const unsigned dup_grid = grid_for((capacity + kChunk - 1) / kChunk, kWaves, 1 << 30);
 
   if (full_keys) {
@@ -597,6 +642,11 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
     onesweep_passes<uint64_t>(kb, vb, n_dup, capacity, 0, passes, base_ent, w, w.tickets + kMaxPasses,
                               lb, s);
+    const int64_t nr = 2 * (int64_t)cp.tiles_total;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nr, kBlock, 4096)), dim3(kBlock), 0, s, ranges, nr, 0u);
+    if (capacity > 0)
+      hipLaunchKernelGGL(ranges_kernel<uint64_t>, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock),
+                         0, s, keys, 32, n_dup, capacity, ranges);
   } else {
     // 1. records in (depth, id) order
     hipLaunchKernelGGL(depth_keys_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s, rec,
@@ -643,13 +693,18 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
         hipLaunchKernelGGL(compose_keys_kernel, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock),
                            0, s, tkeys, vals, rec, n_dup, capacity, keys);
     }
-    return hipGetLastError();
   }
-  const int64_t nr = 2 * (int64_t)cp.tiles_total;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nr, kBlock, 4096)), dim3(kBlock), 0, s, ranges, nr, 0u);
-  if (capacity > 0)
-    hipLaunchKernelGGL(ranges_kernel<uint64_t>, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock), 0,
-                       s, keys, 32, n_dup, capacity, ranges);
+  // 6. tiles by decreasing list length, for the persistent raster
+  if (tile_order) {
+    const int64_t nt = (int64_t)cp.tiles_total;
+    uint32_t* ob[2] = {w.okeys[0], w.okeys[1]};
+    uint32_t* ov[2] = {tile_order, w.oalt};  // two passes: the order lands in tile_order
+    hipLaunchKernelGGL(order_keys_kernel, dim3(grid_for(nt, kBlock, 1024)), dim3(kBlock), 0, s, ranges, nt,
+                       ob[0], ov[0], hist_rec + 4 * kRadix);
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec + 4 * kRadix,
+                       base_rec + 4 * kRadix, 2);
+    onesweep_passes<uint32_t>(ob, ov, nullptr, nt, 0, 2, base_rec + 4 * kRadix, w, w.tickets + 4, lb, s);
+  }
   return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ class Frame:
     n_contrib: torch.Tensor
     capacity: int
     ws_render: torch.Tensor
+    tile_order: torch.Tensor | None = None
 
     def image(self, c: int) -> torch.Tensor:
         """[3,H,W] view of camera c's image."""
@@ -92,12 +93,16 @@ def _bytes(n: int, device) -> torch.Tensor:
     return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
 
 
-def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity: int | None = None) -> Frame:
+def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity: int | None = None,
+                 persistent: bool = True, keys: bool = True) -> Frame:
     """Run the forward rasterizer.  ``cams`` is a C camera array from
     ``binding.make_cameras``; ``opts`` an ``hgs_options``.  With
     ``capacity`` None the entry count is read back (one synchronisation) and
     the key buffers are sized exactly; otherwise they have ``capacity``
-    entries and an overflow is reported in ``frame.overflow``."""
+    entries and an overflow is reported in ``frame.overflow``.  With
+    ``persistent`` the raster takes tiles longest-list first from a
+    persistent grid; ``keys`` False skips the 64-bit sort keys (the raster
+    does not need them)."""
     dev = soa.device
     nc = len(cams)
     n_rec = n * nc
@@ -112,22 +117,25 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
     if capacity is None:
         capacity = int(n_dup.item())
     tiles_total = B.hgs_tiles_total(cams, opts)
-    keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+    full = bool(opts.flags & B.HGS_FLAG_SORT_FULL_KEYS)
+    keys_t = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev) if (keys or full) else None
     values = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
     ranges = torch.empty(max(2 * tiles_total, 1), dtype=torch.int32, device=dev)
+    order = torch.empty(max(tiles_total, 1), dtype=torch.int32, device=dev) if persistent else None
     overflow = torch.zeros(1, dtype=torch.int32, device=dev)
     ws_sort = _bytes(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, cams, opts, capacity), dev)
-    B.hgs_bin_sort(records, tiles, offsets, n_dup, n_rec, cams, opts, keys, values, capacity, ranges,
-                   overflow, ws_sort, stream)
+    B.hgs_bin_sort(records, tiles, offsets, n_dup, n_rec, cams, opts, keys_t, values, capacity, ranges,
+                   order, overflow, ws_sort, stream)
     npix = B.hgs_pixels_total(cams)
     images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
     T_final = torch.empty(npix, dtype=torch.float32, device=dev)
     last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
     n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
     ws_r = _bytes(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), dev)
-    B.hgs_render_fwd(records, values, ranges, cams, opts, images, T_final, last_idx, n_contrib, ws_r, stream)
-    return Frame(soa, n, sh_degree, cams, opts, records, tiles, offsets, n_dup, keys, values, ranges,
-                 overflow, images, T_final, last_idx, n_contrib, capacity, ws_r)
+    B.hgs_render_fwd(records, values, ranges, order, cams, opts, images, T_final, last_idx, n_contrib, ws_r,
+                     stream)
+    return Frame(soa, n, sh_degree, cams, opts, records, tiles, offsets, n_dup, keys_t, values, ranges,
+                 overflow, images, T_final, last_idx, n_contrib, capacity, ws_r, order)
 
 
 def backward_pass(fr: Frame, dL_dimages: torch.Tensor, record_grads: torch.Tensor | None = None,
@@ -142,8 +150,8 @@ def backward_pass(fr: Frame, dL_dimages: torch.Tensor, record_grads: torch.Tenso
         grads = torch.zeros_like(fr.soa)
     params = B.params_struct(fr.soa, fr.n, fr.soa.shape[1], fr.sh_degree)
     gs = B.grads_struct(grads, fr.soa.shape[1])
-    B.hgs_render_bwd(params, fr.cams, fr.opts, fr.records, fr.values, fr.ranges, fr.T_final, fr.last_idx,
-                     dL_dimages, record_grads, gs, fr.ws_render, _stream())
+    B.hgs_render_bwd(params, fr.cams, fr.opts, fr.records, fr.values, fr.ranges, fr.tile_order, fr.T_final,
+                     fr.last_idx, dL_dimages, record_grads, gs, fr.ws_render, _stream())
     return grads, record_grads
 
 

@@ -35,11 +35,11 @@ def split_opts(kw):
     return gpu, O.options(**orc)
 
 
-def gpu_forward(scene, cams, capacity=None, **kw):
+def gpu_forward(scene, cams, capacity=None, persistent=True, **kw):
     gkw, _ = split_opts(kw)
     soa = R.scene_to_soa(scene)
     fr = R.forward_pass(soa, scene["means"].shape[0], scene["sh_degree"], B.make_cameras(cams),
-                        B.default_options(**gkw), capacity=capacity)
+                        B.default_options(**gkw), capacity=capacity, persistent=persistent)
     torch.cuda.synchronize()
     return fr
 

@@ -1,0 +1,76 @@
+"""Multi-view batching: HIP-graph capture of the whole forward + loss +
+backward step, overflow handling, the autotuner."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2406_02720_amd import batch as BT
+from paper_2406_02720_amd import raster as R
+from paper_2406_02720_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(n=5000, n_cams=3):
+    scene, cams = scenes.make_config(4, n=n, n_cams=n_cams)
+    cams = [scenes.pinhole(w, h, c["R"], c["t"]) for c, (w, h) in zip(cams, ((160, 120), (129, 84), (200, 106)))]
+    return scene, cams
+
+
+def _target(cams):
+    return torch.cat([torch.as_tensor(t).reshape(-1) for t in scenes.target_image(cams)]).cuda()
+
+
+def test_graph_replays_match_eager_steps():
+    scene, cams = _scene()
+    soa = R.scene_to_soa(scene)
+    target = _target(cams)
+    loss = BT.l1_loss_grad(target)
+    eager = BT.BatchedRasterizer(soa, scene["means"].shape[0], scene["sh_degree"], cams)
+    eager.step(loss)
+    torch.cuda.synchronize()
+    img_ref, g_ref = eager.images.clone(), eager.grads.clone()
+    br = BT.BatchedRasterizer(soa, scene["means"].shape[0], scene["sh_degree"], cams)
+    br.capture(loss)
+    for rep in range(3):
+        br.images.zero_()
+        br.grads.zero_()
+        assert not br.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(br.images, img_ref), rep
+        assert torch.allclose(br.grads, g_ref, rtol=1e-4, atol=1e-7), rep
+        # unrelated eager work between replays
+        eager.step(loss)
+        torch.cuda.synchronize()
+    assert torch.equal(br.image(1), img_ref[3 * 160 * 120:3 * (160 * 120 + 129 * 84)].view(3, 84, 129))
+
+
+def test_graph_overflow_recaptures_with_more_room():
+    scene, cams = _scene(n=3000)
+    soa = R.scene_to_soa(scene)
+    loss = BT.l1_loss_grad(_target(cams))
+    ref = BT.BatchedRasterizer(soa, 3000, scene["sh_degree"], cams)
+    ref.step(loss)
+    br = BT.BatchedRasterizer(soa, 3000, scene["sh_degree"], cams, capacity=64)
+    br.capture(loss)
+    assert br.replay()                       # overflowed, re-captured and rerun
+    torch.cuda.synchronize()
+    assert br.capacity >= int(ref.n_dup.item())
+    assert int(br.overflow.item()) == 0
+    assert torch.equal(br.images, ref.images)
+    assert not br.replay()
+
+
+def test_autotune_returns_a_valid_config_and_caches(tmp_path):
+    scene, cams = _scene(n=2000, n_cams=2)
+    soa = R.scene_to_soa(scene)
+    path = tmp_path / "tune.json"
+    t, b, ms = BT.autotune(soa, 2000, scene["sh_degree"], cams, _target(cams), cache_path=str(path),
+                           steps=2, warmup=1, tiles=(8, 16), batches=(128, 256))
+    assert (t, b) in {(8, 128), (8, 256), (16, 128), (16, 256)}
+    assert ms[f"{t}x{b}"] == min(ms.values())
+    cache = json.loads(path.read_text())
+    assert BT.shape_class(2000, cams) in cache
+    assert BT.autotune(soa, 2000, scene["sh_degree"], cams, None, cache_path=str(path))[:2] == (t, b)

@@ -107,7 +107,13 @@ def _check_render(scene, cams, fr, pres, mode="rec"):
         assert err[ok].max() <= 1e-4, err[ok].max()
         np.testing.assert_array_equal(cnt[ok], ref["n_contrib"].numpy()[ok])
         assert np.abs(T - ref["T_final"].numpy())[ok].max() <= 1e-4
-        last_id = np.where(last >= 0, vals[np.maximum(last, 0)].astype(np.int64) - c * n, -1)
+        starts = u32(fr.ranges).reshape(-1, 2)[:, 0].astype(np.int64)
+        T = fr.opts.tile
+        cam = cams[c]
+        toff = sum(((cc["width"] + T - 1) // T) * ((cc["height"] + T - 1) // T) for cc in cams[:c])
+        ys, xs = np.meshgrid(np.arange(cam["height"]) // T, np.arange(cam["width"]) // T, indexing="ij")
+        tstart = starts[toff + ys * ((cam["width"] + T - 1) // T) + xs]
+        last_id = np.where(last >= 0, vals[np.maximum(tstart + last, 0)].astype(np.int64) - c * n, -1)
         np.testing.assert_array_equal(last_id[ok], ref["last_id"].numpy()[ok])
     assert flagged_total <= 0.02 * pix_total, (flagged_total, pix_total)
     return flagged_total, pix_total
@@ -141,10 +147,34 @@ def test_outputs_identical_across_tile_batch_and_runs():
             assert torch.equal(fr.T_final.cpu(), ref.T_final.cpu())
     again = gpu_forward(scene, cams)
     assert torch.equal(again.images.cpu(), base)
+    # one workgroup per tile instead of the persistent grid
+    plain = gpu_forward(scene, cams, persistent=False)
+    assert torch.equal(plain.images.cpu(), base) and torch.equal(plain.last_idx.cpu(), ref.last_idx.cpu())
     # the batched multi-view call equals one call per view
     for c, cam in enumerate(cams):
         single = gpu_forward(scene, [cam])
         assert torch.equal(single.image(0).cpu(), ref.image(c).cpu())
+
+
+def test_tile_order_is_longest_list_first():
+    scene, cams = CASES["cfg4_three_views"]
+    fr = gpu_forward(scene, cams)
+    order = fr.tile_order.cpu().numpy().astype(np.int64)
+    r = u32(fr.ranges).reshape(-1, 2).astype(np.int64)
+    lengths = r[:, 1] - r[:, 0]
+    assert sorted(order.tolist()) == list(range(lengths.size))
+    np.testing.assert_array_equal(order, np.lexsort((np.arange(lengths.size), -lengths)))
+
+
+def test_persistent_backward_equals_per_tile_backward():
+    scene, cams = CASES["cfg4_three_views"]
+    a = gpu_forward(scene, cams, persistent=True)
+    b = gpu_forward(scene, cams, persistent=False)
+    dl = torch.randn(a.images.numel(), device="cuda")
+    ga, _ = R.backward_pass(a, dl)
+    gb, _ = R.backward_pass(b, dl)
+    torch.cuda.synchronize()
+    assert torch.allclose(ga, gb, rtol=1e-4, atol=1e-7)
 
 
 def test_flipped_normals_swap_halves():
@@ -242,7 +272,8 @@ def test_raster_bwd_record_gradients_match_oracle():
     n_rec = fr.n
     rg = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, device="cuda")
     st = torch.cuda.current_stream().cuda_stream
-    B.hgs_raster_bwd(fr.records, fr.values, fr.ranges, fr.cams, fr.opts, fr.T_final, fr.last_idx, dl, rg, st)
+    B.hgs_raster_bwd(fr.records, fr.values, fr.ranges, fr.tile_order, fr.cams, fr.opts, fr.T_final, fr.last_idx,
+                     dl, rg, fr.ws_render, st)
     torch.cuda.synchronize()
     got = rg.cpu().numpy().reshape(n_rec, B.HGS_RECORD_GRAD_FLOATS).astype(np.float64)
     idx, ref = O.record_grads(scene, cam, w)

@@ -73,3 +73,11 @@ def test_host_side_validation_and_sizes():
     big[0].width, big[0].height, big[0].fx, big[0].fy = 70000, 10, 1.0, 1.0
     assert B.hgs_tiles_total(big, o) == -1
     assert lib.hgs_strerror(B.HGS_ECAPACITY) == b"buffer too small"
+
+
+def test_autotune_shape_class_is_stable():
+    from paper_2406_02720_amd import batch
+    _, cams = scenes.make_config(4, n=10, n_cams=3)
+    a = batch.shape_class(500_000, cams)
+    assert a == batch.shape_class(510_000, cams) and a.endswith("_v3")
+    assert a != batch.shape_class(500_000, cams[:2])
