@@ -143,7 +143,8 @@ void hgs_default_options(hgs_options* opts);
 
 /* Workspace sizes (bytes) of the calls that take one.  `which` is one of the
  * HGS_WS_* values; n_rec = n_cams * n; capacity = key capacity of
- * hgs_bin_sort.  Returns 0 for invalid arguments. */
+ * hgs_bin_sort.  Returns 0 for invalid arguments.  The hgs_bin_sort
+ * workspace must be 256-byte aligned (any hipMalloc result is). */
 #define HGS_WS_PREPROCESS 0
 #define HGS_WS_BIN_SORT 1
 #define HGS_WS_RENDER 2

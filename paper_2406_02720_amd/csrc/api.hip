@@ -196,6 +196,8 @@ int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint6
   const size_t need = hgs::sort_workspace_bytes(n_rec, capacity, (int64_t)cp.tiles_total, full_keys);
   if (!workspace || workspace_bytes < need)
     return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", need);
+  if (((uintptr_t)workspace & 255u) != 0)
+    return fail(HGS_EINVAL, "workspace must be 256-byte aligned");
   hipError_t h = hgs::launch_bin_sort((const hgs::Record*)records, tiles_touched, offsets, n_dup,
                                       n_rec, n_rec / n_cams, cp, keys, values, capacity, ranges,
                                       tile_order, overflow, workspace, full_keys, stream);

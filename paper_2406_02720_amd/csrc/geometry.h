@@ -146,7 +146,8 @@ __device__ __forceinline__ void quat_rot(const float* q, double* qh, double& qn,
   if (qn == 0.0) {
     qw = 1.0; qx = qy = qz = 0.0;
   } else {
-    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    const double iq = 1.0 / qn;
+    qw *= iq; qx *= iq; qy *= iq; qz *= iq;
   }
   qh[0] = qw; qh[1] = qx; qh[2] = qy; qh[3] = qz;
   R[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
@@ -203,22 +204,23 @@ __device__ __forceinline__ Sym3 splitting_cov(const KernelGeo& k) {
     v1[0] = 1.0; v1[1] = 0.0; v1[2] = 0.0;
     v2[0] = 0.0; v2[1] = 1.0; v2[2] = 0.0;
   } else {
-    const double l1 = sqrt(ny * ny + nx * nx);
-    v1[0] = ny / l1; v1[1] = -nx / l1; v1[2] = 0.0;
+    const double i1 = 1.0 / sqrt(ny * ny + nx * nx);
+    v1[0] = ny * i1; v1[1] = -nx * i1; v1[2] = 0.0;
     const double c0 = ny * v1[2] - nz * v1[1];
     const double c1 = nz * v1[0] - nx * v1[2];
     const double c2 = nx * v1[1] - ny * v1[0];
-    const double l2 = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-    v2[0] = c0 / l2; v2[1] = c1 / l2; v2[2] = c2 / l2;
+    const double i2 = 1.0 / sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    v2[0] = c0 * i2; v2[1] = c1 * i2; v2[2] = c2 * i2;
   }
   // covariance in the basis (v1, v2, n)
   const double C00 = sym_form(k.Sw, v1, v1), C01 = sym_form(k.Sw, v1, v2);
   const double C02 = sym_form(k.Sw, v1, k.nh), C11 = sym_form(k.Sw, v2, v2);
   const double C12 = sym_form(k.Sw, v2, k.nh), C22 = sym_form(k.Sw, k.nh, k.nh);
-  const double ap = C00 - C02 * C02 / C22;
-  const double bp = C01 - C02 * C12 / C22;
-  const double cp = C11 - C12 * C12 / C22;
-  const double dp = fmin(ap, cp) / 100.0;
+  const double i22 = 1.0 / C22;
+  const double ap = C00 - C02 * C02 * i22;
+  const double bp = C01 - C02 * C12 * i22;
+  const double cp = C11 - C12 * C12 * i22;
+  const double dp = fmin(ap, cp) * 0.01;
   // back to world: S = ap v1 v1^T + bp (v1 v2^T + v2 v1^T) + cp v2 v2^T + dp n n^T
   Sym3 S;
   const double* nh = k.nh;
@@ -261,13 +263,14 @@ __device__ __forceinline__ void view_geo(const KernelGeo& k, const CamDev& cam, 
   const double fx = cam.fx, fy = cam.fy;
   const double lx = fov_clamp * (double)cam.width / (2.0 * fx);
   const double ly = fov_clamp * (double)cam.height / (2.0 * fy);
-  const double rx = tx / tz, ry = ty / tz;
+  const double iz = 1.0 / tz;
+  const double rx = tx * iz, ry = ty * iz;
   vg.xc = fmin(fmax(rx, -lx), lx);
   vg.yc = fmin(fmax(ry, -ly), ly);
   vg.clx = !(rx >= -lx && rx <= lx);
   vg.cly = !(ry >= -ly && ry <= ly);
-  const double J00 = fx / tz, J02 = -fx * vg.xc / tz;
-  const double J11 = fy / tz, J12 = -fy * vg.yc / tz;
+  const double J00 = fx * iz, J02 = -fx * vg.xc * iz;
+  const double J11 = fy * iz, J12 = -fy * vg.yc * iz;
   for (int c = 0; c < 3; ++c) {
     vg.M[c] = J00 * (double)R[0 * 3 + c] + J02 * (double)R[2 * 3 + c];
     vg.M[3 + c] = J11 * (double)R[1 * 3 + c] + J12 * (double)R[2 * 3 + c];
@@ -279,11 +282,12 @@ __device__ __forceinline__ void view_geo(const KernelGeo& k, const CamDev& cam, 
   vg.B = vg.M[3] * S0[0] + vg.M[4] * S0[1] + vg.M[5] * S0[2];
   vg.C = vg.M[3] * S1[0] + vg.M[4] * S1[1] + vg.M[5] * S1[2] + lowpass;
   vg.det = vg.A * vg.C - vg.B * vg.B;
-  vg.qa = vg.C / vg.det;
-  vg.qb = -vg.B / vg.det;
-  vg.qc = vg.A / vg.det;
-  vg.mx = fx * tx / tz + (double)cam.cx;
-  vg.my = fy * ty / tz + (double)cam.cy;
+  const double idet = 1.0 / vg.det;
+  vg.qa = vg.C * idet;
+  vg.qb = -vg.B * idet;
+  vg.qc = vg.A * idet;
+  vg.mx = fx * rx + (double)cam.cx;
+  vg.my = fy * ry + (double)cam.cy;
   vg.g[0] = vg.M[0] * k.Sn[0] + vg.M[1] * k.Sn[1] + vg.M[2] * k.Sn[2];
   vg.g[1] = vg.M[3] * k.Sn[0] + vg.M[4] * k.Sn[1] + vg.M[5] * k.Sn[2];
   vg.w[0] = vg.qa * vg.g[0] + vg.qb * vg.g[1];

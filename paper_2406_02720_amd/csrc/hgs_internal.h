@@ -22,8 +22,8 @@ struct CamDev {
   uint64_t pix_off;
 };
 
-// Passed by value as a kernel argument (well under the 4 KiB limit), so a
-// launch captures the cameras without any host->device copy.
+// Passed by value as a kernel argument (under the 4 KiB limit), so a launch
+// captures the cameras without any host->device copy.
 struct CamPack {
   int32_t n_cams;
   int32_t tile;       // tile edge (8, 16 or 32)
@@ -45,6 +45,8 @@ struct alignas(16) Record {
   uint32_t xr, yr, depth, tiles;
 };
 static_assert(sizeof(Record) == HGS_RECORD_BYTES, "record layout");
+// explicit arguments beside the pack and the implicit ones stay under 4 KiB
+static_assert(sizeof(CamPack) <= 3584, "camera pack must fit the kernel-argument segment");
 
 struct Opts {
   float lowpass, kappa, alpha_min, alpha_max, t_min, fov_clamp;

@@ -117,19 +117,14 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
     r.qa = r.qb = r.qc = r.alpha2 = 0.0f;
     r.r = r.g = r.b = r.d_o = 0.0f;
     r.xr = r.yr = r.depth = 0u;
-    ViewGeo vg;
-    view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
-    bool ok = params_ok && finite(vg.t[2]) && vg.t[2] > (double)cam.znear;
-    ok = ok && finite(vg.det) && vg.det > 0.0 && finite(vg.qa) && finite(vg.qb) &&
-         finite(vg.qc) && finite(vg.mx) && finite(vg.my) && finite(vg.k[0]) && finite(vg.k[1]);
+    // SH colour first (its basis values die before the geometry starts)
     double col0 = 0.0, col1 = 0.0, col2 = 0.0;
-    if (ok) {
-      // SH colour from the camera centre towards the kernel
+    if (params_ok) {
       double oc[3];
       camera_centre(cam, oc);
       double dx = kg.mu[0] - oc[0], dy = kg.mu[1] - oc[1], dz = kg.mu[2] - oc[2];
-      const double dl = sqrt(dx * dx + dy * dy + dz * dz);
-      dx /= dl; dy /= dl; dz /= dl;
+      const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+      dx *= il; dy *= il; dz *= il;
       double Y[K];
       sh_eval<D>(dx, dy, dz, Y);
 #pragma unroll
@@ -141,8 +136,13 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
       col0 = fmax(col0 + 0.5, 0.0);
       col1 = fmax(col1 + 0.5, 0.0);
       col2 = fmax(col2 + 0.5, 0.0);
-      ok = finite(col0) && finite(col1) && finite(col2);
     }
+    ViewGeo vg;
+    view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
+    bool ok = params_ok && finite(vg.t[2]) && vg.t[2] > (double)cam.znear;
+    ok = ok && finite(vg.det) && vg.det > 0.0 && finite(vg.qa) && finite(vg.qb) &&
+         finite(vg.qc) && finite(vg.mx) && finite(vg.my) && finite(vg.k[0]) && finite(vg.k[1]);
+    ok = ok && finite(col0) && finite(col1) && finite(col2);
     Box bx;
     if (ok) {
       bx = half_box(kg, vg, Ss, a1, a2, o);
@@ -336,7 +336,8 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
       camera_centre(cam, oc);
       const double dv0 = kg.mu[0] - oc[0], dv1 = kg.mu[1] - oc[1], dv2 = kg.mu[2] - oc[2];
       const double dl = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
-      const double d0 = dv0 / dl, d1 = dv1 / dl, d2 = dv2 / dl;
+      const double il = 1.0 / dl;
+      const double d0 = dv0 * il, d1 = dv1 * il, d2 = dv2 * il;
       double Y[K];
       sh_eval<D>(d0, d1, d2, Y);
       double raw[3] = {0.0, 0.0, 0.0};
@@ -361,9 +362,9 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
       double gd0, gd1, gd2;
       sh_grad<D>(d0, d1, d2, wk, &gd0, &gd1, &gd2);
       const double dot = gd0 * d0 + gd1 * d1 + gd2 * d2;
-      g_mu[0] += (gd0 - d0 * dot) / dl;
-      g_mu[1] += (gd1 - d1 * dot) / dl;
-      g_mu[2] += (gd2 - d2 * dot) / dl;
+      g_mu[0] += (gd0 - d0 * dot) * il;
+      g_mu[1] += (gd1 - d1 * dot) * il;
+      g_mu[2] += (gd2 - d2 * dot) * il;
     }
 
     // ---- k = w r, r = (2 s2)^-1/2, w = Q g, s2 = v - g.w (or 1e-12 v)

@@ -15,8 +15,8 @@
 // Backward: each lane replays its pixels back to front from the last blended
 // entry, dividing the transmittance back out, and sums its pixels'
 // gradients for the entry; the 12 sums are then reduced across the 64 lanes
-// with DPP row operations and one lane issues the float atomics, so there is
-// one reduction and one set of atomics per (entry, 256 pixels).
+// (DPP and lane swaps, reduce-scatter) and four lanes issue the float atomics,
+// so there is one reduction and one set of atomics per (entry, 256 pixels).
 
 #include "hgs_internal.h"
 
@@ -31,70 +31,79 @@ namespace {
 
 constexpr float kTwoOverSqrtPi = 1.12837916709551257390f;
 
-// erfc(x) from the Chebyshev-fitted form of Numerical Recipes (Press et al.,
-// 2nd ed., Sec. 6.2, "erfcc"): erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2)
-// for z = |x|, fractional error below 1.2e-7 everywhere; erfc(-z) = 2 -
-// erfc(z).  Branch-free (one v_rcp, one exp2, ten fma), so the lanes
-// of a wavefront never diverge on the argument's range.  Result in [0, 2].
+// erfc(x) for the half factor.  For z = |x| <= 3.9, log2 erfc(z) is smooth
+// and is fitted by a degree-10 polynomial (least squares in the Chebyshev
+// basis of [0, 3.9], coefficients rounded to float and checked in float
+// Horner arithmetic: absolute error below 5e-8); beyond 3.9 the argument is
+// clamped (erfc(3.9) = 3.5e-8).  erfc(-z) = 2 - erfc(z).  No reciprocal,
+// one exp2, ten fma; branch-free, result in [0, 2].
 __device__ __forceinline__ float erfc_fast(float x) {
-  const float z = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
-  float p = 0.17087277f;
-  p = fmaf(p, t, -0.82215223f);
-  p = fmaf(p, t, 1.48851587f);
-  p = fmaf(p, t, -1.13520398f);
-  p = fmaf(p, t, 0.27886807f);
-  p = fmaf(p, t, -0.18628806f);
-  p = fmaf(p, t, 0.09678418f);
-  p = fmaf(p, t, 0.37409196f);
-  p = fmaf(p, t, 1.00002368f);
-  p = fmaf(p, t, -1.26551223f);
-  const float e = t * __expf(fmaf(-z, z, p));
+  const float z = fminf(fabsf(x), 3.9f);
+  float p = -1.3359800732359872e-06f;
+  p = fmaf(p, z, 2.5692050257930532e-05f);
+  p = fmaf(p, z, -0.00021396989177446812f);
+  p = fmaf(p, z, 0.0009886942571029067f);
+  p = fmaf(p, z, -0.0024599749594926834f);
+  p = fmaf(p, z, 0.0002238718152511865f);
+  p = fmaf(p, z, 0.027670344337821007f);
+  p = fmaf(p, z, -0.1483006626367569f);
+  p = fmaf(p, z, -0.9184418320655823f);
+  p = fmaf(p, z, -1.6279075145721436f);
+  p = fmaf(p, z, 6.547596242967302e-09f);
+  const float e = __builtin_amdgcn_exp2f(p);
   return x >= 0.0f ? e : 2.0f - e;
-}
-
-struct Pair {
-  bool live;   // in rect and power <= 0
-  float dx, dy, G, I, HG, a;
-};
-
-// One pixel against one record.  Pure function of its inputs, so the forward
-// and backward passes take identical decisions.  `amax_half` is
-// max(alpha2, alpha2 + 2 d_o) rounded as below: since I lies in [0, 2] and
-// every rounding is monotone, HG <= G * amax_half, so a pair whose bound is
-// already below alpha_min is skipped without the half factor -- the same
-// decision the full evaluation takes.
-__device__ __forceinline__ void eval_pair(const Record& r, float amax_half, int px, int py,
-                                          float alpha_min, float alpha_max, Pair& P) {
-  const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
-  const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
-  P.live = px >= x0 && px <= x1 && py >= y0 && py <= y1;
-  if (!P.live) return;
-  P.dx = ((float)(px - x0) + 0.5f) - r.mx;
-  P.dy = ((float)(py - y0) + 0.5f) - r.my;
-  const float quad = fmaf(r.qa * P.dx, P.dx, (r.qc * P.dy) * P.dy);
-  const float power = fmaf(-0.5f, quad, -((r.qb * P.dx) * P.dy));
-  P.live = !(power > 0.0f);
-  if (!P.live) return;
-  P.G = __expf(power);
-  if (P.G * amax_half < alpha_min) {  // cannot reach alpha_min
-    P.a = 0.0f;
-    P.HG = 0.0f;
-    P.I = 1.0f;
-    return;
-  }
-  if (r.d_o != 0.0f) {
-    P.I = erfc_fast(-fmaf(r.kx, P.dx, r.ky * P.dy));
-    P.HG = fmaf(r.d_o, P.I, r.alpha2) * P.G;
-  } else {
-    P.I = 1.0f;
-    P.HG = r.alpha2 * P.G;
-  }
-  P.a = fminf(alpha_max, P.HG);
 }
 
 __device__ __forceinline__ float half_bound(const Record& r) {
   return fmaxf(r.alpha2, fmaf(r.d_o, 2.0f, r.alpha2));
+}
+
+// Per-record values that a lane's pixels share (they lie in one column).
+struct Column {
+  bool in;            // pixel column inside [x0, x1]
+  float dx, qadx, qbdx;
+};
+
+__device__ __forceinline__ Column column_of(const Record& r, int px, int x0, int x1) {
+  Column c;
+  c.in = px >= x0 && px <= x1;
+  c.dx = ((float)(px - x0) + 0.5f) - r.mx;
+  c.qadx = r.qa * c.dx;
+  c.qbdx = r.qb * c.dx;
+  return c;
+}
+
+// One pixel against one record, in two parts so that the lanes of a
+// wavefront can skip the second together.  Pure functions of their inputs:
+// the forward and backward passes take identical decisions.
+//   gauss:  offset, Gaussian G = exp(-q/2) of the dilated conic, and whether
+//           the pair can reach alpha_min at all: `amax_half` =
+//           max(alpha2, alpha2 + 2 d_o) bounds (alpha2 + d_o I) since I lies in
+//           [0, 2] and every rounding is monotone, so a pair whose bound
+//           G * amax_half is below alpha_min is dropped without the half factor
+//           -- the decision the full evaluation would take.
+//   opacity: half factor I (Eq. 7-8) and paired opacity HG = (alpha2 + d_o I) G
+//           (Eq. 10), alpha = min(alpha_max, HG).
+struct Pair {
+  bool pass;   // in rect, power <= 0, bound reaches alpha_min
+  float dy, G, I, HG, a;
+};
+
+__device__ __forceinline__ void pair_gauss(const Record& r, const Column& c, bool row_in, int py, int y0,
+                                           float amax_half, float alpha_min, Pair& P) {
+  P.dy = ((float)(py - y0) + 0.5f) - r.my;
+  const float quad = fmaf(c.qadx, c.dx, (r.qc * P.dy) * P.dy);
+  const float power = fmaf(-0.5f, quad, -(c.qbdx * P.dy));
+  P.G = __expf(power);
+  P.pass = c.in && row_in && !(power > 0.0f) && !(P.G * amax_half < alpha_min);
+}
+
+// `split` = (d_o != 0), uniform over the wavefront; without it I = 1.
+__device__ __forceinline__ void pair_opacity(const Record& r, const Column& c, bool split, float alpha_max,
+                                             Pair& P) {
+  P.I = split ? erfc_fast(-fmaf(r.kx, c.dx, r.ky * P.dy)) : 1.0f;
+  P.HG = fmaf(r.d_o, P.I, r.alpha2) * P.G;
+  P.a = fminf(alpha_max, P.HG);
 }
 
 template <int T>
@@ -109,19 +118,45 @@ __device__ __forceinline__ Record load_record(const Record* __restrict__ rec, ui
   return rec[id];
 }
 
-// Sum over the 64 lanes; the total lands in lane 63.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
 }
-__device__ __forceinline__ float wave_sum_last(float v) {
-  v += dpp<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x124, 0xf>(v);  // row_ror:4
-  v += dpp<0x128, 0xf>(v);  // row_ror:8   (every lane holds its row's sum)
-  v += dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
+
+// Sums of the 12 record-gradient terms over the 64 lanes, as a
+// reduce-scatter: exchanging half of the values with the lane one apart
+// (then two apart) leaves each lane with 3 partial sums of its own terms,
+// q = 6 (lane & 1) + 3 ((lane >> 1) & 1) + i; those are summed over the 16
+// lanes sharing lane & 3 (row rotations by 4 and 8, then the gfx950 row and
+// half swaps).  Lanes 0..3 end up holding all 12 totals, 45 VALU operations
+// in place of 72 for twelve full reductions.
+__device__ __forceinline__ float swap_sum16(float v) {
+  const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+__device__ __forceinline__ float swap_sum32(float v) {
+  const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+__device__ __forceinline__ void wave_reduce12(const float* g, int lane, float* out3) {
+  const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0;
+  float h[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float send = b0 ? g[i] : g[i + 6];
+    const float keep = b0 ? g[i + 6] : g[i];
+    h[i] = keep + dpp<0xb1, 0xf>(send);      // quad_perm [1,0,3,2]
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float send = b1 ? h[i] : h[i + 3];
+    const float keep = b1 ? h[i + 3] : h[i];
+    float v = keep + dpp<0x4e, 0xf>(send);   // quad_perm [2,3,0,1]
+    v += dpp<0x124, 0xf>(v);                 // row_ror:4
+    v += dpp<0x128, 0xf>(v);                 // row_ror:8
+    v = swap_sum16(v);
+    out3[i] = swap_sum32(v);
+  }
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -133,7 +168,14 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// Uniform over the wavefront (the compiler cannot always prove it).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // One wavefront's block of pixels (sub-block `wave` of `tile`), front to back.
+// Per record, everything that does not depend on the lane is tested once for
+// the wavefront (rect rows against each strip of the block, any pixel still
+// open, any pair reaching alpha_min, d_o == 0); the per-pixel updates are
+// selects, so the lanes never branch apart.
 template <int T, int IPL>
 __device__ __forceinline__ void fwd_block(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
@@ -142,14 +184,15 @@ __device__ __forceinline__ void fwd_block(
     uint32_t tile, int wave, int lane) {
   using Gm = Geometry<T>;
   constexpr int PPL = Gm::PPL;
+  constexpr int RS = Gm::ROWSTEP;
   if (tile >= cp.tiles_total) return;  // never index past the tile arrays
   const int c = cam_of_tile(cp, tile);
   const CamDev& cam = cp.cam[c];
   const uint32_t lt = tile - cam.tile_off;
   const int ty = (int)(lt / (uint32_t)cam.tiles_x);
   const int tx = (int)(lt - (uint32_t)ty * (uint32_t)cam.tiles_x);
-  const int ox = tx * T + (wave % (T / Gm::SUB)) * Gm::SUB;
-  const int oy = ty * T + (wave / (T / Gm::SUB)) * Gm::SUB;
+  const int ox = uniform(tx * T + (wave % (T / Gm::SUB)) * Gm::SUB);
+  const int oy = uniform(ty * T + (wave / (T / Gm::SUB)) * Gm::SUB);
   const int px = ox + lane % Gm::SUB;
   int py[PPL];
   bool inside[PPL];
@@ -158,7 +201,7 @@ __device__ __forceinline__ void fwd_block(
   bool done[PPL];
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    py[j] = oy + lane / Gm::SUB + j * Gm::ROWSTEP;
+    py[j] = oy + lane / Gm::SUB + j * RS;
     inside[j] = px < cam.width && py[j] < cam.height;
     Tr[j] = 1.0f;
     C0[j] = C1[j] = C2[j] = 0.0f;
@@ -171,12 +214,15 @@ __device__ __forceinline__ void fwd_block(
   const uint32_t* __restrict__ lst = vals + ranges[2 * tile];
   const int64_t len = (int64_t)ranges[2 * tile + 1] - (int64_t)ranges[2 * tile];
   const float amin = o.alpha_min, amax = o.alpha_max, tmin = o.t_min;
-
-  for (int64_t base = 0; base < len; base += 64 * IPL) {
+  bool open = true;   // some pixel of the block still takes entries (uniform)
+  {
     bool any = false;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) any |= !done[j];
-    if (__ballot(any) == 0ull) break;
+    open = __ballot(any) != 0ull;
+  }
+
+  for (int64_t base = 0; open && base < len; base += 64 * IPL) {
     uint32_t ids[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
@@ -187,31 +233,46 @@ __device__ __forceinline__ void fwd_block(
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       const int lim = (int)nb - k * 64;
-      if (lim <= 0) break;
+      if (lim <= 0 || !open) break;
       const int cntk = lim < 64 ? lim : 64;
-      for (int l = 0; l < cntk; ++l) {
+      for (int l = 0; l < cntk && open; ++l) {
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
-        const float hb = half_bound(r);
+        const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
+        const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
+        if (y1 < oy || y0 > oy + Gm::SUB - 1 || x1 < ox || x0 > ox + Gm::SUB - 1) continue;
         const int32_t pos = (int32_t)(base + k * 64 + l);
+        const float hb = half_bound(r);
+        const bool split = r.d_o != 0.0f;
+        const Column col = column_of(r, px, x0, x1);
+        bool ended = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          if (done[j]) continue;
+          const int row = oy + j * RS;                       // first row of strip j
+          if (row + RS - 1 < y0 || row > y1) continue;        // strip misses the rect rows
           Pair P;
-          eval_pair(r, hb, px, py[j], amin, amax, P);
-          if (!P.live || P.a < amin) continue;
+          pair_gauss(r, col, py[j] >= y0 && py[j] <= y1 && !done[j], py[j], y0, hb, amin, P);
+          if (__ballot(P.pass) == 0ull) continue;
+          pair_opacity(r, col, split, amax, P);
+          const bool blend = P.pass && !(P.a < amin);
           const float Tn = Tr[j] * (1.0f - P.a);
-          if (Tn < tmin) {
-            done[j] = true;
-            continue;
-          }
-          const float w = P.a * Tr[j];
+          const bool stop = blend && Tn < tmin;
+          const bool take = blend && !stop;
+          const float w = take ? P.a * Tr[j] : 0.0f;
           C0[j] = fmaf(r.r, w, C0[j]);
           C1[j] = fmaf(r.g, w, C1[j]);
           C2[j] = fmaf(r.b, w, C2[j]);
-          Tr[j] = Tn;
-          ++cnt[j];
-          last[j] = pos;
+          Tr[j] = take ? Tn : Tr[j];
+          cnt[j] += take ? 1 : 0;
+          last[j] = take ? pos : last[j];
+          done[j] = done[j] || stop;
+          ended |= stop;
+        }
+        if (__ballot(ended) != 0ull) {
+          bool any = false;
+#pragma unroll
+          for (int j = 0; j < PPL; ++j) any |= !done[j];
+          open = __ballot(any) != 0ull;
         }
       }
     }
@@ -264,7 +325,10 @@ __global__ __launch_bounds__(64) void render_fwd_persistent_kernel(
                       (int)(w % WAVES), lane);
 }
 
-// One wavefront's block of pixels, back to front.
+// One wavefront's block of pixels, back to front.  Same uniform skips as the
+// forward pass; a pixel takes part in an entry only at or before its last
+// blended one, and the state of the other lanes is kept by selects (their
+// gradient terms are exact zeros).
 template <int T, int IPL>
 __device__ __forceinline__ void bwd_block(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
@@ -273,45 +337,47 @@ __device__ __forceinline__ void bwd_block(
     const float* __restrict__ dL_dimg, float* __restrict__ rgrad, uint32_t tile, int wave, int lane) {
   using Gm = Geometry<T>;
   constexpr int PPL = Gm::PPL;
+  constexpr int RS = Gm::ROWSTEP;
   if (tile >= cp.tiles_total) return;  // never index past the tile arrays
   const int c = cam_of_tile(cp, tile);
   const CamDev& cam = cp.cam[c];
   const uint32_t lt = tile - cam.tile_off;
   const int ty = (int)(lt / (uint32_t)cam.tiles_x);
   const int tx = (int)(lt - (uint32_t)ty * (uint32_t)cam.tiles_x);
-  const int ox = tx * T + (wave % (T / Gm::SUB)) * Gm::SUB;
-  const int oy = ty * T + (wave / (T / Gm::SUB)) * Gm::SUB;
+  const int ox = uniform(tx * T + (wave % (T / Gm::SUB)) * Gm::SUB);
+  const int oy = uniform(ty * T + (wave / (T / Gm::SUB)) * Gm::SUB);
   const int px = ox + lane % Gm::SUB;
   const uint64_t plane = (uint64_t)cam.width * cam.height;
   const float* g = dL_dimg + 3 * cam.pix_off;
 
   int py[PPL];
-  int32_t last[PPL];
-  float Tf[PPL], Tr[PPL], dL0[PPL], dL1[PPL], dL2[PPL];
-  float acc0[PPL], acc1[PPL], acc2[PPL], la[PPL], lc0[PPL], lc1[PPL], lc2[PPL], bgdot[PPL];
+  int32_t last[PPL], top_j[PPL];
+  float Tr[PPL], dL0[PPL], dL1[PPL], dL2[PPL];
+  float acc0[PPL], acc1[PPL], acc2[PPL], tbg[PPL];
   int top = -1;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    py[j] = oy + lane / Gm::SUB + j * Gm::ROWSTEP;
+    py[j] = oy + lane / Gm::SUB + j * RS;
     const bool inside = px < cam.width && py[j] < cam.height;
     last[j] = -1;
-    Tf[j] = 1.0f;
+    float Tf = 1.0f;
     dL0[j] = dL1[j] = dL2[j] = 0.0f;
     if (inside) {
       const uint64_t pix = (uint64_t)py[j] * cam.width + px;
-      Tf[j] = T_final[cam.pix_off + pix];
+      Tf = T_final[cam.pix_off + pix];
       last[j] = last_idx[cam.pix_off + pix];
       dL0[j] = g[pix];
       dL1[j] = g[plane + pix];
       dL2[j] = g[2 * plane + pix];
     }
-    Tr[j] = Tf[j];
+    Tr[j] = Tf;
     acc0[j] = acc1[j] = acc2[j] = 0.0f;
-    la[j] = lc0[j] = lc1[j] = lc2[j] = 0.0f;
-    bgdot[j] = o.bg[0] * dL0[j] + o.bg[1] * dL1[j] + o.bg[2] * dL2[j];
-    top = last[j] > top ? last[j] : top;
+    // the background seen through the final transmittance: its share of
+    // dL/dalpha is -T_final / (1 - alpha) * (bg . dL)
+    tbg[j] = -Tf * (o.bg[0] * dL0[j] + o.bg[1] * dL1[j] + o.bg[2] * dL2[j]);
+    top_j[j] = uniform(wave_max(last[j]));   // last entry any pixel of strip j blended
+    top = top_j[j] > top ? top_j[j] : top;
   }
-  top = wave_max(top);
   if (top < 0) return;
   const uint32_t* __restrict__ lst = vals + ranges[2 * tile];
   const float amin = o.alpha_min, amax = o.alpha_max;
@@ -333,61 +399,68 @@ __device__ __forceinline__ void bwd_block(
       for (int l = 0; l < cntk; ++l) {
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
-        const float hb = half_bound(r);
+        const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
+        const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
+        if (y1 < oy || y0 > oy + Gm::SUB - 1 || x1 < ox || x0 > ox + Gm::SUB - 1) continue;
         const int32_t pos = hi - (k * 64 + l);
+        const float hb = half_bound(r);
+        const bool split = r.d_o != 0.0f;
+        const Column col = column_of(r, px, x0, x1);
         float gs[HGS_RECORD_GRAD_FLOATS];
 #pragma unroll
         for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q) gs[q] = 0.0f;
         bool any = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          if (pos > last[j]) continue;
+          const int row = oy + j * RS;
+          if (row + RS - 1 < y0 || row > y1 || pos > top_j[j]) continue;
           Pair P;
-          eval_pair(r, hb, px, py[j], amin, amax, P);
-          if (!P.live || P.a < amin) continue;
+          pair_gauss(r, col, py[j] >= y0 && py[j] <= y1 && pos <= last[j], py[j], y0, hb, amin, P);
+          if (__ballot(P.pass) == 0ull) continue;
+          pair_opacity(r, col, split, amax, P);
+          const bool m = P.pass && !(P.a < amin);
+          if (__ballot(m) == 0ull) continue;
           any = true;
           const float a = P.a;
-          const float Tb = Tr[j] / (1.0f - a);
-          const float wcol = a * Tb;
+          const float inv1ma = __builtin_amdgcn_rcpf(1.0f - a);  // 1 - a >= 1 - alpha_max
+          const float Tb = Tr[j] * inv1ma;
+          const float wcol = m ? a * Tb : 0.0f;
           gs[9] += wcol * dL0[j];
           gs[10] += wcol * dL1[j];
           gs[11] += wcol * dL2[j];
-          acc0[j] = la[j] * lc0[j] + (1.0f - la[j]) * acc0[j];
-          acc1[j] = la[j] * lc1[j] + (1.0f - la[j]) * acc1[j];
-          acc2[j] = la[j] * lc2[j] + (1.0f - la[j]) * acc2[j];
-          la[j] = a;
-          lc0[j] = r.r;
-          lc1[j] = r.g;
-          lc2[j] = r.b;
+          // acc: colour of the entries behind this one (already replayed)
           float dLda = ((r.r - acc0[j]) * dL0[j] + (r.g - acc1[j]) * dL1[j] + (r.b - acc2[j]) * dL2[j]) * Tb;
-          dLda += -Tf[j] / (1.0f - a) * bgdot[j];
-          Tr[j] = Tb;
-          const float dHG = (P.HG > amax) ? 0.0f : dLda;
+          dLda = fmaf(inv1ma, tbg[j], dLda);
+          acc0[j] = m ? a * r.r + (1.0f - a) * acc0[j] : acc0[j];
+          acc1[j] = m ? a * r.g + (1.0f - a) * acc1[j] : acc1[j];
+          acc2[j] = m ? a * r.b + (1.0f - a) * acc2[j] : acc2[j];
+          Tr[j] = m ? Tb : Tr[j];
+          const float dHG = (!m || P.HG > amax) ? 0.0f : dLda;
           const float dG = dHG * (r.alpha2 + r.d_o * P.I);
           gs[7] += dHG * P.G;
           gs[8] += dHG * P.I * P.G;
           float du = 0.0f;
-          if (r.d_o != 0.0f) {
-            const float u = r.kx * P.dx + r.ky * P.dy;
+          if (split) {
+            const float u = r.kx * col.dx + r.ky * P.dy;
             du = dHG * r.d_o * P.G * kTwoOverSqrtPi * __expf(-u * u);
           }
-          gs[5] += du * P.dx;
+          gs[5] += du * col.dx;
           gs[6] += du * P.dy;
           const float GG = dG * P.G;
-          gs[0] += GG * (r.qa * P.dx + r.qb * P.dy) - du * r.kx;
-          gs[1] += GG * (r.qb * P.dx + r.qc * P.dy) - du * r.ky;
-          gs[2] += -0.5f * GG * P.dx * P.dx;
-          gs[3] += -GG * P.dx * P.dy;
+          gs[0] += GG * (col.qadx + r.qb * P.dy) - du * r.kx;
+          gs[1] += GG * (col.qbdx + r.qc * P.dy) - du * r.ky;
+          gs[2] += -0.5f * GG * col.dx * col.dx;
+          gs[3] += -GG * col.dx * P.dy;
           gs[4] += -0.5f * GG * P.dy * P.dy;
         }
-        if (__ballot(any) == 0ull) continue;
+        if (!any) continue;
+        float tot[3];
+        wave_reduce12(gs, lane, tot);
+        if (lane < 4) {
+          float* dst = rgrad + (uint64_t)id * HGS_RECORD_GRAD_FLOATS + 6 * (lane & 1) + 3 * (lane >> 1);
 #pragma unroll
-        for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q) gs[q] = wave_sum_last(gs[q]);
-        if (lane == 63) {
-          float* dst = rgrad + (uint64_t)id * HGS_RECORD_GRAD_FLOATS;
-#pragma unroll
-          for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q)
-            if (gs[q] != 0.0f) atomicAdd(dst + q, gs[q]);
+          for (int i = 0; i < 3; ++i)
+            if (tot[i] != 0.0f) atomicAdd(dst + i, tot[i]);
         }
       }
     }
@@ -405,7 +478,7 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
 }
 
 template <int T, int IPL>
-__global__ __launch_bounds__(64) void render_bwd_persistent_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void render_bwd_persistent_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
     const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,

@@ -46,7 +46,11 @@ template <typename K>
 struct SweepItems {
   static constexpr int value = sizeof(K) == 4 ? 32 : 16;
 };
-constexpr int kPartMin = kBlock * 16;  // smallest partition, sizes the look-back
+// the record and tile-order sorts (a few million keys at most) use 2048-key
+// partitions so that their passes still spread over every CU
+constexpr int kSmallItems = 8;
+constexpr int kPartMinEntries = kBlock * 16;          // smallest entry partition
+constexpr int kPartMinSmall = kBlock * kSmallItems;   // record / tile-order partition
 // Digit histograms are accumulated in kHistCopies replicas (block b adds to
 // replica b % kHistCopies): thousands of blocks adding to one 256-word
 // histogram serialise on a few cache lines.
@@ -328,13 +332,12 @@ __global__ __launch_bounds__(kBlock) void depth_hist_weighted_kernel(const Recor
 }
 
 // ---------------------------------------------------------------------------
-template <typename K>
+template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint64_t* __restrict__ n_dev, int64_t capacity, int shift,
     const uint32_t* __restrict__ digit_base, uint64_t* __restrict__ lookback,
     uint64_t* __restrict__ lookback_next, uint32_t* __restrict__ ticket) {
-  constexpr int ITEMS = SweepItems<K>::value;
   constexpr int PART = kBlock * ITEMS;
   __shared__ K s_keys[PART];
   __shared__ uint32_t s_vals[PART];
@@ -462,6 +465,43 @@ __global__ __launch_bounds__(kBlock) void ranges_kernel(const K* __restrict__ ke
     ranges[2 * (uint64_t)tile + 1] = (uint32_t)(i + 1);
 }
 
+// The same for sorted 32-bit tile keys, eight consecutive keys per thread
+// (two 16-byte loads; the keys buffer is 256-byte aligned), grid-strided.
+constexpr int kRangeItems = 8;
+__global__ __launch_bounds__(kBlock) void ranges_u32_kernel(const uint32_t* __restrict__ keys,
+                                                            const uint64_t* __restrict__ n_dup,
+                                                            int64_t capacity,
+                                                            uint32_t* __restrict__ ranges) {
+  const uint64_t n = entry_count(n_dup, capacity);
+  const uint64_t groups = (n + kRangeItems - 1) / kRangeItems;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < groups; g += stride) {
+    const uint64_t i0 = g * kRangeItems;
+    uint32_t k[kRangeItems];
+    if (i0 + kRangeItems <= n) {
+      const uint4 a = *reinterpret_cast<const uint4*>(keys + i0);
+      const uint4 b = *reinterpret_cast<const uint4*>(keys + i0 + 4);
+      k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+      k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kRangeItems; ++j) k[j] = i0 + j < n ? keys[i0 + j] : 0u;
+    }
+    const uint32_t before = i0 > 0 ? keys[i0 - 1] : 0u;
+    const uint64_t after_i = i0 + kRangeItems;
+    const uint32_t after = after_i < n ? keys[after_i] : 0u;
+#pragma unroll
+    for (int j = 0; j < kRangeItems; ++j) {
+      const uint64_t i = i0 + j;
+      if (i >= n) break;
+      const uint32_t prev = j > 0 ? k[j - 1] : before;
+      const uint32_t next = j + 1 < kRangeItems ? k[j + 1] : after;
+      if (i == 0 || prev != k[j]) ranges[2 * (uint64_t)k[j]] = (uint32_t)i;
+      if (i + 1 == n || next != k[j]) ranges[2 * (uint64_t)k[j] + 1] = (uint32_t)(i + 1);
+    }
+  }
+}
+
 // Processing order of the tiles, longest list first: 16-bit key
 // 0xffff - min(length, 0xffff), value = tile id, and the histograms of its
 // two digits.
@@ -530,9 +570,10 @@ struct SortWs {
 
 SortWs carve(void* ws, int64_t n_rec, int64_t capacity, int64_t n_tiles, bool full_keys) {
   SortWs w{};
-  int64_t m = capacity > n_rec ? capacity : n_rec;
-  m = m > n_tiles ? m : n_tiles;
-  const int64_t parts = (m + kPartMin - 1) / kPartMin;
+  const int64_t small = n_rec > n_tiles ? n_rec : n_tiles;
+  const int64_t pe = (capacity + kPartMinEntries - 1) / kPartMinEntries;
+  const int64_t ps = (small + kPartMinSmall - 1) / kPartMinSmall;
+  const int64_t parts = pe > ps ? pe : ps;
   w.parts = parts > 0 ? parts : 1;
   const size_t nr = (size_t)(n_rec > 0 ? n_rec : 1), cap = (size_t)(capacity > 0 ? capacity : 1);
   char* p = (char*)ws;
@@ -575,18 +616,18 @@ unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
 // clears the other one over its partitions for the next pass; the first
 // buffer is cleared here over the phase's partition bound, so no state from
 // an earlier phase (with a different partition count) survives.
-template <typename K>
+template <typename K, int ITEMS>
 void onesweep_passes(K** kb, uint32_t** vb, const uint64_t* n_dev, int64_t cap, int first_shift,
                      int passes, const uint32_t* bases, SortWs& w, uint32_t* tickets, int& lb,
                      hipStream_t s) {
-  constexpr int PART = kBlock * SweepItems<K>::value;
+  constexpr int PART = kBlock * ITEMS;
   const int64_t parts = (cap + PART - 1) / PART > 0 ? (cap + PART - 1) / PART : 1;
   const unsigned grid = (unsigned)parts;
   if (passes <= 0) return;
   hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_for(parts * kRadix, kBlock, 4096)), dim3(kBlock), 0, s,
                      w.lookback[lb & 1], parts * kRadix);
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(onesweep_kernel<K>, dim3(grid), dim3(kBlock), 0, s, kb[p & 1], vb[p & 1],
+    hipLaunchKernelGGL((onesweep_kernel<K, ITEMS>), dim3(grid), dim3(kBlock), 0, s, kb[p & 1], vb[p & 1],
                        kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, cap, first_shift + 8 * p,
                        bases + p * kRadix, w.lookback[lb & 1], w.lookback[(lb + 1) & 1], tickets + p);
     ++lb;
@@ -640,8 +681,8 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        offsets, (const uint32_t*)w.chunk_start, n_dup, n_rec, n_per_cam, cp, (void*)kb[0],
                        vb[0], capacity, overflow, hist_ent + 4 * kRadix, 32, passes - 4);
     hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
-    onesweep_passes<uint64_t>(kb, vb, n_dup, capacity, 0, passes, base_ent, w, w.tickets + kMaxPasses,
-                              lb, s);
+    onesweep_passes<uint64_t, SweepItems<uint64_t>::value>(kb, vb, n_dup, capacity, 0, passes, base_ent, w,
+                                                           w.tickets + kMaxPasses, lb, s);
     const int64_t nr = 2 * (int64_t)cp.tiles_total;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nr, kBlock, 4096)), dim3(kBlock), 0, s, ranges, nr, 0u);
     if (capacity > 0)
@@ -653,7 +694,8 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        tiles, n_rec, w.rkeys[0], w.rids[0], hist_rec);
     hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec, base_rec, 4);
     if (n_rec > 0)
-      onesweep_passes<uint32_t>(w.rkeys, w.rids, nullptr, n_rec, 0, 4, base_rec, w, w.tickets, lb, s);
+      onesweep_passes<uint32_t, kSmallItems>(w.rkeys, w.rids, nullptr, n_rec, 0, 4, base_rec, w, w.tickets,
+                                             lb, s);
     const uint32_t* order = w.rids[0];  // four passes: back in buffer 0
     // 2. entry offsets in that order
     hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(n_rec, kBlock, 1 << 30)), dim3(kBlock), 0, s,
@@ -679,16 +721,16 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        cp, (void*)kb[0], vb[0], capacity, overflow, hist_ent, 0, passes);
     if (passes > 0) {
       hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
-      onesweep_passes<uint32_t>(kb, vb, n_dup, capacity, 0, passes, base_ent, w, w.tickets + kMaxPasses,
-                                lb, s);
+      onesweep_passes<uint32_t, SweepItems<uint32_t>::value>(kb, vb, n_dup, capacity, 0, passes, base_ent, w,
+                                                             w.tickets + kMaxPasses, lb, s);
     }
     const uint32_t* tkeys = kb[passes & 1];
     // 5. ranges (and 64-bit keys if asked for)
     const int64_t nr = 2 * (int64_t)cp.tiles_total;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nr, kBlock, 4096)), dim3(kBlock), 0, s, ranges, nr, 0u);
     if (capacity > 0) {
-      hipLaunchKernelGGL(ranges_kernel<uint32_t>, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock),
-                         0, s, tkeys, 0, n_dup, capacity, ranges);
+      hipLaunchKernelGGL(ranges_u32_kernel, dim3(grid_for((capacity + kRangeItems - 1) / kRangeItems, kBlock, 8192)),
+                         dim3(kBlock), 0, s, tkeys, n_dup, capacity, ranges);
       if (keys)
         hipLaunchKernelGGL(compose_keys_kernel, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock),
                            0, s, tkeys, vals, rec, n_dup, capacity, keys);
@@ -703,7 +745,8 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        ob[0], ov[0], hist_rec + 4 * kRadix);
     hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec + 4 * kRadix,
                        base_rec + 4 * kRadix, 2);
-    onesweep_passes<uint32_t>(ob, ov, nullptr, nt, 0, 2, base_rec + 4 * kRadix, w, w.tickets + 4, lb, s);
+    onesweep_passes<uint32_t, kSmallItems>(ob, ov, nullptr, nt, 0, 2, base_rec + 4 * kRadix, w, w.tickets + 4,
+                                           lb, s);
   }
   return hipGetLastError();
 }

@@ -74,3 +74,35 @@ def test_autotune_returns_a_valid_config_and_caches(tmp_path):
     cache = json.loads(path.read_text())
     assert BT.shape_class(2000, cams) in cache
     assert BT.autotune(soa, 2000, scene["sh_degree"], cams, None, cache_path=str(path))[:2] == (t, b)
+
+
+def test_batched_views_equal_a_per_view_loop():
+    """One batched call over uneven views gives each view's image exactly as
+    a call on that view alone, and the per-parameter gradients summed over
+    the per-view calls."""
+    scene, cams = _scene(n=4000, n_cams=3)
+    soa = R.scene_to_soa(scene)
+    n, deg = scene["means"].shape[0], scene["sh_degree"]
+    target = _target(cams)
+    inv = 1.0 / float(target.numel())
+    br = BT.BatchedRasterizer(soa, n, deg, cams)
+    br.step(BT.l1_loss_grad(target))
+    torch.cuda.synchronize()
+    total = torch.zeros_like(soa)
+    off = 0
+    for c, cam in enumerate(cams):
+        npx = 3 * cam["width"] * cam["height"]
+        t = target[off:off + npx]
+
+        def lf(images, dL, t=t):
+            torch.sub(images, t, out=dL)
+            torch.sign(dL, out=dL)
+            dL.mul_(inv)
+        v = BT.BatchedRasterizer(soa, n, deg, [cam])
+        v.step(lf)
+        torch.cuda.synchronize()
+        assert torch.equal(v.images, br.images[off:off + npx]), c
+        total += v.grads
+        off += npx
+    rel = float((total - br.grads).norm() / br.grads.norm())
+    assert rel <= 1e-5, rel

@@ -174,7 +174,11 @@ def test_persistent_backward_equals_per_tile_backward():
     ga, _ = R.backward_pass(a, dl)
     gb, _ = R.backward_pass(b, dl)
     torch.cuda.synchronize()
-    assert torch.allclose(ga, gb, rtol=1e-4, atol=1e-7)
+    # same per-entry sums; only the order of the float atomics differs
+    # between the two schedules, so compare each parameter plane by norm
+    diff = (ga - gb).norm(dim=1)
+    scale = ga.norm(dim=1).clamp_min(1e-30)
+    assert float((diff / scale).max()) <= 1e-5
 
 
 def test_flipped_normals_swap_halves():

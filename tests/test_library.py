@@ -81,3 +81,26 @@ def test_autotune_shape_class_is_stable():
     a = batch.shape_class(500_000, cams)
     assert a == batch.shape_class(510_000, cams) and a.endswith("_v3")
     assert a != batch.shape_class(500_000, cams[:2])
+
+
+def test_raster_erfc_approximation_error_bound():
+    """The half factor's erfc in the raster kernels is exp2 of a fitted
+    polynomial in |x| (clamped at 3.9): its coefficients, read from the
+    kernel source and evaluated in float32 Horner arithmetic, stay within
+    1e-7 of erfc over the whole real line (the sign by erfc(-z) = 2 - erfc(z))."""
+    import re
+    from scipy.special import erfc
+    src = open(os.path.join(ROOT, "paper_2406_02720_amd", "csrc", "render.hip")).read()
+    body = src[src.index("float erfc_fast(float x)"):]
+    body = body[:body.index("}")]
+    zmax = float(re.search(r"fminf\(fabsf\(x\), ([0-9.]+)f\)", body).group(1))
+    lead = float(re.search(r"float p = ([-0-9.e]+)f;", body).group(1))
+    rest = [float(c) for c in re.findall(r"p = fmaf\(p, z, ([-0-9.e]+)f\);", body)]
+    x = np.linspace(-8.0, 8.0, 400001).astype(np.float32)
+    z = np.minimum(np.abs(x), np.float32(zmax))
+    p = np.full_like(z, np.float32(lead))
+    for c in rest:
+        p = (p * z + np.float32(c)).astype(np.float32)   # fma rounds once; this rounds twice
+    e = np.exp2(p.astype(np.float64))
+    approx = np.where(x >= 0, e, 2.0 - e)
+    assert np.abs(approx - erfc(x.astype(np.float64))).max() < 1e-7
