@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--cpu-pixels", type=int, default=256, help="pixels of the oracle CPU sample")
+    ap.add_argument("--cpu-pixels", type=int, default=1024, help="pixels of the oracle CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage timings to stderr")
     ap.add_argument("--full-keys", action="store_true", help="sort the 64-bit keys over all bits")
