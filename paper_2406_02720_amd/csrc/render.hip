@@ -54,64 +54,100 @@ __device__ __forceinline__ float erfc_fast(float x) {
   return x >= 0.0f ? e : 2.0f - e;
 }
 
-__device__ __forceinline__ float half_bound(const Record& r) {
-  return fmaxf(r.alpha2, fmaf(r.d_o, 2.0f, r.alpha2));
+constexpr float kLog2e = 1.44269504088896340736f;
+
+// Per-record values that do not depend on the lane (computed once per
+// wavefront): the conic scaled to log2 units, so that G = exp2(p2) with
+// p2 = -log2(e) q / 2, and a bound below which no pair of the record can
+// reach alpha_min (see pair_gauss).
+struct RecordU {
+  float A, B, C;     // -log2(e)/2 qa, -log2(e) qb, -log2(e)/2 qc
+  float hb;          // max(alpha2, alpha2 + 2 d_o) >= alpha2 + d_o I for I in [0, 2]
+  float p2_min;      // log2(alpha_min) - log2(hb) less a margin of 2^-10
+  float x0f, y0f;
+  bool split;        // d_o != 0
+};
+
+// `log2_amin` = log2(alpha_min), once per kernel.
+__device__ __forceinline__ RecordU record_uniform(const Record& r, int x0, int y0, float log2_amin) {
+  RecordU u;
+  u.A = r.qa * (-0.5f * kLog2e);
+  u.B = r.qb * (-kLog2e);
+  u.C = r.qc * (-0.5f * kLog2e);
+  u.hb = fmaxf(r.alpha2, fmaf(r.d_o, 2.0f, r.alpha2));
+  u.p2_min = (log2_amin - __builtin_amdgcn_logf(u.hb)) - 0.0009765625f;
+  u.x0f = (float)x0;
+  u.y0f = (float)y0;
+  u.split = r.d_o != 0.0f;
+  return u;
 }
 
 // Per-record values that a lane's pixels share (they lie in one column).
+// fpx = px + 1/2 is the pixel centre; fpx - x0 is exact in float.
 struct Column {
-  bool in;            // pixel column inside [x0, x1]
-  float dx, qadx, qbdx;
+  float dx, Adx2, Bdx, kxdx;
 };
 
-__device__ __forceinline__ Column column_of(const Record& r, int px, int x0, int x1) {
+__device__ __forceinline__ Column column_of(const Record& r, const RecordU& u, float fpx) {
   Column c;
-  c.in = px >= x0 && px <= x1;
-  c.dx = ((float)(px - x0) + 0.5f) - r.mx;
-  c.qadx = r.qa * c.dx;
-  c.qbdx = r.qb * c.dx;
+  c.dx = (fpx - u.x0f) - r.mx;
+  c.Adx2 = (u.A * c.dx) * c.dx;
+  c.Bdx = u.B * c.dx;
+  c.kxdx = r.kx * c.dx;
   return c;
 }
 
-// One pixel against one record, in two parts so that the lanes of a
-// wavefront can skip the second together.  Pure functions of their inputs:
-// the forward and backward passes take identical decisions.
-//   gauss:  offset, Gaussian G = exp(-q/2) of the dilated conic, and whether
-//           the pair can reach alpha_min at all: `amax_half` =
-//           max(alpha2, alpha2 + 2 d_o) bounds (alpha2 + d_o I) since I lies in
-//           [0, 2] and every rounding is monotone, so a pair whose bound
-//           G * amax_half is below alpha_min is dropped without the half factor
-//           -- the decision the full evaluation would take.
-//   opacity: half factor I (Eq. 7-8) and paired opacity HG = (alpha2 + d_o I) G
-//           (Eq. 10), alpha = min(alpha_max, HG).
-struct Pair {
-  bool pass;   // in rect, power <= 0, bound reaches alpha_min
-  float dy, G, I, HG, a;
-};
+// One pixel against one record, in stages that the lanes of a wavefront
+// skip together.  Every decision is a 64-bit lane mask (ballots of single
+// comparisons, combined on the scalar unit), and per-lane updates select on
+// a mask; forward and backward evaluate the same expressions, so they take
+// identical decisions.
+//   1. rect: pixel centre in the record's rect (column and row masks).
+//   2. p2 = log2 G = -log2(e) q / 2 of the dilated conic; p2 <= 0 and
+//      p2 >= p2_min.  A pair below p2_min has G * hb < alpha_min for the
+//      rounded G too (the 2^-10 margin covers the exp2 and log2 rounding),
+//      so it cannot reach alpha_min: the skip is exact.
+//   3. G = exp2(p2); G * hb >= alpha_min (hb bounds alpha2 + d_o I since I
+//      lies in [0, 2] and every rounding is monotone).
+//   4. half factor I (Eq. 7-8), HG = (alpha2 + d_o I) G (Eq. 10),
+//      alpha = min(alpha_max, HG) >= alpha_min.
+__device__ __forceinline__ uint64_t lanes(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool in_mask(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
-__device__ __forceinline__ void pair_gauss(const Record& r, const Column& c, bool row_in, int py, int y0,
-                                           float amax_half, float alpha_min, Pair& P) {
-  P.dy = ((float)(py - y0) + 0.5f) - r.my;
-  const float quad = fmaf(c.qadx, c.dx, (r.qc * P.dy) * P.dy);
-  const float power = fmaf(-0.5f, quad, -(c.qbdx * P.dy));
-  P.G = __expf(power);
-  P.pass = c.in && row_in && !(power > 0.0f) && !(P.G * amax_half < alpha_min);
+__device__ __forceinline__ float log2_gauss(const RecordU& u, const Column& c, float dy) {
+  return fmaf(u.C * dy, dy, fmaf(c.Bdx, dy, c.Adx2));
 }
 
-// `split` = (d_o != 0), uniform over the wavefront; without it I = 1.
-__device__ __forceinline__ void pair_opacity(const Record& r, const Column& c, bool split, float alpha_max,
-                                             Pair& P) {
-  P.I = split ? erfc_fast(-fmaf(r.kx, c.dx, r.ky * P.dy)) : 1.0f;
-  P.HG = fmaf(r.d_o, P.I, r.alpha2) * P.G;
-  P.a = fminf(alpha_max, P.HG);
+__device__ __forceinline__ float half_factor(const Record& r, const RecordU& u, const Column& c, float dy) {
+  return u.split ? erfc_fast(-fmaf(r.ky, dy, c.kxdx)) : 1.0f;
 }
 
+// A wavefront's block is SUB x SUB pixels; lane l holds column l % SUB of
+// rows l / SUB + j * ROWSTEP (j < PPL), so "strip" j is ROWSTEP full rows.
 template <int T>
 struct Geometry {
   static constexpr int SUB = (T == 8) ? 8 : 16;       // pixels per wavefront side
   static constexpr int PPL = SUB * SUB / 64;          // pixels per lane
   static constexpr int WAVES = (T / SUB) * (T / SUB); // wavefronts per tile
   static constexpr int ROWSTEP = 64 / SUB;            // rows between a lane's pixels
+  // one bit per row of a strip: bit r * SUB
+  static constexpr uint64_t REP = (SUB == 16) ? 0x0001000100010001ull : 0x0101010101010101ull;
+
+  // lanes whose column lies in [x0, x1] (block columns start at ox)
+  static __device__ __forceinline__ uint64_t col_mask(int x0, int x1, int ox) {
+    const int c0 = x0 - ox > 0 ? x0 - ox : 0;
+    const int c1 = x1 - ox < SUB - 1 ? x1 - ox : SUB - 1;
+    if (c0 > c1) return 0ull;
+    return ((2ull << c1) - (1ull << c0)) * REP;
+  }
+  // lanes of the strip starting at row `row0` whose row lies in [y0, y1]
+  static __device__ __forceinline__ uint64_t row_mask(int y0, int y1, int row0) {
+    const int r0 = y0 - row0 > 0 ? y0 - row0 : 0;
+    const int r1 = y1 - row0 < ROWSTEP - 1 ? y1 - row0 : ROWSTEP - 1;
+    if (r0 > r1) return 0ull;
+    const uint64_t hi = (r1 + 1) * SUB >= 64 ? ~0ull : (1ull << ((r1 + 1) * SUB)) - 1ull;
+    return hi & ~((1ull << (r0 * SUB)) - 1ull);
+  }
 };
 
 __device__ __forceinline__ Record load_record(const Record* __restrict__ rec, uint32_t id) {
@@ -172,10 +208,10 @@ __device__ __forceinline__ int wave_max(int v) {
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // One wavefront's block of pixels (sub-block `wave` of `tile`), front to back.
-// Per record, everything that does not depend on the lane is tested once for
-// the wavefront (rect rows against each strip of the block, any pixel still
+// Per record, everything that does not depend on the lane is decided once
+// for the wavefront on lane masks (rect against each strip, pixels still
 // open, any pair reaching alpha_min, d_o == 0); the per-pixel updates are
-// selects, so the lanes never branch apart.
+// selects on a mask, so the lanes never branch apart.
 template <int T, int IPL>
 __device__ __forceinline__ void fwd_block(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
@@ -194,35 +230,30 @@ __device__ __forceinline__ void fwd_block(
   const int ox = uniform(tx * T + (wave % (T / Gm::SUB)) * Gm::SUB);
   const int oy = uniform(ty * T + (wave / (T / Gm::SUB)) * Gm::SUB);
   const int px = ox + lane % Gm::SUB;
-  int py[PPL];
-  bool inside[PPL];
+  const float fpx = (float)px + 0.5f;
+  const int py0 = oy + lane / Gm::SUB;
   float Tr[PPL], C0[PPL], C1[PPL], C2[PPL];
   int32_t cnt[PPL], last[PPL];
-  bool done[PPL];
+  uint64_t open[PPL];   // lanes whose pixel j still takes entries
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    py[j] = oy + lane / Gm::SUB + j * RS;
-    inside[j] = px < cam.width && py[j] < cam.height;
     Tr[j] = 1.0f;
     C0[j] = C1[j] = C2[j] = 0.0f;
     cnt[j] = 0;
     last[j] = -1;
-    done[j] = !inside[j];
+    open[j] = lanes(px < cam.width && py0 + j * RS < cam.height);
   }
   // the tile's list; positions below are indices into it (fit int32: a
   // list holds at most one entry per record)
   const uint32_t* __restrict__ lst = vals + ranges[2 * tile];
   const int64_t len = (int64_t)ranges[2 * tile + 1] - (int64_t)ranges[2 * tile];
   const float amin = o.alpha_min, amax = o.alpha_max, tmin = o.t_min;
-  bool open = true;   // some pixel of the block still takes entries (uniform)
-  {
-    bool any = false;
+  const float l2amin = __builtin_amdgcn_logf(amin);
+  uint64_t any_open = 0ull;
 #pragma unroll
-    for (int j = 0; j < PPL; ++j) any |= !done[j];
-    open = __ballot(any) != 0ull;
-  }
+  for (int j = 0; j < PPL; ++j) any_open |= open[j];
 
-  for (int64_t base = 0; open && base < len; base += 64 * IPL) {
+  for (int64_t base = 0; any_open != 0ull && base < len; base += 64 * IPL) {
     uint32_t ids[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
@@ -233,46 +264,51 @@ __device__ __forceinline__ void fwd_block(
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       const int lim = (int)nb - k * 64;
-      if (lim <= 0 || !open) break;
+      if (lim <= 0 || any_open == 0ull) break;
       const int cntk = lim < 64 ? lim : 64;
-      for (int l = 0; l < cntk && open; ++l) {
+      for (int l = 0; l < cntk && any_open != 0ull; ++l) {
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
         const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
-        if (y1 < oy || y0 > oy + Gm::SUB - 1 || x1 < ox || x0 > ox + Gm::SUB - 1) continue;
+        const uint64_t cols = Gm::col_mask(x0, x1, ox);
+        if (cols == 0ull) continue;
         const int32_t pos = (int32_t)(base + k * 64 + l);
-        const float hb = half_bound(r);
-        const bool split = r.d_o != 0.0f;
-        const Column col = column_of(r, px, x0, x1);
+        const RecordU u = record_uniform(r, x0, y0, l2amin);
+        const Column col = column_of(r, u, fpx);
         bool ended = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          const int row = oy + j * RS;                       // first row of strip j
-          if (row + RS - 1 < y0 || row > y1) continue;        // strip misses the rect rows
-          Pair P;
-          pair_gauss(r, col, py[j] >= y0 && py[j] <= y1 && !done[j], py[j], y0, hb, amin, P);
-          if (__ballot(P.pass) == 0ull) continue;
-          pair_opacity(r, col, split, amax, P);
-          const bool blend = P.pass && !(P.a < amin);
-          const float Tn = Tr[j] * (1.0f - P.a);
-          const bool stop = blend && Tn < tmin;
-          const bool take = blend && !stop;
-          const float w = take ? P.a * Tr[j] : 0.0f;
+          uint64_t m = open[j] & cols & Gm::row_mask(y0, y1, oy + j * RS);
+          if (m == 0ull) continue;
+          const float dy = ((float)(py0 + j * RS) + 0.5f - u.y0f) - r.my;
+          const float p2 = log2_gauss(u, col, dy);
+          m &= lanes(!(p2 > 0.0f)) & lanes(!(p2 < u.p2_min));
+          if (m == 0ull) continue;
+          const float G = __builtin_amdgcn_exp2f(p2);
+          m &= lanes(!(G * u.hb < amin));
+          if (m == 0ull) continue;
+          const float I = half_factor(r, u, col, dy);
+          const float a = fminf(amax, fmaf(r.d_o, I, r.alpha2) * G);
+          m &= lanes(!(a < amin));
+          if (m == 0ull) continue;
+          const float Tn = Tr[j] * (1.0f - a);
+          const uint64_t stop = m & lanes(Tn < tmin);
+          const bool take = in_mask(m & ~stop);
+          const float w = take ? a * Tr[j] : 0.0f;
           C0[j] = fmaf(r.r, w, C0[j]);
           C1[j] = fmaf(r.g, w, C1[j]);
           C2[j] = fmaf(r.b, w, C2[j]);
           Tr[j] = take ? Tn : Tr[j];
           cnt[j] += take ? 1 : 0;
           last[j] = take ? pos : last[j];
-          done[j] = done[j] || stop;
-          ended |= stop;
+          open[j] &= ~stop;
+          ended |= stop != 0ull;
         }
-        if (__ballot(ended) != 0ull) {
-          bool any = false;
+        if (ended) {
+          any_open = 0ull;
 #pragma unroll
-          for (int j = 0; j < PPL; ++j) any |= !done[j];
-          open = __ballot(any) != 0ull;
+          for (int j = 0; j < PPL; ++j) any_open |= open[j];
         }
       }
     }
@@ -281,8 +317,9 @@ __device__ __forceinline__ void fwd_block(
   float* im = img + 3 * cam.pix_off;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    if (!inside[j]) continue;
-    const uint64_t pix = (uint64_t)py[j] * cam.width + px;
+    const int py = py0 + j * RS;
+    if (!(px < cam.width && py < cam.height)) continue;
+    const uint64_t pix = (uint64_t)py * cam.width + px;
     im[pix] = fmaf(Tr[j], o.bg[0], C0[j]);
     im[plane + pix] = fmaf(Tr[j], o.bg[1], C1[j]);
     im[2 * plane + pix] = fmaf(Tr[j], o.bg[2], C2[j]);
@@ -325,7 +362,7 @@ __global__ __launch_bounds__(64) void render_fwd_persistent_kernel(
                       (int)(w % WAVES), lane);
 }
 
-// One wavefront's block of pixels, back to front.  Same uniform skips as the
+// One wavefront's block of pixels, back to front.  Same masks as the
 // forward pass; a pixel takes part in an entry only at or before its last
 // blended one, and the state of the other lanes is kept by selects (their
 // gradient terms are exact zeros).
@@ -347,23 +384,24 @@ __device__ __forceinline__ void bwd_block(
   const int ox = uniform(tx * T + (wave % (T / Gm::SUB)) * Gm::SUB);
   const int oy = uniform(ty * T + (wave / (T / Gm::SUB)) * Gm::SUB);
   const int px = ox + lane % Gm::SUB;
+  const float fpx = (float)px + 0.5f;
+  const int py0 = oy + lane / Gm::SUB;
   const uint64_t plane = (uint64_t)cam.width * cam.height;
   const float* g = dL_dimg + 3 * cam.pix_off;
 
-  int py[PPL];
   int32_t last[PPL], top_j[PPL];
   float Tr[PPL], dL0[PPL], dL1[PPL], dL2[PPL];
   float acc0[PPL], acc1[PPL], acc2[PPL], tbg[PPL];
   int top = -1;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    py[j] = oy + lane / Gm::SUB + j * RS;
-    const bool inside = px < cam.width && py[j] < cam.height;
+    const int py = py0 + j * RS;
+    const bool inside = px < cam.width && py < cam.height;
     last[j] = -1;
     float Tf = 1.0f;
     dL0[j] = dL1[j] = dL2[j] = 0.0f;
     if (inside) {
-      const uint64_t pix = (uint64_t)py[j] * cam.width + px;
+      const uint64_t pix = (uint64_t)py * cam.width + px;
       Tf = T_final[cam.pix_off + pix];
       last[j] = last_idx[cam.pix_off + pix];
       dL0[j] = g[pix];
@@ -381,6 +419,7 @@ __device__ __forceinline__ void bwd_block(
   if (top < 0) return;
   const uint32_t* __restrict__ lst = vals + ranges[2 * tile];
   const float amin = o.alpha_min, amax = o.alpha_max;
+  const float l2amin = __builtin_amdgcn_logf(amin);
 
   // list indices top, top-1, ..., 0 in rounds of 64 * IPL
   for (int32_t hi = top; hi >= 0; hi -= 64 * IPL) {
@@ -401,57 +440,67 @@ __device__ __forceinline__ void bwd_block(
         const Record r = load_record(rec, id);
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
         const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
-        if (y1 < oy || y0 > oy + Gm::SUB - 1 || x1 < ox || x0 > ox + Gm::SUB - 1) continue;
+        const uint64_t cols = Gm::col_mask(x0, x1, ox);
+        if (cols == 0ull) continue;
         const int32_t pos = hi - (k * 64 + l);
-        const float hb = half_bound(r);
-        const bool split = r.d_o != 0.0f;
-        const Column col = column_of(r, px, x0, x1);
+        const RecordU u = record_uniform(r, x0, y0, l2amin);
+        const Column col = column_of(r, u, fpx);
         float gs[HGS_RECORD_GRAD_FLOATS];
 #pragma unroll
         for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q) gs[q] = 0.0f;
         bool any = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          const int row = oy + j * RS;
-          if (row + RS - 1 < y0 || row > y1 || pos > top_j[j]) continue;
-          Pair P;
-          pair_gauss(r, col, py[j] >= y0 && py[j] <= y1 && pos <= last[j], py[j], y0, hb, amin, P);
-          if (__ballot(P.pass) == 0ull) continue;
-          pair_opacity(r, col, split, amax, P);
-          const bool m = P.pass && !(P.a < amin);
-          if (__ballot(m) == 0ull) continue;
+          if (pos > top_j[j]) continue;
+          uint64_t m = cols & Gm::row_mask(y0, y1, oy + j * RS);
+          if (m == 0ull) continue;
+          m &= lanes(pos <= last[j]);
+          if (m == 0ull) continue;
+          const float dy = ((float)(py0 + j * RS) + 0.5f - u.y0f) - r.my;
+          const float p2 = log2_gauss(u, col, dy);
+          m &= lanes(!(p2 > 0.0f)) & lanes(!(p2 < u.p2_min));
+          if (m == 0ull) continue;
+          const float G = __builtin_amdgcn_exp2f(p2);
+          m &= lanes(!(G * u.hb < amin));
+          if (m == 0ull) continue;
+          const float I = half_factor(r, u, col, dy);
+          const float HG = fmaf(r.d_o, I, r.alpha2) * G;
+          const float a = fminf(amax, HG);
+          m &= lanes(!(a < amin));
+          if (m == 0ull) continue;
           any = true;
-          const float a = P.a;
+          const bool on = in_mask(m);
           const float inv1ma = __builtin_amdgcn_rcpf(1.0f - a);  // 1 - a >= 1 - alpha_max
           const float Tb = Tr[j] * inv1ma;
-          const float wcol = m ? a * Tb : 0.0f;
+          const float wcol = on ? a * Tb : 0.0f;
           gs[9] += wcol * dL0[j];
           gs[10] += wcol * dL1[j];
           gs[11] += wcol * dL2[j];
           // acc: colour of the entries behind this one (already replayed)
           float dLda = ((r.r - acc0[j]) * dL0[j] + (r.g - acc1[j]) * dL1[j] + (r.b - acc2[j]) * dL2[j]) * Tb;
           dLda = fmaf(inv1ma, tbg[j], dLda);
-          acc0[j] = m ? a * r.r + (1.0f - a) * acc0[j] : acc0[j];
-          acc1[j] = m ? a * r.g + (1.0f - a) * acc1[j] : acc1[j];
-          acc2[j] = m ? a * r.b + (1.0f - a) * acc2[j] : acc2[j];
-          Tr[j] = m ? Tb : Tr[j];
-          const float dHG = (!m || P.HG > amax) ? 0.0f : dLda;
-          const float dG = dHG * (r.alpha2 + r.d_o * P.I);
-          gs[7] += dHG * P.G;
-          gs[8] += dHG * P.I * P.G;
+          acc0[j] = on ? a * r.r + (1.0f - a) * acc0[j] : acc0[j];
+          acc1[j] = on ? a * r.g + (1.0f - a) * acc1[j] : acc1[j];
+          acc2[j] = on ? a * r.b + (1.0f - a) * acc2[j] : acc2[j];
+          Tr[j] = on ? Tb : Tr[j];
+          // no gradient through the alpha_max clamp
+          const float dHG = in_mask(m & lanes(!(HG > amax))) ? dLda : 0.0f;
+          const float dG = dHG * (r.alpha2 + r.d_o * I);
+          gs[7] += dHG * G;
+          gs[8] += dHG * I * G;
           float du = 0.0f;
-          if (split) {
-            const float u = r.kx * col.dx + r.ky * P.dy;
-            du = dHG * r.d_o * P.G * kTwoOverSqrtPi * __expf(-u * u);
+          if (u.split) {
+            const float w = fmaf(r.ky, dy, col.kxdx);
+            du = dHG * r.d_o * G * kTwoOverSqrtPi * __builtin_amdgcn_exp2f(-kLog2e * w * w);
           }
           gs[5] += du * col.dx;
-          gs[6] += du * P.dy;
-          const float GG = dG * P.G;
-          gs[0] += GG * (col.qadx + r.qb * P.dy) - du * r.kx;
-          gs[1] += GG * (col.qbdx + r.qc * P.dy) - du * r.ky;
+          gs[6] += du * dy;
+          const float GG = dG * G;
+          gs[0] += GG * (r.qa * col.dx + r.qb * dy) - du * r.kx;
+          gs[1] += GG * (r.qb * col.dx + r.qc * dy) - du * r.ky;
           gs[2] += -0.5f * GG * col.dx * col.dx;
-          gs[3] += -GG * col.dx * P.dy;
-          gs[4] += -0.5f * GG * P.dy * P.dy;
+          gs[3] += -GG * col.dx * dy;
+          gs[4] += -0.5f * GG * dy * dy;
         }
         if (!any) continue;
         float tot[3];
