@@ -211,9 +211,18 @@ def main():
         passes = (32 + tb + 7) // 8
         bytes_sort = (n_rec * 28 + n_dup * 12 + passes * n_dup * 24 + n_dup * 8 + tiles_total * 8)
     else:
-        passes = (tb + 7) // 8
-        bytes_sort = (n_rec * (12 + 4 * 16 + 12 + 16 + 28) + n_dup * 8 + passes * n_dup * 16
-                      + n_dup * 4 + tiles_total * 8)
+        # placement: depth keys (16 B) and four record passes (16 B each) per
+        # record, the record rects read for counting and for placing (16 B
+        # each), the count array [blocks][tiles] written, read for the totals,
+        # read and rewritten as offsets, read for placing (16 B per cell),
+        # 4 B written per entry, tile totals / starts / ranges (20 B per tile);
+        # blocks as the library sizes them (>= 1024 records, <= 16 Mi cells)
+        passes = 0
+        rb = max(1024, -(-(n_rec * tiles_total) // (16 << 20)))
+        rb = -(-rb // 64) * 64
+        n_blocks = -(-n_rec // rb)
+        bytes_sort = (n_rec * (16 + 4 * 16 + 16 + 16) + 16 * n_blocks * tiles_total + 4 * n_dup
+                      + 20 * tiles_total)
     bytes_pbwd = n * (param_bytes + param_bytes) + n_rec * (48 + 48 + 4)
     # FP32 operations of one pair, written out (fma = 2): evaluation
     # (offsets, quadratic form, exp, half factor, Eq. 10 opacity, clamp) and,
@@ -247,7 +256,7 @@ def main():
     if args.stages:
         for name in stage_names:
             print(f"{name:15s} {st[name]:8.3f} ms", file=sys.stderr)
-        print(f"n_dup {n_dup}  tile passes {passes}  pairs {pairs}  blended {blended}  step {ms_step:.3f} ms",
+        print(f"n_dup {n_dup}  entry passes {passes}  pairs {pairs}  blended {blended}  step {ms_step:.3f} ms",
               file=sys.stderr)
         print(json.dumps(roof), file=sys.stderr)
 
@@ -274,7 +283,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS.get(args.config, str(args.config)), "n_kernels": n,
                    "views": len(cams), "pixels": W, "tile": args.tile, "batch": args.batch,
-                   "entries": n_dup, "sort": "full_keys" if args.full_keys else "depth_first",
+                   "entries": n_dup, "sort": "full_keys" if args.full_keys else "placement",
                    "raster": "per_tile" if args.per_tile else "persistent"},
         "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
         "fwd_bwd_over_fwd": round((fwd_ms + bwd_ms) / fwd_ms, 3),

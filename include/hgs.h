@@ -13,8 +13,9 @@
  * Pipeline (each call only enqueues work on `stream`; nothing blocks):
  *   hgs_preprocess  projection, half factor, valid region, SH colour, depth,
  *                   tiles touched and their exclusive scan
- *   hgs_bin_sort    one (tile | depth, record) entry per covered tile, a
- *                   stable radix sort of the 64-bit keys, per-tile ranges
+ *   hgs_bin_sort    one (tile | depth, record) entry per covered tile in
+ *                   key order (depth sort of the records, then placement
+ *                   by counting), per-tile ranges
  *   hgs_render_fwd  per-pixel front-to-back blending
  *   hgs_render_bwd  per-pixel back-to-front replay, per-record gradients,
  *                   chain rule to every kernel parameter
@@ -67,8 +68,9 @@ extern "C" {
                                     no half-aware region and no opacity cull  */
 #define HGS_FLAG_SORT_FULL_KEYS 2u /* hgs_bin_sort: radix-sort the duplicated
                                     entries over all 32 + tile bits of their
-                                    64-bit keys instead of sorting the records
-                                    by depth first (same result)              */
+                                    64-bit keys instead of placing them by
+                                    counting after a depth sort of the
+                                    records (same result)                     */
 
 /* Pinhole camera.  R is the world->camera rotation (row-major 3x3), t the
  * translation (x_cam = R x_world + t).  fx, fy, cx, cy in pixels.  Kernels
@@ -178,20 +180,22 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
                    uint64_t* offsets, uint64_t* n_dup, void* workspace, size_t workspace_bytes,
                    hipStream_t stream);
 
-/* Duplicate every record once per tile of its tile rectangle with key
- * (global tile << 32 | fp32 depth bits) and value record id, sort the
- * entries by key with a stable LSD radix sort (so equal keys stay in record
- * order), and write the [start, end) range of every tile.  By default the
- * radix passes over the 32 depth bits run on the records before duplication
- * (every entry of a record shares its depth) and only the tile bits are
- * sorted over the entries; HGS_FLAG_SORT_FULL_KEYS sorts the duplicated
- * 64-bit keys over all bits.  Both give the same order.
+/* The tile lists of the tile-based rasterizer (Sec. 3.1, built as in 3D-GS):
+ * one (tile, record) entry per tile of every record's tile rectangle, in the
+ * order of the key (global tile << 32 | fp32 depth bits), ties by record id,
+ * and the [start, end) range of every tile.  By default the records are
+ * radix-sorted by (depth, id) and each entry is then written straight to its
+ * final position (per-tile counts over blocks of depth-ordered records,
+ * their scans, then cursors that hand out each tile's positions in record
+ * order); HGS_FLAG_SORT_FULL_KEYS duplicates the 64-bit keys and radix-sorts
+ * them over all bits.  Both give the same entries, ranges and order.
  *   records, tiles_touched, offsets, n_dup   from hgs_preprocess (device)
  *   n_rec          n_cams * n
  *   keys, values   device, `capacity` entries each (out: sorted entries in
  *                  the first *n_dup positions); keys may be NULL unless
  *                  HGS_FLAG_SORT_FULL_KEYS is set (the raster needs only the
- *                  values and ranges)
+ *                  values and ranges; by default keys, when given, are
+ *                  written from the ranges after placement)
  *   ranges         device, uint32 [tiles_total][2] (out); a tile without
  *                  entries gets [0, 0)
  *   tile_order     device, uint32 [tiles_total] (out), may be NULL: the tile

@@ -282,7 +282,7 @@ __device__ __forceinline__ void add_sym_outer(Sym3& S, const double* u, const do
   S.yz += w * 0.5 * (u[1] * v[2] + u[2] * v[1]);
 }
 
-template <int D>
+template <int D, bool MULTI>
 __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     Params p, CamPack cp, Opts o, const Record* __restrict__ rec,
     float* __restrict__ rgrad, Grads G) {
@@ -305,13 +305,17 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   Sym3 g_Sw = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double g_nh[3] = {0.0, 0.0, 0.0};
   double g_a1 = 0.0, g_a2 = 0.0;
-  float g_sh[3 * K];
+  // SH gradients: summed over cameras in registers with several cameras,
+  // stored as soon as they are known with one
+  float g_sh[MULTI ? 3 * K : 1];
 #pragma unroll
-  for (int j = 0; j < 3 * K; ++j) g_sh[j] = 0.0f;
+  for (int j = 0; j < (MULTI ? 3 * K : 1); ++j) g_sh[j] = 0.0f;
+  bool sh_done = false;
 
   for (int c = 0; c < cp.n_cams; ++c) {
     const int64_t ri = (int64_t)c * p.n + i;
-    if (rec[ri].tiles == 0) continue;  // culled: no gradient, nothing to clear
+    const Record& R = rec[ri];
+    if (R.tiles == 0) continue;  // culled: no gradient, nothing to clear
     float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS;
     float4* gr4 = reinterpret_cast<float4*>(gr);
     const float4 r0 = gr4[0], r1 = gr4[1], r2 = gr4[2];
@@ -330,41 +334,42 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     ViewGeo vg;
     view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
 
-    // ---- colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - o) / |mu - o|
+    // ---- colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - o) / |mu - o|.
+    // In FP32 (no decision depends on it); the clamp is active exactly where
+    // the stored colour is 0, so each coefficient is read once.
     {
       double oc[3];
       camera_centre(cam, oc);
       const double dv0 = kg.mu[0] - oc[0], dv1 = kg.mu[1] - oc[1], dv2 = kg.mu[2] - oc[2];
       const double dl = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
       const double il = 1.0 / dl;
-      const double d0 = dv0 * il, d1 = dv1 * il, d2 = dv2 * il;
-      double Y[K];
+      const float d0 = (float)(dv0 * il), d1 = (float)(dv1 * il), d2 = (float)(dv2 * il);
+      const float gc[3] = {R.r > 0.0f ? (float)gcol[0] : 0.0f, R.g > 0.0f ? (float)gcol[1] : 0.0f,
+                           R.b > 0.0f ? (float)gcol[2] : 0.0f};
+      float Y[K];
       sh_eval<D>(d0, d1, d2, Y);
-      double raw[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < K; ++kk)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[kk] * (double)p.sh[(kk * 3 + ch) * S + i];
-      double gc[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) gc[ch] = (raw[ch] + 0.5 > 0.0) ? gcol[ch] : 0.0;
-      double wk[K];
+      float wk[K];
 #pragma unroll
       for (int kk = 0; kk < K; ++kk) {
-        double acc = 0.0;
+        float acc = 0.0f;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-          g_sh[kk * 3 + ch] += (float)(gc[ch] * Y[kk]);
-          acc += gc[ch] * (double)p.sh[(kk * 3 + ch) * S + i];
+          const float v = gc[ch] * Y[kk];
+          if constexpr (MULTI)
+            g_sh[kk * 3 + ch] += v;
+          else
+            G.sh[(kk * 3 + ch) * S + i] = v;
+          acc = fmaf(gc[ch], p.sh[(kk * 3 + ch) * S + i], acc);
         }
         wk[kk] = acc;
       }
-      double gd0, gd1, gd2;
+      sh_done = true;
+      float gd0, gd1, gd2;
       sh_grad<D>(d0, d1, d2, wk, &gd0, &gd1, &gd2);
-      const double dot = gd0 * d0 + gd1 * d1 + gd2 * d2;
-      g_mu[0] += (gd0 - d0 * dot) * il;
-      g_mu[1] += (gd1 - d1 * dot) * il;
-      g_mu[2] += (gd2 - d2 * dot) * il;
+      const float dot = gd0 * d0 + gd1 * d1 + gd2 * d2;
+      g_mu[0] += (double)(gd0 - d0 * dot) * il;
+      g_mu[1] += (double)(gd1 - d1 * dot) * il;
+      g_mu[2] += (double)(gd2 - d2 * dot) * il;
     }
 
     // ---- k = w r, r = (2 s2)^-1/2, w = Q g, s2 = v - g.w (or 1e-12 v)
@@ -512,8 +517,13 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   for (int c = 0; c < 4; ++c) G.quats[c * S + i] = (float)gq_raw[c];
   G.opac1[i] = (float)g_a1;
   G.opac2[i] = (float)g_a2;
+  if constexpr (MULTI) {
 #pragma unroll
-  for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = g_sh[j];
+    for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = g_sh[j];
+  } else if (!sh_done) {
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = 0.0f;
+  }
 }
 
 }  // namespace
@@ -555,12 +565,16 @@ hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts&
                                  hipStream_t s) {
   if (p.n == 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
+#define HGS_PBWD(D_, M_) \
+  hipLaunchKernelGGL((preprocess_bwd_kernel<D_, M_>), dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g)
+  const bool multi = cp.n_cams > 1;
   switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(preprocess_bwd_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
-    case 1: hipLaunchKernelGGL(preprocess_bwd_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
-    case 2: hipLaunchKernelGGL(preprocess_bwd_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
-    default: hipLaunchKernelGGL(preprocess_bwd_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+    case 0: if (multi) HGS_PBWD(0, true); else HGS_PBWD(0, false); break;
+    case 1: if (multi) HGS_PBWD(1, true); else HGS_PBWD(1, false); break;
+    case 2: if (multi) HGS_PBWD(2, true); else HGS_PBWD(2, false); break;
+    default: if (multi) HGS_PBWD(3, true); else HGS_PBWD(3, false); break;
   }
+#undef HGS_PBWD
   return hipGetLastError();
 }
 

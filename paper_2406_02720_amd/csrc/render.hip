@@ -57,27 +57,24 @@ __device__ __forceinline__ float erfc_fast(float x) {
 constexpr float kLog2e = 1.44269504088896340736f;
 
 // Per-record values that do not depend on the lane (computed once per
-// wavefront): the conic scaled to log2 units, so that G = exp2(p2) with
-// p2 = -log2(e) q / 2, and a bound below which no pair of the record can
-// reach alpha_min (see pair_gauss).
+// wavefront): a bound below which no pair of the record can reach alpha_min
+// (see below) and the rect corner as floats.
 struct RecordU {
-  float A, B, C;     // -log2(e)/2 qa, -log2(e) qb, -log2(e)/2 qc
   float hb;          // max(alpha2, alpha2 + 2 d_o) >= alpha2 + d_o I for I in [0, 2]
   float p2_min;      // log2(alpha_min) - log2(hb) less a margin of 2^-10
   float x0f, y0f;
+  float y1p;         // y1 + 1/2: a pixel row py lies in the rect iff y0 < py + 1/2 < y1 + 1
   bool split;        // d_o != 0
 };
 
 // `log2_amin` = log2(alpha_min), once per kernel.
-__device__ __forceinline__ RecordU record_uniform(const Record& r, int x0, int y0, float log2_amin) {
+__device__ __forceinline__ RecordU record_uniform(const Record& r, int x0, int y0, int y1, float log2_amin) {
   RecordU u;
-  u.A = r.qa * (-0.5f * kLog2e);
-  u.B = r.qb * (-kLog2e);
-  u.C = r.qc * (-0.5f * kLog2e);
   u.hb = fmaxf(r.alpha2, fmaf(r.d_o, 2.0f, r.alpha2));
   u.p2_min = (log2_amin - __builtin_amdgcn_logf(u.hb)) - 0.0009765625f;
   u.x0f = (float)x0;
   u.y0f = (float)y0;
+  u.y1p = (float)y1 + 1.0f;
   u.split = r.d_o != 0.0f;
   return u;
 }
@@ -85,14 +82,14 @@ __device__ __forceinline__ RecordU record_uniform(const Record& r, int x0, int y
 // Per-record values that a lane's pixels share (they lie in one column).
 // fpx = px + 1/2 is the pixel centre; fpx - x0 is exact in float.
 struct Column {
-  float dx, Adx2, Bdx, kxdx;
+  float dx, qadx, qbdx, kxdx;
 };
 
 __device__ __forceinline__ Column column_of(const Record& r, const RecordU& u, float fpx) {
   Column c;
   c.dx = (fpx - u.x0f) - r.mx;
-  c.Adx2 = (u.A * c.dx) * c.dx;
-  c.Bdx = u.B * c.dx;
+  c.qadx = r.qa * c.dx;
+  c.qbdx = r.qb * c.dx;
   c.kxdx = r.kx * c.dx;
   return c;
 }
@@ -103,10 +100,11 @@ __device__ __forceinline__ Column column_of(const Record& r, const RecordU& u, f
 // a mask; forward and backward evaluate the same expressions, so they take
 // identical decisions.
 //   1. rect: pixel centre in the record's rect (column and row masks).
-//   2. p2 = log2 G = -log2(e) q / 2 of the dilated conic; p2 <= 0 and
-//      p2 >= p2_min.  A pair below p2_min has G * hb < alpha_min for the
-//      rounded G too (the 2^-10 margin covers the exp2 and log2 rounding),
-//      so it cannot reach alpha_min: the skip is exact.
+//   2. power = -q / 2 of the dilated conic, p2 = log2(e) power (so that
+//      G = exp2(p2)); power <= 0 and p2 >= p2_min.  A pair below p2_min has
+//      G * hb < alpha_min for the rounded G too (the 2^-10 margin covers the
+//      exp2 and log2 rounding), so it cannot reach alpha_min: the skip is
+//      exact.
 //   3. G = exp2(p2); G * hb >= alpha_min (hb bounds alpha2 + d_o I since I
 //      lies in [0, 2] and every rounding is monotone).
 //   4. half factor I (Eq. 7-8), HG = (alpha2 + d_o I) G (Eq. 10),
@@ -114,8 +112,9 @@ __device__ __forceinline__ Column column_of(const Record& r, const RecordU& u, f
 __device__ __forceinline__ uint64_t lanes(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ __forceinline__ bool in_mask(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
-__device__ __forceinline__ float log2_gauss(const RecordU& u, const Column& c, float dy) {
-  return fmaf(u.C * dy, dy, fmaf(c.Bdx, dy, c.Adx2));
+__device__ __forceinline__ float gauss_power(const Record& r, const Column& c, float dy) {
+  const float quad = fmaf(c.qadx, c.dx, (r.qc * dy) * dy);
+  return fmaf(-0.5f, quad, -(c.qbdx * dy));
 }
 
 __device__ __forceinline__ float half_factor(const Record& r, const RecordU& u, const Column& c, float dy) {
@@ -133,20 +132,20 @@ struct Geometry {
   // one bit per row of a strip: bit r * SUB
   static constexpr uint64_t REP = (SUB == 16) ? 0x0001000100010001ull : 0x0101010101010101ull;
 
+  // strips (bit j) whose rows meet [y0, y1] (block rows start at oy)
+  static __device__ __forceinline__ uint32_t strip_bits(int y0, int y1, int oy) {
+    const int a = y0 - oy, b = y1 - oy;
+    if (b < 0 || a > SUB - 1) return 0u;
+    const int ja = a > 0 ? a / ROWSTEP : 0;
+    const int jb = b < SUB - 1 ? b / ROWSTEP : PPL - 1;
+    return (2u << jb) - (1u << ja);
+  }
   // lanes whose column lies in [x0, x1] (block columns start at ox)
   static __device__ __forceinline__ uint64_t col_mask(int x0, int x1, int ox) {
     const int c0 = x0 - ox > 0 ? x0 - ox : 0;
     const int c1 = x1 - ox < SUB - 1 ? x1 - ox : SUB - 1;
     if (c0 > c1) return 0ull;
     return ((2ull << c1) - (1ull << c0)) * REP;
-  }
-  // lanes of the strip starting at row `row0` whose row lies in [y0, y1]
-  static __device__ __forceinline__ uint64_t row_mask(int y0, int y1, int row0) {
-    const int r0 = y0 - row0 > 0 ? y0 - row0 : 0;
-    const int r1 = y1 - row0 < ROWSTEP - 1 ? y1 - row0 : ROWSTEP - 1;
-    if (r0 > r1) return 0ull;
-    const uint64_t hi = (r1 + 1) * SUB >= 64 ? ~0ull : (1ull << ((r1 + 1) * SUB)) - 1ull;
-    return hi & ~((1ull << (r0 * SUB)) - 1ull);
   }
 };
 
@@ -272,18 +271,22 @@ __device__ __forceinline__ void fwd_block(
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
         const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
         const uint64_t cols = Gm::col_mask(x0, x1, ox);
-        if (cols == 0ull) continue;
+        const uint32_t strips = Gm::strip_bits(y0, y1, oy);
+        if (cols == 0ull || strips == 0u) continue;
         const int32_t pos = (int32_t)(base + k * 64 + l);
-        const RecordU u = record_uniform(r, x0, y0, l2amin);
+        const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
         bool ended = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          uint64_t m = open[j] & cols & Gm::row_mask(y0, y1, oy + j * RS);
+          if (!((strips >> j) & 1u)) continue;
+          const float fpy = (float)(py0 + j * RS) + 0.5f;
+          uint64_t m = open[j] & cols & lanes(fpy > u.y0f) & lanes(fpy < u.y1p);
           if (m == 0ull) continue;
-          const float dy = ((float)(py0 + j * RS) + 0.5f - u.y0f) - r.my;
-          const float p2 = log2_gauss(u, col, dy);
-          m &= lanes(!(p2 > 0.0f)) & lanes(!(p2 < u.p2_min));
+          const float dy = (fpy - u.y0f) - r.my;
+          const float power = gauss_power(r, col, dy);
+          const float p2 = power * kLog2e;
+          m &= lanes(!(power > 0.0f)) & lanes(!(p2 < u.p2_min));
           if (m == 0ull) continue;
           const float G = __builtin_amdgcn_exp2f(p2);
           m &= lanes(!(G * u.hb < amin));
@@ -441,9 +444,10 @@ __device__ __forceinline__ void bwd_block(
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
         const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
         const uint64_t cols = Gm::col_mask(x0, x1, ox);
-        if (cols == 0ull) continue;
+        const uint32_t strips = Gm::strip_bits(y0, y1, oy);
+        if (cols == 0ull || strips == 0u) continue;
         const int32_t pos = hi - (k * 64 + l);
-        const RecordU u = record_uniform(r, x0, y0, l2amin);
+        const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
         float gs[HGS_RECORD_GRAD_FLOATS];
 #pragma unroll
@@ -451,14 +455,14 @@ __device__ __forceinline__ void bwd_block(
         bool any = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          if (pos > top_j[j]) continue;
-          uint64_t m = cols & Gm::row_mask(y0, y1, oy + j * RS);
+          if (pos > top_j[j] || !((strips >> j) & 1u)) continue;
+          const float fpy = (float)(py0 + j * RS) + 0.5f;
+          uint64_t m = cols & lanes(fpy > u.y0f) & lanes(fpy < u.y1p) & lanes(pos <= last[j]);
           if (m == 0ull) continue;
-          m &= lanes(pos <= last[j]);
-          if (m == 0ull) continue;
-          const float dy = ((float)(py0 + j * RS) + 0.5f - u.y0f) - r.my;
-          const float p2 = log2_gauss(u, col, dy);
-          m &= lanes(!(p2 > 0.0f)) & lanes(!(p2 < u.p2_min));
+          const float dy = (fpy - u.y0f) - r.my;
+          const float power = gauss_power(r, col, dy);
+          const float p2 = power * kLog2e;
+          m &= lanes(!(power > 0.0f)) & lanes(!(p2 < u.p2_min));
           if (m == 0ull) continue;
           const float G = __builtin_amdgcn_exp2f(p2);
           m &= lanes(!(G * u.hb < amin));
@@ -496,8 +500,8 @@ __device__ __forceinline__ void bwd_block(
           gs[5] += du * col.dx;
           gs[6] += du * dy;
           const float GG = dG * G;
-          gs[0] += GG * (r.qa * col.dx + r.qb * dy) - du * r.kx;
-          gs[1] += GG * (r.qb * col.dx + r.qc * dy) - du * r.ky;
+          gs[0] += GG * (col.qadx + r.qb * dy) - du * r.kx;
+          gs[1] += GG * (col.qbdx + r.qc * dy) - du * r.ky;
           gs[2] += -0.5f * GG * col.dx * col.dx;
           gs[3] += -GG * col.dx * dy;
           gs[4] += -0.5f * GG * dy * dy;

@@ -1,24 +1,34 @@
 // Binning and sorting of (tile | depth, record) entries.
 //
 // The entries must end up ordered by the 64-bit key tile << 32 | depth bits,
-// ties by record id.  An LSD radix sort does this with 8-bit digits, low
-// digits first.  Every entry of a record carries that record's depth, so the
-// four passes over the depth digits can be applied to the N records before
-// they are duplicated ("depth-first"):
+// ties by record id: each tile's list holds the records covering it in
+// (depth, id) order.
+//
+// Default path ("placement").  Every entry of a record carries that
+// record's depth, so the depth order is established once, on the N records:
 //
 //   1. depth keys of the records (+ their digit histograms), four one-sweep
-//      passes over the N records -> record ids in (depth, id) order;
-//   2. tiles touched in that order, exclusive scan -> entry offsets;
-//   3. duplicate: one (tile, record id) entry per covered tile, written in
-//      record order (+ histograms of the tile digits);
-//   4. one-sweep passes over the ceil(log2 tiles) tile bits of the entries
-//      (32-bit keys) -- stable, so equal tiles keep (depth, id) order;
-//   5. tile ranges.
+//      passes over the records -> record ids in (depth, id) order;
+//   2. the ordered records are cut into blocks of RB consecutive records and
+//      the tiles into bands of kBand consecutive tile ids.  For each (block,
+//      band) a wavefront counts how many of the block's records cover each
+//      tile of the band (two LDS increments per rect row into a difference
+//      array, then a prefix sum) -> counts[block][tile];
+//   3. per tile: total over blocks, exclusive scan over tiles -> the tile's
+//      first entry (its range), and per block the running offset, i.e. where
+//      the block's first entry for that tile goes;
+//   4. for each (block, band) a wavefront loads those offsets into LDS as
+//      cursors and walks the block's records in order; a record's covered
+//      tiles (one per lane) take their cursor's position and advance it.
+//      Records are walked one after another, so each tile's positions are
+//      handed out in (depth, id) order: the result is exactly the sorted
+//      entry list, and no entry key is ever written or sorted.
 //
-// The entries then move through only ceil(tile bits / 8) passes instead of
-// ceil((32 + tile bits) / 8).  With HGS_FLAG_SORT_FULL_KEYS the entries are
-// instead duplicated with full 64-bit keys in record order and sorted over
-// all 32 + tile bits.  Both produce the same entry order.
+// The entries cost one 4-byte write each (their record id) instead of a
+// duplication and ceil(tile bits / 8) sorting passes over 8-byte pairs.
+// With HGS_FLAG_SORT_FULL_KEYS the entries are instead duplicated with full
+// 64-bit keys in record order and sorted over all 32 + tile bits, the
+// literal form of the method's sort; both paths produce the same order.
 //
 // One-sweep pass (Onesweep, Adinets & Merrill 2022): a block takes a
 // partition ticket (forward progress: earlier partitions belong to blocks
@@ -173,13 +183,6 @@ __global__ __launch_bounds__(kBlock) void depth_keys_kernel(const Record* __rest
   }
   __syncthreads();
   flush_hist(s_h, 4 * kRadix, hist);
-}
-
-__global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* __restrict__ ids,
-                                                               const uint32_t* __restrict__ tiles,
-                                                               int64_t n, uint32_t* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) out[i] = tiles[ids[i]];
 }
 
 // Output chunks of the duplication: a wavefront writes the entries
@@ -465,43 +468,6 @@ __global__ __launch_bounds__(kBlock) void ranges_kernel(const K* __restrict__ ke
     ranges[2 * (uint64_t)tile + 1] = (uint32_t)(i + 1);
 }
 
-// The same for sorted 32-bit tile keys, eight consecutive keys per thread
-// (two 16-byte loads; the keys buffer is 256-byte aligned), grid-strided.
-constexpr int kRangeItems = 8;
-__global__ __launch_bounds__(kBlock) void ranges_u32_kernel(const uint32_t* __restrict__ keys,
-                                                            const uint64_t* __restrict__ n_dup,
-                                                            int64_t capacity,
-                                                            uint32_t* __restrict__ ranges) {
-  const uint64_t n = entry_count(n_dup, capacity);
-  const uint64_t groups = (n + kRangeItems - 1) / kRangeItems;
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < groups; g += stride) {
-    const uint64_t i0 = g * kRangeItems;
-    uint32_t k[kRangeItems];
-    if (i0 + kRangeItems <= n) {
-      const uint4 a = *reinterpret_cast<const uint4*>(keys + i0);
-      const uint4 b = *reinterpret_cast<const uint4*>(keys + i0 + 4);
-      k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
-      k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
-    } else {
-#pragma unroll
-      for (int j = 0; j < kRangeItems; ++j) k[j] = i0 + j < n ? keys[i0 + j] : 0u;
-    }
-    const uint32_t before = i0 > 0 ? keys[i0 - 1] : 0u;
-    const uint64_t after_i = i0 + kRangeItems;
-    const uint32_t after = after_i < n ? keys[after_i] : 0u;
-#pragma unroll
-    for (int j = 0; j < kRangeItems; ++j) {
-      const uint64_t i = i0 + j;
-      if (i >= n) break;
-      const uint32_t prev = j > 0 ? k[j - 1] : before;
-      const uint32_t next = j + 1 < kRangeItems ? k[j + 1] : after;
-      if (i == 0 || prev != k[j]) ranges[2 * (uint64_t)k[j]] = (uint32_t)i;
-      if (i + 1 == n || next != k[j]) ranges[2 * (uint64_t)k[j] + 1] = (uint32_t)(i + 1);
-    }
-  }
-}
-
 // Processing order of the tiles, longest list first: 16-bit key
 // 0xffff - min(length, 0xffff), value = tile id, and the histograms of its
 // two digits.
@@ -530,34 +496,234 @@ __global__ __launch_bounds__(kBlock) void order_keys_kernel(const uint32_t* __re
   flush_hist(s_h, 2 * kRadix, hist);
 }
 
-// 64-bit keys of the depth-first path, when the caller asks for them.
-__global__ __launch_bounds__(kBlock) void compose_keys_kernel(const uint32_t* __restrict__ tile_keys,
+// Optional 64-bit keys of the placed entries: one wavefront per tile writes
+// tile << 32 | depth bits over the tile's range.
+__global__ __launch_bounds__(64) void keys_from_ranges_kernel(const uint32_t* __restrict__ ranges,
                                                               const uint32_t* __restrict__ vals,
                                                               const Record* __restrict__ rec,
-                                                              const uint64_t* __restrict__ n_dup,
-                                                              int64_t capacity,
-                                                              uint64_t* __restrict__ keys) {
-  const uint64_t n = entry_count(n_dup, capacity);
-  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  keys[i] = ((uint64_t)tile_keys[i] << 32) | rec[vals[i]].depth;
+                                                              int64_t n_tiles, uint64_t* __restrict__ keys) {
+  const int64_t t = blockIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t a = ranges[2 * t], e = ranges[2 * t + 1];
+  for (uint32_t p = a + threadIdx.x; p < e; p += 64)
+    keys[p] = ((uint64_t)t << 32) | rec[vals[p]].depth;
+}
+
+// ---------------------------------------------------------------------------
+// placement path
+// ---------------------------------------------------------------------------
+constexpr int kBand = 2048;                  // tiles per band: LDS cursors of one wavefront
+constexpr int64_t kCountBudget = 16ll << 20; // counts[block][tile] entries kept below ~64 MB
+constexpr int64_t kMinBlockRecords = 1024;
+
+struct PlaceGeom {
+  int64_t rb;        // records per block (a multiple of 64)
+  int64_t n_blocks;
+  int64_t n_bands;
+};
+
+PlaceGeom place_geom(int64_t n_rec, int64_t n_tiles) {
+  PlaceGeom g;
+  const int64_t nr = n_rec > 0 ? n_rec : 1, nt = n_tiles > 0 ? n_tiles : 1;
+  // blocks x tiles bounded by kCountBudget (as 128-bit product: n_rec * n_tiles may not fit 64 bits)
+  const unsigned __int128 prod = (unsigned __int128)nr * (unsigned __int128)nt;
+  int64_t rb = (int64_t)((prod + kCountBudget - 1) / kCountBudget);
+  rb = rb < kMinBlockRecords ? kMinBlockRecords : rb;
+  rb = (rb + 63) / 64 * 64;
+  g.rb = rb;
+  g.n_blocks = (nr + rb - 1) / rb;
+  g.n_bands = (nt + kBand - 1) / kBand;
+  return g;
+}
+
+// A record's tile rectangle in global tile ids: row ty covers
+// first + (ty - ty0) * stride .. + w - 1.
+struct TileRect {
+  uint32_t first;    // tile id of (tx0, ty0)
+  uint32_t w, h;     // in tiles
+  uint32_t stride;   // tiles per row of the camera
+};
+
+__device__ __forceinline__ TileRect tile_rect(const Record& R, const CamPack& cp, int64_t n_per_cam,
+                                              uint32_t r) {
+  const CamDev& C = cp.cam[(int)(r / (uint64_t)n_per_cam)];
+  const int sh = cp.tile_shift;
+  const uint32_t tx0 = (R.xr & 0xffffu) >> sh, tx1 = (R.xr >> 16) >> sh;
+  const uint32_t ty0 = (R.yr & 0xffffu) >> sh, ty1 = (R.yr >> 16) >> sh;
+  TileRect t;
+  t.stride = (uint32_t)C.tiles_x;
+  t.first = C.tile_off + ty0 * t.stride + tx0;
+  t.w = tx1 - tx0 + 1;
+  t.h = ty1 - ty0 + 1;
+  return t;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t x, int lane, uint32_t* total) {
+  uint32_t inc = x;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  *total = __shfl(inc, 63, 64);
+  return inc - x;
+}
+
+// counts[b][t] for t in band k: records of block b covering tile t.
+__global__ __launch_bounds__(64) void place_count_kernel(
+    const Record* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
+    int64_t n_rec, int64_t n_per_cam, CamPack cp, int64_t rb, int64_t n_bands, int64_t n_tiles,
+    uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_d[kBand + 1];
+  __shared__ uint32_t s_off[64];
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x / n_bands, k = blockIdx.x % n_bands;
+  const int64_t lo = k * kBand;
+  const int64_t hi = lo + kBand < n_tiles ? lo + kBand : n_tiles;
+  const int nt = (int)(hi - lo);
+  for (int i = lane; i <= nt; i += 64) s_d[i] = 0u;
+  __syncthreads();
+  const int64_t j0 = b * rb, j1 = j0 + rb < n_rec ? j0 + rb : n_rec;
+  for (int64_t j = j0 + lane; j < j1; j += 64) {
+    const uint32_t r = order[j];
+    if (tiles[r] == 0u) continue;
+    const TileRect t = tile_rect(rec[r], cp, n_per_cam, r);
+    for (uint32_t y = 0; y < t.h; ++y) {
+      const int64_t a = (int64_t)t.first + (int64_t)y * t.stride, e = a + t.w;
+      if (a >= hi || e <= lo) continue;
+      atomicAdd(&s_d[(a > lo ? a : lo) - lo], 1u);
+      atomicSub(&s_d[(e < hi ? e : hi) - lo], 1u);
+    }
+  }
+  __syncthreads();
+  // inclusive prefix of the difference array: lane-local over a chunk, then
+  // the chunk offsets, written out coalesced
+  const int chunk = (nt + 63) / 64;
+  const int c0 = lane * chunk, c1 = c0 + chunk < nt ? c0 + chunk : nt;
+  uint32_t run = 0;
+  for (int i = c0; i < c1; ++i) {
+    run += s_d[i];
+    s_d[i] = run;
+  }
+  uint32_t tot;
+  s_off[lane] = wave_excl_scan_u32(run, lane, &tot);
+  __syncthreads();
+  uint32_t* dst = counts + b * n_tiles + lo;
+  for (int i = lane; i < nt; i += 64) dst[i] = s_d[i] + s_off[i / chunk];
+}
+
+// Per tile: entries over all blocks, and the tile's range ([0, 0) when
+// empty, or when the entries overflow the capacity).
+__global__ __launch_bounds__(kBlock) void place_totals_kernel(const uint32_t* __restrict__ counts,
+                                                              int64_t n_blocks, int64_t n_tiles,
+                                                              uint32_t* __restrict__ totals) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n_tiles) return;
+  uint32_t v = 0;
+  for (int64_t b = 0; b < n_blocks; ++b) v += counts[b * n_tiles + t];
+  totals[t] = v;
+}
+
+// counts[b][t] <- position of block b's first entry of tile t; ranges.
+__global__ __launch_bounds__(kBlock) void place_offsets_kernel(
+    uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, const uint64_t* __restrict__ starts,
+    const uint64_t* __restrict__ n_dup, int64_t capacity, int64_t n_blocks, int64_t n_tiles,
+    uint32_t* __restrict__ ranges) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n_tiles) return;
+  const bool over = *n_dup > (uint64_t)capacity;
+  const uint32_t tot = totals[t];
+  const uint32_t a = (uint32_t)starts[t];
+  ranges[2 * t] = (tot && !over) ? a : 0u;
+  ranges[2 * t + 1] = (tot && !over) ? a + tot : 0u;
+  if (over) return;
+  uint32_t run = a;
+  for (int64_t b = 0; b < n_blocks; ++b) {
+    const uint32_t c = counts[b * n_tiles + t];
+    counts[b * n_tiles + t] = run;
+    run += c;
+  }
+}
+
+// The entries of block b in band k: cursors in LDS, records one after
+// another (their covered tiles across the lanes), so every tile hands out
+// its positions in record order.
+__global__ __launch_bounds__(64) void place_emit_kernel(
+    const Record* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
+    int64_t n_rec, int64_t n_per_cam, CamPack cp, int64_t rb, int64_t n_bands, int64_t n_tiles,
+    const uint32_t* __restrict__ offsets, const uint64_t* __restrict__ n_dup, int64_t capacity,
+    int32_t* __restrict__ overflow, uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_cur[kBand];
+  const int lane = threadIdx.x;
+  const bool over = *n_dup > (uint64_t)capacity;
+  if (blockIdx.x == 0 && lane == 0) *overflow = over ? 1 : 0;
+  if (over) return;
+  const int64_t b = blockIdx.x / n_bands, k = blockIdx.x % n_bands;
+  const int64_t lo = k * kBand;
+  const int64_t hi = lo + kBand < n_tiles ? lo + kBand : n_tiles;
+  const int nt = (int)(hi - lo);
+  const uint32_t* src = offsets + b * n_tiles + lo;
+  for (int i = lane; i < nt; i += 64) s_cur[i] = src[i];
+  __syncthreads();
+  const int64_t j0 = b * rb, j1 = j0 + rb < n_rec ? j0 + rb : n_rec;
+  for (int64_t jb = j0; jb < j1; jb += 64) {
+    const int64_t j = jb + lane;
+    uint32_t r = 0, first = 0, w = 0, h = 0, stride = 0;
+    bool in = false;
+    if (j < j1) {
+      r = order[j];
+      if (tiles[r] != 0u) {
+        const TileRect t = tile_rect(rec[r], cp, n_per_cam, r);
+        first = t.first; w = t.w; h = t.h; stride = t.stride;
+        const int64_t last = (int64_t)first + (int64_t)(h - 1) * stride + (w - 1);
+        in = (int64_t)first < hi && last >= lo;
+      }
+    }
+    uint64_t m = __builtin_amdgcn_ballot_w64(in);
+    while (m != 0ull) {
+      const int src_lane = (int)__builtin_ctzll(m);
+      m &= m - 1ull;
+      const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)r, src_lane);
+      const uint32_t F = (uint32_t)__builtin_amdgcn_readlane((int)first, src_lane);
+      const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)w, src_lane);
+      const uint32_t H = (uint32_t)__builtin_amdgcn_readlane((int)h, src_lane);
+      const uint32_t S = (uint32_t)__builtin_amdgcn_readlane((int)stride, src_lane);
+      const uint32_t n = W * H;
+      const float inv_w = 1.0f / (float)W;
+      for (uint32_t q = 0; q < n; q += 64) {
+        const uint32_t e = q + (uint32_t)lane;
+        // row = e / W: float estimate, corrected (e < 2^24)
+        int row = (int)((float)e * inv_w);
+        int col = (int)e - row * (int)W;
+        if (col < 0) { --row; col += (int)W; }
+        if (col >= (int)W) { ++row; col -= (int)W; }
+        const int64_t tile = (int64_t)F + (int64_t)row * S + col;
+        if (e < n && tile >= lo && tile < hi) {
+          const uint32_t pos = s_cur[tile - lo];
+          s_cur[tile - lo] = pos + 1u;
+          vals[pos] = R;
+        }
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SortWs {
-  // depth-first path
+  // placement path
   uint32_t* rkeys[2];
   uint32_t* rids[2];
-  uint32_t* counts;
-  uint64_t* offsets;
+  uint32_t* counts;    // [n_blocks][n_tiles], then offsets
+  uint32_t* totals;    // [n_tiles]
+  uint64_t* starts;    // [n_tiles]
   void* scan_ws;
-  uint32_t* tkeys[2];
-  // both paths
+  // full-key path
   uint64_t* alt_keys64;
   uint32_t* alt_vals;
   uint32_t* chunk_start;
+  // both paths
   uint32_t* okeys[2];  // tile order sort
   uint32_t* oalt;
   uint32_t* hist;      // [kHistCopies][2][kMaxPasses][256]: record passes, entry passes
@@ -565,17 +731,20 @@ struct SortWs {
   uint32_t* tickets;   // [2][kMaxPasses]
   uint64_t* lookback[2];
   int64_t parts;
+  PlaceGeom geom;
   size_t bytes;
 };
 
 SortWs carve(void* ws, int64_t n_rec, int64_t capacity, int64_t n_tiles, bool full_keys) {
   SortWs w{};
   const int64_t small = n_rec > n_tiles ? n_rec : n_tiles;
-  const int64_t pe = (capacity + kPartMinEntries - 1) / kPartMinEntries;
+  const int64_t pe = full_keys ? (capacity + kPartMinEntries - 1) / kPartMinEntries : 0;
   const int64_t ps = (small + kPartMinSmall - 1) / kPartMinSmall;
   const int64_t parts = pe > ps ? pe : ps;
   w.parts = parts > 0 ? parts : 1;
+  w.geom = place_geom(n_rec, n_tiles);
   const size_t nr = (size_t)(n_rec > 0 ? n_rec : 1), cap = (size_t)(capacity > 0 ? capacity : 1);
+  const size_t nt = (size_t)(n_tiles > 0 ? n_tiles : 1);
   char* p = (char*)ws;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -585,17 +754,16 @@ SortWs carve(void* ws, int64_t n_rec, int64_t capacity, int64_t n_tiles, bool fu
   };
   if (full_keys) {
     w.alt_keys64 = (uint64_t*)take(cap * 8);
+    w.alt_vals = (uint32_t*)take(cap * 4);
+    w.chunk_start = (uint32_t*)take((cap + kChunk - 1) / kChunk * 4 + 4);
   } else {
     for (int b = 0; b < 2; ++b) w.rkeys[b] = (uint32_t*)take(nr * 4);
     for (int b = 0; b < 2; ++b) w.rids[b] = (uint32_t*)take(nr * 4);
-    w.counts = (uint32_t*)take(nr * 4);
-    w.offsets = (uint64_t*)take(nr * 8);
-    w.scan_ws = take(scan_workspace_bytes(n_rec) + 256);
-    for (int b = 0; b < 2; ++b) w.tkeys[b] = (uint32_t*)take(cap * 4);
+    w.counts = (uint32_t*)take((size_t)w.geom.n_blocks * nt * 4);
+    w.totals = (uint32_t*)take(nt * 4);
+    w.starts = (uint64_t*)take(nt * 8);
+    w.scan_ws = take(scan_workspace_bytes((int64_t)nt) + 256);
   }
-  w.alt_vals = (uint32_t*)take(cap * 4);
-  w.chunk_start = (uint32_t*)take((cap + kChunk - 1) / kChunk * 4 + 4);
-  const size_t nt = (size_t)(n_tiles > 0 ? n_tiles : 1);
   for (int b = 0; b < 2; ++b) w.okeys[b] = (uint32_t*)take(nt * 4);
   w.oalt = (uint32_t*)take(nt * 4);
   w.hist = (uint32_t*)take((size_t)kHistCopies * kHistWords * 4);
@@ -697,44 +865,26 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
       onesweep_passes<uint32_t, kSmallItems>(w.rkeys, w.rids, nullptr, n_rec, 0, 4, base_rec, w, w.tickets,
                                              lb, s);
     const uint32_t* order = w.rids[0];  // four passes: back in buffer 0
-    // 2. entry offsets in that order
-    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(n_rec, kBlock, 1 << 30)), dim3(kBlock), 0, s,
-                       order, tiles, n_rec, w.counts);
-    hipError_t e = launch_scan(w.counts, n_rec, w.offsets, (uint64_t*)((char*)w.scan_ws),
-                               (char*)w.scan_ws + 256, s);
+    const int64_t nt = (int64_t)cp.tiles_total;
+    const PlaceGeom& g = w.geom;
+    const unsigned items = (unsigned)(g.n_blocks * g.n_bands);
+    // 2. counts[block][tile]
+    hipLaunchKernelGGL(place_count_kernel, dim3(items), dim3(64), 0, s, rec, order, tiles, n_rec, n_per_cam,
+                       cp, g.rb, g.n_bands, nt, w.counts);
+    // 3. tile totals, their scan, per-block offsets and the ranges
+    hipLaunchKernelGGL(place_totals_kernel, dim3(grid_for(nt, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
+                       (const uint32_t*)w.counts, g.n_blocks, nt, w.totals);
+    hipError_t e = launch_scan(w.totals, nt, w.starts, (uint64_t*)w.scan_ws, (char*)w.scan_ws + 256, s);
     if (e != hipSuccess) return e;
-    // 3-4. entries with 32-bit tile keys, sorted over the tile bits
-    const int passes = (tb + 7) / 8;
-    uint32_t* kb[2] = {w.tkeys[0], w.tkeys[1]};
-    uint32_t* vb[2];
-    if (passes % 2 == 0) {
-      vb[0] = vals; vb[1] = w.alt_vals;
-    } else {
-      vb[0] = w.alt_vals; vb[1] = vals;
-    }
-    if (n_rec > 0)
-      hipLaunchKernelGGL(chunk_start_kernel, dim3(grid_for(n_rec, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
-                         order, tiles, (const uint64_t*)w.offsets, n_rec,
-                         (uint64_t)((capacity + kChunk - 1) / kChunk), w.chunk_start);
-    hipLaunchKernelGGL(duplicate_kernel<false>, dim3(dup_grid), dim3(kBlock), 0, s, rec, order, tiles,
-                       (const uint64_t*)w.offsets, (const uint32_t*)w.chunk_start, n_dup, n_rec, n_per_cam,
-                       cp, (void*)kb[0], vb[0], capacity, overflow, hist_ent, 0, passes);
-    if (passes > 0) {
-      hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
-      onesweep_passes<uint32_t, SweepItems<uint32_t>::value>(kb, vb, n_dup, capacity, 0, passes, base_ent, w,
-                                                             w.tickets + kMaxPasses, lb, s);
-    }
-    const uint32_t* tkeys = kb[passes & 1];
-    // 5. ranges (and 64-bit keys if asked for)
-    const int64_t nr = 2 * (int64_t)cp.tiles_total;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nr, kBlock, 4096)), dim3(kBlock), 0, s, ranges, nr, 0u);
-    if (capacity > 0) {
-      hipLaunchKernelGGL(ranges_u32_kernel, dim3(grid_for((capacity + kRangeItems - 1) / kRangeItems, kBlock, 8192)),
-                         dim3(kBlock), 0, s, tkeys, n_dup, capacity, ranges);
-      if (keys)
-        hipLaunchKernelGGL(compose_keys_kernel, dim3(grid_for(capacity, kBlock, 1ll << 31)), dim3(kBlock),
-                           0, s, tkeys, vals, rec, n_dup, capacity, keys);
-    }
+    hipLaunchKernelGGL(place_offsets_kernel, dim3(grid_for(nt, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
+                       w.counts, (const uint32_t*)w.totals, (const uint64_t*)w.starts, n_dup, capacity,
+                       g.n_blocks, nt, ranges);
+    // 4. the entries
+    hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(64), 0, s, rec, order, tiles, n_rec, n_per_cam, cp,
+                       g.rb, g.n_bands, nt, (const uint32_t*)w.counts, n_dup, capacity, overflow, vals);
+    if (keys)
+      hipLaunchKernelGGL(keys_from_ranges_kernel, dim3(nt > 0 ? (unsigned)nt : 1u), dim3(64), 0, s,
+                         (const uint32_t*)ranges, (const uint32_t*)vals, rec, nt, keys);
   }
   // 6. tiles by decreasing list length, for the persistent raster
   if (tile_order) {
