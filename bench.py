@@ -34,6 +34,42 @@ WORKLOADS = {
 }
 
 
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hbm_traffic_1M_1080p.txt")
+TRAFFIC_SOURCES = ("include/hgs.h", "paper_2406_02720_amd/csrc/hgs_internal.h",
+                   "paper_2406_02720_amd/csrc/geometry.h", "paper_2406_02720_amd/csrc/preprocess.hip",
+                   "paper_2406_02720_amd/csrc/sort.hip", "paper_2406_02720_amd/csrc/render.hip",
+                   "paper_2406_02720_amd/build.py")
+
+
+def sources_digest() -> str:
+    """sha256 over the kernel sources and build flags: the HBM counters in
+    profiles/ belong to the build whose digest they record."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_prefix: str):
+    """HBM bytes per launch of the kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel factors it
+    records; None when the summary is missing or was taken on other sources."""
+    try:
+        lines = open(PROFILE_TRAFFIC).read().splitlines()
+    except OSError:
+        return None
+    digest = next((l.split(":", 1)[1].strip() for l in lines if l.startswith("sources_sha256:")), None)
+    if digest != sources_digest():
+        return None
+    for l in lines:
+        if l.startswith("kernel ") and kernel_prefix in l:
+            fields = dict(kv.split("=") for kv in l.split()[1:] if "=" in kv)
+            return int(float(fields["traffic_bytes"]))
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,10 +252,10 @@ def main():
         # each), the count array [blocks][tiles] written, read for the totals,
         # read and rewritten as offsets, read for placing (16 B per cell),
         # 4 B written per entry, tile totals / starts / ranges (20 B per tile);
-        # blocks as the library sizes them (>= 1024 records, <= 16 Mi cells)
+        # blocks as the library sizes them (about 64 entries per block and tile)
         passes = 0
-        rb = max(1024, -(-(n_rec * tiles_total) // (16 << 20)))
-        rb = -(-rb // 64) * 64
+        nb = min(max(cap // (max(tiles_total, 1) * 64), 1), 1 << 16)
+        rb = -(-(-(-n_rec // nb)) // 64) * 64
         n_blocks = -(-n_rec // rb)
         bytes_sort = (n_rec * (16 + 4 * 16 + 16 + 16) + 16 * n_blocks * tiles_total + 4 * n_dup
                       + 20 * tiles_total)
@@ -251,7 +287,10 @@ def main():
     dominant = max(("render_fwd", "raster_bwd", "preprocess_bwd"), key=lambda k: st[k])
     roofline = {k: v for k, v in roof[dominant].items() if k not in ("ms", "bytes", "flops")}
     roofline["kernel"] = dominant
-    roofline["traffic"] = None
+    kname = {"render_fwd": "render_fwd", "raster_bwd": "render_bwd", "preprocess_bwd": "preprocess_bwd"}[dominant]
+    if dominant in ("render_fwd", "raster_bwd") and not args.per_tile:
+        kname += f"_persistent_kernel<{args.tile},{args.batch // 64}>"
+    roofline["traffic"] = measured_traffic(kname)
 
     if args.stages:
         for name in stage_names:

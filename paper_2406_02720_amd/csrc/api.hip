@@ -145,7 +145,7 @@ size_t hgs_workspace_bytes(int32_t which, int64_t n_rec, const hgs_camera* cams,
       if (check_opts(opts) != HGS_OK || capacity < 0) return 0;
       hgs::CamPack cp;
       if (make_pack(cams, n_cams, opts, &cp) != HGS_OK) return 0;
-      return hgs::sort_workspace_bytes(n_rec, capacity, (int64_t)cp.tiles_total,
+      return hgs::sort_workspace_bytes(n_rec, capacity, cp,
                                        (opts->flags & HGS_FLAG_SORT_FULL_KEYS) != 0);
     }
     case HGS_WS_RENDER:
@@ -193,7 +193,7 @@ int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint6
   if (!n_dup || !ranges || !overflow || (n_rec > 0 && (!records || !tiles_touched || !offsets)) ||
       (capacity > 0 && (!values || (full_keys && !keys))))
     return fail(HGS_EINVAL, "a pointer is null");
-  const size_t need = hgs::sort_workspace_bytes(n_rec, capacity, (int64_t)cp.tiles_total, full_keys);
+  const size_t need = hgs::sort_workspace_bytes(n_rec, capacity, cp, full_keys);
   if (!workspace || workspace_bytes < need)
     return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", need);
   if (((uintptr_t)workspace & 255u) != 0)

@@ -112,7 +112,7 @@ size_t scan_workspace_bytes(int64_t n);
 hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint64_t* total,
                        void* ws, hipStream_t s);
 int tile_bits(uint32_t tiles_total);
-size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, int64_t n_tiles, bool full_keys);
+size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, const CamPack& cp, bool full_keys);
 hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint64_t* offsets,
                            const uint64_t* n_dup, int64_t n_rec, int64_t n_per_cam,
                            const CamPack& cp, uint64_t* keys, uint32_t* vals, int64_t capacity,

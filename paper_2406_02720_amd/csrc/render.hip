@@ -117,8 +117,15 @@ __device__ __forceinline__ float gauss_power(const Record& r, const Column& c, f
   return fmaf(-0.5f, quad, -(c.qbdx * dy));
 }
 
-__device__ __forceinline__ float half_factor(const Record& r, const RecordU& u, const Column& c, float dy) {
-  return u.split ? erfc_fast(-fmaf(r.ky, dy, c.kxdx)) : 1.0f;
+// I = erfc(x), x = -(k . offset).  When every lane of mask m has |x| >= 3.9
+// the polynomial is clamped for all of them, and I is erfc_fast(3.9) or
+// 2 - erfc_fast(3.9) (`e39`, once per kernel): the same bits, no polynomial.
+__device__ __forceinline__ float half_factor(const Record& r, const RecordU& u, const Column& c, float dy,
+                                             uint64_t m, float e39) {
+  if (!u.split) return 1.0f;
+  const float x = -fmaf(r.ky, dy, c.kxdx);
+  if ((lanes(fabsf(x) < 3.9f) & m) == 0ull) return x >= 0.0f ? e39 : 2.0f - e39;
+  return erfc_fast(x);
 }
 
 // A wavefront's block is SUB x SUB pixels; lane l holds column l % SUB of
@@ -248,6 +255,7 @@ __device__ __forceinline__ void fwd_block(
   const int64_t len = (int64_t)ranges[2 * tile + 1] - (int64_t)ranges[2 * tile];
   const float amin = o.alpha_min, amax = o.alpha_max, tmin = o.t_min;
   const float l2amin = __builtin_amdgcn_logf(amin);
+  const float e39 = erfc_fast(3.9f);
   uint64_t any_open = 0ull;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) any_open |= open[j];
@@ -291,7 +299,7 @@ __device__ __forceinline__ void fwd_block(
           const float G = __builtin_amdgcn_exp2f(p2);
           m &= lanes(!(G * u.hb < amin));
           if (m == 0ull) continue;
-          const float I = half_factor(r, u, col, dy);
+          const float I = half_factor(r, u, col, dy, m, e39);
           const float a = fminf(amax, fmaf(r.d_o, I, r.alpha2) * G);
           m &= lanes(!(a < amin));
           if (m == 0ull) continue;
@@ -423,6 +431,7 @@ __device__ __forceinline__ void bwd_block(
   const uint32_t* __restrict__ lst = vals + ranges[2 * tile];
   const float amin = o.alpha_min, amax = o.alpha_max;
   const float l2amin = __builtin_amdgcn_logf(amin);
+  const float e39 = erfc_fast(3.9f);
 
   // list indices top, top-1, ..., 0 in rounds of 64 * IPL
   for (int32_t hi = top; hi >= 0; hi -= 64 * IPL) {
@@ -467,7 +476,7 @@ __device__ __forceinline__ void bwd_block(
           const float G = __builtin_amdgcn_exp2f(p2);
           m &= lanes(!(G * u.hb < amin));
           if (m == 0ull) continue;
-          const float I = half_factor(r, u, col, dy);
+          const float I = half_factor(r, u, col, dy, m, e39);
           const float HG = fmaf(r.d_o, I, r.alpha2) * G;
           const float a = fminf(amax, HG);
           m &= lanes(!(a < amin));

@@ -512,49 +512,89 @@ __global__ __launch_bounds__(64) void keys_from_ranges_kernel(const uint32_t* __
 // ---------------------------------------------------------------------------
 // placement path
 // ---------------------------------------------------------------------------
-constexpr int kBand = 2048;                  // tiles per band: LDS cursors of one wavefront
-constexpr int64_t kCountBudget = 16ll << 20; // counts[block][tile] entries kept below ~64 MB
-constexpr int64_t kMinBlockRecords = 1024;
+constexpr int kBandTiles = 256;          // a band: whole tile rows of one camera, >= 256 tiles
+constexpr int kSegment = 64;             // target entries per (block, tile) segment
+
+// Tile rows per band of a camera with `tiles_x` tiles per row.
+__host__ __device__ inline int band_rows(int tiles_x) {
+  return tiles_x >= kBandTiles ? 1 : kBandTiles / tiles_x;
+}
 
 struct PlaceGeom {
-  int64_t rb;        // records per block (a multiple of 64)
+  int64_t rb;          // records per block (a multiple of 64)
   int64_t n_blocks;
   int64_t n_bands;
+  int band_tiles;      // largest band (LDS cursors)
 };
 
-PlaceGeom place_geom(int64_t n_rec, int64_t n_tiles) {
+// Blocks are sized so that each (block, tile) segment of the output holds
+// about kSegment entries when `capacity` is close to the entry count (the
+// segments of neighbouring blocks share cache lines only at their ends).
+PlaceGeom place_geom(int64_t n_rec, int64_t capacity, const CamPack& cp) {
   PlaceGeom g;
-  const int64_t nr = n_rec > 0 ? n_rec : 1, nt = n_tiles > 0 ? n_tiles : 1;
-  // blocks x tiles bounded by kCountBudget (as 128-bit product: n_rec * n_tiles may not fit 64 bits)
-  const unsigned __int128 prod = (unsigned __int128)nr * (unsigned __int128)nt;
-  int64_t rb = (int64_t)((prod + kCountBudget - 1) / kCountBudget);
-  rb = rb < kMinBlockRecords ? kMinBlockRecords : rb;
+  const int64_t nr = n_rec > 0 ? n_rec : 1, nt = cp.tiles_total > 0 ? (int64_t)cp.tiles_total : 1;
+  int64_t nb = capacity / (nt * kSegment);
+  nb = nb < 1 ? 1 : (nb > (1 << 16) ? (1 << 16) : nb);
+  int64_t rb = (nr + nb - 1) / nb;
   rb = (rb + 63) / 64 * 64;
   g.rb = rb;
   g.n_blocks = (nr + rb - 1) / rb;
-  g.n_bands = (nt + kBand - 1) / kBand;
+  g.n_bands = 0;
+  g.band_tiles = 1;
+  for (int c = 0; c < cp.n_cams; ++c) {
+    const int tx = cp.cam[c].tiles_x, ty = cp.cam[c].tiles_y, rows = band_rows(tx);
+    g.n_bands += (ty + rows - 1) / rows;
+    g.band_tiles = rows * tx > g.band_tiles ? rows * tx : g.band_tiles;
+  }
+  g.n_bands = g.n_bands > 0 ? g.n_bands : 1;
   return g;
 }
 
-// A record's tile rectangle in global tile ids: row ty covers
-// first + (ty - ty0) * stride .. + w - 1.
+struct Band {
+  int cam;
+  int r0, r1;          // tile rows [r0, r1)
+  int tx;              // tiles per row
+  uint32_t lo;         // first tile id
+  int n;               // tiles in the band
+  bool valid;
+};
+
+__device__ __forceinline__ Band band_of(const CamPack& cp, int64_t k) {
+  Band b{};
+  b.valid = false;
+  for (int c = 0; c < cp.n_cams; ++c) {
+    const int tx = cp.cam[c].tiles_x, ty = cp.cam[c].tiles_y, rows = band_rows(tx);
+    const int64_t nb = (ty + rows - 1) / rows;
+    if (k < nb) {
+      b.cam = c;
+      b.r0 = (int)k * rows;
+      b.r1 = b.r0 + rows < ty ? b.r0 + rows : ty;
+      b.tx = tx;
+      b.lo = cp.cam[c].tile_off + (uint32_t)(b.r0 * tx);
+      b.n = (b.r1 - b.r0) * tx;
+      b.valid = true;
+      return b;
+    }
+    k -= nb;
+  }
+  return b;
+}
+
+// A record's tile rectangle: columns [tx0, tx0 + w), rows [ty0, ty1].
 struct TileRect {
-  uint32_t first;    // tile id of (tx0, ty0)
-  uint32_t w, h;     // in tiles
-  uint32_t stride;   // tiles per row of the camera
+  int cam;
+  int tx0, w, ty0, ty1;
 };
 
 __device__ __forceinline__ TileRect tile_rect(const Record& R, const CamPack& cp, int64_t n_per_cam,
                                               uint32_t r) {
-  const CamDev& C = cp.cam[(int)(r / (uint64_t)n_per_cam)];
   const int sh = cp.tile_shift;
-  const uint32_t tx0 = (R.xr & 0xffffu) >> sh, tx1 = (R.xr >> 16) >> sh;
-  const uint32_t ty0 = (R.yr & 0xffffu) >> sh, ty1 = (R.yr >> 16) >> sh;
   TileRect t;
-  t.stride = (uint32_t)C.tiles_x;
-  t.first = C.tile_off + ty0 * t.stride + tx0;
-  t.w = tx1 - tx0 + 1;
-  t.h = ty1 - ty0 + 1;
+  t.cam = (int)(r / (uint64_t)n_per_cam);
+  t.tx0 = (int)((R.xr & 0xffffu) >> sh);
+  t.w = (int)((R.xr >> 16) >> sh) - t.tx0 + 1;
+  t.ty0 = (int)((R.yr & 0xffffu) >> sh);
+  t.ty1 = (int)((R.yr >> 16) >> sh);
   return t;
 }
 
@@ -569,18 +609,18 @@ __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t x, int lane, uin
   return inc - x;
 }
 
-// counts[b][t] for t in band k: records of block b covering tile t.
+// counts[b][t] for the tiles t of band k: records of block b covering t.
 __global__ __launch_bounds__(64) void place_count_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
     int64_t n_rec, int64_t n_per_cam, CamPack cp, int64_t rb, int64_t n_bands, int64_t n_tiles,
     uint32_t* __restrict__ counts) {
-  __shared__ uint32_t s_d[kBand + 1];
+  extern __shared__ uint32_t s_d[];   // band tiles + 1
   __shared__ uint32_t s_off[64];
   const int lane = threadIdx.x;
-  const int64_t b = blockIdx.x / n_bands, k = blockIdx.x % n_bands;
-  const int64_t lo = k * kBand;
-  const int64_t hi = lo + kBand < n_tiles ? lo + kBand : n_tiles;
-  const int nt = (int)(hi - lo);
+  const int64_t b = blockIdx.x / n_bands;
+  const Band B = band_of(cp, blockIdx.x % n_bands);
+  if (!B.valid) return;
+  const int nt = B.n;
   for (int i = lane; i <= nt; i += 64) s_d[i] = 0u;
   __syncthreads();
   const int64_t j0 = b * rb, j1 = j0 + rb < n_rec ? j0 + rb : n_rec;
@@ -588,11 +628,12 @@ __global__ __launch_bounds__(64) void place_count_kernel(
     const uint32_t r = order[j];
     if (tiles[r] == 0u) continue;
     const TileRect t = tile_rect(rec[r], cp, n_per_cam, r);
-    for (uint32_t y = 0; y < t.h; ++y) {
-      const int64_t a = (int64_t)t.first + (int64_t)y * t.stride, e = a + t.w;
-      if (a >= hi || e <= lo) continue;
-      atomicAdd(&s_d[(a > lo ? a : lo) - lo], 1u);
-      atomicSub(&s_d[(e < hi ? e : hi) - lo], 1u);
+    if (t.cam != B.cam || t.ty1 < B.r0 || t.ty0 >= B.r1) continue;
+    const int ya = t.ty0 > B.r0 ? t.ty0 : B.r0, yb = t.ty1 < B.r1 - 1 ? t.ty1 : B.r1 - 1;
+    for (int y = ya; y <= yb; ++y) {
+      const int a = (y - B.r0) * B.tx + t.tx0;
+      atomicAdd(&s_d[a], 1u);
+      atomicSub(&s_d[a + t.w], 1u);
     }
   }
   __syncthreads();
@@ -608,23 +649,25 @@ __global__ __launch_bounds__(64) void place_count_kernel(
   uint32_t tot;
   s_off[lane] = wave_excl_scan_u32(run, lane, &tot);
   __syncthreads();
-  uint32_t* dst = counts + b * n_tiles + lo;
+  uint32_t* dst = counts + b * n_tiles + B.lo;
   for (int i = lane; i < nt; i += 64) dst[i] = s_d[i] + s_off[i / chunk];
 }
 
-// Per tile: entries over all blocks, and the tile's range ([0, 0) when
-// empty, or when the entries overflow the capacity).
+// Per tile: entries over all blocks.
 __global__ __launch_bounds__(kBlock) void place_totals_kernel(const uint32_t* __restrict__ counts,
                                                               int64_t n_blocks, int64_t n_tiles,
                                                               uint32_t* __restrict__ totals) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= n_tiles) return;
   uint32_t v = 0;
+#pragma unroll 8
   for (int64_t b = 0; b < n_blocks; ++b) v += counts[b * n_tiles + t];
   totals[t] = v;
 }
 
-// counts[b][t] <- position of block b's first entry of tile t; ranges.
+// counts[b][t] <- position of block b's first entry of tile t; the ranges
+// ([0, 0) for an empty tile, and for every tile when the entries overflow
+// the capacity).
 __global__ __launch_bounds__(kBlock) void place_offsets_kernel(
     uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, const uint64_t* __restrict__ starts,
     const uint64_t* __restrict__ n_dup, int64_t capacity, int64_t n_blocks, int64_t n_tiles,
@@ -638,6 +681,7 @@ __global__ __launch_bounds__(kBlock) void place_offsets_kernel(
   ranges[2 * t + 1] = (tot && !over) ? a + tot : 0u;
   if (over) return;
   uint32_t run = a;
+#pragma unroll 8
   for (int64_t b = 0; b < n_blocks; ++b) {
     const uint32_t c = counts[b * n_tiles + t];
     counts[b * n_tiles + t] = run;
@@ -645,38 +689,43 @@ __global__ __launch_bounds__(kBlock) void place_offsets_kernel(
   }
 }
 
-// The entries of block b in band k: cursors in LDS, records one after
-// another (their covered tiles across the lanes), so every tile hands out
-// its positions in record order.
+// The entries of block b in band k: cursors in LDS, the block's records one
+// after another (their covered tiles in the band across the lanes), so
+// every tile hands out its positions in record order.
 __global__ __launch_bounds__(64) void place_emit_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
-    int64_t n_rec, int64_t n_per_cam, CamPack cp, int64_t rb, int64_t n_bands, int64_t n_tiles,
-    const uint32_t* __restrict__ offsets, const uint64_t* __restrict__ n_dup, int64_t capacity,
-    int32_t* __restrict__ overflow, uint32_t* __restrict__ vals) {
-  __shared__ uint32_t s_cur[kBand];
+    int64_t n_rec, int64_t n_per_cam, CamPack cp, int64_t rb, int64_t n_bands,
+    const uint32_t* __restrict__ offsets, int64_t n_tiles, const uint64_t* __restrict__ n_dup,
+    int64_t capacity, int32_t* __restrict__ overflow, uint32_t* __restrict__ vals) {
+  extern __shared__ uint32_t s_cur[];   // band tiles
   const int lane = threadIdx.x;
   const bool over = *n_dup > (uint64_t)capacity;
   if (blockIdx.x == 0 && lane == 0) *overflow = over ? 1 : 0;
   if (over) return;
-  const int64_t b = blockIdx.x / n_bands, k = blockIdx.x % n_bands;
-  const int64_t lo = k * kBand;
-  const int64_t hi = lo + kBand < n_tiles ? lo + kBand : n_tiles;
-  const int nt = (int)(hi - lo);
-  const uint32_t* src = offsets + b * n_tiles + lo;
-  for (int i = lane; i < nt; i += 64) s_cur[i] = src[i];
+  const int64_t b = blockIdx.x / n_bands;
+  const Band B = band_of(cp, blockIdx.x % n_bands);
+  if (!B.valid) return;
+  const uint32_t* src = offsets + b * n_tiles + B.lo;
+  for (int i = lane; i < B.n; i += 64) s_cur[i] = src[i];
   __syncthreads();
   const int64_t j0 = b * rb, j1 = j0 + rb < n_rec ? j0 + rb : n_rec;
   for (int64_t jb = j0; jb < j1; jb += 64) {
     const int64_t j = jb + lane;
-    uint32_t r = 0, first = 0, w = 0, h = 0, stride = 0;
+    uint32_t r = 0;
+    int x0 = 0, w = 0, ya = 0, nrow = 0;
     bool in = false;
     if (j < j1) {
       r = order[j];
       if (tiles[r] != 0u) {
         const TileRect t = tile_rect(rec[r], cp, n_per_cam, r);
-        first = t.first; w = t.w; h = t.h; stride = t.stride;
-        const int64_t last = (int64_t)first + (int64_t)(h - 1) * stride + (w - 1);
-        in = (int64_t)first < hi && last >= lo;
+        if (t.cam == B.cam && t.ty1 >= B.r0 && t.ty0 < B.r1) {
+          ya = t.ty0 > B.r0 ? t.ty0 : B.r0;
+          const int yb = t.ty1 < B.r1 - 1 ? t.ty1 : B.r1 - 1;
+          x0 = t.tx0;
+          w = t.w;
+          nrow = yb - ya + 1;
+          in = true;
+        }
       }
     }
     uint64_t m = __builtin_amdgcn_ballot_w64(in);
@@ -684,23 +733,22 @@ __global__ __launch_bounds__(64) void place_emit_kernel(
       const int src_lane = (int)__builtin_ctzll(m);
       m &= m - 1ull;
       const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)r, src_lane);
-      const uint32_t F = (uint32_t)__builtin_amdgcn_readlane((int)first, src_lane);
-      const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)w, src_lane);
-      const uint32_t H = (uint32_t)__builtin_amdgcn_readlane((int)h, src_lane);
-      const uint32_t S = (uint32_t)__builtin_amdgcn_readlane((int)stride, src_lane);
-      const uint32_t n = W * H;
-      const float inv_w = 1.0f / (float)W;
-      for (uint32_t q = 0; q < n; q += 64) {
-        const uint32_t e = q + (uint32_t)lane;
-        // row = e / W: float estimate, corrected (e < 2^24)
-        int row = (int)((float)e * inv_w);
-        int col = (int)e - row * (int)W;
-        if (col < 0) { --row; col += (int)W; }
-        if (col >= (int)W) { ++row; col -= (int)W; }
-        const int64_t tile = (int64_t)F + (int64_t)row * S + col;
-        if (e < n && tile >= lo && tile < hi) {
-          const uint32_t pos = s_cur[tile - lo];
-          s_cur[tile - lo] = pos + 1u;
+      const int X0 = __builtin_amdgcn_readlane(x0, src_lane);
+      const int W = __builtin_amdgcn_readlane(w, src_lane);
+      const int YA = __builtin_amdgcn_readlane(ya, src_lane);
+      const int n = W * __builtin_amdgcn_readlane(nrow, src_lane);
+      // local tile of entry e: row YA + e / W, column X0 + e % W
+      const int base = (YA - B.r0) * B.tx + X0;
+      for (int q = 0; q < n; q += 64) {
+        const int e = q + lane;
+        int row = (int)((float)e * __builtin_amdgcn_rcpf((float)W));
+        int col = e - row * W;
+        if (col < 0) { --row; col += W; }
+        if (col >= W) { ++row; col -= W; }
+        if (e < n) {
+          const int t = base + row * B.tx + col;
+          const uint32_t pos = s_cur[t];
+          s_cur[t] = pos + 1u;
           vals[pos] = R;
         }
       }
@@ -735,14 +783,15 @@ struct SortWs {
   size_t bytes;
 };
 
-SortWs carve(void* ws, int64_t n_rec, int64_t capacity, int64_t n_tiles, bool full_keys) {
+SortWs carve(void* ws, int64_t n_rec, int64_t capacity, const CamPack& cp, bool full_keys) {
+  const int64_t n_tiles = (int64_t)cp.tiles_total;
   SortWs w{};
   const int64_t small = n_rec > n_tiles ? n_rec : n_tiles;
   const int64_t pe = full_keys ? (capacity + kPartMinEntries - 1) / kPartMinEntries : 0;
   const int64_t ps = (small + kPartMinSmall - 1) / kPartMinSmall;
   const int64_t parts = pe > ps ? pe : ps;
   w.parts = parts > 0 ? parts : 1;
-  w.geom = place_geom(n_rec, n_tiles);
+  w.geom = place_geom(n_rec, capacity, cp);
   const size_t nr = (size_t)(n_rec > 0 ? n_rec : 1), cap = (size_t)(capacity > 0 ? capacity : 1);
   const size_t nt = (size_t)(n_tiles > 0 ? n_tiles : 1);
   char* p = (char*)ws;
@@ -810,8 +859,8 @@ int tile_bits(uint32_t tiles_total) {
   return tb;
 }
 
-size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, int64_t n_tiles, bool full_keys) {
-  return carve(nullptr, n_rec, capacity, n_tiles, full_keys).bytes;
+size_t sort_workspace_bytes(int64_t n_rec, int64_t capacity, const CamPack& cp, bool full_keys) {
+  return carve(nullptr, n_rec, capacity, cp, full_keys).bytes;
 }
 
 hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint64_t* offsets,
@@ -819,7 +868,7 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                            const CamPack& cp, uint64_t* keys, uint32_t* vals, int64_t capacity,
                            uint32_t* ranges, uint32_t* tile_order, int32_t* overflow, void* ws,
                            bool full_keys, hipStream_t s) {
-  SortWs w = carve(ws, n_rec, capacity, (int64_t)cp.tiles_total, full_keys);
+  SortWs w = carve(ws, n_rec, capacity, cp, full_keys);
   const int tb = tile_bits(cp.tiles_total);
   uint32_t* hist_rec = w.hist;                       // replica 0; replicas follow
   uint32_t* hist_ent = w.hist + kMaxPasses * kRadix;
@@ -869,7 +918,8 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     const PlaceGeom& g = w.geom;
     const unsigned items = (unsigned)(g.n_blocks * g.n_bands);
     // 2. counts[block][tile]
-    hipLaunchKernelGGL(place_count_kernel, dim3(items), dim3(64), 0, s, rec, order, tiles, n_rec, n_per_cam,
+    const size_t lds = (size_t)(g.band_tiles + 1) * sizeof(uint32_t);
+    hipLaunchKernelGGL(place_count_kernel, dim3(items), dim3(64), lds, s, rec, order, tiles, n_rec, n_per_cam,
                        cp, g.rb, g.n_bands, nt, w.counts);
     // 3. tile totals, their scan, per-block offsets and the ranges
     hipLaunchKernelGGL(place_totals_kernel, dim3(grid_for(nt, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
@@ -880,8 +930,8 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        w.counts, (const uint32_t*)w.totals, (const uint64_t*)w.starts, n_dup, capacity,
                        g.n_blocks, nt, ranges);
     // 4. the entries
-    hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(64), 0, s, rec, order, tiles, n_rec, n_per_cam, cp,
-                       g.rb, g.n_bands, nt, (const uint32_t*)w.counts, n_dup, capacity, overflow, vals);
+    hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(64), lds, s, rec, order, tiles, n_rec, n_per_cam, cp,
+                       g.rb, g.n_bands, (const uint32_t*)w.counts, nt, n_dup, capacity, overflow, vals);
     if (keys)
       hipLaunchKernelGGL(keys_from_ranges_kernel, dim3(nt > 0 ? (unsigned)nt : 1u), dim3(64), 0, s,
                          (const uint32_t*)ranges, (const uint32_t*)vals, rec, nt, keys);
