@@ -247,18 +247,11 @@ def main():
         passes = (32 + tb + 7) // 8
         bytes_sort = (n_rec * 28 + n_dup * 12 + passes * n_dup * 24 + n_dup * 8 + tiles_total * 8)
     else:
-        # placement: depth keys (16 B) and four record passes (16 B each) per
-        # record, the record rects read for counting and for placing (16 B
-        # each), the count array [blocks][tiles] written, read for the totals,
-        # read and rewritten as offsets, read for placing (16 B per cell),
-        # 4 B written per entry, tile totals / starts / ranges (20 B per tile);
-        # blocks as the library sizes them (about 64 entries per block and tile)
+        # placement: what it must move at least -- depth keys (16 B) and four
+        # record passes (16 B each) per record, each record's tile rectangle
+        # read once (16 B), 4 B written per entry, the ranges (8 B per tile)
         passes = 0
-        nb = min(max(cap // (max(tiles_total, 1) * 64), 1), 1 << 16)
-        rb = -(-(-(-n_rec // nb)) // 64) * 64
-        n_blocks = -(-n_rec // rb)
-        bytes_sort = (n_rec * (16 + 4 * 16 + 16 + 16) + 16 * n_blocks * tiles_total + 4 * n_dup
-                      + 20 * tiles_total)
+        bytes_sort = n_rec * (16 + 4 * 16 + 16) + 4 * n_dup + 8 * tiles_total
     bytes_pbwd = n * (param_bytes + param_bytes) + n_rec * (48 + 48 + 4)
     # FP32 operations of one pair, written out (fma = 2): evaluation
     # (offsets, quadratic form, exp, half factor, Eq. 10 opacity, clamp) and,

@@ -80,45 +80,11 @@ __device__ __forceinline__ int clamp_floor(double x, int hi) {
   return v > hi ? hi : v;
 }
 
-// View-dependent colour of every (camera, kernel): real SH up to degree D
-// along the view direction from the camera centre, + 1/2, clamped at 0,
-// in FP32 (the colour takes no integer decision).  Written into the
-// record's colour slots, where the projection kernel picks it up; kept in a
-// kernel of its own so that the 3 (D+1)^2 coefficients and the SH basis are
-// never live beside the FP64 geometry.
 template <int D>
-__global__ __launch_bounds__(kPreBlock) void sh_colour_kernel(Params p, CamPack cp, Record* __restrict__ rec) {
-  constexpr int K = (D + 1) * (D + 1);
-  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
-  if (i >= p.n) return;
-  const int64_t S = p.stride;
-  const double mx = p.means[i], my = p.means[S + i], mz = p.means[2 * S + i];
-  for (int c = 0; c < cp.n_cams; ++c) {
-    double oc[3];
-    camera_centre(cp.cam[c], oc);
-    const double ex = mx - oc[0], ey = my - oc[1], ez = mz - oc[2];
-    const double il = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
-    float Y[K];
-    sh_eval<D>((float)(ex * il), (float)(ey * il), (float)(ez * il), Y);
-    float col0 = 0.0f, col1 = 0.0f, col2 = 0.0f;
-#pragma unroll
-    for (int kk = 0; kk < K; ++kk) {
-      col0 = fmaf(Y[kk], p.sh[(kk * 3 + 0) * S + i], col0);
-      col1 = fmaf(Y[kk], p.sh[(kk * 3 + 1) * S + i], col1);
-      col2 = fmaf(Y[kk], p.sh[(kk * 3 + 2) * S + i], col2);
-    }
-    Record& r = rec[(int64_t)c * p.n + i];
-    r.r = fmaxf(col0 + 0.5f, 0.0f);
-    r.g = fmaxf(col1 + 0.5f, 0.0f);
-    r.b = fmaxf(col2 + 0.5f, 0.0f);
-  }
-}
-
-// Projection of every (camera, kernel) into its record; the colour slots
-// already hold the SH colour (sh_colour_kernel runs first).
 __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack cp, Opts o,
                                                                Record* __restrict__ rec,
                                                                uint32_t* __restrict__ tiles_out) {
+  constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   if (i >= p.n) return;
   const int64_t S = p.stride;
@@ -151,14 +117,32 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
     r.qa = r.qb = r.qc = r.alpha2 = 0.0f;
     r.r = r.g = r.b = r.d_o = 0.0f;
     r.xr = r.yr = r.depth = 0u;
-    const int64_t ri = (int64_t)c * p.n + i;
-    const float col0 = rec[ri].r, col1 = rec[ri].g, col2 = rec[ri].b;
+    // SH colour first (its basis values die before the geometry starts)
+    double col0 = 0.0, col1 = 0.0, col2 = 0.0;
+    if (params_ok) {
+      double oc[3];
+      camera_centre(cam, oc);
+      double dx = kg.mu[0] - oc[0], dy = kg.mu[1] - oc[1], dz = kg.mu[2] - oc[2];
+      const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+      dx *= il; dy *= il; dz *= il;
+      double Y[K];
+      sh_eval<D>(dx, dy, dz, Y);
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) {
+        col0 += Y[kk] * (double)p.sh[(kk * 3 + 0) * S + i];
+        col1 += Y[kk] * (double)p.sh[(kk * 3 + 1) * S + i];
+        col2 += Y[kk] * (double)p.sh[(kk * 3 + 2) * S + i];
+      }
+      col0 = fmax(col0 + 0.5, 0.0);
+      col1 = fmax(col1 + 0.5, 0.0);
+      col2 = fmax(col2 + 0.5, 0.0);
+    }
     ViewGeo vg;
     view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
     bool ok = params_ok && finite(vg.t[2]) && vg.t[2] > (double)cam.znear;
     ok = ok && finite(vg.det) && vg.det > 0.0 && finite(vg.qa) && finite(vg.qb) &&
          finite(vg.qc) && finite(vg.mx) && finite(vg.my) && finite(vg.k[0]) && finite(vg.k[1]);
-    ok = ok && finite((double)col0) && finite((double)col1) && finite((double)col2);
+    ok = ok && finite(col0) && finite(col1) && finite(col2);
     Box bx;
     if (ok) {
       bx = half_box(kg, vg, Ss, a1, a2, o);
@@ -183,9 +167,9 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
           r.qb = (float)vg.qb;
           r.qc = (float)vg.qc;
           r.alpha2 = a2;
-          r.r = col0;
-          r.g = col1;
-          r.b = col2;
+          r.r = (float)col0;
+          r.g = (float)col1;
+          r.b = (float)col2;
           r.d_o = (float)(((double)a1 - (double)a2) / 2.0);
           r.xr = (uint32_t)x0 | ((uint32_t)x1 << 16);
           r.yr = (uint32_t)y0 | ((uint32_t)y1 << 16);
@@ -194,6 +178,7 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
       }
     }
     r.tiles = tiles;
+    const int64_t ri = (int64_t)c * p.n + i;
     rec[ri] = r;
     tiles_out[ri] = tiles;
   }
@@ -297,74 +282,11 @@ __device__ __forceinline__ void add_sym_outer(Sym3& S, const double* u, const do
   S.yz += w * 0.5 * (u[1] * v[2] + u[2] * v[1]);
 }
 
-// Backward of the SH colour: gradients of the 3 (D+1)^2 coefficients and
-// the colour's share of the centre gradient (through the view direction),
-// written to G.sh and G.means; preprocess_bwd_kernel adds the geometric
-// share to G.means afterwards.  FP32; the clamp at 0 is active exactly where
-// the stored colour is 0.
-template <int D, bool MULTI>
-__global__ __launch_bounds__(kPreBlock) void sh_colour_bwd_kernel(Params p, CamPack cp,
-                                                                   const Record* __restrict__ rec,
-                                                                   const float* __restrict__ rgrad, Grads G) {
-  constexpr int K = (D + 1) * (D + 1);
-  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
-  if (i >= p.n) return;
-  const int64_t S = p.stride;
-  const double mx = p.means[i], my = p.means[S + i], mz = p.means[2 * S + i];
-  // summed over cameras in registers with several cameras; with one, each
-  // is stored as soon as it is known
-  float g_sh[MULTI ? 3 * K : 1];
-#pragma unroll
-  for (int j = 0; j < (MULTI ? 3 * K : 1); ++j) g_sh[j] = 0.0f;
-  double g_mu[3] = {0.0, 0.0, 0.0};
-  bool stored = false;
-  for (int c = 0; c < cp.n_cams; ++c) {
-    const int64_t ri = (int64_t)c * p.n + i;
-    const Record& R = rec[ri];
-    if (R.tiles == 0) continue;  // culled: no gradient
-    const float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS + 9;
-    const float gc[3] = {R.r > 0.0f ? gr[0] : 0.0f, R.g > 0.0f ? gr[1] : 0.0f, R.b > 0.0f ? gr[2] : 0.0f};
-    double oc[3];
-    camera_centre(cp.cam[c], oc);
-    const double ex = mx - oc[0], ey = my - oc[1], ez = mz - oc[2];
-    const double il = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
-    const float d0 = (float)(ex * il), d1 = (float)(ey * il), d2 = (float)(ez * il);
-    float Y[K];
-    sh_eval<D>(d0, d1, d2, Y);
-#pragma unroll
-    for (int kk = 0; kk < K; ++kk)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        if constexpr (MULTI)
-          g_sh[kk * 3 + ch] = fmaf(gc[ch], Y[kk], g_sh[kk * 3 + ch]);
-        else
-          G.sh[(kk * 3 + ch) * S + i] = gc[ch] * Y[kk];
-      }
-    stored = true;
-    // direction gradient: sum_k w_k dY_k/dd with w_k = sum_ch gc_ch f_k,ch
-    float wk[K];
-#pragma unroll
-    for (int kk = 0; kk < K; ++kk)
-      wk[kk] = fmaf(gc[0], p.sh[(kk * 3 + 0) * S + i],
-                    fmaf(gc[1], p.sh[(kk * 3 + 1) * S + i], gc[2] * p.sh[(kk * 3 + 2) * S + i]));
-    float gd0, gd1, gd2;
-    sh_grad<D>(d0, d1, d2, wk, &gd0, &gd1, &gd2);
-    const float dot = gd0 * d0 + gd1 * d1 + gd2 * d2;
-    g_mu[0] += (double)(gd0 - d0 * dot) * il;
-    g_mu[1] += (double)(gd1 - d1 * dot) * il;
-    g_mu[2] += (double)(gd2 - d2 * dot) * il;
-  }
-  if (MULTI || !stored) {
-#pragma unroll
-    for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = MULTI ? g_sh[MULTI ? j : 0] : 0.0f;
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) G.means[c * S + i] = (float)g_mu[c];
-}
-
+template <int D>
 __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     Params p, CamPack cp, Opts o, const Record* __restrict__ rec,
     float* __restrict__ rgrad, Grads G) {
+  constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   if (i >= p.n) return;
   const int64_t S = p.stride;
@@ -383,6 +305,9 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   Sym3 g_Sw = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double g_nh[3] = {0.0, 0.0, 0.0};
   double g_a1 = 0.0, g_a2 = 0.0;
+  float g_sh[3 * K];
+#pragma unroll
+  for (int j = 0; j < 3 * K; ++j) g_sh[j] = 0.0f;
 
   for (int c = 0; c < cp.n_cams; ++c) {
     const int64_t ri = (int64_t)c * p.n + i;
@@ -395,6 +320,7 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     const double gqa = r0.z, gqb = r0.w, gqc = r1.x;
     const double gkx = r1.y, gky = r1.z;
     const double galpha2 = r1.w, gdo = r2.x;
+    const double gcol[3] = {r2.y, r2.z, r2.w};
 
     // alpha2 and (alpha1 - alpha2) / 2
     g_a2 += galpha2 - 0.5 * gdo;
@@ -403,6 +329,43 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     const CamDev& cam = cp.cam[c];
     ViewGeo vg;
     view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
+
+    // ---- colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - o) / |mu - o|
+    {
+      double oc[3];
+      camera_centre(cam, oc);
+      const double dv0 = kg.mu[0] - oc[0], dv1 = kg.mu[1] - oc[1], dv2 = kg.mu[2] - oc[2];
+      const double dl = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
+      const double il = 1.0 / dl;
+      const double d0 = dv0 * il, d1 = dv1 * il, d2 = dv2 * il;
+      double Y[K];
+      sh_eval<D>(d0, d1, d2, Y);
+      double raw[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[kk] * (double)p.sh[(kk * 3 + ch) * S + i];
+      double gc[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) gc[ch] = (raw[ch] + 0.5 > 0.0) ? gcol[ch] : 0.0;
+      double wk[K];
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) {
+        double acc = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          g_sh[kk * 3 + ch] += (float)(gc[ch] * Y[kk]);
+          acc += gc[ch] * (double)p.sh[(kk * 3 + ch) * S + i];
+        }
+        wk[kk] = acc;
+      }
+      double gd0, gd1, gd2;
+      sh_grad<D>(d0, d1, d2, wk, &gd0, &gd1, &gd2);
+      const double dot = gd0 * d0 + gd1 * d1 + gd2 * d2;
+      g_mu[0] += (gd0 - d0 * dot) * il;
+      g_mu[1] += (gd1 - d1 * dot) * il;
+      g_mu[2] += (gd2 - d2 * dot) * il;
+    }
 
     // ---- k = w r, r = (2 s2)^-1/2, w = Q g, s2 = v - g.w (or 1e-12 v)
     double gg0 = 0.0, gg1 = 0.0, gv = 0.0;
@@ -541,7 +504,7 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    G.means[c * S + i] = (float)(g_mu[c] + (double)G.means[c * S + i]);  // + the colour's share
+    G.means[c * S + i] = (float)g_mu[c];
     G.scales[c * S + i] = (float)g_s[c];
     G.normals[c * S + i] = (float)gn_raw[c];
   }
@@ -549,6 +512,8 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   for (int c = 0; c < 4; ++c) G.quats[c * S + i] = (float)gq_raw[c];
   G.opac1[i] = (float)g_a1;
   G.opac2[i] = (float)g_a2;
+#pragma unroll
+  for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = g_sh[j];
 }
 
 }  // namespace
@@ -558,12 +523,11 @@ hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, 
   if (p.n == 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
   switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(sh_colour_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, rec); break;
-    case 1: hipLaunchKernelGGL(sh_colour_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, rec); break;
-    case 2: hipLaunchKernelGGL(sh_colour_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, rec); break;
-    default: hipLaunchKernelGGL(sh_colour_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, rec); break;
+    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
+    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
+    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
+    default: hipLaunchKernelGGL(preprocess_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
   }
-  hipLaunchKernelGGL(preprocess_kernel, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles);
   return hipGetLastError();
 }
 
@@ -591,18 +555,12 @@ hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts&
                                  hipStream_t s) {
   if (p.n == 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
-#define HGS_CBWD(D_, M_) \
-  hipLaunchKernelGGL((sh_colour_bwd_kernel<D_, M_>), dim3(grid), dim3(kPreBlock), 0, s, p, cp, rec, rec_grads, g)
-  const bool multi = cp.n_cams > 1;
   switch (p.sh_degree) {
-    case 0: if (multi) HGS_CBWD(0, true); else HGS_CBWD(0, false); break;
-    case 1: if (multi) HGS_CBWD(1, true); else HGS_CBWD(1, false); break;
-    case 2: if (multi) HGS_CBWD(2, true); else HGS_CBWD(2, false); break;
-    default: if (multi) HGS_CBWD(3, true); else HGS_CBWD(3, false); break;
+    case 0: hipLaunchKernelGGL(preprocess_bwd_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+    case 1: hipLaunchKernelGGL(preprocess_bwd_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+    case 2: hipLaunchKernelGGL(preprocess_bwd_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+    default: hipLaunchKernelGGL(preprocess_bwd_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
   }
-#undef HGS_CBWD
-  // after the colour pass: it reads the colour gradients this pass clears
-  hipLaunchKernelGGL(preprocess_bwd_kernel, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g);
   return hipGetLastError();
 }
 

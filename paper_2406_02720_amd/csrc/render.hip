@@ -136,24 +136,7 @@ struct Geometry {
   static constexpr int PPL = SUB * SUB / 64;          // pixels per lane
   static constexpr int WAVES = (T / SUB) * (T / SUB); // wavefronts per tile
   static constexpr int ROWSTEP = 64 / SUB;            // rows between a lane's pixels
-  // one bit per row of a strip: bit r * SUB
-  static constexpr uint64_t REP = (SUB == 16) ? 0x0001000100010001ull : 0x0101010101010101ull;
 
-  // strips (bit j) whose rows meet [y0, y1] (block rows start at oy)
-  static __device__ __forceinline__ uint32_t strip_bits(int y0, int y1, int oy) {
-    const int a = y0 - oy, b = y1 - oy;
-    if (b < 0 || a > SUB - 1) return 0u;
-    const int ja = a > 0 ? a / ROWSTEP : 0;
-    const int jb = b < SUB - 1 ? b / ROWSTEP : PPL - 1;
-    return (2u << jb) - (1u << ja);
-  }
-  // lanes whose column lies in [x0, x1] (block columns start at ox)
-  static __device__ __forceinline__ uint64_t col_mask(int x0, int x1, int ox) {
-    const int c0 = x0 - ox > 0 ? x0 - ox : 0;
-    const int c1 = x1 - ox < SUB - 1 ? x1 - ox : SUB - 1;
-    if (c0 > c1) return 0ull;
-    return ((2ull << c1) - (1ull << c0)) * REP;
-  }
 };
 
 __device__ __forceinline__ Record load_record(const Record* __restrict__ rec, uint32_t id) {
@@ -278,16 +261,14 @@ __device__ __forceinline__ void fwd_block(
         const Record r = load_record(rec, id);
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
         const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
-        const uint64_t cols = Gm::col_mask(x0, x1, ox);
-        const uint32_t strips = Gm::strip_bits(y0, y1, oy);
-        if (cols == 0ull || strips == 0u) continue;
+        const uint64_t cols = lanes(px >= x0) & lanes(px <= x1);
+        if (cols == 0ull) continue;
         const int32_t pos = (int32_t)(base + k * 64 + l);
         const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
         bool ended = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          if (!((strips >> j) & 1u)) continue;
           const float fpy = (float)(py0 + j * RS) + 0.5f;
           uint64_t m = open[j] & cols & lanes(fpy > u.y0f) & lanes(fpy < u.y1p);
           if (m == 0ull) continue;
@@ -452,9 +433,8 @@ __device__ __forceinline__ void bwd_block(
         const Record r = load_record(rec, id);
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
         const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
-        const uint64_t cols = Gm::col_mask(x0, x1, ox);
-        const uint32_t strips = Gm::strip_bits(y0, y1, oy);
-        if (cols == 0ull || strips == 0u) continue;
+        const uint64_t cols = lanes(px >= x0) & lanes(px <= x1);
+        if (cols == 0ull) continue;
         const int32_t pos = hi - (k * 64 + l);
         const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
@@ -464,7 +444,7 @@ __device__ __forceinline__ void bwd_block(
         bool any = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          if (pos > top_j[j] || !((strips >> j) & 1u)) continue;
+          if (pos > top_j[j]) continue;
           const float fpy = (float)(py0 + j * RS) + 0.5f;
           uint64_t m = cols & lanes(fpy > u.y0f) & lanes(fpy < u.y1p) & lanes(pos <= last[j]);
           if (m == 0ull) continue;

@@ -512,8 +512,8 @@ __global__ __launch_bounds__(64) void keys_from_ranges_kernel(const uint32_t* __
 // ---------------------------------------------------------------------------
 // placement path
 // ---------------------------------------------------------------------------
-constexpr int kBandTiles = 256;          // a band: whole tile rows of one camera, >= 256 tiles
-constexpr int kSegment = 64;             // target entries per (block, tile) segment
+constexpr int kBandTiles = 256;      // a band: whole tile rows of one camera, >= 256 tiles
+constexpr int kBlockPairs = 1024;    // (record, band) pairs per placement block
 
 // Tile rows per band of a camera with `tiles_x` tiles per row.
 __host__ __device__ inline int band_rows(int tiles_x) {
@@ -521,32 +521,33 @@ __host__ __device__ inline int band_rows(int tiles_x) {
 }
 
 struct PlaceGeom {
-  int64_t rb;          // records per block (a multiple of 64)
-  int64_t n_blocks;
   int64_t n_bands;
   int band_tiles;      // largest band (LDS cursors)
+  int max_bands;       // most bands of one camera (bound on bands per record)
+  int64_t pairs_max;   // bound on (record, band) pairs
+  int64_t items_max;   // bound on (band, block) items
+  int band_bits;       // bits of a band id
 };
 
-// Blocks are sized so that each (block, tile) segment of the output holds
-// about kSegment entries when `capacity` is close to the entry count (the
-// segments of neighbouring blocks share cache lines only at their ends).
 PlaceGeom place_geom(int64_t n_rec, int64_t capacity, const CamPack& cp) {
-  PlaceGeom g;
-  const int64_t nr = n_rec > 0 ? n_rec : 1, nt = cp.tiles_total > 0 ? (int64_t)cp.tiles_total : 1;
-  int64_t nb = capacity / (nt * kSegment);
-  nb = nb < 1 ? 1 : (nb > (1 << 16) ? (1 << 16) : nb);
-  int64_t rb = (nr + nb - 1) / nb;
-  rb = (rb + 63) / 64 * 64;
-  g.rb = rb;
-  g.n_blocks = (nr + rb - 1) / rb;
-  g.n_bands = 0;
+  PlaceGeom g{};
   g.band_tiles = 1;
   for (int c = 0; c < cp.n_cams; ++c) {
     const int tx = cp.cam[c].tiles_x, ty = cp.cam[c].tiles_y, rows = band_rows(tx);
-    g.n_bands += (ty + rows - 1) / rows;
+    const int nb = (ty + rows - 1) / rows;
+    g.n_bands += nb;
+    g.max_bands = nb > g.max_bands ? nb : g.max_bands;
     g.band_tiles = rows * tx > g.band_tiles ? rows * tx : g.band_tiles;
   }
   g.n_bands = g.n_bands > 0 ? g.n_bands : 1;
+  // every pair holds at least one entry, and a record meets at most
+  // max_bands bands
+  const int64_t by_rec = (n_rec > 0 ? n_rec : 0) * (int64_t)(g.max_bands > 0 ? g.max_bands : 1);
+  g.pairs_max = capacity < by_rec ? capacity : by_rec;
+  g.pairs_max = g.pairs_max > 0 ? g.pairs_max : 1;
+  g.items_max = g.n_bands + (g.pairs_max + kBlockPairs - 1) / kBlockPairs;
+  g.band_bits = 0;
+  while ((1ll << g.band_bits) < g.n_bands) ++g.band_bits;
   return g;
 }
 
@@ -556,12 +557,11 @@ struct Band {
   int tx;              // tiles per row
   uint32_t lo;         // first tile id
   int n;               // tiles in the band
-  bool valid;
 };
 
+// Band k (global numbering: the bands of camera 0, then of camera 1, ...).
 __device__ __forceinline__ Band band_of(const CamPack& cp, int64_t k) {
   Band b{};
-  b.valid = false;
   for (int c = 0; c < cp.n_cams; ++c) {
     const int tx = cp.cam[c].tiles_x, ty = cp.cam[c].tiles_y, rows = band_rows(tx);
     const int64_t nb = (ty + rows - 1) / rows;
@@ -572,7 +572,6 @@ __device__ __forceinline__ Band band_of(const CamPack& cp, int64_t k) {
       b.tx = tx;
       b.lo = cp.cam[c].tile_off + (uint32_t)(b.r0 * tx);
       b.n = (b.r1 - b.r0) * tx;
-      b.valid = true;
       return b;
     }
     k -= nb;
@@ -580,22 +579,23 @@ __device__ __forceinline__ Band band_of(const CamPack& cp, int64_t k) {
   return b;
 }
 
-// A record's tile rectangle: columns [tx0, tx0 + w), rows [ty0, ty1].
-struct TileRect {
-  int cam;
-  int tx0, w, ty0, ty1;
-};
+// First band of camera c and its rows per band.
+__device__ __forceinline__ void camera_bands(const CamPack& cp, int c, int64_t* first, int* rows) {
+  int64_t f = 0;
+  for (int i = 0; i < c; ++i) {
+    const int r = band_rows(cp.cam[i].tiles_x);
+    f += (cp.cam[i].tiles_y + r - 1) / r;
+  }
+  *first = f;
+  *rows = band_rows(cp.cam[c].tiles_x);
+}
 
-__device__ __forceinline__ TileRect tile_rect(const Record& R, const CamPack& cp, int64_t n_per_cam,
-                                              uint32_t r) {
-  const int sh = cp.tile_shift;
-  TileRect t;
-  t.cam = (int)(r / (uint64_t)n_per_cam);
-  t.tx0 = (int)((R.xr & 0xffffu) >> sh);
-  t.w = (int)((R.xr >> 16) >> sh) - t.tx0 + 1;
-  t.ty0 = (int)((R.yr & 0xffffu) >> sh);
-  t.ty1 = (int)((R.yr >> 16) >> sh);
-  return t;
+// A record's tile rectangle, packed: record id, tx0 | w << 16, ty0 | ty1 << 16,
+// camera.
+__device__ __forceinline__ uint4 tile_desc(const Record& R, int sh, uint32_t r, int cam) {
+  const uint32_t tx0 = (R.xr & 0xffffu) >> sh, tx1 = (R.xr >> 16) >> sh;
+  const uint32_t ty0 = (R.yr & 0xffffu) >> sh, ty1 = (R.yr >> 16) >> sh;
+  return make_uint4(r, tx0 | ((tx1 - tx0 + 1) << 16), ty0 | (ty1 << 16), (uint32_t)cam);
 }
 
 __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t x, int lane, uint32_t* total) {
@@ -609,36 +609,141 @@ __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t x, int lane, uin
   return inc - x;
 }
 
-// counts[b][t] for the tiles t of band k: records of block b covering t.
-__global__ __launch_bounds__(64) void place_count_kernel(
-    const Record* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
-    int64_t n_rec, int64_t n_per_cam, CamPack cp, int64_t rb, int64_t n_bands, int64_t n_tiles,
-    uint32_t* __restrict__ counts) {
-  extern __shared__ uint32_t s_d[];   // band tiles + 1
-  __shared__ uint32_t s_off[64];
-  const int lane = threadIdx.x;
-  const int64_t b = blockIdx.x / n_bands;
-  const Band B = band_of(cp, blockIdx.x % n_bands);
-  if (!B.valid) return;
-  const int nt = B.n;
-  for (int i = lane; i <= nt; i += 64) s_d[i] = 0u;
+// Per slot j of the depth order: the record's tile rectangle and the number
+// of bands it meets.
+__global__ __launch_bounds__(kBlock) void place_desc_kernel(const Record* __restrict__ rec,
+                                                            const uint32_t* __restrict__ order,
+                                                            const uint32_t* __restrict__ tiles, int64_t n_rec,
+                                                            int64_t n_per_cam, CamPack cp, uint4* __restrict__ desc,
+                                                            uint32_t* __restrict__ nbands) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n_rec) return;
+  const uint32_t r = order[j];
+  uint32_t nb = 0;
+  uint4 d = make_uint4(r, 0u, 0u, 0u);
+  if (tiles[r] != 0u) {
+    const int cam = (int)(r / (uint64_t)n_per_cam);
+    d = tile_desc(rec[r], cp.tile_shift, r, cam);
+    const uint32_t rows = (uint32_t)band_rows(cp.cam[cam].tiles_x);
+    nb = (d.z >> 16) / rows - (d.z & 0xffffu) / rows + 1;
+  }
+  desc[j] = d;
+  nbands[j] = nb;
+}
+
+// (band, slot) pairs in slot order, with the histograms of the band digits.
+__global__ __launch_bounds__(kBlock) void place_pairs_kernel(const uint4* __restrict__ desc,
+                                                             const uint32_t* __restrict__ nbands,
+                                                             const uint64_t* __restrict__ poff, int64_t n_rec,
+                                                             int64_t pairs_max, CamPack cp, uint32_t* __restrict__ pkey,
+                                                             uint32_t* __restrict__ pval, uint32_t* __restrict__ hist,
+                                                             int hist_passes) {
+  __shared__ uint32_t s_h[kMaxPasses * kRadix];
+  for (int i = threadIdx.x; i < hist_passes * kRadix; i += kBlock) s_h[i] = 0u;
   __syncthreads();
-  const int64_t j0 = b * rb, j1 = j0 + rb < n_rec ? j0 + rb : n_rec;
-  for (int64_t j = j0 + lane; j < j1; j += 64) {
-    const uint32_t r = order[j];
-    if (tiles[r] == 0u) continue;
-    const TileRect t = tile_rect(rec[r], cp, n_per_cam, r);
-    if (t.cam != B.cam || t.ty1 < B.r0 || t.ty0 >= B.r1) continue;
-    const int ya = t.ty0 > B.r0 ? t.ty0 : B.r0, yb = t.ty1 < B.r1 - 1 ? t.ty1 : B.r1 - 1;
-    for (int y = ya; y <= yb; ++y) {
-      const int a = (y - B.r0) * B.tx + t.tx0;
-      atomicAdd(&s_d[a], 1u);
-      atomicSub(&s_d[a + t.w], 1u);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n_rec; base += stride) {
+    const int64_t j = base + threadIdx.x;
+    uint32_t nb = 0, kb0 = 0;
+    uint64_t o = 0;
+    if (j < n_rec) {
+      nb = nbands[j];
+      if (nb) {
+        const uint4 d = desc[j];
+        int64_t first;
+        int rows;
+        camera_bands(cp, (int)d.w, &first, &rows);
+        kb0 = (uint32_t)first + (d.z & 0xffffu) / (uint32_t)rows;
+        o = poff[j];
+      }
+    }
+    // the wavefront walks the pairs of its lanes' records together, so the
+    // digit histograms see every pair once
+    uint32_t most = nb;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      const uint32_t t = __shfl_xor(most, m, 64);
+      most = t > most ? t : most;
+    }
+    for (uint32_t b = 0; b < most; ++b) {
+      const bool ok = b < nb && o + b < (uint64_t)pairs_max;  // past the bound only on overflow
+      const uint32_t k = kb0 + b;
+      if (ok) {
+        pkey[o + b] = k;
+        pval[o + b] = (uint32_t)j;
+      }
+      for (int p = 0; p < hist_passes; ++p) wave_hist_add(s_h + p * kRadix, (k >> (8 * p)) & 0xffu, ok);
     }
   }
   __syncthreads();
-  // inclusive prefix of the difference array: lane-local over a chunk, then
-  // the chunk offsets, written out coalesced
+  flush_hist(s_h, hist_passes * kRadix, hist);
+}
+
+// [start, end) of every band in the sorted pairs (bands without pairs keep
+// the cleared [0, 0)).
+__global__ __launch_bounds__(kBlock) void place_band_ranges_kernel(const uint32_t* __restrict__ pkey,
+                                                                   const uint64_t* __restrict__ n_pairs,
+                                                                   int64_t pairs_max, uint32_t* __restrict__ brange) {
+  const uint64_t n = *n_pairs > (uint64_t)pairs_max ? 0ull : *n_pairs;  // more pairs: entries overflow
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const uint32_t k = pkey[i];
+    if (i == 0 || pkey[i - 1] != k) brange[2 * (uint64_t)k] = (uint32_t)i;
+    if (i + 1 == n || pkey[i + 1] != k) brange[2 * (uint64_t)k + 1] = (uint32_t)(i + 1);
+  }
+}
+
+// Blocks of kBlockPairs pairs per band.
+__global__ __launch_bounds__(kBlock) void place_band_items_kernel(const uint32_t* __restrict__ brange,
+                                                                  int64_t n_bands, uint32_t* __restrict__ nitems) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n_bands) return;
+  const uint32_t len = brange[2 * k + 1] - brange[2 * k];
+  nitems[k] = (len + kBlockPairs - 1) / kBlockPairs;
+}
+
+// item -> band for the items of every band (items of band k start at item0[k]).
+__global__ __launch_bounds__(kBlock) void place_item_bands_kernel(const uint32_t* __restrict__ nitems,
+                                                                  const uint64_t* __restrict__ item0,
+                                                                  int64_t n_bands, uint32_t* __restrict__ item_band) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n_bands) return;
+  const uint64_t a = item0[k];
+  for (uint32_t i = 0; i < nitems[k]; ++i) item_band[a + i] = (uint32_t)k;
+}
+
+// counts[item][t] for the tiles t of the item's band: how many of the
+// item's records cover t (two LDS increments per rect row into a
+// difference array, then its prefix sum).
+__global__ __launch_bounds__(64) void place_count_kernel(
+    const uint4* __restrict__ desc, const uint32_t* __restrict__ pval, const uint32_t* __restrict__ brange,
+    const uint32_t* __restrict__ item_band, const uint64_t* __restrict__ item0, const uint64_t* __restrict__ n_items,
+    CamPack cp, int band_tiles, uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t s_d[];   // band tiles + 1
+  __shared__ uint32_t s_off[64];
+  const int lane = threadIdx.x;
+  const uint64_t item = blockIdx.x;
+  if (item >= *n_items) return;
+  const uint32_t k = item_band[item];
+  const Band B = band_of(cp, k);
+  const int nt = B.n;
+  for (int i = lane; i <= nt; i += 64) s_d[i] = 0u;
+  __syncthreads();
+  const uint64_t p0 = brange[2 * (uint64_t)k] + (item - item0[k]) * kBlockPairs;
+  const uint64_t pe = brange[2 * (uint64_t)k + 1];
+  const uint64_t p1 = p0 + kBlockPairs < pe ? p0 + kBlockPairs : pe;
+  for (uint64_t i = p0 + lane; i < p1; i += 64) {
+    const uint4 d = desc[pval[i]];
+    const int tx0 = (int)(d.y & 0xffffu), w = (int)(d.y >> 16);
+    const int ty0 = (int)(d.z & 0xffffu), ty1 = (int)(d.z >> 16);
+    const int ya = ty0 > B.r0 ? ty0 : B.r0, yb = ty1 < B.r1 - 1 ? ty1 : B.r1 - 1;
+    for (int y = ya; y <= yb; ++y) {
+      const int a = (y - B.r0) * B.tx + tx0;
+      atomicAdd(&s_d[a], 1u);
+      atomicSub(&s_d[a + w], 1u);
+    }
+  }
+  __syncthreads();
   const int chunk = (nt + 63) / 64;
   const int c0 = lane * chunk, c1 = c0 + chunk < nt ? c0 + chunk : nt;
   uint32_t run = 0;
@@ -649,99 +754,107 @@ __global__ __launch_bounds__(64) void place_count_kernel(
   uint32_t tot;
   s_off[lane] = wave_excl_scan_u32(run, lane, &tot);
   __syncthreads();
-  uint32_t* dst = counts + b * n_tiles + B.lo;
+  uint32_t* dst = counts + item * (uint64_t)band_tiles;
   for (int i = lane; i < nt; i += 64) dst[i] = s_d[i] + s_off[i / chunk];
 }
 
-// Per tile: entries over all blocks.
+// Band of tile t and t's index inside it.
+__device__ __forceinline__ void tile_band(const CamPack& cp, uint32_t t, int64_t* k, int* local) {
+  const int c = cam_of_tile(cp, t);
+  int64_t first;
+  int rows;
+  camera_bands(cp, c, &first, &rows);
+  const uint32_t lt = t - cp.cam[c].tile_off;
+  const int tx = cp.cam[c].tiles_x;
+  const int row = (int)(lt / (uint32_t)tx);
+  *k = first + row / rows;
+  *local = (int)lt - (row / rows) * rows * tx;
+}
+
+// Per tile: entries over the items of its band.
 __global__ __launch_bounds__(kBlock) void place_totals_kernel(const uint32_t* __restrict__ counts,
-                                                              int64_t n_blocks, int64_t n_tiles,
-                                                              uint32_t* __restrict__ totals) {
+                                                              const uint32_t* __restrict__ nitems,
+                                                              const uint64_t* __restrict__ item0, CamPack cp,
+                                                              int band_tiles, uint32_t* __restrict__ totals) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n_tiles) return;
+  if (t >= (int64_t)cp.tiles_total) return;
+  int64_t k;
+  int local;
+  tile_band(cp, (uint32_t)t, &k, &local);
+  const uint32_t* c = counts + item0[k] * (uint64_t)band_tiles + local;
   uint32_t v = 0;
-#pragma unroll 8
-  for (int64_t b = 0; b < n_blocks; ++b) v += counts[b * n_tiles + t];
+  for (uint32_t i = 0; i < nitems[k]; ++i) v += c[(uint64_t)i * band_tiles];
   totals[t] = v;
 }
 
-// counts[b][t] <- position of block b's first entry of tile t; the ranges
-// ([0, 0) for an empty tile, and for every tile when the entries overflow
-// the capacity).
+// counts[item][t] <- position of the item's first entry of tile t; the
+// ranges ([0, 0) for an empty tile, and for every tile when the entries
+// overflow the capacity).
 __global__ __launch_bounds__(kBlock) void place_offsets_kernel(
-    uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, const uint64_t* __restrict__ starts,
-    const uint64_t* __restrict__ n_dup, int64_t capacity, int64_t n_blocks, int64_t n_tiles,
-    uint32_t* __restrict__ ranges) {
+    uint32_t* __restrict__ counts, const uint32_t* __restrict__ nitems, const uint64_t* __restrict__ item0,
+    const uint32_t* __restrict__ totals, const uint64_t* __restrict__ starts, const uint64_t* __restrict__ n_dup,
+    int64_t capacity, CamPack cp, int band_tiles, uint32_t* __restrict__ ranges) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n_tiles) return;
+  if (t >= (int64_t)cp.tiles_total) return;
   const bool over = *n_dup > (uint64_t)capacity;
   const uint32_t tot = totals[t];
   const uint32_t a = (uint32_t)starts[t];
   ranges[2 * t] = (tot && !over) ? a : 0u;
   ranges[2 * t + 1] = (tot && !over) ? a + tot : 0u;
   if (over) return;
+  int64_t k;
+  int local;
+  tile_band(cp, (uint32_t)t, &k, &local);
+  uint32_t* c = counts + item0[k] * (uint64_t)band_tiles + local;
   uint32_t run = a;
-#pragma unroll 8
-  for (int64_t b = 0; b < n_blocks; ++b) {
-    const uint32_t c = counts[b * n_tiles + t];
-    counts[b * n_tiles + t] = run;
-    run += c;
+  for (uint32_t i = 0; i < nitems[k]; ++i) {
+    const uint32_t v = c[(uint64_t)i * band_tiles];
+    c[(uint64_t)i * band_tiles] = run;
+    run += v;
   }
 }
 
-// The entries of block b in band k: cursors in LDS, the block's records one
-// after another (their covered tiles in the band across the lanes), so
-// every tile hands out its positions in record order.
+// The entries of one item: cursors in LDS, the item's records one after
+// another (their covered tiles in the band across the lanes), so every
+// tile hands out its positions in record order.
 __global__ __launch_bounds__(64) void place_emit_kernel(
-    const Record* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles,
-    int64_t n_rec, int64_t n_per_cam, CamPack cp, int64_t rb, int64_t n_bands,
-    const uint32_t* __restrict__ offsets, int64_t n_tiles, const uint64_t* __restrict__ n_dup,
+    const uint4* __restrict__ desc, const uint32_t* __restrict__ pval, const uint32_t* __restrict__ brange,
+    const uint32_t* __restrict__ item_band, const uint64_t* __restrict__ item0, const uint64_t* __restrict__ n_items,
+    CamPack cp, int band_tiles, const uint32_t* __restrict__ offsets, const uint64_t* __restrict__ n_dup,
     int64_t capacity, int32_t* __restrict__ overflow, uint32_t* __restrict__ vals) {
   extern __shared__ uint32_t s_cur[];   // band tiles
   const int lane = threadIdx.x;
   const bool over = *n_dup > (uint64_t)capacity;
   if (blockIdx.x == 0 && lane == 0) *overflow = over ? 1 : 0;
-  if (over) return;
-  const int64_t b = blockIdx.x / n_bands;
-  const Band B = band_of(cp, blockIdx.x % n_bands);
-  if (!B.valid) return;
-  const uint32_t* src = offsets + b * n_tiles + B.lo;
+  const uint64_t item = blockIdx.x;
+  if (over || item >= *n_items) return;
+  const uint32_t k = item_band[item];
+  const Band B = band_of(cp, k);
+  const uint32_t* src = offsets + item * (uint64_t)band_tiles;
   for (int i = lane; i < B.n; i += 64) s_cur[i] = src[i];
   __syncthreads();
-  const int64_t j0 = b * rb, j1 = j0 + rb < n_rec ? j0 + rb : n_rec;
-  for (int64_t jb = j0; jb < j1; jb += 64) {
-    const int64_t j = jb + lane;
-    uint32_t r = 0;
-    int x0 = 0, w = 0, ya = 0, nrow = 0;
-    bool in = false;
-    if (j < j1) {
-      r = order[j];
-      if (tiles[r] != 0u) {
-        const TileRect t = tile_rect(rec[r], cp, n_per_cam, r);
-        if (t.cam == B.cam && t.ty1 >= B.r0 && t.ty0 < B.r1) {
-          ya = t.ty0 > B.r0 ? t.ty0 : B.r0;
-          const int yb = t.ty1 < B.r1 - 1 ? t.ty1 : B.r1 - 1;
-          x0 = t.tx0;
-          w = t.w;
-          nrow = yb - ya + 1;
-          in = true;
-        }
-      }
-    }
-    uint64_t m = __builtin_amdgcn_ballot_w64(in);
-    while (m != 0ull) {
-      const int src_lane = (int)__builtin_ctzll(m);
-      m &= m - 1ull;
-      const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)r, src_lane);
-      const int X0 = __builtin_amdgcn_readlane(x0, src_lane);
-      const int W = __builtin_amdgcn_readlane(w, src_lane);
-      const int YA = __builtin_amdgcn_readlane(ya, src_lane);
-      const int n = W * __builtin_amdgcn_readlane(nrow, src_lane);
-      // local tile of entry e: row YA + e / W, column X0 + e % W
-      const int base = (YA - B.r0) * B.tx + X0;
+  const uint64_t p0 = brange[2 * (uint64_t)k] + (item - item0[k]) * kBlockPairs;
+  const uint64_t pe = brange[2 * (uint64_t)k + 1];
+  const uint64_t p1 = p0 + kBlockPairs < pe ? p0 + kBlockPairs : pe;
+  for (uint64_t pb = p0; pb < p1; pb += 64) {
+    const uint64_t i = pb + lane;
+    uint4 d = make_uint4(0u, 0u, 0u, 0u);
+    if (i < p1) d = desc[pval[i]];
+    const int cnt = p1 - pb < 64 ? (int)(p1 - pb) : 64;
+    for (int l = 0; l < cnt; ++l) {
+      const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)d.x, l);
+      const uint32_t XW = (uint32_t)__builtin_amdgcn_readlane((int)d.y, l);
+      const uint32_t YY = (uint32_t)__builtin_amdgcn_readlane((int)d.z, l);
+      const int X0 = (int)(XW & 0xffffu), W = (int)(XW >> 16);
+      const int ty0 = (int)(YY & 0xffffu), ty1 = (int)(YY >> 16);
+      const int ya = ty0 > B.r0 ? ty0 : B.r0, yb = ty1 < B.r1 - 1 ? ty1 : B.r1 - 1;
+      const int n = W * (yb - ya + 1);
+      // local tile of entry e: row ya + e / W, column X0 + e % W
+      const int base = (ya - B.r0) * B.tx + X0;
+      const float inv_w = __builtin_amdgcn_rcpf((float)W);
       for (int q = 0; q < n; q += 64) {
         const int e = q + lane;
-        int row = (int)((float)e * __builtin_amdgcn_rcpf((float)W));
+        int row = (int)((float)e * inv_w);
         int col = e - row * W;
         if (col < 0) { --row; col += W; }
         if (col >= W) { ++row; col -= W; }
@@ -763,9 +876,19 @@ struct SortWs {
   // placement path
   uint32_t* rkeys[2];
   uint32_t* rids[2];
-  uint32_t* counts;    // [n_blocks][n_tiles], then offsets
+  uint4* desc;         // [n_rec] tile rectangles in depth order
+  uint32_t* nbands;    // [n_rec]
+  uint64_t* poff;      // [n_rec] first pair of each slot
+  uint32_t* pkey[2];   // [pairs_max] band of each (record, band) pair
+  uint32_t* pval[2];   // [pairs_max] its slot
+  uint32_t* brange;    // [n_bands][2]
+  uint32_t* nitems;    // [n_bands]
+  uint64_t* item0;     // [n_bands]
+  uint32_t* item_band; // [items_max]
+  uint32_t* counts;    // [items_max][band_tiles], then offsets
   uint32_t* totals;    // [n_tiles]
   uint64_t* starts;    // [n_tiles]
+  uint64_t* scalars;   // n_pairs, n_items, tile total
   void* scan_ws;
   // full-key path
   uint64_t* alt_keys64;
@@ -774,7 +897,7 @@ struct SortWs {
   // both paths
   uint32_t* okeys[2];  // tile order sort
   uint32_t* oalt;
-  uint32_t* hist;      // [kHistCopies][2][kMaxPasses][256]: record passes, entry passes
+  uint32_t* hist;      // [kHistCopies][2][kMaxPasses][256]: record passes, entry (or pair) passes
   uint32_t* bases;     // [2][kMaxPasses][256] scanned
   uint32_t* tickets;   // [2][kMaxPasses]
   uint64_t* lookback[2];
@@ -786,14 +909,17 @@ struct SortWs {
 SortWs carve(void* ws, int64_t n_rec, int64_t capacity, const CamPack& cp, bool full_keys) {
   const int64_t n_tiles = (int64_t)cp.tiles_total;
   SortWs w{};
-  const int64_t small = n_rec > n_tiles ? n_rec : n_tiles;
+  w.geom = place_geom(n_rec, capacity, cp);
+  const PlaceGeom& g = w.geom;
+  int64_t small = n_rec > n_tiles ? n_rec : n_tiles;
+  if (!full_keys) small = small > g.pairs_max ? small : g.pairs_max;
   const int64_t pe = full_keys ? (capacity + kPartMinEntries - 1) / kPartMinEntries : 0;
   const int64_t ps = (small + kPartMinSmall - 1) / kPartMinSmall;
   const int64_t parts = pe > ps ? pe : ps;
   w.parts = parts > 0 ? parts : 1;
-  w.geom = place_geom(n_rec, capacity, cp);
   const size_t nr = (size_t)(n_rec > 0 ? n_rec : 1), cap = (size_t)(capacity > 0 ? capacity : 1);
   const size_t nt = (size_t)(n_tiles > 0 ? n_tiles : 1);
+  const size_t nbd = (size_t)g.n_bands, np = (size_t)g.pairs_max, ni = (size_t)g.items_max;
   char* p = (char*)ws;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -808,10 +934,24 @@ SortWs carve(void* ws, int64_t n_rec, int64_t capacity, const CamPack& cp, bool 
   } else {
     for (int b = 0; b < 2; ++b) w.rkeys[b] = (uint32_t*)take(nr * 4);
     for (int b = 0; b < 2; ++b) w.rids[b] = (uint32_t*)take(nr * 4);
-    w.counts = (uint32_t*)take((size_t)w.geom.n_blocks * nt * 4);
+    w.desc = (uint4*)take(nr * 16);
+    w.nbands = (uint32_t*)take(nr * 4);
+    w.poff = (uint64_t*)take(nr * 8);
+    for (int b = 0; b < 2; ++b) w.pkey[b] = (uint32_t*)take(np * 4);
+    for (int b = 0; b < 2; ++b) w.pval[b] = (uint32_t*)take(np * 4);
+    w.brange = (uint32_t*)take(nbd * 8);
+    w.nitems = (uint32_t*)take(nbd * 4);
+    w.item0 = (uint64_t*)take(nbd * 8);
+    w.item_band = (uint32_t*)take(ni * 4);
+    w.counts = (uint32_t*)take(ni * (size_t)g.band_tiles * 4);
     w.totals = (uint32_t*)take(nt * 4);
     w.starts = (uint64_t*)take(nt * 8);
-    w.scan_ws = take(scan_workspace_bytes((int64_t)nt) + 256);
+    w.scalars = (uint64_t*)take(4 * 8);
+    size_t sw = scan_workspace_bytes((int64_t)nr);
+    const size_t s2 = scan_workspace_bytes((int64_t)nt), s3 = scan_workspace_bytes((int64_t)nbd);
+    sw = sw > s2 ? sw : s2;
+    sw = sw > s3 ? sw : s3;
+    w.scan_ws = take(sw);
   }
   for (int b = 0; b < 2; ++b) w.okeys[b] = (uint32_t*)take(nt * 4);
   w.oalt = (uint32_t*)take(nt * 4);
@@ -916,22 +1056,54 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     const uint32_t* order = w.rids[0];  // four passes: back in buffer 0
     const int64_t nt = (int64_t)cp.tiles_total;
     const PlaceGeom& g = w.geom;
-    const unsigned items = (unsigned)(g.n_blocks * g.n_bands);
-    // 2. counts[block][tile]
+    uint64_t* n_pairs = w.scalars;
+    uint64_t* n_items = w.scalars + 1;
+    // 2. tile rectangles in depth order, (band, slot) pairs sorted by band
+    //    (stable: slots stay in depth order inside a band)
+    hipLaunchKernelGGL(place_desc_kernel, dim3(grid_for(n_rec, kBlock, 1ll << 31)), dim3(kBlock), 0, s, rec,
+                       order, tiles, n_rec, n_per_cam, cp, w.desc, w.nbands);
+    hipError_t e = launch_scan(w.nbands, n_rec, w.poff, n_pairs, w.scan_ws, s);
+    if (e != hipSuccess) return e;
+    const int bpasses = (g.band_bits + 7) / 8;
+    hipLaunchKernelGGL(place_pairs_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s,
+                       (const uint4*)w.desc, (const uint32_t*)w.nbands, (const uint64_t*)w.poff, n_rec,
+                       g.pairs_max, cp, w.pkey[0], w.pval[0], hist_ent, bpasses);
+    if (bpasses > 0) {
+      hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, bpasses);
+      onesweep_passes<uint32_t, kSmallItems>(w.pkey, w.pval, n_pairs, g.pairs_max, 0, bpasses, base_ent, w,
+                                             w.tickets + kMaxPasses, lb, s);
+    }
+    const uint32_t* pkey = w.pkey[bpasses & 1];
+    const uint32_t* pval = w.pval[bpasses & 1];
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(2 * g.n_bands, kBlock, 4096)), dim3(kBlock), 0, s,
+                       w.brange, 2 * g.n_bands, 0u);
+    hipLaunchKernelGGL(place_band_ranges_kernel, dim3(grid_for(g.pairs_max, kBlock, 8192)), dim3(kBlock), 0, s,
+                       pkey, (const uint64_t*)n_pairs, g.pairs_max, w.brange);
+    hipLaunchKernelGGL(place_band_items_kernel, dim3(grid_for(g.n_bands, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
+                       (const uint32_t*)w.brange, g.n_bands, w.nitems);
+    e = launch_scan(w.nitems, g.n_bands, w.item0, n_items, w.scan_ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(place_item_bands_kernel, dim3(grid_for(g.n_bands, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
+                       (const uint32_t*)w.nitems, (const uint64_t*)w.item0, g.n_bands, w.item_band);
+    // 3. counts[item][tile], tile totals, their scan, per-item offsets, ranges
     const size_t lds = (size_t)(g.band_tiles + 1) * sizeof(uint32_t);
-    hipLaunchKernelGGL(place_count_kernel, dim3(items), dim3(64), lds, s, rec, order, tiles, n_rec, n_per_cam,
-                       cp, g.rb, g.n_bands, nt, w.counts);
-    // 3. tile totals, their scan, per-block offsets and the ranges
+    const unsigned items = (unsigned)g.items_max;
+    hipLaunchKernelGGL(place_count_kernel, dim3(items), dim3(64), lds, s, (const uint4*)w.desc, pval,
+                       (const uint32_t*)w.brange, (const uint32_t*)w.item_band, (const uint64_t*)w.item0,
+                       (const uint64_t*)n_items, cp, g.band_tiles, w.counts);
     hipLaunchKernelGGL(place_totals_kernel, dim3(grid_for(nt, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
-                       (const uint32_t*)w.counts, g.n_blocks, nt, w.totals);
-    hipError_t e = launch_scan(w.totals, nt, w.starts, (uint64_t*)w.scan_ws, (char*)w.scan_ws + 256, s);
+                       (const uint32_t*)w.counts, (const uint32_t*)w.nitems, (const uint64_t*)w.item0, cp,
+                       g.band_tiles, w.totals);
+    e = launch_scan(w.totals, nt, w.starts, w.scalars + 2, w.scan_ws, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(place_offsets_kernel, dim3(grid_for(nt, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
-                       w.counts, (const uint32_t*)w.totals, (const uint64_t*)w.starts, n_dup, capacity,
-                       g.n_blocks, nt, ranges);
+                       w.counts, (const uint32_t*)w.nitems, (const uint64_t*)w.item0, (const uint32_t*)w.totals,
+                       (const uint64_t*)w.starts, n_dup, capacity, cp, g.band_tiles, ranges);
     // 4. the entries
-    hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(64), lds, s, rec, order, tiles, n_rec, n_per_cam, cp,
-                       g.rb, g.n_bands, (const uint32_t*)w.counts, nt, n_dup, capacity, overflow, vals);
+    hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(64), lds, s, (const uint4*)w.desc, pval,
+                       (const uint32_t*)w.brange, (const uint32_t*)w.item_band, (const uint64_t*)w.item0,
+                       (const uint64_t*)n_items, cp, g.band_tiles, (const uint32_t*)w.counts, n_dup, capacity,
+                       overflow, vals);
     if (keys)
       hipLaunchKernelGGL(keys_from_ranges_kernel, dim3(nt > 0 ? (unsigned)nt : 1u), dim3(64), 0, s,
                          (const uint32_t*)ranges, (const uint32_t*)vals, rec, nt, keys);
