@@ -225,12 +225,30 @@ int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint6
  *              tile list (values[start .. end) of its tile), of the last
  *              blended entry; -1 if none
  *   n_contrib  device, int32 per pixel (out): number of blended kernels
+ *   depth      device, float per pixel (out), may be NULL: the blended
+ *              camera-space depth of the kernel centres, sum of w_i z_i with
+ *              the colour weights w_i (no background term; the depth maps of
+ *              Sec. 4, divide by 1 - T_final for the expected depth)
  *   workspace  device, hgs_workspace_bytes(HGS_WS_RENDER, ...) bytes */
 int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* ranges,
                    const uint32_t* tile_order, const hgs_camera* cams, int32_t n_cams,
                    const hgs_options* opts, float* images, float* T_final, int32_t* last_idx,
-                   int32_t* n_contrib, void* workspace, size_t workspace_bytes,
+                   int32_t* n_contrib, float* depth, void* workspace, size_t workspace_bytes,
                    hipStream_t stream);
+
+/* Surface normals estimated from the depth map (Sec. 4 shows them; the
+ * estimate follows 2D-GS): per pixel the expected depth d = depth / (1 -
+ * T_final) is back-projected through the camera, P = d ((u + 1/2 - cx) / fx,
+ * (v + 1/2 - cy) / fy, 1), and n = -(P(u+1, v) - P(u-1, v)) x (P(u, v+1) -
+ * P(u, v-1)), normalised: camera axes, facing the camera.  Zero on the image
+ * border, next to a pixel with 1 - T_final = 0, and where the cross product
+ * vanishes.  Computed in FP64.
+ *   depth, T_final  device, float per pixel, as from hgs_render_fwd
+ *   normals         device, float [3][H][W] per camera, camera c at
+ *                   3 * pixel offset c (out)
+ * HGS_EINVAL for a null pointer or bad cameras. */
+int hgs_depth_normals(const float* depth, const float* T_final, const hgs_camera* cams, int32_t n_cams,
+                      float* normals, hipStream_t stream);
 
 /* Gradient of a scalar loss L given dL/d(image) (same layout as `images`).
  * Replays every pixel back to front from last_idx using T_final (no blend

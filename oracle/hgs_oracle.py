@@ -387,7 +387,7 @@ def raster_records(pre: dict, mode: str = "e2e", leaves: dict | None = None) -> 
     g = pre["rec"]
     corner = torch.stack([rec[:, 0], rec[:, 2]], -1).to(F64)
     fields = dict(mu_rel=g["mean2d"] - corner, conic=g["conic"], k=g["k"],
-                  alpha2=g["alpha2"], d_o=g["d_o"], colour=g["colour"])
+                  alpha2=g["alpha2"], d_o=g["d_o"], colour=g["colour"], z=g["tz"])
     if leaves is not None:
         fields = {k: v.detach().clone().requires_grad_(True) for k, v in fields.items()}
         leaves.update(fields)
@@ -457,10 +457,12 @@ def _composite(recs: dict, cand: torch.Tensor, px: torch.Tensor, py: torch.Tenso
     T_before = torch.cat([torch.ones_like(T_incl[:, :1]), T_incl[:, :-1]], 1)
     w = a_b * T_before
     colour = w @ recs["colour"][cand] if cand.numel() else torch.zeros(px.shape[0], 3, dtype=F64)
+    # accumulated depth: the same weights on the kernels' camera-space z
+    depth = w @ recs["z"][cand] if cand.numel() else torch.zeros(px.shape[0], dtype=F64)
     T_final = T_incl[:, -1] if cand.numel() else torch.ones(px.shape[0], dtype=F64)
     bg = torch.tensor(o["bg"], dtype=F64)
     out = colour + T_final[:, None] * bg
-    return out, T_final, count, last, margin
+    return out, T_final, count, last, margin, depth
 
 
 def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64, leaves: dict | None = None) -> dict:
@@ -481,7 +483,7 @@ def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64, leaves: d
         chunk = 256
     pixels = torch.as_tensor(np.asarray(pixels), dtype=torch.int64)
     rect = recs["rect"]
-    outs, Ts, cnts, lasts, margins = [], [], [], [], []
+    outs, Ts, cnts, lasts, margins, depths = [], [], [], [], [], []
     for s in range(0, pixels.shape[0], chunk):
         px, py = pixels[s:s + chunk, 0], pixels[s:s + chunk, 1]
         hit = ((rect[:, 0] <= px.max()) & (rect[:, 1] >= px.min()) &
@@ -492,7 +494,8 @@ def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64, leaves: d
             any_in = ((px[:, None] >= r[None, :, 0]) & (px[:, None] <= r[None, :, 1]) &
                       (py[:, None] >= r[None, :, 2]) & (py[:, None] <= r[None, :, 3])).any(0)
             cand = cand[any_in]
-        out, T, cnt, last, mg = _composite(recs, cand, px, py, o)
+        out, T, cnt, last, mg, dep = _composite(recs, cand, px, py, o)
+        depths.append(dep)
         lasts.append(torch.where(last >= 0, recs["id"][cand][last.clamp(min=0)] if cand.numel() else last,
                                  torch.full_like(last, -1)))
         outs.append(out)
@@ -501,15 +504,44 @@ def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64, leaves: d
         margins.append(mg)
     out = torch.cat(outs)
     res = dict(values=out, T_final=torch.cat(Ts), n_contrib=torch.cat(cnts),
-               last_id=torch.cat(lasts), margin=torch.cat(margins), pixels=pixels)
+               last_id=torch.cat(lasts), margin=torch.cat(margins), depth=torch.cat(depths), pixels=pixels)
     if full:
         inv = np.empty_like(order)
         inv[order] = np.arange(order.size)
         inv_t = torch.from_numpy(inv)
         res["image"] = out[inv_t].T.reshape(3, H, W)
-        for k in ("T_final", "n_contrib", "last_id", "margin"):
+        for k in ("T_final", "n_contrib", "last_id", "margin", "depth"):
             res[k] = res[k][inv_t].reshape((H, W) + tuple(res[k].shape[1:]))
     return res
+
+
+def depth_normals(depth, T_final, cam: dict) -> np.ndarray:
+    """Surface normals estimated from a rendered depth map, as the paper does
+    for its normal maps (after 2D-GS): the expected depth d = D / (1 - T)
+    back-projected through the pinhole to P(u, v) = d ((u + 1/2 - cx) / fx,
+    (v + 1/2 - cy) / fy, 1), and n = -(P(u+1,v) - P(u-1,v)) x (P(u,v+1) -
+    P(u,v-1)) normalised (camera axes; facing the camera).  Zero on the
+    border, where any of the four neighbours has 1 - T = 0, and where the
+    cross product vanishes.  depth, T_final: [H, W]; returns [3, H, W]."""
+    D = np.asarray(depth, np.float64)
+    T = np.asarray(T_final, np.float64)
+    H, W = D.shape
+    acc = 1.0 - T
+    d = np.where(acc > 0, D / np.where(acc > 0, acc, 1.0), 0.0)
+    u = (np.arange(W) + 0.5 - float(cam["cx"])) / float(cam["fx"])
+    v = (np.arange(H) + 0.5 - float(cam["cy"])) / float(cam["fy"])
+    P = np.stack([d * u[None, :], d * v[:, None], d], 0)
+    n = np.zeros((3, H, W))
+    if H < 3 or W < 3:
+        return n
+    dx = P[:, 1:-1, 2:] - P[:, 1:-1, :-2]
+    dy = P[:, 2:, 1:-1] - P[:, :-2, 1:-1]
+    c = -np.cross(dx, dy, axis=0)
+    norm = np.sqrt((c * c).sum(0))
+    ok = ((acc[1:-1, 2:] > 0) & (acc[1:-1, :-2] > 0) & (acc[2:, 1:-1] > 0) & (acc[:-2, 1:-1] > 0)
+          & (norm > 0))
+    n[:, 1:-1, 1:-1] = np.where(ok, c / np.where(ok, norm, 1.0), 0.0)
+    return n
 
 
 def render_grad(scene: dict, cams: list, dL_dout: list, o: dict | None = None, pixels=None) -> dict:

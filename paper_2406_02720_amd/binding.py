@@ -23,7 +23,7 @@ HGS_WS_PREPROCESS, HGS_WS_BIN_SORT, HGS_WS_RENDER = 0, 1, 2
 
 EXPORTS = ("hgs_default_options", "hgs_workspace_bytes", "hgs_tiles_total", "hgs_pixels_total",
            "hgs_preprocess", "hgs_bin_sort", "hgs_render_fwd", "hgs_render_bwd",
-           "hgs_raster_bwd", "hgs_preprocess_bwd", "hgs_strerror", "hgs_last_error")
+           "hgs_raster_bwd", "hgs_preprocess_bwd", "hgs_depth_normals", "hgs_strerror", "hgs_last_error")
 
 
 class hgs_camera(C.Structure):
@@ -86,9 +86,11 @@ def load(path: str = LIB_PATH):
     lib.hgs_bin_sort.argtypes = [vp, vp, vp, vp, i64, P(hgs_camera), i32, P(hgs_options), vp, vp, i64,
                                  vp, vp, vp, vp, sz, vp]
     lib.hgs_bin_sort.restype = C.c_int
-    lib.hgs_render_fwd.argtypes = [vp, vp, vp, vp, P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp,
+    lib.hgs_render_fwd.argtypes = [vp, vp, vp, vp, P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp, vp,
                                    vp, sz, vp]
     lib.hgs_render_fwd.restype = C.c_int
+    lib.hgs_depth_normals.argtypes = [vp, vp, P(hgs_camera), i32, vp, vp]
+    lib.hgs_depth_normals.restype = C.c_int
     lib.hgs_render_bwd.argtypes = [P(hgs_params), P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp,
                                    vp, vp, vp, vp, P(hgs_param_grads), vp, sz, vp]
     lib.hgs_render_bwd.restype = C.c_int
@@ -190,11 +192,15 @@ def hgs_bin_sort(records, tiles, offsets, n_dup, n_rec, cams, opts, keys, values
 
 
 def hgs_render_fwd(records, values, ranges, tile_order, cams, opts, images, T_final, last_idx, n_contrib, ws,
-                   stream):
+                   stream, depth=None):
     check(load().hgs_render_fwd(_ptr(records), _ptr(values), _ptr(ranges), _ptr(tile_order), cams, len(cams),
                                 C.byref(opts),
-                                _ptr(images), _ptr(T_final), _ptr(last_idx), _ptr(n_contrib), _ptr(ws),
-                                ws.numel() * ws.element_size(), stream))
+                                _ptr(images), _ptr(T_final), _ptr(last_idx), _ptr(n_contrib), _ptr(depth),
+                                _ptr(ws), ws.numel() * ws.element_size(), stream))
+
+
+def hgs_depth_normals(depth, T_final, cams, normals, stream):
+    check(load().hgs_depth_normals(_ptr(depth), _ptr(T_final), cams, len(cams), _ptr(normals), stream))
 
 
 def hgs_render_bwd(params, cams, opts, records, values, ranges, tile_order, T_final, last_idx, dL_dimages,

@@ -208,7 +208,7 @@ int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint6
 int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* ranges,
                    const uint32_t* tile_order, const hgs_camera* cams, int32_t n_cams,
                    const hgs_options* opts, float* images,
-                   float* T_final, int32_t* last_idx, int32_t* n_contrib, void* workspace,
+                   float* T_final, int32_t* last_idx, int32_t* n_contrib, float* depth, void* workspace,
                    size_t workspace_bytes, hipStream_t stream) {
   int e;
   if ((e = check_opts(opts)) != HGS_OK) return e;
@@ -220,8 +220,22 @@ int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* 
     return fail(HGS_ECAPACITY, "workspace too small");
   const hgs::Opts o = hgs::to_opts(*opts);
   hipError_t h = hgs::launch_render_fwd((const hgs::Record*)records, values, ranges, tile_order, cp, o,
-                                        images, T_final, last_idx, n_contrib, workspace, stream);
+                                        images, T_final, last_idx, n_contrib, depth, workspace, stream);
   if (h != hipSuccess) return hip_fail(h, "render_fwd launch");
+  return HGS_OK;
+}
+
+int hgs_depth_normals(const float* depth, const float* T_final, const hgs_camera* cams, int32_t n_cams,
+                      float* normals, hipStream_t stream) {
+  if (!depth || !T_final || !normals) return fail(HGS_EINVAL, "a pointer is null");
+  hgs_options o;
+  hgs_default_options(&o);
+  hgs::CamPack cp;
+  int e;
+  if ((e = make_pack(cams, n_cams, &o, &cp)) != HGS_OK) return e;
+  const int64_t n_pix = hgs_pixels_total(cams, n_cams);
+  hipError_t h = hgs::launch_depth_normals(depth, T_final, cp, (uint64_t)n_pix, normals, stream);
+  if (h != hipSuccess) return hip_fail(h, "depth_normals launch");
   return HGS_OK;
 }
 

@@ -124,7 +124,9 @@ size_t render_workspace_bytes();
 hipError_t launch_render_fwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                              const uint32_t* tile_order, const CamPack& cp, const Opts& o,
                              float* img, float* T_final, int32_t* last_idx, int32_t* n_contrib,
-                             void* ws, hipStream_t s);
+                             float* depth, void* ws, hipStream_t s);
+hipError_t launch_depth_normals(const float* depth, const float* T_final, const CamPack& cp, uint64_t n_pix,
+                                float* normals, hipStream_t s);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t s);
 hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                              const uint32_t* tile_order, const CamPack& cp, const Opts& o,

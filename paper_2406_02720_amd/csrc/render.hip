@@ -201,12 +201,12 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // for the wavefront on lane masks (rect against each strip, pixels still
 // open, any pair reaching alpha_min, d_o == 0); the per-pixel updates are
 // selects on a mask, so the lanes never branch apart.
-template <int T, int IPL>
+template <int T, int IPL, bool DEPTH>
 __device__ __forceinline__ void fwd_block(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const CamPack& cp, const Opts& o, float* __restrict__ img,
     float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib,
-    uint32_t tile, int wave, int lane) {
+    float* __restrict__ depth, uint32_t tile, int wave, int lane) {
   using Gm = Geometry<T>;
   constexpr int PPL = Gm::PPL;
   constexpr int RS = Gm::ROWSTEP;
@@ -221,13 +221,13 @@ __device__ __forceinline__ void fwd_block(
   const int px = ox + lane % Gm::SUB;
   const float fpx = (float)px + 0.5f;
   const int py0 = oy + lane / Gm::SUB;
-  float Tr[PPL], C0[PPL], C1[PPL], C2[PPL];
+  float Tr[PPL], C0[PPL], C1[PPL], C2[PPL], Dz[PPL];
   int32_t cnt[PPL], last[PPL];
   uint64_t open[PPL];   // lanes whose pixel j still takes entries
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     Tr[j] = 1.0f;
-    C0[j] = C1[j] = C2[j] = 0.0f;
+    C0[j] = C1[j] = C2[j] = Dz[j] = 0.0f;
     cnt[j] = 0;
     last[j] = -1;
     open[j] = lanes(px < cam.width && py0 + j * RS < cam.height);
@@ -291,6 +291,7 @@ __device__ __forceinline__ void fwd_block(
           C0[j] = fmaf(r.r, w, C0[j]);
           C1[j] = fmaf(r.g, w, C1[j]);
           C2[j] = fmaf(r.b, w, C2[j]);
+          if constexpr (DEPTH) Dz[j] = fmaf(__uint_as_float(r.depth), w, Dz[j]);
           Tr[j] = take ? Tn : Tr[j];
           cnt[j] += take ? 1 : 0;
           last[j] = take ? pos : last[j];
@@ -318,6 +319,7 @@ __device__ __forceinline__ void fwd_block(
     T_final[cam.pix_off + pix] = Tr[j];
     last_idx[cam.pix_off + pix] = last[j];
     n_contrib[cam.pix_off + pix] = cnt[j];
+    if constexpr (DEPTH) depth[cam.pix_off + pix] = Dz[j];
   }
 }
 
@@ -328,30 +330,31 @@ __device__ __forceinline__ uint32_t next_work(uint32_t* counter, int lane) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)w);
 }
 
-template <int T, int IPL>
+template <int T, int IPL, bool DEPTH>
 __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, CamPack cp, Opts o, float* __restrict__ img,
-    float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib) {
-  fwd_block<T, IPL>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, blockIdx.x,
-                    threadIdx.x >> 6, threadIdx.x & 63);
+    float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib,
+    float* __restrict__ depth) {
+  fwd_block<T, IPL, DEPTH>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, depth, blockIdx.x,
+                           threadIdx.x >> 6, threadIdx.x & 63);
 }
 
 // Persistent form: one wavefront per workgroup, a grid sized to the chip;
 // every wavefront takes work items (tile rank, sub-block) from a counter,
 // tiles in `order` (longest list first) so that long tiles do not start last.
-template <int T, int IPL>
+template <int T, int IPL, bool DEPTH>
 __global__ __launch_bounds__(64) void render_fwd_persistent_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
     float* __restrict__ img, float* __restrict__ T_final, int32_t* __restrict__ last_idx,
-    int32_t* __restrict__ n_contrib, uint32_t* __restrict__ counter) {
+    int32_t* __restrict__ n_contrib, float* __restrict__ depth, uint32_t* __restrict__ counter) {
   constexpr uint32_t WAVES = Geometry<T>::WAVES;
   const uint32_t n_work = cp.tiles_total * WAVES;
   const int lane = threadIdx.x & 63;
   for (uint32_t w = next_work(counter, lane); w < n_work; w = next_work(counter, lane))
-    fwd_block<T, IPL>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, order[w / WAVES],
-                      (int)(w % WAVES), lane);
+    fwd_block<T, IPL, DEPTH>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, depth,
+                             order[w / WAVES], (int)(w % WAVES), lane);
 }
 
 // One wavefront's block of pixels, back to front.  Same masks as the
@@ -555,22 +558,30 @@ unsigned persistent_grid(F kernel, uint32_t n_work) {
   return (unsigned)(g < n_work ? g : (n_work > 0 ? n_work : 1));
 }
 
-template <int T, int B>
-hipError_t fwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
-                      const uint32_t* order, const CamPack& cp, const Opts& o, float* img, float* Tf,
-                      int32_t* li, int32_t* nc, void* ws, hipStream_t s) {
+template <int T, int B, bool DEPTH>
+hipError_t fwd_launch_d(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
+                        const uint32_t* order, const CamPack& cp, const Opts& o, float* img, float* Tf,
+                        int32_t* li, int32_t* nc, float* depth, void* ws, hipStream_t s) {
   if (order) {
     uint32_t* counter = static_cast<uint32_t*>(ws);
     hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
     const uint32_t n_work = cp.tiles_total * Geometry<T>::WAVES;
-    hipLaunchKernelGGL((render_fwd_persistent_kernel<T, B / 64>),
-                       dim3(persistent_grid(render_fwd_persistent_kernel<T, B / 64>, n_work)), dim3(64), 0,
-                       s, rec, vals, ranges, order, cp, o, img, Tf, li, nc, counter);
+    hipLaunchKernelGGL((render_fwd_persistent_kernel<T, B / 64, DEPTH>),
+                       dim3(persistent_grid(render_fwd_persistent_kernel<T, B / 64, DEPTH>, n_work)), dim3(64), 0,
+                       s, rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, counter);
   } else {
-    hipLaunchKernelGGL((render_fwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
-                       0, s, rec, vals, ranges, cp, o, img, Tf, li, nc);
+    hipLaunchKernelGGL((render_fwd_kernel<T, B / 64, DEPTH>), dim3(cp.tiles_total),
+                       dim3(64 * Geometry<T>::WAVES), 0, s, rec, vals, ranges, cp, o, img, Tf, li, nc, depth);
   }
   return hipGetLastError();
+}
+
+template <int T, int B>
+hipError_t fwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
+                      const uint32_t* order, const CamPack& cp, const Opts& o, float* img, float* Tf,
+                      int32_t* li, int32_t* nc, float* depth, void* ws, hipStream_t s) {
+  return depth ? fwd_launch_d<T, B, true>(rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, ws, s)
+               : fwd_launch_d<T, B, false>(rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, ws, s);
 }
 
 template <int T, int B>
@@ -591,6 +602,55 @@ hipError_t bwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* r
   return hipGetLastError();
 }
 
+// Normals estimated from the accumulated depth (see launch_depth_normals).
+__global__ __launch_bounds__(256) void depth_normals_kernel(const float* __restrict__ depth,
+                                                            const float* __restrict__ T_final, CamPack cp,
+                                                            uint64_t n_pix, float* __restrict__ normals) {
+  const uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n_pix) return;
+  int c = 0;
+  for (int i = 1; i < cp.n_cams; ++i)
+    if (p >= cp.cam[i].pix_off) c = i;
+  const CamDev& cam = cp.cam[c];
+  const int W = cam.width, H = cam.height;
+  const uint64_t local = p - cam.pix_off;
+  const int v = (int)(local / (uint64_t)W), u = (int)(local - (uint64_t)v * W);
+  const float* D = depth + cam.pix_off;
+  const float* Tf = T_final + cam.pix_off;
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+  if (u >= 1 && u < W - 1 && v >= 1 && v < H - 1) {
+    const int du[4] = {1, -1, 0, 0}, dv[4] = {0, 0, 1, -1};
+    double P[4][3];
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t pq = (uint64_t)(v + dv[q]) * W + (u + du[q]);
+      const double acc = 1.0 - (double)Tf[pq];
+      ok = ok && acc > 0.0;
+      const double d = acc > 0.0 ? (double)D[pq] / acc : 0.0;
+      P[q][0] = d * (((double)(u + du[q]) + 0.5 - (double)cam.cx) / (double)cam.fx);
+      P[q][1] = d * (((double)(v + dv[q]) + 0.5 - (double)cam.cy) / (double)cam.fy);
+      P[q][2] = d;
+    }
+    if (ok) {
+      const double ax = P[0][0] - P[1][0], ay = P[0][1] - P[1][1], az = P[0][2] - P[1][2];
+      const double bx = P[2][0] - P[3][0], by = P[2][1] - P[3][1], bz = P[2][2] - P[3][2];
+      const double cx = -(ay * bz - az * by), cy = -(az * bx - ax * bz), cz = -(ax * by - ay * bx);
+      const double nn = sqrt(cx * cx + cy * cy + cz * cz);
+      if (nn > 0.0) {
+        n0 = cx / nn;
+        n1 = cy / nn;
+        n2 = cz / nn;
+      }
+    }
+  }
+  float* out = normals + 3 * cam.pix_off;
+  const uint64_t plane = (uint64_t)W * H;
+  out[local] = (float)n0;
+  out[plane + local] = (float)n1;
+  out[2 * plane + local] = (float)n2;
+}
+
 #define HGS_DISPATCH(T_, B_, CALL) \
   if (o.tile == T_ && o.batch == B_) return CALL<T_, B_>
 
@@ -601,9 +661,9 @@ size_t render_workspace_bytes() { return 256; }
 hipError_t launch_render_fwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                              const uint32_t* tile_order, const CamPack& cp, const Opts& o,
                              float* img, float* T_final, int32_t* last_idx, int32_t* n_contrib,
-                             void* ws, hipStream_t s) {
+                             float* depth, void* ws, hipStream_t s) {
   if (cp.tiles_total == 0) return hipSuccess;
-#define ARGS (rec, vals, ranges, tile_order, cp, o, img, T_final, last_idx, n_contrib, ws, s)
+#define ARGS (rec, vals, ranges, tile_order, cp, o, img, T_final, last_idx, n_contrib, depth, ws, s)
   HGS_DISPATCH(8, 128, fwd_launch) ARGS;
   HGS_DISPATCH(8, 256, fwd_launch) ARGS;
   HGS_DISPATCH(8, 512, fwd_launch) ARGS;
@@ -642,6 +702,14 @@ hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint
   HGS_DISPATCH(32, 512, bwd_launch) ARGS;
 #undef ARGS
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_depth_normals(const float* depth, const float* T_final, const CamPack& cp, uint64_t n_pix,
+                                float* normals, hipStream_t s) {
+  if (n_pix == 0) return hipSuccess;
+  hipLaunchKernelGGL(depth_normals_kernel, dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, s, depth,
+                     T_final, cp, n_pix, normals);
+  return hipGetLastError();
 }
 
 }  // namespace hgs

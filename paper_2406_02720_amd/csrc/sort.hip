@@ -512,7 +512,8 @@ __global__ __launch_bounds__(64) void keys_from_ranges_kernel(const uint32_t* __
 // ---------------------------------------------------------------------------
 // placement path
 // ---------------------------------------------------------------------------
-constexpr int kBandTiles = 256;      // a band: whole tile rows of one camera, >= 256 tiles
+constexpr int kBandTiles = 1024;     // a band: whole tile rows of one camera, >= 1024 tiles
+constexpr int kItemGroup = 32;       // items per partial sum in the tile scans
 constexpr int kBlockPairs = 1024;    // (record, band) pairs per placement block
 
 // Tile rows per band of a camera with `tiles_x` tiles per row.
@@ -758,56 +759,68 @@ __global__ __launch_bounds__(64) void place_count_kernel(
   for (int i = lane; i < nt; i += 64) dst[i] = s_d[i] + s_off[i / chunk];
 }
 
-// Band of tile t and t's index inside it.
-__device__ __forceinline__ void tile_band(const CamPack& cp, uint32_t t, int64_t* k, int* local) {
-  const int c = cam_of_tile(cp, t);
-  int64_t first;
-  int rows;
-  camera_bands(cp, c, &first, &rows);
-  const uint32_t lt = t - cp.cam[c].tile_off;
-  const int tx = cp.cam[c].tiles_x;
-  const int row = (int)(lt / (uint32_t)tx);
-  *k = first + row / rows;
-  *local = (int)lt - (row / rows) * rows * tx;
-}
 
-// Per tile: entries over the items of its band.
-__global__ __launch_bounds__(kBlock) void place_totals_kernel(const uint32_t* __restrict__ counts,
-                                                              const uint32_t* __restrict__ nitems,
-                                                              const uint64_t* __restrict__ item0, CamPack cp,
-                                                              int band_tiles, uint32_t* __restrict__ totals) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= (int64_t)cp.tiles_total) return;
-  int64_t k;
-  int local;
-  tile_band(cp, (uint32_t)t, &k, &local);
-  const uint32_t* c = counts + item0[k] * (uint64_t)band_tiles + local;
+// Tile scans over the items of a band, in groups of kItemGroup items: one
+// wavefront per (band, 64-tile chunk, group) so that thousands of
+// wavefronts share the work.  Pass 1 stores each group's per-tile sum (in
+// the group's first item row of `gsum`) and adds it to the tile total.
+__global__ __launch_bounds__(64) void place_group_sums_kernel(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ nitems, const uint64_t* __restrict__ item0,
+    CamPack cp, int band_tiles, int64_t n_bands, int chunks, int groups, uint32_t* __restrict__ gsum,
+    uint32_t* __restrict__ totals) {
+  const int64_t w = blockIdx.x;
+  const int64_t k = w / ((int64_t)chunks * groups);
+  const int rem = (int)(w - k * (int64_t)chunks * groups);
+  const int chunk = rem / groups, g = rem % groups;
+  if (k >= n_bands) return;
+  const Band B = band_of(cp, k);
+  const int t = chunk * 64 + (int)threadIdx.x;
+  const uint32_t ni = nitems[k];
+  const uint32_t i0 = (uint32_t)g * kItemGroup;
+  if (t >= B.n || i0 >= ni) return;
+  const uint32_t i1 = i0 + kItemGroup < ni ? i0 + kItemGroup : ni;
+  const uint32_t* c = counts + item0[k] * (uint64_t)band_tiles + t;
   uint32_t v = 0;
-  for (uint32_t i = 0; i < nitems[k]; ++i) v += c[(uint64_t)i * band_tiles];
-  totals[t] = v;
+#pragma unroll 8
+  for (uint32_t i = i0; i < i1; ++i) v += c[(uint64_t)i * band_tiles];
+  gsum[(item0[k] + i0) * (uint64_t)band_tiles + t] = v;
+  atomicAdd(&totals[B.lo + t], v);
 }
 
-// counts[item][t] <- position of the item's first entry of tile t; the
+// Pass 2: counts[item][t] <- position of the item's first entry of tile t
+// (tile start + the groups before + the items before in the group); the
 // ranges ([0, 0) for an empty tile, and for every tile when the entries
 // overflow the capacity).
-__global__ __launch_bounds__(kBlock) void place_offsets_kernel(
-    uint32_t* __restrict__ counts, const uint32_t* __restrict__ nitems, const uint64_t* __restrict__ item0,
-    const uint32_t* __restrict__ totals, const uint64_t* __restrict__ starts, const uint64_t* __restrict__ n_dup,
-    int64_t capacity, CamPack cp, int band_tiles, uint32_t* __restrict__ ranges) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= (int64_t)cp.tiles_total) return;
+__global__ __launch_bounds__(64) void place_offsets_kernel(
+    uint32_t* __restrict__ counts, const uint32_t* __restrict__ gsum, const uint32_t* __restrict__ nitems,
+    const uint64_t* __restrict__ item0, const uint32_t* __restrict__ totals, const uint64_t* __restrict__ starts,
+    const uint64_t* __restrict__ n_dup, int64_t capacity, CamPack cp, int band_tiles, int64_t n_bands, int chunks,
+    int groups, uint32_t* __restrict__ ranges) {
+  const int64_t w = blockIdx.x;
+  const int64_t k = w / ((int64_t)chunks * groups);
+  const int rem = (int)(w - k * (int64_t)chunks * groups);
+  const int chunk = rem / groups, g = rem % groups;
+  if (k >= n_bands) return;
+  const Band B = band_of(cp, k);
+  const int t = chunk * 64 + (int)threadIdx.x;
+  if (t >= B.n) return;
   const bool over = *n_dup > (uint64_t)capacity;
-  const uint32_t tot = totals[t];
-  const uint32_t a = (uint32_t)starts[t];
-  ranges[2 * t] = (tot && !over) ? a : 0u;
-  ranges[2 * t + 1] = (tot && !over) ? a + tot : 0u;
-  if (over) return;
-  int64_t k;
-  int local;
-  tile_band(cp, (uint32_t)t, &k, &local);
-  uint32_t* c = counts + item0[k] * (uint64_t)band_tiles + local;
+  const uint64_t tg = B.lo + (uint64_t)t;
+  const uint32_t a = (uint32_t)starts[tg];
+  if (g == 0) {
+    const uint32_t tot = totals[tg];
+    ranges[2 * tg] = (tot && !over) ? a : 0u;
+    ranges[2 * tg + 1] = (tot && !over) ? a + tot : 0u;
+  }
+  const uint32_t ni = nitems[k];
+  const uint32_t i0 = (uint32_t)g * kItemGroup;
+  if (over || i0 >= ni) return;
+  const uint32_t i1 = i0 + kItemGroup < ni ? i0 + kItemGroup : ni;
+  const uint64_t row0 = item0[k];
   uint32_t run = a;
-  for (uint32_t i = 0; i < nitems[k]; ++i) {
+  for (uint32_t gi = 0; gi < i0; gi += kItemGroup) run += gsum[(row0 + gi) * (uint64_t)band_tiles + t];
+  uint32_t* c = counts + row0 * (uint64_t)band_tiles + t;
+  for (uint32_t i = i0; i < i1; ++i) {
     const uint32_t v = c[(uint64_t)i * band_tiles];
     c[(uint64_t)i * band_tiles] = run;
     run += v;
@@ -837,20 +850,27 @@ __global__ __launch_bounds__(64) void place_emit_kernel(
   const uint64_t pe = brange[2 * (uint64_t)k + 1];
   const uint64_t p1 = p0 + kBlockPairs < pe ? p0 + kBlockPairs : pe;
   for (uint64_t pb = p0; pb < p1; pb += 64) {
+    // the lanes decode 64 pairs at once: record, first local tile, width,
+    // entries in the band
     const uint64_t i = pb + lane;
-    uint4 d = make_uint4(0u, 0u, 0u, 0u);
-    if (i < p1) d = desc[pval[i]];
+    uint32_t dR = 0, dW = 1;
+    int dbase = 0, dn = 0;
+    if (i < p1) {
+      const uint4 d = desc[pval[i]];
+      const int tx0 = (int)(d.y & 0xffffu), ty0 = (int)(d.z & 0xffffu), ty1 = (int)(d.z >> 16);
+      const int ya = ty0 > B.r0 ? ty0 : B.r0, yb = ty1 < B.r1 - 1 ? ty1 : B.r1 - 1;
+      dR = d.x;
+      dW = d.y >> 16;
+      dbase = (ya - B.r0) * B.tx + tx0;
+      dn = (int)dW * (yb - ya + 1);
+    }
     const int cnt = p1 - pb < 64 ? (int)(p1 - pb) : 64;
     for (int l = 0; l < cnt; ++l) {
-      const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)d.x, l);
-      const uint32_t XW = (uint32_t)__builtin_amdgcn_readlane((int)d.y, l);
-      const uint32_t YY = (uint32_t)__builtin_amdgcn_readlane((int)d.z, l);
-      const int X0 = (int)(XW & 0xffffu), W = (int)(XW >> 16);
-      const int ty0 = (int)(YY & 0xffffu), ty1 = (int)(YY >> 16);
-      const int ya = ty0 > B.r0 ? ty0 : B.r0, yb = ty1 < B.r1 - 1 ? ty1 : B.r1 - 1;
-      const int n = W * (yb - ya + 1);
-      // local tile of entry e: row ya + e / W, column X0 + e % W
-      const int base = (ya - B.r0) * B.tx + X0;
+      const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)dR, l);
+      const int W = __builtin_amdgcn_readlane((int)dW, l);
+      const int base = __builtin_amdgcn_readlane(dbase, l);
+      const int n = __builtin_amdgcn_readlane(dn, l);
+      // local tile of entry e: base + (e / W) * tx + e % W
       const float inv_w = __builtin_amdgcn_rcpf((float)W);
       for (int q = 0; q < n; q += 64) {
         const int e = q + lane;
@@ -886,6 +906,7 @@ struct SortWs {
   uint64_t* item0;     // [n_bands]
   uint32_t* item_band; // [items_max]
   uint32_t* counts;    // [items_max][band_tiles], then offsets
+  uint32_t* gsum;      // [items_max][band_tiles]: per item group, at its first item
   uint32_t* totals;    // [n_tiles]
   uint64_t* starts;    // [n_tiles]
   uint64_t* scalars;   // n_pairs, n_items, tile total
@@ -944,6 +965,7 @@ SortWs carve(void* ws, int64_t n_rec, int64_t capacity, const CamPack& cp, bool 
     w.item0 = (uint64_t*)take(nbd * 8);
     w.item_band = (uint32_t*)take(ni * 4);
     w.counts = (uint32_t*)take(ni * (size_t)g.band_tiles * 4);
+    w.gsum = (uint32_t*)take(ni * (size_t)g.band_tiles * 4);
     w.totals = (uint32_t*)take(nt * 4);
     w.starts = (uint64_t*)take(nt * 8);
     w.scalars = (uint64_t*)take(4 * 8);
@@ -1091,14 +1113,21 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     hipLaunchKernelGGL(place_count_kernel, dim3(items), dim3(64), lds, s, (const uint4*)w.desc, pval,
                        (const uint32_t*)w.brange, (const uint32_t*)w.item_band, (const uint64_t*)w.item0,
                        (const uint64_t*)n_items, cp, g.band_tiles, w.counts);
-    hipLaunchKernelGGL(place_totals_kernel, dim3(grid_for(nt, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
-                       (const uint32_t*)w.counts, (const uint32_t*)w.nitems, (const uint64_t*)w.item0, cp,
-                       g.band_tiles, w.totals);
+    // tile totals by groups of items (a band holds at most n_per_cam pairs)
+    const int chunks = (g.band_tiles + 63) / 64;
+    const int64_t items_band = (n_per_cam + kBlockPairs - 1) / kBlockPairs;
+    const int groups = (int)((items_band + kItemGroup - 1) / kItemGroup > 0 ? (items_band + kItemGroup - 1) / kItemGroup : 1);
+    const unsigned scan_grid = (unsigned)(g.n_bands * chunks * groups);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nt, kBlock, 4096)), dim3(kBlock), 0, s, w.totals, nt, 0u);
+    hipLaunchKernelGGL(place_group_sums_kernel, dim3(scan_grid), dim3(64), 0, s, (const uint32_t*)w.counts,
+                       (const uint32_t*)w.nitems, (const uint64_t*)w.item0, cp, g.band_tiles, g.n_bands, chunks,
+                       groups, w.gsum, w.totals);
     e = launch_scan(w.totals, nt, w.starts, w.scalars + 2, w.scan_ws, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(place_offsets_kernel, dim3(grid_for(nt, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
-                       w.counts, (const uint32_t*)w.nitems, (const uint64_t*)w.item0, (const uint32_t*)w.totals,
-                       (const uint64_t*)w.starts, n_dup, capacity, cp, g.band_tiles, ranges);
+    hipLaunchKernelGGL(place_offsets_kernel, dim3(scan_grid), dim3(64), 0, s, w.counts, (const uint32_t*)w.gsum,
+                       (const uint32_t*)w.nitems, (const uint64_t*)w.item0, (const uint32_t*)w.totals,
+                       (const uint64_t*)w.starts, n_dup, capacity, cp, g.band_tiles, g.n_bands, chunks, groups,
+                       ranges);
     // 4. the entries
     hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(64), lds, s, (const uint4*)w.desc, pval,
                        (const uint32_t*)w.brange, (const uint32_t*)w.item_band, (const uint64_t*)w.item0,

@@ -72,6 +72,7 @@ class Frame:
     capacity: int
     ws_render: torch.Tensor
     tile_order: torch.Tensor | None = None
+    depth: torch.Tensor | None = None
 
     def image(self, c: int) -> torch.Tensor:
         """[3,H,W] view of camera c's image."""
@@ -94,7 +95,7 @@ def _bytes(n: int, device) -> torch.Tensor:
 
 
 def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity: int | None = None,
-                 persistent: bool = True, keys: bool = True) -> Frame:
+                 persistent: bool = True, keys: bool = True, depth: bool = False) -> Frame:
     """Run the forward rasterizer.  ``cams`` is a C camera array from
     ``binding.make_cameras``; ``opts`` an ``hgs_options``.  With
     ``capacity`` None the entry count is read back (one synchronisation) and
@@ -102,7 +103,7 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
     entries and an overflow is reported in ``frame.overflow``.  With
     ``persistent`` the raster takes tiles longest-list first from a
     persistent grid; ``keys`` False skips the 64-bit sort keys (the raster
-    does not need them)."""
+    does not need them); ``depth`` adds the blended depth per pixel."""
     dev = soa.device
     nc = len(cams)
     n_rec = n * nc
@@ -131,11 +132,22 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
     T_final = torch.empty(npix, dtype=torch.float32, device=dev)
     last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
     n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+    depth_t = torch.empty(npix, dtype=torch.float32, device=dev) if depth else None
     ws_r = _bytes(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), dev)
     B.hgs_render_fwd(records, values, ranges, order, cams, opts, images, T_final, last_idx, n_contrib, ws_r,
-                     stream)
+                     stream, depth=depth_t)
     return Frame(soa, n, sh_degree, cams, opts, records, tiles, offsets, n_dup, keys_t, values, ranges,
-                 overflow, images, T_final, last_idx, n_contrib, capacity, ws_r, order)
+                 overflow, images, T_final, last_idx, n_contrib, capacity, ws_r, order, depth_t)
+
+
+def depth_normals(fr: Frame) -> torch.Tensor:
+    """Normals estimated from the frame's depth (forward_pass(depth=True)),
+    packed like the images: [3][H][W] per camera."""
+    if fr.depth is None:
+        raise ValueError("the frame was rendered without depth")
+    out = torch.empty(3 * fr.T_final.numel(), dtype=torch.float32, device=fr.T_final.device)
+    B.hgs_depth_normals(fr.depth, fr.T_final, fr.cams, out, _stream())
+    return out
 
 
 def backward_pass(fr: Frame, dL_dimages: torch.Tensor, record_grads: torch.Tensor | None = None,

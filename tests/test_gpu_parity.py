@@ -442,3 +442,45 @@ def test_placement_equals_full_key_sort_at_4k_tile8():
     np.testing.assert_array_equal(va, vb)
     np.testing.assert_array_equal(ka, kb)
     np.testing.assert_array_equal(u32(a.tile_order), u32(b.tile_order))
+
+
+def test_blended_depth_matches_oracle():
+    """The optional depth output of hgs_render_fwd against the oracle's
+    blended depth (REC mode), relative to the depth scale, on the pixels
+    whose decisions are not ambiguous; no depth requested gives the same
+    image."""
+    scene, cams = CASES["cfg2_small"]
+    fr = gpu_forward(scene, cams)
+    frd = R.forward_pass(R.scene_to_soa(scene), scene["means"].shape[0], scene["sh_degree"],
+                         B.make_cameras(cams), B.default_options(), depth=True)
+    torch.cuda.synchronize()
+    assert torch.equal(fr.images, frd.images)
+    pre = oracle_pre(scene, cams)[0]
+    ref = O.render(pre, "rec")
+    ok = ~ambiguous(ref["margin"])
+    D = frd.per_pixel(frd.depth, 0).cpu().numpy()
+    Dr = ref["depth"].numpy()
+    scale = float(np.abs(Dr).max())
+    assert scale > 0
+    assert np.abs(D - Dr)[ok].max() <= 1e-4 * scale
+
+
+def test_depth_normals_match_oracle_on_the_same_depth():
+    """hgs_depth_normals against the oracle's estimate from the same depth
+    and transmittance maps (the GPU's), two cameras of different sizes."""
+    scene, cams = CASES["cfg4_three_views"]
+    cams = cams[:2]
+    fr = R.forward_pass(R.scene_to_soa(scene), scene["means"].shape[0], scene["sh_degree"],
+                        B.make_cameras(cams), B.default_options(), depth=True)
+    nrm = R.depth_normals(fr)
+    torch.cuda.synchronize()
+    off = 0
+    for c, cam in enumerate(cams):
+        H, W = cam["height"], cam["width"]
+        D = fr.per_pixel(fr.depth, c).cpu().numpy()
+        T = fr.per_pixel(fr.T_final, c).cpu().numpy()
+        ref = O.depth_normals(D, T, cam)
+        got = nrm[3 * off:3 * (off + H * W)].view(3, H, W).cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-5
+        assert (np.abs(ref).sum(0) > 0).mean() > 0.05
+        off += H * W

@@ -593,3 +593,52 @@ def test_sh_colour_matches_scipy_expansion():
             col += 1
     np.testing.assert_allclose(g["colour"], np.maximum(ref, 0), atol=1e-13)
     assert (ref < 0).any()          # the clamp is exercised
+
+
+# ---------------------------------------------------------------------------
+# depth and depth-derived normals (Sec. 4 depth maps and normal maps)
+# ---------------------------------------------------------------------------
+def test_depth_of_kernels_at_one_depth_is_opacity_times_depth():
+    """All kernels at one camera depth z: the blended depth sum_i w_i z is
+    (1 - T_final) z, by the compositing identity, whatever the opacities,
+    half factors and overlaps."""
+    scene, _ = scenes.make_config(1, n=800)
+    scene = dict(scene)
+    means = scene["means"].copy()
+    means[:, 2] = 0.25                                   # camera on -z at 4: z = 4.25
+    scene["means"] = means
+    cam = scenes.axis_camera(64, 48)
+    o = O.options()
+    with torch.no_grad():
+        pre = O.preprocess(O.scene_to_torch(scene), O.camera_to_torch(cam), o)
+        r = O.render(pre, "e2e")
+    D, T = r["depth"].numpy(), r["T_final"].numpy()
+    assert (1.0 - T).max() > 0.5
+    np.testing.assert_allclose(D, (1.0 - T) * 4.25, rtol=1e-12, atol=1e-12)
+
+
+def test_depth_normals_of_a_plane_are_its_normal():
+    """A plane seen through the pinhole: the back-projected points of its
+    depth map lie on the plane, so every interior normal is the plane normal
+    (turned to face the camera); the border and pixels next to empty ones
+    are zero."""
+    cam = scenes.pinhole(40, 30, np.eye(3), (0.0, 0.0, 0.0))
+    nrm = np.array([0.3, -0.2, -1.0])
+    nrm /= np.linalg.norm(nrm)
+    dist = 5.0                                          # plane: n . X = -dist (in front, z > 0)
+    u = (np.arange(40) + 0.5 - float(cam["cx"])) / float(cam["fx"])
+    v = (np.arange(30) + 0.5 - float(cam["cy"])) / float(cam["fy"])
+    ray = np.stack([np.broadcast_to(u[None, :], (30, 40)), np.broadcast_to(v[:, None], (30, 40)),
+                    np.ones((30, 40))], 0)
+    z = -dist / np.tensordot(nrm, ray, axes=(0, 0))     # depth of the plane along each pixel ray
+    assert (z > 0).all()
+    T = np.full((30, 40), 0.25)
+    n = O.depth_normals(z * (1.0 - T), T, cam)
+    np.testing.assert_allclose(n[:, 1:-1, 1:-1], np.broadcast_to(nrm[:, None, None], (3, 28, 38)), atol=1e-12)
+    assert (n[:, 0, :] == 0).all() and (n[:, :, -1] == 0).all()
+    T2 = T.copy()
+    T2[10, 10] = 1.0                                    # an empty pixel: its four neighbours lose their normal
+    n2 = O.depth_normals(z * (1.0 - T2), T2, cam)
+    for (y, x) in ((9, 10), (11, 10), (10, 9), (10, 11)):
+        assert (n2[:, y, x] == 0).all()
+    np.testing.assert_allclose(n2[:, 10, 10], nrm, atol=1e-12)
