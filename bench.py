@@ -88,6 +88,9 @@ def parse():
     ap.add_argument("--multiview", action="store_true",
                     help="add the multi-view comparison (batched graph step against a per-view loop)")
     ap.add_argument("--multiview-steps", type=int, default=10)
+    ap.add_argument("--train", action="store_true",
+                    help="add the training step after the backward pass (Adam, densification statistics, "
+                         "densify) on the same 1M kernels")
     ap.add_argument("--autotune", metavar="JSON", default=None,
                     help="autotune tile size and batch depth for the multi-view workload, caching in JSON")
     return ap.parse_args()
@@ -295,6 +298,9 @@ def main():
     multi = None
     if args.multiview:
         multi = multiview(args)
+    train = None
+    if args.train:
+        train = train_bench(args, n, deg, records, rgrad, ca, opts, cams)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -325,7 +331,67 @@ def main():
         "cpu_baseline": cpu,
         "multiview": multi,
     }
+    if train is not None:
+        out["train"] = train
     print(json.dumps(out), flush=True)
+
+
+def train_bench(args, n, deg, records, rgrad, ca, opts, cams):
+    """The step after the backward pass on the bench's kernels: one fused
+    Adam step over every raw plane (HBM-bound: per kernel and plane 16 B
+    read, 12 B written, plus 4 B for each of the 5 activated planes), the
+    densification statistics of one view, and one densify / prune call."""
+    import numpy as np
+    import torch
+
+    from paper_2406_02720_amd import binding as B
+    from paper_2406_02720_amd import scenes
+    from paper_2406_02720_amd import train as TR
+
+    dev = torch.device("cuda:0")
+    st = scenes.train_state(n, deg, extent=2.0, seed=77)
+    planes = np.concatenate([st["raw"][k] for k in ("means", "scales", "quats", "normals", "opac1", "opac2", "sh")])
+    grads = np.concatenate([st["grads"][k] for k in ("means", "scales", "quats", "normals", "opac1", "opac2", "sh")])
+    state = TR.TrainState(torch.from_numpy(planes).to(dev), n, deg, extent=2.0)
+    g = torch.from_numpy(grads).to(dev)
+    del planes, grads
+    P = g.shape[0]
+    reps = max(args.steps, 5)
+    for _ in range(3):
+        state.adam_step(g)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        state.adam_step(g)
+    e1.record()
+    torch.cuda.synchronize()
+    adam_ms = e0.elapsed_time(e1) / reps
+    adam_bytes = n * (P * 28 + 5 * 4)
+    stream = torch.cuda.current_stream().cuda_stream
+    e0.record()
+    for _ in range(reps):
+        B.hgs_densify_stats(records, rgrad, ca, opts, n, state.grad_accum, state.grad_count, state.max_radii,
+                            stream)
+    e1.record()
+    torch.cuda.synchronize()
+    stats_ms = e0.elapsed_time(e1) / reps
+    state.grad_accum.copy_(torch.from_numpy(st["accum"]).to(dev))
+    state.grad_count.copy_(torch.from_numpy(st["count"]).to(dev))
+    state.max_radii.copy_(torch.from_numpy(st["radii"]).to(dev))
+    smp = torch.from_numpy(np.ascontiguousarray(st["samples"])).to(dev)
+    torch.cuda.synchronize()
+    e0.record()
+    n_new = state.densify(samples=smp)
+    e1.record()
+    torch.cuda.synchronize()
+    dens_ms = e0.elapsed_time(e1)
+    a = adam_bytes / (adam_ms * 1e-3) / 1e9
+    return {"n_kernels": n, "planes": P, "adam_ms": round(adam_ms, 4),
+            "adam_roofline": {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(a / HBM_PEAK_GBS, 4), "bytes": adam_bytes},
+            "densify_stats_ms": round(stats_ms, 4), "densify_ms_incl_readback": round(dens_ms, 4),
+            "densify_n_out": n_new}
 
 
 def multiview(args):

@@ -71,6 +71,11 @@ extern "C" {
                                     64-bit keys instead of placing them by
                                     counting after a depth sort of the
                                     records (same result)                     */
+#define HGS_FLAG_MIP_2D 4u       /* the screen low-pass is Mip-Splatting's 2-D
+                                    mip filter (lowpass ~0.1 px^2): both
+                                    opacities times sqrt(det S / det(S +
+                                    lowpass I)), S the undilated screen
+                                    covariance (Mip-Splatting-HGS, Sec. 4)   */
 
 /* Pinhole camera.  R is the world->camera rotation (row-major 3x3), t the
  * translation (x_cam = R x_world + t).  fx, fy, cx, cy in pixels.  Kernels
@@ -95,6 +100,12 @@ typedef struct hgs_camera {
  *   opac2   1 plane   opacity of the -normal half
  *   sh      3 (D+1)^2 planes, plane (k * 3 + channel) holds coefficient k of
  *                     the real spherical harmonics of degree <= D (0..3)
+ *   filter3d 1 plane (optional, NULL = none): variance f of Mip-Splatting's
+ *                     3-D smoothing filter (Mip-Splatting-HGS, Sec. 4):
+ *                     the covariance becomes Sigma + f I everywhere (half
+ *                     factor and valid region included) and both opacities
+ *                     are multiplied by sqrt(det Sigma / det(Sigma + f I));
+ *                     see hgs_mip_filter3d.  Not differentiated.
  * A non-finite value in any of the fields above culls the kernel (as does a
  * non-finite colour). */
 typedef struct hgs_params {
@@ -109,6 +120,7 @@ typedef struct hgs_params {
   int64_t stride;
   int32_t sh_degree;
   int32_t reserved;
+  const float* filter3d;
 } hgs_params;
 
 /* Gradients of the scalar loss with respect to every field of hgs_params,
@@ -290,6 +302,130 @@ int hgs_raster_bwd(const void* records, const uint32_t* values, const uint32_t* 
 int hgs_preprocess_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
                        const hgs_options* opts, const void* records, float* record_grads,
                        const hgs_param_grads* grads, hipStream_t stream);
+
+/* Mip-Splatting's 3-D filter variance per kernel (used by Mip-Splatting-HGS,
+ * Sec. 4): the kernel's sampling rate nu is the largest fx / z over the
+ * cameras that see its centre (camera z > znear and the projected centre
+ * inside the image widened by `margin` times its size on every side); the
+ * variance is s / nu^2 (s = 0.2 in Mip-Splatting).  Kernels seen by no
+ * camera get the smallest rate among the seen ones (the widest filter), or 0
+ * if no kernel is seen.  means: device, 3 planes of `stride`; filter3d:
+ * device float[n] (out); workspace: device, 256 bytes.  Errors: HGS_EINVAL
+ * for null pointers, bad cameras, n < 0, stride < n, s < 0, margin < 0. */
+int hgs_mip_filter3d(const float* means, int64_t n, int64_t stride, const hgs_camera* cams, int32_t n_cams,
+                     float s, float margin, float* filter3d, void* workspace, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Training step after the backward pass (Sec. 4, implementation: the normal
+ * uses 3D-GS's three unused normal parameters, one opacity per half, the
+ * 3D-GS training recipe otherwise, normal learning rate 0.003; Supp.,
+ * training settings: opacity and normal learning rates divided by 1.4 every
+ * 5000 iterations, pruning opacity threshold 0.01, opacity reset to 0.02).
+ *
+ * The optimised ("raw") parameters use the hgs_params plane layout with
+ * log-scales in place of scales and opacity logits in place of opacities;
+ * the rasterizer takes exp(log-scale) and sigmoid(logit).  An
+ * hgs_param_grads struct names any set of mutable planes in that layout:
+ * raw values, Adam moments, activated copies.  All pointers are device
+ * pointers; n kernels, plane p of a field at ptr + p * stride.
+ * ------------------------------------------------------------------------ */
+
+/* Adam step constants.  lr_*: learning rate per group; beta1, beta2, eps;
+ * step: the step number t >= 1 (bias corrections 1 - beta^t). */
+typedef struct hgs_adam_config {
+  float lr_means, lr_scales, lr_quats, lr_normals, lr_opacity, lr_sh_dc, lr_sh_rest;
+  float beta1;   /* [0.9]   */
+  float beta2;   /* [0.999] */
+  float eps;     /* [1e-15] */
+  int32_t step;
+  int32_t reserved;
+} hgs_adam_config;
+
+/* The half-Gaussian schedule at iteration `step` (1-based) for a scene of
+ * radius `extent`: means 1.6e-4 * extent decaying log-linearly to
+ * 1.6e-6 * extent at 30000; log-scales 0.005; quaternions 0.001; SH degree
+ * 0 0.0025, higher 0.0025 / 20; opacities 0.05 and normals `normal_lr`
+ * (0.003; 0.3 was used for one dataset), both times 1.4^-floor(step/5000).
+ * Host only.  HGS_EINVAL for step < 1, extent <= 0 or a null cfg. */
+int hgs_adam_schedule(int32_t step, float extent, float normal_lr, hgs_adam_config* cfg);
+
+/* One Adam step on every raw plane.  grads: loss gradient with respect to
+ * the ACTIVATED parameters (as hgs_render_bwd writes it); the chain rule
+ * through exp and sigmoid is applied here.  raw, m, v are updated in place;
+ * act receives the activated values (a plane of act may alias the raw plane
+ * where the activation is the identity, which then skips its write).
+ * Errors: HGS_EINVAL for null pointers, n < 0, stride < n, bad sh_degree,
+ * step < 1; HGS_EHIP on a launch failure. */
+int hgs_adam_step(const hgs_adam_config* cfg, int64_t n, int64_t stride, int32_t sh_degree,
+                  const hgs_param_grads* raw, const hgs_param_grads* grads, const hgs_param_grads* m,
+                  const hgs_param_grads* v, const hgs_param_grads* act, hipStream_t stream);
+
+/* act = activation(raw) for the log-scale and opacity planes and a copy of
+ * the others (planes of act that alias raw are skipped). */
+int hgs_activate(int64_t n, int64_t stride, int32_t sh_degree, const hgs_param_grads* raw,
+                 const hgs_param_grads* act, hipStream_t stream);
+
+/* Densification statistics of 3D-GS, accumulated over the cameras of one
+ * step: for every record with tiles > 0 (visible), grad_accum[i] += the
+ * norm of the loss gradient with respect to the record's screen centre in
+ * normalised device coordinates (the pixel-space gradient in record_grads
+ * times W/2 and H/2), grad_count[i] += 1, and max_radii[i] = max(max_radii[i],
+ * ceil(kappa * sqrt(lambda_max))) of the dilated screen covariance (from the
+ * record's conic, FP64).  Call after hgs_raster_bwd and before
+ * hgs_preprocess_bwd (which clears record_grads).  records, record_grads:
+ * as given to hgs_raster_bwd, n kernels per camera.  grad_accum float[n],
+ * grad_count int32[n], max_radii float[n]: device, accumulated (the caller
+ * clears them). */
+int hgs_densify_stats(const void* records, const float* record_grads, const hgs_camera* cams, int32_t n_cams,
+                      const hgs_options* opts, int64_t n, float* grad_accum, int32_t* grad_count,
+                      float* max_radii, hipStream_t stream);
+
+/* Densify / prune thresholds ([] = hgs_densify_default values). */
+typedef struct hgs_densify_config {
+  float extent;             /* scene radius (> 0)                            */
+  float grad_threshold;     /* [0.0002] average NDC centre gradient          */
+  float percent_dense;      /* [0.01]   clone below, split above, x extent    */
+  float min_opacity;        /* [0.01]   prune when BOTH halves are below      */
+  float max_screen_radius;  /* [0] px, 0 = off (3D-GS: 20 after the first
+                                opacity reset)                               */
+  float max_world_scale;    /* [0] x extent, 0 = off (3D-GS: 0.1 together
+                                with the screen rule)                        */
+} hgs_densify_config;
+
+void hgs_densify_default(float extent, hgs_densify_config* cfg);
+size_t hgs_densify_workspace_bytes(int64_t n);
+
+/* Clone, split and prune (3D-GS densification with the half-Gaussian
+ * opacity threshold).  A kernel whose average gradient
+ * grad_accum / grad_count reaches grad_threshold (grad_count > 0) is cloned
+ * when its largest scale is <= percent_dense * extent, else split into two
+ * children centred at mean + R(q) (scale * z) with z = samples[c][0..2][i]
+ * (standard normal draws, float [2][3][n], the caller's), log-scales reduced
+ * by log(0.8 * 2), everything else copied; the parent of a split is
+ * removed.  Pruned: both opacities below min_opacity, or (when enabled)
+ * max_radii > max_screen_radius or largest scale > max_world_scale * extent
+ * (new kernels have radius 0).  Thresholds are compared on the raw values
+ * (log / logit of the threshold, FP64).  Output order: surviving kernels,
+ * clones, first children, second children, each in kernel order; raw_out,
+ * m_out, v_out (planes of stride stride_out >= capacity, distinct from the
+ * inputs) get the raw values and moments (zero for new kernels).  *n_out
+ * (device int64) receives the new count; if it exceeds capacity nothing is
+ * written and *overflow (device int32) is 1.  workspace:
+ * hgs_densify_workspace_bytes(n) bytes.  The densification statistics are
+ * not carried over (the caller clears them for the new kernels). */
+int hgs_densify(const hgs_densify_config* cfg, int64_t n, int64_t stride, int32_t sh_degree,
+                const hgs_param_grads* raw, const hgs_param_grads* m, const hgs_param_grads* v,
+                const float* grad_accum, const int32_t* grad_count, const float* max_radii, const float* samples,
+                int64_t capacity, int64_t stride_out, const hgs_param_grads* raw_out,
+                const hgs_param_grads* m_out, const hgs_param_grads* v_out, int64_t* n_out, int32_t* overflow,
+                void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Opacity reset (Supp., training settings): each half's opacity becomes
+ * min(opacity, value) (value 0.02 in the paper), its Adam moments are
+ * cleared, and act's opacity planes (if not NULL and not aliasing raw) are
+ * refreshed.  Only the opac1/opac2 fields of raw, m, v, act are used. */
+int hgs_reset_opacity(float value, int64_t n, const hgs_param_grads* raw, const hgs_param_grads* m,
+                      const hgs_param_grads* v, const hgs_param_grads* act, hipStream_t stream);
 
 const char* hgs_strerror(int code);
 const char* hgs_last_error(void);

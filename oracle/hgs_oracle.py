@@ -61,6 +61,7 @@ DEFAULT_OPTIONS = dict(
     fov_clamp=_f32(1.3),
     bg=(0.0, 0.0, 0.0),
     full_box=False,             # True: both halves splatted with the full ellipse box
+    mip2d=False,                # True: the low-pass is Mip-Splatting's 2-D mip filter
 )
 
 
@@ -88,6 +89,8 @@ def scene_to_torch(scene: dict, requires_grad: bool = False) -> dict:
             t.requires_grad_(True)
         out[k] = t
     out["sh_degree"] = int(scene["sh_degree"])
+    if scene.get("filter3d") is not None:      # Mip-Splatting 3-D filter variance (a constant)
+        out["filter3d"] = torch.tensor(np.asarray(scene["filter3d"], np.float64), dtype=F64)
     return out
 
 
@@ -200,6 +203,15 @@ def _geometry(sc: dict, cam: dict, o: dict, idx: torch.Tensor) -> dict:
     tx, ty, tz = t.unbind(-1)
 
     Sw = world_covariance(sc["scales"][idx], sc["quats"][idx])  # Eq. 2
+    # Mip-Splatting's 3-D smoothing filter: Sigma + f I, opacity times
+    # sqrt(det Sigma / det(Sigma + f I)); everything after uses the filtered
+    # covariance (the half factor included)
+    comp = torch.ones_like(tx)
+    if sc.get("filter3d") is not None:
+        f = sc["filter3d"][idx]
+        Sw0 = Sw
+        Sw = Sw0 + f[:, None, None] * torch.eye(3, dtype=F64)
+        comp = torch.sqrt(torch.linalg.det(Sw0) / torch.linalg.det(Sw))
 
     # Eq. 3: local affine approximation of the projection (Jacobian rows for
     # the two screen coordinates; the third row never enters the result).
@@ -212,9 +224,15 @@ def _geometry(sc: dict, cam: dict, o: dict, idx: torch.Tensor) -> dict:
                      torch.stack([zero, fy / tz, -fy * yc / tz], -1)], -2)
     M = J @ Rc                                                # 2x3 world -> screen
     lam = o["lowpass"] * torch.eye(2, dtype=F64)
-    Shat = M @ Sw @ M.transpose(-1, -2) + lam                 # Eq. 6 (+ dilation)
+    Shat0 = M @ Sw @ M.transpose(-1, -2)
+    Shat = Shat0 + lam                                        # Eq. 6 (+ dilation)
     A, B, C = Shat[..., 0, 0], Shat[..., 0, 1], Shat[..., 1, 1]
     det = A * C - B * B
+    if o.get("mip2d"):
+        # Mip-Splatting's 2-D mip filter: the dilation is the filter, the
+        # opacity is compensated by sqrt(det Shat0 / det(Shat0 + lowpass I))
+        det0 = torch.clamp(torch.linalg.det(Shat0), min=0.0)
+        comp = comp * torch.sqrt(det0 / det)
     conic = torch.stack([C / det, -B / det, A / det], -1)     # inverse (a, b, c)
     mean2d = torch.stack([fx * tx / tz + cx, fy * ty / tz + cy], -1)
 
@@ -246,8 +264,8 @@ def _geometry(sc: dict, cam: dict, o: dict, idx: torch.Tensor) -> dict:
     shc = sc["sh"][idx][:, : (deg + 1) ** 2, :]
     colour = torch.clamp((Y.unsqueeze(-1) * shc).sum(-2) + 0.5, min=0.0)
 
-    a1 = sc["opac1"][idx]
-    a2 = sc["opac2"][idx]
+    a1 = sc["opac1"][idx] * comp
+    a2 = sc["opac2"][idx] * comp
     return dict(t=t, tz=tz, Sw=Sw, M=M, Shat=Shat, det=det, conic=conic, mean2d=mean2d,
                 n_hat=n_hat, nzero=nzero, g=g, v=v, k=k, colour=colour,
                 alpha2=a2, d_o=(a1 - a2) / 2.0, a1=a1, a2=a2)
@@ -513,6 +531,37 @@ def render(pre: dict, mode: str = "e2e", pixels=None, chunk: int = 64, leaves: d
         for k in ("T_final", "n_contrib", "last_id", "margin", "depth"):
             res[k] = res[k][inv_t].reshape((H, W) + tuple(res[k].shape[1:]))
     return res
+
+
+def mip_filter3d(means, cams: list, s: float = 0.2, margin: float = 0.15) -> np.ndarray:
+    """Mip-Splatting's 3-D smoothing filter variance per kernel (used by
+    Mip-Splatting-HGS, Sec. 4): the sampling rate nu of a kernel is the
+    largest fx / z over the cameras that see its centre (z > znear, the
+    projection inside the image widened by ``margin`` on each side);
+    variance = s / nu^2.  A kernel no camera sees takes the smallest rate of
+    the seen ones; 0 when none is seen.  Float64, left-to-right sums."""
+    mu = np.asarray(means, np.float32).astype(np.float64)
+    s, margin = float(np.float32(s)), float(np.float32(margin))
+    nu = np.zeros(mu.shape[0])
+    for cam in cams:
+        R = np.asarray(cam["R"], np.float32).astype(np.float64)
+        t = np.asarray(cam["t"], np.float32).astype(np.float64)
+        tc = [R[r, 0] * mu[:, 0] + R[r, 1] * mu[:, 1] + R[r, 2] * mu[:, 2] + t[r] for r in range(3)]
+        fx, fy = float(np.float32(cam["fx"])), float(np.float32(cam["fy"]))
+        cx, cy = float(np.float32(cam["cx"])), float(np.float32(cam["cy"]))
+        W, H = float(cam["width"]), float(cam["height"])
+        z = tc[2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            x = fx * tc[0] / z + cx
+            y = fy * tc[1] / z + cy
+            ok = (z > float(np.float32(cam["znear"]))) & (x >= -margin * W) & (x <= (1.0 + margin) * W) \
+                & (y >= -margin * H) & (y <= (1.0 + margin) * H)
+            nu = np.where(ok, np.maximum(nu, fx / z), nu)
+    seen = nu > 0
+    if not seen.any():
+        return np.zeros(mu.shape[0])
+    nu = np.where(seen, nu, nu[seen].min())
+    return s / (nu * nu)
 
 
 def depth_normals(depth, T_final, cam: dict) -> np.ndarray:

@@ -19,11 +19,15 @@ HGS_RECORD_BYTES = 64
 HGS_RECORD_GRAD_FLOATS = 12
 HGS_FLAG_FULL_BOX = 1
 HGS_FLAG_SORT_FULL_KEYS = 2
+HGS_FLAG_MIP_2D = 4
 HGS_WS_PREPROCESS, HGS_WS_BIN_SORT, HGS_WS_RENDER = 0, 1, 2
 
 EXPORTS = ("hgs_default_options", "hgs_workspace_bytes", "hgs_tiles_total", "hgs_pixels_total",
            "hgs_preprocess", "hgs_bin_sort", "hgs_render_fwd", "hgs_render_bwd",
-           "hgs_raster_bwd", "hgs_preprocess_bwd", "hgs_depth_normals", "hgs_strerror", "hgs_last_error")
+           "hgs_raster_bwd", "hgs_preprocess_bwd", "hgs_depth_normals", "hgs_mip_filter3d",
+           "hgs_adam_schedule", "hgs_adam_step",
+           "hgs_activate", "hgs_densify_stats", "hgs_densify_default", "hgs_densify_workspace_bytes",
+           "hgs_densify", "hgs_reset_opacity", "hgs_strerror", "hgs_last_error")
 
 
 class hgs_camera(C.Structure):
@@ -36,7 +40,7 @@ class hgs_params(C.Structure):
     _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
                 ("normals", C.c_void_p), ("opac1", C.c_void_p), ("opac2", C.c_void_p),
                 ("sh", C.c_void_p), ("n", C.c_int64), ("stride", C.c_int64),
-                ("sh_degree", C.c_int32), ("reserved", C.c_int32)]
+                ("sh_degree", C.c_int32), ("reserved", C.c_int32), ("filter3d", C.c_void_p)]
 
 
 class hgs_param_grads(C.Structure):
@@ -50,6 +54,18 @@ class hgs_options(C.Structure):
                 ("kappa", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
                 ("t_min", C.c_float), ("fov_clamp", C.c_float), ("bg", C.c_float * 3),
                 ("flags", C.c_uint32)]
+
+
+class hgs_adam_config(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_scales", C.c_float), ("lr_quats", C.c_float),
+                ("lr_normals", C.c_float), ("lr_opacity", C.c_float), ("lr_sh_dc", C.c_float),
+                ("lr_sh_rest", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32), ("reserved", C.c_int32)]
+
+
+class hgs_densify_config(C.Structure):
+    _fields_ = [("extent", C.c_float), ("grad_threshold", C.c_float), ("percent_dense", C.c_float),
+                ("min_opacity", C.c_float), ("max_screen_radius", C.c_float), ("max_world_scale", C.c_float)]
 
 
 class HGSError(RuntimeError):
@@ -100,6 +116,26 @@ def load(path: str = LIB_PATH):
     lib.hgs_preprocess_bwd.argtypes = [P(hgs_params), P(hgs_camera), i32, P(hgs_options), vp, vp,
                                        P(hgs_param_grads), vp]
     lib.hgs_preprocess_bwd.restype = C.c_int
+    lib.hgs_mip_filter3d.argtypes = [vp, i64, i64, P(hgs_camera), i32, C.c_float, C.c_float, vp, vp, vp]
+    lib.hgs_mip_filter3d.restype = C.c_int
+    PG = P(hgs_param_grads)
+    lib.hgs_adam_schedule.argtypes = [i32, C.c_float, C.c_float, P(hgs_adam_config)]
+    lib.hgs_adam_schedule.restype = C.c_int
+    lib.hgs_adam_step.argtypes = [P(hgs_adam_config), i64, i64, i32, PG, PG, PG, PG, PG, vp]
+    lib.hgs_adam_step.restype = C.c_int
+    lib.hgs_activate.argtypes = [i64, i64, i32, PG, PG, vp]
+    lib.hgs_activate.restype = C.c_int
+    lib.hgs_densify_stats.argtypes = [vp, vp, P(hgs_camera), i32, P(hgs_options), i64, vp, vp, vp, vp]
+    lib.hgs_densify_stats.restype = C.c_int
+    lib.hgs_densify_default.argtypes = [C.c_float, P(hgs_densify_config)]
+    lib.hgs_densify_default.restype = None
+    lib.hgs_densify_workspace_bytes.argtypes = [i64]
+    lib.hgs_densify_workspace_bytes.restype = sz
+    lib.hgs_densify.argtypes = [P(hgs_densify_config), i64, i64, i32, PG, PG, PG, vp, vp, vp, vp, i64, i64,
+                                PG, PG, PG, vp, vp, vp, sz, vp]
+    lib.hgs_densify.restype = C.c_int
+    lib.hgs_reset_opacity.argtypes = [C.c_float, i64, PG, PG, PG, PG, vp]
+    lib.hgs_reset_opacity.restype = C.c_int
     lib.hgs_strerror.argtypes = [C.c_int]
     lib.hgs_strerror.restype = C.c_char_p
     lib.hgs_last_error.argtypes = []
@@ -123,6 +159,8 @@ def default_options(**kw) -> hgs_options:
             o.flags = (o.flags | HGS_FLAG_FULL_BOX) if v else (o.flags & ~HGS_FLAG_FULL_BOX)
         elif k == "sort_full_keys":
             o.flags = (o.flags | HGS_FLAG_SORT_FULL_KEYS) if v else (o.flags & ~HGS_FLAG_SORT_FULL_KEYS)
+        elif k == "mip2d":
+            o.flags = (o.flags | HGS_FLAG_MIP_2D) if v else (o.flags & ~HGS_FLAG_MIP_2D)
         else:
             setattr(o, k, v)
     return o
@@ -221,3 +259,51 @@ def hgs_raster_bwd(records, values, ranges, tile_order, cams, opts, T_final, las
 def hgs_preprocess_bwd(params, cams, opts, records, record_grads, grads, stream):
     check(load().hgs_preprocess_bwd(C.byref(params), cams, len(cams), C.byref(opts), _ptr(records),
                                     _ptr(record_grads), C.byref(grads), stream))
+
+
+def hgs_mip_filter3d(means, n, stride, cams, s, margin, filter3d, ws, stream):
+    check(load().hgs_mip_filter3d(_ptr(means), n, stride, cams, len(cams), s, margin, _ptr(filter3d), _ptr(ws),
+                                  stream))
+
+
+def hgs_adam_schedule(step: int, extent: float, normal_lr: float = 0.003) -> hgs_adam_config:
+    cfg = hgs_adam_config()
+    check(load().hgs_adam_schedule(step, extent, normal_lr, C.byref(cfg)))
+    return cfg
+
+
+def hgs_adam_step(cfg, n, stride, sh_degree, raw, grads, m, v, act, stream):
+    check(load().hgs_adam_step(C.byref(cfg), n, stride, sh_degree, C.byref(raw), C.byref(grads), C.byref(m),
+                               C.byref(v), C.byref(act), stream))
+
+
+def hgs_activate(n, stride, sh_degree, raw, act, stream):
+    check(load().hgs_activate(n, stride, sh_degree, C.byref(raw), C.byref(act), stream))
+
+
+def hgs_densify_stats(records, record_grads, cams, opts, n, accum, count, max_radii, stream):
+    check(load().hgs_densify_stats(_ptr(records), _ptr(record_grads), cams, len(cams), C.byref(opts), n,
+                                   _ptr(accum), _ptr(count), _ptr(max_radii), stream))
+
+
+def hgs_densify_default(extent: float) -> hgs_densify_config:
+    cfg = hgs_densify_config()
+    load().hgs_densify_default(extent, C.byref(cfg))
+    return cfg
+
+
+def hgs_densify_workspace_bytes(n: int) -> int:
+    return int(load().hgs_densify_workspace_bytes(n))
+
+
+def hgs_densify(cfg, n, stride, sh_degree, raw, m, v, accum, count, max_radii, samples, capacity, stride_out,
+                raw_out, m_out, v_out, n_out, overflow, ws, stream):
+    check(load().hgs_densify(C.byref(cfg), n, stride, sh_degree, C.byref(raw), C.byref(m), C.byref(v),
+                             _ptr(accum), _ptr(count), _ptr(max_radii), _ptr(samples), capacity, stride_out,
+                             C.byref(raw_out), C.byref(m_out), C.byref(v_out), _ptr(n_out), _ptr(overflow),
+                             _ptr(ws), ws.numel() * ws.element_size(), stream))
+
+
+def hgs_reset_opacity(value, n, raw, m, v, act, stream):
+    check(load().hgs_reset_opacity(value, n, C.byref(raw), C.byref(m), C.byref(v),
+                                   None if act is None else C.byref(act), stream))

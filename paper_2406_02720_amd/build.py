@@ -15,7 +15,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhgs.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "render.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "render.hip", "train.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

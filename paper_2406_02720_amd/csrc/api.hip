@@ -2,6 +2,7 @@
 // the launch sequence of each entry point.  No entry point allocates device
 // memory or synchronises the stream.
 
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -97,6 +98,7 @@ int make_params(const hgs_params* p, hgs::Params* out) {
   out->opac1 = p->opac1;
   out->opac2 = p->opac2;
   out->sh = p->sh;
+  out->filter3d = p->filter3d;
   out->n = p->n;
   out->stride = p->stride;
   out->sh_degree = p->sh_degree;
@@ -104,6 +106,27 @@ int make_params(const hgs_params* p, hgs::Params* out) {
 }
 
 }  // namespace
+
+// A mutable plane set with every field present.
+int planes_ok(const hgs_param_grads* g, const char* what) {
+  if (!g) return fail(HGS_EINVAL, "%s is null", what);
+  if (!g->means || !g->scales || !g->quats || !g->normals || !g->opac1 || !g->opac2 || !g->sh)
+    return fail(HGS_EINVAL, "%s: a plane pointer is null", what);
+  return HGS_OK;
+}
+
+hgs::Grads to_grads(const hgs_param_grads& g) {
+  return hgs::Grads{g.means, g.scales, g.quats, g.normals, g.opac1, g.opac2, g.sh};
+}
+
+int check_sizes(int64_t n, int64_t stride, int32_t sh_degree) {
+  if (n < 0) return fail(HGS_EINVAL, "n must be >= 0");
+  if (stride < n) return fail(HGS_EINVAL, "stride must be >= n");
+  if (sh_degree < 0 || sh_degree > 3) return fail(HGS_EINVAL, "sh_degree must be 0..3");
+  return HGS_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 extern "C" {
 
@@ -301,6 +324,180 @@ int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_c
                           dL_dimages, record_grads, workspace, workspace_bytes, stream)) != HGS_OK)
     return e;
   return hgs_preprocess_bwd(params, cams, n_cams, opts, records, record_grads, grads, stream);
+}
+
+int hgs_mip_filter3d(const float* means, int64_t n, int64_t stride, const hgs_camera* cams, int32_t n_cams,
+                     float s, float margin, float* filter3d, void* workspace, hipStream_t stream) {
+  int e;
+  hgs_options o;
+  hgs_default_options(&o);
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, &o, &cp)) != HGS_OK) return e;
+  if (n < 0 || stride < n) return fail(HGS_EINVAL, "need 0 <= n <= stride");
+  if (!(s >= 0.0f) || !(margin >= 0.0f)) return fail(HGS_EINVAL, "s and margin must be >= 0");
+  if (n == 0) return HGS_OK;
+  if (!means || !filter3d || !workspace) return fail(HGS_EINVAL, "a pointer is null");
+  const hipError_t h = hgs::launch_mip_filter3d(means, n, stride, cp, (double)s, (double)margin, filter3d,
+                                                (uint32_t*)workspace, stream);
+  if (h != hipSuccess) return hip_fail(h, "mip_filter3d launch");
+  return HGS_OK;
+}
+
+int hgs_adam_schedule(int32_t step, float extent, float normal_lr, hgs_adam_config* cfg) {
+  if (!cfg) return fail(HGS_EINVAL, "cfg is null");
+  if (step < 1) return fail(HGS_EINVAL, "step must be >= 1");
+  if (!(extent > 0.0f)) return fail(HGS_EINVAL, "extent must be > 0");
+  const double r = step >= 30000 ? 1.0 : (double)step / 30000.0;
+  const double lr0 = 1.6e-4 * (double)extent, lr1 = 1.6e-6 * (double)extent;
+  const double decay = pow(1.4, -(double)(step / 5000));
+  cfg->lr_means = (float)exp((1.0 - r) * log(lr0) + r * log(lr1));
+  cfg->lr_scales = 0.005f;
+  cfg->lr_quats = 0.001f;
+  cfg->lr_normals = (float)((double)normal_lr * decay);
+  cfg->lr_opacity = (float)(0.05 * decay);
+  cfg->lr_sh_dc = 0.0025f;
+  cfg->lr_sh_rest = (float)(0.0025 / 20.0);
+  cfg->beta1 = 0.9f;
+  cfg->beta2 = 0.999f;
+  cfg->eps = 1e-15f;
+  cfg->step = step;
+  cfg->reserved = 0;
+  return HGS_OK;
+}
+
+int hgs_adam_step(const hgs_adam_config* cfg, int64_t n, int64_t stride, int32_t sh_degree,
+                  const hgs_param_grads* raw, const hgs_param_grads* grads, const hgs_param_grads* m,
+                  const hgs_param_grads* v, const hgs_param_grads* act, hipStream_t stream) {
+  int e;
+  if (!cfg) return fail(HGS_EINVAL, "cfg is null");
+  if (cfg->step < 1) return fail(HGS_EINVAL, "step must be >= 1");
+  if ((e = check_sizes(n, stride, sh_degree)) != HGS_OK) return e;
+  if (n == 0) return HGS_OK;
+  if ((e = planes_ok(raw, "raw")) != HGS_OK || (e = planes_ok(grads, "grads")) != HGS_OK ||
+      (e = planes_ok(m, "m")) != HGS_OK || (e = planes_ok(v, "v")) != HGS_OK ||
+      (e = planes_ok(act, "act")) != HGS_OK)
+    return e;
+  hgs::AdamPlan plan{};
+  const double c1 = 1.0 - pow((double)cfg->beta1, (double)cfg->step);
+  const double c2 = 1.0 - pow((double)cfg->beta2, (double)cfg->step);
+  const float lrs[8] = {cfg->lr_means, cfg->lr_scales, cfg->lr_quats, cfg->lr_normals,
+                        cfg->lr_opacity, cfg->lr_opacity, cfg->lr_sh_dc, cfg->lr_sh_rest};
+  for (int k = 0; k < 8; ++k) plan.step_size[k] = (float)((double)lrs[k] / c1);
+  plan.beta1 = cfg->beta1;
+  plan.beta2 = cfg->beta2;
+  plan.inv_sqrt_bc2 = (float)(1.0 / sqrt(c2));
+  plan.eps = cfg->eps;
+  const float* gp[7] = {grads->means, grads->scales, grads->quats, grads->normals,
+                        grads->opac1, grads->opac2, grads->sh};
+  bool vec = stride % 4 == 0;
+  const hgs_param_grads* sets[5] = {raw, m, v, act, grads};
+  for (const hgs_param_grads* g : sets)
+    vec = vec && aligned16(g->means) && aligned16(g->scales) && aligned16(g->quats) && aligned16(g->normals) &&
+          aligned16(g->opac1) && aligned16(g->opac2) && aligned16(g->sh);
+  plan.vec4 = vec ? 1 : 0;
+  const hipError_t h = hgs::launch_adam(to_grads(*raw), gp, to_grads(*m), to_grads(*v), to_grads(*act), n, stride,
+                                        sh_degree, plan, stream);
+  if (h != hipSuccess) return hip_fail(h, "adam launch");
+  return HGS_OK;
+}
+
+int hgs_activate(int64_t n, int64_t stride, int32_t sh_degree, const hgs_param_grads* raw,
+                 const hgs_param_grads* act, hipStream_t stream) {
+  int e;
+  if ((e = check_sizes(n, stride, sh_degree)) != HGS_OK) return e;
+  if (n == 0) return HGS_OK;
+  if ((e = planes_ok(raw, "raw")) != HGS_OK || (e = planes_ok(act, "act")) != HGS_OK) return e;
+  const hipError_t h = hgs::launch_activate(to_grads(*raw), to_grads(*act), n, stride, sh_degree, stream);
+  if (h != hipSuccess) return hip_fail(h, "activate launch");
+  return HGS_OK;
+}
+
+int hgs_densify_stats(const void* records, const float* record_grads, const hgs_camera* cams, int32_t n_cams,
+                      const hgs_options* opts, int64_t n, float* grad_accum, int32_t* grad_count,
+                      float* max_radii, hipStream_t stream) {
+  int e;
+  if ((e = check_opts(opts)) != HGS_OK) return e;
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
+  if (n < 0) return fail(HGS_EINVAL, "n must be >= 0");
+  if (n > (int64_t)INT32_MAX / HGS_MAX_CAMERAS) return fail(HGS_EINVAL, "n too large");
+  if (n == 0) return HGS_OK;
+  if (!records || !record_grads || !grad_accum || !grad_count || !max_radii)
+    return fail(HGS_EINVAL, "a pointer is null");
+  const hipError_t h = hgs::launch_densify_stats((const hgs::Record*)records, record_grads, cp, n,
+                                                 (double)opts->kappa, grad_accum, grad_count, max_radii, stream);
+  if (h != hipSuccess) return hip_fail(h, "densify_stats launch");
+  return HGS_OK;
+}
+
+void hgs_densify_default(float extent, hgs_densify_config* cfg) {
+  if (!cfg) return;
+  cfg->extent = extent;
+  cfg->grad_threshold = 0.0002f;
+  cfg->percent_dense = 0.01f;
+  cfg->min_opacity = 0.01f;
+  cfg->max_screen_radius = 0.0f;
+  cfg->max_world_scale = 0.0f;
+}
+
+size_t hgs_densify_workspace_bytes(int64_t n) { return n < 0 ? 0 : hgs::densify_workspace_bytes(n); }
+
+int hgs_densify(const hgs_densify_config* cfg, int64_t n, int64_t stride, int32_t sh_degree,
+                const hgs_param_grads* raw, const hgs_param_grads* m, const hgs_param_grads* v,
+                const float* grad_accum, const int32_t* grad_count, const float* max_radii, const float* samples,
+                int64_t capacity, int64_t stride_out, const hgs_param_grads* raw_out,
+                const hgs_param_grads* m_out, const hgs_param_grads* v_out, int64_t* n_out, int32_t* overflow,
+                void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  int e;
+  if (!cfg) return fail(HGS_EINVAL, "cfg is null");
+  if ((e = check_sizes(n, stride, sh_degree)) != HGS_OK) return e;
+  if (capacity < 0 || stride_out < capacity) return fail(HGS_EINVAL, "need 0 <= capacity <= stride_out");
+  if (n > (int64_t)UINT32_MAX) return fail(HGS_EINVAL, "n too large");
+  if (!(cfg->extent > 0.0f) || !(cfg->percent_dense > 0.0f) || !(cfg->min_opacity > 0.0f) ||
+      !(cfg->min_opacity < 1.0f) || !(cfg->grad_threshold >= 0.0f) || !(cfg->max_screen_radius >= 0.0f) ||
+      !(cfg->max_world_scale >= 0.0f))
+    return fail(HGS_EINVAL, "densify threshold out of range");
+  if (!n_out || !overflow) return fail(HGS_EINVAL, "n_out or overflow is null");
+  if ((e = planes_ok(raw, "raw")) != HGS_OK || (e = planes_ok(m, "m")) != HGS_OK ||
+      (e = planes_ok(v, "v")) != HGS_OK || (e = planes_ok(raw_out, "raw_out")) != HGS_OK ||
+      (e = planes_ok(m_out, "m_out")) != HGS_OK || (e = planes_ok(v_out, "v_out")) != HGS_OK)
+    return e;
+  if (n > 0 && (!grad_accum || !grad_count || !max_radii || !samples)) return fail(HGS_EINVAL, "a pointer is null");
+  if (!workspace || workspace_bytes < hgs::densify_workspace_bytes(n))
+    return fail(HGS_ECAPACITY, "workspace too small");
+  hgs::DensifyPlan dp{};
+  const double ext = (double)cfg->extent, mo = (double)cfg->min_opacity;
+  dp.grad_threshold = (double)cfg->grad_threshold;
+  dp.log_dense = log((double)cfg->percent_dense * ext);
+  dp.logit_min_opacity = log(mo / (1.0 - mo));
+  dp.world_on = cfg->max_world_scale > 0.0f ? 1 : 0;
+  dp.log_world = dp.world_on ? log((double)cfg->max_world_scale * ext) : 0.0;
+  dp.screen_on = cfg->max_screen_radius > 0.0f ? 1 : 0;
+  dp.max_screen = (double)cfg->max_screen_radius;
+  dp.shrink = (float)log(0.8 * 2.0);
+  const hipError_t h = hgs::launch_densify(to_grads(*raw), to_grads(*m), to_grads(*v), n, stride, sh_degree, dp,
+                                           grad_accum, grad_count, max_radii, samples, capacity, stride_out,
+                                           to_grads(*raw_out), to_grads(*m_out), to_grads(*v_out), n_out,
+                                           overflow, workspace, stream);
+  if (h != hipSuccess) return hip_fail(h, "densify launch");
+  return HGS_OK;
+}
+
+int hgs_reset_opacity(float value, int64_t n, const hgs_param_grads* raw, const hgs_param_grads* m,
+                      const hgs_param_grads* v, const hgs_param_grads* act, hipStream_t stream) {
+  if (!(value > 0.0f) || !(value < 1.0f)) return fail(HGS_EINVAL, "value must be in (0, 1)");
+  if (n < 0) return fail(HGS_EINVAL, "n must be >= 0");
+  if (n == 0) return HGS_OK;
+  if (!raw || !m || !v || !raw->opac1 || !raw->opac2 || !m->opac1 || !m->opac2 || !v->opac1 || !v->opac2)
+    return fail(HGS_EINVAL, "an opacity plane pointer is null");
+  if (act && (!act->opac1 || !act->opac2)) return fail(HGS_EINVAL, "act opacity plane is null");
+  const hgs_param_grads none{};
+  const double vv = (double)value;
+  const float cap = (float)log(vv / (1.0 - vv));
+  const hipError_t h = hgs::launch_reset_opacity(to_grads(*raw), to_grads(*m), to_grads(*v),
+                                                 to_grads(act ? *act : none), n, cap, stream);
+  if (h != hipSuccess) return hip_fail(h, "reset_opacity launch");
+  return HGS_OK;
 }
 
 const char* hgs_strerror(int code) {

@@ -170,10 +170,15 @@ struct KernelGeo {
   double Sn[3];   // Sigma_w n
   double v;       // n^T Sigma_w n
   bool nzero;
+  double f;       // 3-D filter variance (0: none)
+  double comp3;   // sqrt(det Sigma / det(Sigma + f I))
 };
 
+// With a 3-D filter variance f > 0 (Mip-Splatting) the covariance is
+// Sigma + f I; comp3 = prod_i s_i / sqrt(s_i^2 + f) is the opacity factor
+// sqrt(det Sigma / det(Sigma + f I)) (the eigenvalues of Sigma are s_i^2).
 __device__ __forceinline__ void kernel_geo(const float* mu, const float* s, const float* q,
-                                           const float* n, KernelGeo& k) {
+                                           const float* n, KernelGeo& k, double f = 0.0) {
   for (int i = 0; i < 3; ++i) k.mu[i] = (double)mu[i];
   double qh[4], qn, R[9];
   quat_rot(q, qh, qn, R);
@@ -184,6 +189,14 @@ __device__ __forceinline__ void kernel_geo(const float* mu, const float* s, cons
   k.Sw.yy = R[3] * d0 * R[3] + R[4] * d1 * R[4] + R[5] * d2 * R[5];
   k.Sw.yz = R[3] * d0 * R[6] + R[4] * d1 * R[7] + R[5] * d2 * R[8];
   k.Sw.zz = R[6] * d0 * R[6] + R[7] * d1 * R[7] + R[8] * d2 * R[8];
+  k.f = f;
+  k.comp3 = 1.0;
+  if (f > 0.0) {
+    k.Sw.xx += f;
+    k.Sw.yy += f;
+    k.Sw.zz += f;
+    k.comp3 = sqrt(d0 / (d0 + f)) * sqrt(d1 / (d1 + f)) * sqrt(d2 / (d2 + f));
+  }
   const double nx = n[0], ny = n[1], nz = n[2];
   k.nn = sqrt(nx * nx + ny * ny + nz * nz);
   k.nzero = !(k.nn > 0.0);
@@ -244,6 +257,7 @@ struct ViewGeo {
   double M[6];         // 2x3 row-major
   double A, B, C;      // dilated screen covariance
   double det;
+  double det0;         // determinant of the undilated screen covariance
   double qa, qb, qc;   // conic
   double mx, my;       // screen centre
   double g[2], w[2];
@@ -278,10 +292,13 @@ __device__ __forceinline__ void view_geo(const KernelGeo& k, const CamDev& cam, 
   double S0[3], S1[3];  // Sigma_w M^T columns
   sym_mul_vec(k.Sw, vg.M, S0);
   sym_mul_vec(k.Sw, vg.M + 3, S1);
-  vg.A = vg.M[0] * S0[0] + vg.M[1] * S0[1] + vg.M[2] * S0[2] + lowpass;
+  const double A0 = vg.M[0] * S0[0] + vg.M[1] * S0[1] + vg.M[2] * S0[2];
+  const double C0 = vg.M[3] * S1[0] + vg.M[4] * S1[1] + vg.M[5] * S1[2];
   vg.B = vg.M[3] * S0[0] + vg.M[4] * S0[1] + vg.M[5] * S0[2];
-  vg.C = vg.M[3] * S1[0] + vg.M[4] * S1[1] + vg.M[5] * S1[2] + lowpass;
+  vg.A = A0 + lowpass;
+  vg.C = C0 + lowpass;
   vg.det = vg.A * vg.C - vg.B * vg.B;
+  vg.det0 = A0 * C0 - vg.B * vg.B;
   const double idet = 1.0 / vg.det;
   vg.qa = vg.C * idet;
   vg.qb = -vg.B * idet;

@@ -80,6 +80,7 @@ struct Params {
   const float* opac1;
   const float* opac2;
   const float* sh;
+  const float* filter3d;  // may be null
   int64_t n;
   int64_t stride;
   int32_t sh_degree;
@@ -93,6 +94,26 @@ struct Grads {
   float* opac1;
   float* opac2;
   float* sh;
+};
+
+// Host-prepared constants of one Adam step: per learning-rate group (means,
+// scales, quats, normals, opac1, opac2, SH degree 0, SH higher) the step
+// size lr / (1 - beta1^t); 1 / sqrt(1 - beta2^t).
+struct AdamPlan {
+  float step_size[8];
+  float beta1, beta2, inv_sqrt_bc2, eps;
+  int32_t vec4;   // every plane 16-byte aligned with stride % 4 == 0
+};
+
+// Densify thresholds in the raw domain, FP64 (see hgs_densify).
+struct DensifyPlan {
+  double grad_threshold;     // average NDC gradient threshold
+  double log_dense;          // log(percent_dense * extent)
+  double logit_min_opacity;  // logit(min_opacity)
+  double log_world;          // log(max_world_scale * extent)
+  double max_screen;         // screen radius limit, px
+  int32_t world_on, screen_on;
+  float shrink;              // log(0.8 * 2), float32
 };
 
 // Camera of a global tile id (cameras are few: linear scan).
@@ -132,6 +153,24 @@ hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint
                              const uint32_t* tile_order, const CamPack& cp, const Opts& o,
                              const float* T_final, const int32_t* last_idx, const float* dL_dimg,
                              float* rec_grads, void* ws, hipStream_t s);
+hipError_t launch_mip_filter3d(const float* means, int64_t n, int64_t stride, const CamPack& cp, double s,
+                               double margin, float* out, uint32_t* scratch, hipStream_t st);
+int planes_of(int sh_degree);
+hipError_t launch_adam(const Grads& raw, const float* const grad[7], const Grads& m, const Grads& v,
+                       const Grads& act, int64_t n, int64_t stride, int sh_degree, const AdamPlan& plan,
+                       hipStream_t s);
+hipError_t launch_activate(const Grads& raw, const Grads& act, int64_t n, int64_t stride, int sh_degree,
+                           hipStream_t s);
+hipError_t launch_reset_opacity(const Grads& raw, const Grads& m, const Grads& v, const Grads& act, int64_t n,
+                                float cap, hipStream_t s);
+hipError_t launch_densify_stats(const Record* rec, const float* rgrad, const CamPack& cp, int64_t n, double kappa,
+                                float* accum, int32_t* count, float* max_radii, hipStream_t s);
+size_t densify_workspace_bytes(int64_t n);
+hipError_t launch_densify(const Grads& raw, const Grads& m, const Grads& v, int64_t n, int64_t stride,
+                          int sh_degree, const DensifyPlan& dp, const float* accum, const int32_t* count,
+                          const float* max_radii, const float* samples, int64_t capacity, int64_t stride_out,
+                          const Grads& raw_out, const Grads& m_out, const Grads& v_out, int64_t* n_out,
+                          int32_t* overflow, void* ws, hipStream_t s);
 hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o,
                                  const Record* rec, float* rec_grads, const Grads& g,
                                  hipStream_t s);

@@ -29,7 +29,7 @@ struct Box {
 };
 
 __device__ __forceinline__ Box half_box(const KernelGeo& k, const ViewGeo& vg, const Sym3& Ss,
-                                        float a1, float a2, const Opts& o) {
+                                        double a1, double a2, const Opts& o) {
   Box b;
   const double kap = o.kappa;
   const double ex = kap * sqrt(vg.A);
@@ -47,8 +47,8 @@ __device__ __forceinline__ Box half_box(const KernelGeo& k, const ViewGeo& vg, c
     cx = fmin(kap * sqrt(sxx + (double)o.lowpass), ex);
     cy = fmin(kap * sqrt(syy + (double)o.lowpass), ey);
   }
-  const bool s1 = a1 >= o.alpha_min;
-  const bool s2 = a2 >= o.alpha_min;
+  const bool s1 = a1 >= (double)o.alpha_min;
+  const bool s2 = a2 >= (double)o.alpha_min;
   const double gx = vg.g[0], gy = vg.g[1];
   const double ninf = -INFINITY;
   // half +1 (alpha1 side)
@@ -103,8 +103,10 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
     params_ok = params_ok && finite((double)mu[c]) && finite((double)s[c]) && finite((double)nrm[c]);
   for (int c = 0; c < 4; ++c) params_ok = params_ok && finite((double)q[c]);
 
+  const double f3 = p.filter3d ? (double)p.filter3d[i] : 0.0;
+  params_ok = params_ok && finite(f3) && f3 >= 0.0;
   KernelGeo kg;
-  kernel_geo(mu, s, q, nrm, kg);
+  kernel_geo(mu, s, q, nrm, kg, params_ok ? f3 : 0.0);
   Sym3 Ss = kg.Sw;
   if (!(o.flags & HGS_FLAG_FULL_BOX) && !kg.nzero) Ss = splitting_cov(kg);
   const int tsh = cp.tile_shift;
@@ -143,9 +145,13 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
     ok = ok && finite(vg.det) && vg.det > 0.0 && finite(vg.qa) && finite(vg.qb) &&
          finite(vg.qc) && finite(vg.mx) && finite(vg.my) && finite(vg.k[0]) && finite(vg.k[1]);
     ok = ok && finite(col0) && finite(col1) && finite(col2);
+    // opacity compensation of the Mip-Splatting filters (3-D, and 2-D mip)
+    double comp = kg.comp3;
+    if (o.flags & HGS_FLAG_MIP_2D) comp *= sqrt(fmax(vg.det0, 0.0) / vg.det);
+    const double a1e = (double)a1 * comp, a2e = (double)a2 * comp;
     Box bx;
     if (ok) {
-      bx = half_box(kg, vg, Ss, a1, a2, o);
+      bx = half_box(kg, vg, Ss, a1e, a2e, o);
       ok = bx.any;
     }
     if (ok) {
@@ -166,11 +172,11 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
           r.qa = (float)vg.qa;
           r.qb = (float)vg.qb;
           r.qc = (float)vg.qc;
-          r.alpha2 = a2;
+          r.alpha2 = (float)a2e;
           r.r = (float)col0;
           r.g = (float)col1;
           r.b = (float)col2;
-          r.d_o = (float)(((double)a1 - (double)a2) / 2.0);
+          r.d_o = (float)((a1e - a2e) / 2.0);
           r.xr = (uint32_t)x0 | ((uint32_t)x1 << 16);
           r.yr = (uint32_t)y0 | ((uint32_t)y1 << 16);
           r.depth = __float_as_uint((float)vg.t[2]);
@@ -298,8 +304,11 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   }
   for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
 
+  const double f3 = p.filter3d ? (double)p.filter3d[i] : 0.0;
   KernelGeo kg;
-  kernel_geo(mu, s, q, nrm, kg);
+  kernel_geo(mu, s, q, nrm, kg, (isfinite(f3) && f3 >= 0.0) ? f3 : 0.0);
+  const double a1 = (double)p.opac1[i], a2 = (double)p.opac2[i];
+  double g_c3 = 0.0;   // dL / d comp3
 
   double g_mu[3] = {0.0, 0.0, 0.0};
   Sym3 g_Sw = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -322,13 +331,20 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     const double galpha2 = r1.w, gdo = r2.x;
     const double gcol[3] = {r2.y, r2.z, r2.w};
 
-    // alpha2 and (alpha1 - alpha2) / 2
-    g_a2 += galpha2 - 0.5 * gdo;
-    g_a1 += 0.5 * gdo;
-
     const CamDev& cam = cp.cam[c];
     ViewGeo vg;
     view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
+
+    // alpha2 = comp a2 and (alpha1 - alpha2) / 2 = comp (a1 - a2) / 2, with
+    // comp = comp3 c2 (Mip-Splatting compensations; 1 without filters)
+    const bool mip2 = (o.flags & HGS_FLAG_MIP_2D) != 0;
+    const double c2 = mip2 ? (vg.det0 > 0.0 ? sqrt(vg.det0 / vg.det) : 0.0) : 1.0;
+    const double comp = kg.comp3 * c2;
+    g_a2 += comp * (galpha2 - 0.5 * gdo);
+    g_a1 += comp * 0.5 * gdo;
+    const double gcomp = galpha2 * a2 + 0.5 * gdo * (a1 - a2);
+    g_c3 += gcomp * c2;
+    const double g_c2 = gcomp * kg.comp3;
 
     // ---- colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - o) / |mu - o|
     {
@@ -392,9 +408,18 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     // ---- conic = inverse of (A, B; B, C)
     const double A = vg.A, B = vg.B, C = vg.C;
     const double id2 = 1.0 / (vg.det * vg.det);
-    const double gA = (-C * C * gQa + B * C * gQb - B * B * gQc) * id2;
-    const double gB = (2.0 * B * C * gQa - (A * C + B * B) * gQb + 2.0 * A * B * gQc) * id2;
-    const double gC = (-B * B * gQa + A * B * gQb - A * A * gQc) * id2;
+    double gA = (-C * C * gQa + B * C * gQb - B * B * gQc) * id2;
+    double gB = (2.0 * B * C * gQa - (A * C + B * B) * gQb + 2.0 * A * B * gQc) * id2;
+    double gC = (-B * B * gQa + A * B * gQb - A * A * gQc) * id2;
+    // c2 = sqrt(det0 / det): d c2 = c2 / 2 (d det0 / det0 - d det / det),
+    // det0 = (A - l)(C - l) - B^2, det = A C - B^2
+    if (mip2 && vg.det0 > 0.0) {
+      const double h = 0.5 * g_c2 * c2;
+      const double A0 = A - (double)o.lowpass, C0 = C - (double)o.lowpass;
+      gA += h * (C0 / vg.det0 - C / vg.det);
+      gC += h * (A0 / vg.det0 - A / vg.det);
+      gB += h * (2.0 * B / vg.det - 2.0 * B / vg.det0);
+    }
     // G_S = [[gA, gB/2], [gB/2, gC]].  Shat = M Sw M^T: dM += 2 G_S M Sw,
     // dSw += M^T G_S M.  g = M Sn: dM += gg Sn^T, dSn = M^T gg.
     const double* M = vg.M;
@@ -476,6 +501,8 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     sym_mul_vec(g_Sw, col, Gc);
     g_s[c] = 2.0 * sc[c] * (col[0] * Gc[0] + col[1] * Gc[1] + col[2] * Gc[2]);
     const double dsq = sc[c] * sc[c];
+    // comp3 = prod s / sqrt(s^2 + f): d ln comp3 / d s = f / (s (s^2 + f))
+    if (kg.f > 0.0) g_s[c] += g_c3 * kg.comp3 * kg.f / (sc[c] * (dsq + kg.f));
     GR[0 * 3 + c] = 2.0 * Gc[0] * dsq;
     GR[1 * 3 + c] = 2.0 * Gc[1] * dsq;
     GR[2 * 3 + c] = 2.0 * Gc[2] * dsq;
@@ -547,6 +574,65 @@ hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint
   if (blocks > 0)
     hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)blocks), dim3(kScanBlock), 0, s, tiles, n,
                        partial, offsets);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Mip-Splatting 3-D filter variance per kernel: the largest sampling rate
+// fx / z over the cameras that see the centre (in front of the near plane,
+// projected inside the image widened by `margin`), variance s / nu^2.
+// Kernels no camera sees take the smallest rate of the seen ones (FP64,
+// uncontracted, so that the visibility decisions are reproducible).
+__global__ void mip_init_kernel(uint32_t* nu_min) {
+  if (threadIdx.x == 0) nu_min[0] = 0x7f800000u;   // +inf
+}
+
+__global__ __launch_bounds__(kPreBlock) void mip_nu_kernel(const float* __restrict__ means, int64_t n,
+                                                           int64_t stride, CamPack cp, double s, double margin,
+                                                           float* __restrict__ out, uint32_t* __restrict__ nu_min) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  if (i >= n) return;
+  const double m0 = means[i], m1 = means[stride + i], m2 = means[2 * stride + i];
+  double nu = 0.0;
+  for (int c = 0; c < cp.n_cams; ++c) {
+    const CamDev& cam = cp.cam[c];
+    const float* R = cam.R;
+    const double tx = (double)R[0] * m0 + (double)R[1] * m1 + (double)R[2] * m2 + (double)cam.t[0];
+    const double ty = (double)R[3] * m0 + (double)R[4] * m1 + (double)R[5] * m2 + (double)cam.t[1];
+    const double tz = (double)R[6] * m0 + (double)R[7] * m1 + (double)R[8] * m2 + (double)cam.t[2];
+    if (!(tz > (double)cam.znear)) continue;
+    const double fx = cam.fx, fy = cam.fy;
+    const double x = fx * tx / tz + (double)cam.cx, y = fy * ty / tz + (double)cam.cy;
+    const double W = cam.width, H = cam.height;
+    if (x >= -margin * W && x <= (1.0 + margin) * W && y >= -margin * H && y <= (1.0 + margin) * H)
+      nu = fmax(nu, fx / tz);
+  }
+  if (nu > 0.0) {
+    out[i] = (float)(s / (nu * nu));
+    atomicMin(nu_min, __float_as_uint((float)nu));
+  } else {
+    out[i] = -1.0f;
+  }
+}
+
+__global__ __launch_bounds__(kPreBlock) void mip_fill_kernel(int64_t n, double s, const uint32_t* __restrict__ nu_min,
+                                                             float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  if (i >= n || !(out[i] < 0.0f)) return;
+  const uint32_t b = *nu_min;
+  const double nu = b == 0x7f800000u ? 0.0 : (double)__uint_as_float(b);
+  out[i] = nu > 0.0 ? (float)(s / (nu * nu)) : 0.0f;
+}
+
+hipError_t launch_mip_filter3d(const float* means, int64_t n, int64_t stride, const CamPack& cp, double s,
+                               double margin, float* out, uint32_t* scratch, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + kPreBlock - 1) / kPreBlock);
+  hipLaunchKernelGGL(mip_init_kernel, dim3(1), dim3(64), 0, st, scratch);
+  hipLaunchKernelGGL(mip_nu_kernel, dim3(grid), dim3(kPreBlock), 0, st, means, n, stride, cp, s, margin, out,
+                     scratch);
+  hipLaunchKernelGGL(mip_fill_kernel, dim3(grid), dim3(kPreBlock), 0, st, n, s, (const uint32_t*)scratch, out);
   return hipGetLastError();
 }
 

@@ -335,6 +335,8 @@ __global__ __launch_bounds__(kBlock) void depth_hist_weighted_kernel(const Recor
 }
 
 // ---------------------------------------------------------------------------
+constexpr int64_t kSweepGrid = 2048;   // persistent one-sweep workgroups (a few per CU)
+
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
@@ -351,11 +353,15 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   __shared__ uint32_t s_part;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint64_t n = entry_count(n_dev, capacity);
+  const uint64_t parts = (n + PART - 1) / PART;
+  // persistent: partitions are taken by ticket until none is left (a
+  // partition's look-back only waits on lower tickets, held by running
+  // workgroups)
+  for (;;) {
   if (t == 0) s_part = atomicAdd(ticket, 1u);
   for (int i = t; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0u;
   __syncthreads();
-  const uint64_t n = entry_count(n_dev, capacity);
-  const uint64_t parts = (n + PART - 1) / PART;
   const uint32_t part = s_part;
   if (part >= parts) return;
   lookback_next[(uint64_t)part * kRadix + t] = 0ull;
@@ -451,6 +457,8 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
       vout[dst] = s_vals[p];
     }
   }
+  __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -512,9 +520,10 @@ __global__ __launch_bounds__(64) void keys_from_ranges_kernel(const uint32_t* __
 // ---------------------------------------------------------------------------
 // placement path
 // ---------------------------------------------------------------------------
-constexpr int kBandTiles = 1024;     // a band: whole tile rows of one camera, >= 1024 tiles
+constexpr int kBandTiles = 256;      // a band: whole tile rows of one camera, >= 256 tiles
 constexpr int kItemGroup = 32;       // items per partial sum in the tile scans
-constexpr int kBlockPairs = 1024;    // (record, band) pairs per placement block
+constexpr int kBlockPairs = 512;     // (record, band) pairs per placement block
+constexpr int64_t kItemGrid = 2048;  // workgroups that loop over the items (their count is on the device)
 
 // Tile rows per band of a camera with `tiles_x` tiles per row.
 __host__ __device__ inline int band_rows(int tiles_x) {
@@ -723,8 +732,9 @@ __global__ __launch_bounds__(64) void place_count_kernel(
   extern __shared__ uint32_t s_d[];   // band tiles + 1
   __shared__ uint32_t s_off[64];
   const int lane = threadIdx.x;
-  const uint64_t item = blockIdx.x;
-  if (item >= *n_items) return;
+  const uint64_t items = *n_items;
+  for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
+  __syncthreads();
   const uint32_t k = item_band[item];
   const Band B = band_of(cp, k);
   const int nt = B.n;
@@ -757,6 +767,7 @@ __global__ __launch_bounds__(64) void place_count_kernel(
   __syncthreads();
   uint32_t* dst = counts + item * (uint64_t)band_tiles;
   for (int i = lane; i < nt; i += 64) dst[i] = s_d[i] + s_off[i / chunk];
+  }
 }
 
 
@@ -827,65 +838,165 @@ __global__ __launch_bounds__(64) void place_offsets_kernel(
   }
 }
 
-// The entries of one item: cursors in LDS, the item's records one after
-// another (their covered tiles in the band across the lanes), so every
-// tile hands out its positions in record order.
-__global__ __launch_bounds__(64) void place_emit_kernel(
+// The entries of one item, staged in LDS.  Each wavefront takes
+// kEmitPerWave consecutive pairs (records in depth order).  Pass 1 counts
+// per wavefront how many of its records cover each tile of the band; a scan
+// across the wavefronts turns the counts into per-wavefront cursors
+// (relative to the tile's run, 16 bits each, two wavefronts per LDS word),
+// and a scan over the tiles lays the item's runs (one per tile, in tile
+// order) out in the staging area.  Pass 2 walks every wavefront's records
+// one after another (covered tiles across the lanes) and takes each entry's
+// slot with an LDS fetch-and-add, so a tile's slots follow record order.
+// Each run is then copied to its place in the tile's list in one contiguous
+// burst.  An item with more entries than the staging area holds writes its
+// entries straight to their final positions instead.
+constexpr int kEmitWaves = 8;
+constexpr int kEmitThreads = kEmitWaves * 64;
+constexpr int kEmitPerWave = kBlockPairs / kEmitWaves;
+static_assert(kEmitPerWave == 64, "one pair per lane in the decode");
+static_assert(kBlockPairs < 65536, "16-bit cursors");
+constexpr size_t kEmitLdsBytes = 65536 - 256;  // dynamic part; the static s_wsum sits beside it
+
+inline size_t emit_fixed_lds(int band_tiles) {
+  return (size_t)(kEmitWaves / 2 + 2) * (size_t)band_tiles * sizeof(uint32_t);
+}
+
+// Entry e of a record's band part -> its local tile (rows of width W
+// starting at local tile `base`, band row pitch tx).
+__device__ __forceinline__ int entry_tile(int e, int W, float inv_w, int base, int tx) {
+  int row = (int)((float)e * inv_w);
+  int col = e - row * W;
+  if (col < 0) { --row; col += W; }
+  if (col >= W) { ++row; col -= W; }
+  return base + row * tx + col;
+}
+
+__global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
     const uint4* __restrict__ desc, const uint32_t* __restrict__ pval, const uint32_t* __restrict__ brange,
     const uint32_t* __restrict__ item_band, const uint64_t* __restrict__ item0, const uint64_t* __restrict__ n_items,
-    CamPack cp, int band_tiles, const uint32_t* __restrict__ offsets, const uint64_t* __restrict__ n_dup,
-    int64_t capacity, int32_t* __restrict__ overflow, uint32_t* __restrict__ vals) {
-  extern __shared__ uint32_t s_cur[];   // band tiles
-  const int lane = threadIdx.x;
+    CamPack cp, int band_tiles, int stage_cap, const uint32_t* __restrict__ offsets,
+    const uint64_t* __restrict__ n_dup, int64_t capacity, int32_t* __restrict__ overflow,
+    uint32_t* __restrict__ vals) {
+  extern __shared__ uint32_t lds[];
+  uint32_t* s_cur = lds;                                      // [kEmitWaves / 2][band_tiles], 2 x 16 bits
+  uint32_t* s_start = s_cur + (kEmitWaves / 2) * band_tiles;  // [band_tiles] run start in the staging area
+  uint32_t* s_off = s_start + band_tiles;                     // [band_tiles] run start in the tile's list
+  uint32_t* s_stage = s_off + band_tiles;                     // [stage_cap]
+  __shared__ uint32_t s_wsum[kEmitWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const bool over = *n_dup > (uint64_t)capacity;
-  if (blockIdx.x == 0 && lane == 0) *overflow = over ? 1 : 0;
-  const uint64_t item = blockIdx.x;
-  if (over || item >= *n_items) return;
+  if (blockIdx.x == 0 && tid == 0) *overflow = over ? 1 : 0;
+  if (over) return;
+  const uint64_t items = *n_items;
+  for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
+  __syncthreads();   // the previous item's copy-out is done with the LDS
   const uint32_t k = item_band[item];
   const Band B = band_of(cp, k);
+  const int nt = B.n;
+  for (int i = tid; i < (kEmitWaves / 2) * band_tiles; i += kEmitThreads) s_cur[i] = 0u;
   const uint32_t* src = offsets + item * (uint64_t)band_tiles;
-  for (int i = lane; i < B.n; i += 64) s_cur[i] = src[i];
-  __syncthreads();
+  for (int i = tid; i < nt; i += kEmitThreads) s_off[i] = src[i];
+  // this wavefront's pairs, one per lane: record, width, first local tile,
+  // entries in the band
   const uint64_t p0 = brange[2 * (uint64_t)k] + (item - item0[k]) * kBlockPairs;
   const uint64_t pe = brange[2 * (uint64_t)k + 1];
-  const uint64_t p1 = p0 + kBlockPairs < pe ? p0 + kBlockPairs : pe;
-  for (uint64_t pb = p0; pb < p1; pb += 64) {
-    // the lanes decode 64 pairs at once: record, first local tile, width,
-    // entries in the band
-    const uint64_t i = pb + lane;
-    uint32_t dR = 0, dW = 1;
-    int dbase = 0, dn = 0;
-    if (i < p1) {
-      const uint4 d = desc[pval[i]];
-      const int tx0 = (int)(d.y & 0xffffu), ty0 = (int)(d.z & 0xffffu), ty1 = (int)(d.z >> 16);
-      const int ya = ty0 > B.r0 ? ty0 : B.r0, yb = ty1 < B.r1 - 1 ? ty1 : B.r1 - 1;
-      dR = d.x;
-      dW = d.y >> 16;
-      dbase = (ya - B.r0) * B.tx + tx0;
-      dn = (int)dW * (yb - ya + 1);
+  const uint64_t w0 = p0 + (uint64_t)wv * kEmitPerWave;
+  const uint64_t w1 = w0 + kEmitPerWave < pe ? w0 + kEmitPerWave : pe;
+  const int cnt = w1 > w0 ? (int)(w1 - w0) : 0;
+  uint32_t dR = 0, dW = 1;
+  int dbase = 0, dn = 0;
+  if (lane < cnt) {
+    const uint4 d = desc[pval[w0 + lane]];
+    const int tx0 = (int)(d.y & 0xffffu), ty0 = (int)(d.z & 0xffffu), ty1 = (int)(d.z >> 16);
+    const int ya = ty0 > B.r0 ? ty0 : B.r0, yb = ty1 < B.r1 - 1 ? ty1 : B.r1 - 1;
+    dR = d.x;
+    dW = d.y >> 16;
+    dbase = (ya - B.r0) * B.tx + tx0;
+    dn = (int)dW * (yb - ya + 1);
+  }
+  uint32_t* cur = s_cur + (wv >> 1) * band_tiles;
+  const int half = (wv & 1) * 16;
+  const uint32_t inc = 1u << half;
+  __syncthreads();
+  // pass 1: this wavefront's count per tile
+  for (int l = 0; l < cnt; ++l) {
+    const int W = __builtin_amdgcn_readlane((int)dW, l);
+    const int base = __builtin_amdgcn_readlane(dbase, l);
+    const int n = __builtin_amdgcn_readlane(dn, l);
+    const float inv_w = __builtin_amdgcn_rcpf((float)W);
+    for (int q = 0; q < n; q += 64) {
+      const int e = q + lane;
+      const int t = entry_tile(e, W, inv_w, base, B.tx);
+      if (e < n) atomicAdd(&cur[t], inc);
     }
-    const int cnt = p1 - pb < 64 ? (int)(p1 - pb) : 64;
-    for (int l = 0; l < cnt; ++l) {
-      const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)dR, l);
-      const int W = __builtin_amdgcn_readlane((int)dW, l);
-      const int base = __builtin_amdgcn_readlane(dbase, l);
-      const int n = __builtin_amdgcn_readlane(dn, l);
-      // local tile of entry e: base + (e / W) * tx + e % W
-      const float inv_w = __builtin_amdgcn_rcpf((float)W);
-      for (int q = 0; q < n; q += 64) {
-        const int e = q + lane;
-        int row = (int)((float)e * inv_w);
-        int col = e - row * W;
-        if (col < 0) { --row; col += W; }
-        if (col >= W) { ++row; col -= W; }
-        if (e < n) {
-          const int t = base + row * B.tx + col;
-          const uint32_t pos = s_cur[t];
-          s_cur[t] = pos + 1u;
-          vals[pos] = R;
-        }
+  }
+  __syncthreads();
+  // per tile: counts -> offsets across the wavefronts (relative to the
+  // run), the run length; then the runs laid out in tile order
+  const int per = (nt + kEmitThreads - 1) / kEmitThreads;
+  const int t0 = tid * per, t1 = t0 + per < nt ? t0 + per : nt;
+  uint32_t mine = 0;
+  for (int t = t0; t < t1; ++t) {
+    uint32_t run = 0;
+#pragma unroll
+    for (int p = 0; p < kEmitWaves / 2; ++p) {
+      const uint32_t c = s_cur[p * band_tiles + t];
+      const uint32_t lo = run, hi = run + (c & 0xffffu);
+      s_cur[p * band_tiles + t] = lo | (hi << 16);
+      run = hi + (c >> 16);
+    }
+    s_start[t] = run;
+    mine += run;
+  }
+  uint32_t wtot;
+  const uint32_t wex = wave_excl_scan_u32(mine, lane, &wtot);
+  if (lane == 0) s_wsum[wv] = wtot;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kEmitWaves; ++w) {
+    const uint32_t x = s_wsum[w];
+    before += w < wv ? x : 0u;
+    total += x;
+  }
+  const bool staged = total <= (uint32_t)stage_cap;
+  uint32_t at = before + wex;
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t len = s_start[t];
+    s_start[t] = at;
+    at += len;
+  }
+  __syncthreads();
+  // pass 2: slots in record order per tile
+  uint32_t* dst = staged ? s_stage : vals;
+  const uint32_t* run_base = staged ? s_start : s_off;
+  for (int l = 0; l < cnt; ++l) {
+    const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)dR, l);
+    const int W = __builtin_amdgcn_readlane((int)dW, l);
+    const int base = __builtin_amdgcn_readlane(dbase, l);
+    const int n = __builtin_amdgcn_readlane(dn, l);
+    const float inv_w = __builtin_amdgcn_rcpf((float)W);
+    for (int q = 0; q < n; q += 64) {
+      const int e = q + lane;
+      const int t = entry_tile(e, W, inv_w, base, B.tx);
+      if (e < n) {
+        const uint32_t rel = (atomicAdd(&cur[t], inc) >> half) & 0xffffu;
+        dst[run_base[t] + rel] = R;
       }
     }
+  }
+  if (!staged) continue;
+  __syncthreads();
+  // copy out: staging slot i belongs to the last tile whose run starts at
+  // or before i (empty runs share their start with the next run)
+  for (uint32_t i = tid; i < total; i += kEmitThreads) {
+    int lo = 0, hi = nt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_start[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    vals[s_off[lo] + (i - s_start[lo])] = s_stage[i];
+  }
   }
 }
 
@@ -1001,7 +1112,7 @@ void onesweep_passes(K** kb, uint32_t** vb, const uint64_t* n_dev, int64_t cap, 
                      hipStream_t s) {
   constexpr int PART = kBlock * ITEMS;
   const int64_t parts = (cap + PART - 1) / PART > 0 ? (cap + PART - 1) / PART : 1;
-  const unsigned grid = (unsigned)parts;
+  const unsigned grid = (unsigned)(parts < kSweepGrid ? parts : kSweepGrid);
   if (passes <= 0) return;
   hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_for(parts * kRadix, kBlock, 4096)), dim3(kBlock), 0, s,
                      w.lookback[lb & 1], parts * kRadix);
@@ -1109,7 +1220,7 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        (const uint32_t*)w.nitems, (const uint64_t*)w.item0, g.n_bands, w.item_band);
     // 3. counts[item][tile], tile totals, their scan, per-item offsets, ranges
     const size_t lds = (size_t)(g.band_tiles + 1) * sizeof(uint32_t);
-    const unsigned items = (unsigned)g.items_max;
+    const unsigned items = (unsigned)(g.items_max < kItemGrid ? g.items_max : kItemGrid);
     hipLaunchKernelGGL(place_count_kernel, dim3(items), dim3(64), lds, s, (const uint4*)w.desc, pval,
                        (const uint32_t*)w.brange, (const uint32_t*)w.item_band, (const uint64_t*)w.item0,
                        (const uint64_t*)n_items, cp, g.band_tiles, w.counts);
@@ -1129,10 +1240,13 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        (const uint64_t*)w.starts, n_dup, capacity, cp, g.band_tiles, g.n_bands, chunks, groups,
                        ranges);
     // 4. the entries
-    hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(64), lds, s, (const uint4*)w.desc, pval,
-                       (const uint32_t*)w.brange, (const uint32_t*)w.item_band, (const uint64_t*)w.item0,
-                       (const uint64_t*)n_items, cp, g.band_tiles, (const uint32_t*)w.counts, n_dup, capacity,
-                       overflow, vals);
+    const size_t emit_fixed = emit_fixed_lds(g.band_tiles);
+    const int stage_cap = emit_fixed < kEmitLdsBytes ? (int)((kEmitLdsBytes - emit_fixed) / sizeof(uint32_t)) : 0;
+    const size_t emit_lds = emit_fixed + (size_t)stage_cap * sizeof(uint32_t);
+    hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(kEmitThreads), emit_lds, s, (const uint4*)w.desc,
+                       pval, (const uint32_t*)w.brange, (const uint32_t*)w.item_band, (const uint64_t*)w.item0,
+                       (const uint64_t*)n_items, cp, g.band_tiles, stage_cap, (const uint32_t*)w.counts, n_dup,
+                       capacity, overflow, vals);
     if (keys)
       hipLaunchKernelGGL(keys_from_ranges_kernel, dim3(nt > 0 ? (unsigned)nt : 1u), dim3(64), 0, s,
                          (const uint32_t*)ranges, (const uint32_t*)vals, rec, nt, keys);

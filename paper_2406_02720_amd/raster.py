@@ -73,6 +73,8 @@ class Frame:
     ws_render: torch.Tensor
     tile_order: torch.Tensor | None = None
     depth: torch.Tensor | None = None
+    params: object | None = None      # the hgs_params the frame was rendered with
+    filter3d: torch.Tensor | None = None
 
     def image(self, c: int) -> torch.Tensor:
         """[3,H,W] view of camera c's image."""
@@ -95,7 +97,8 @@ def _bytes(n: int, device) -> torch.Tensor:
 
 
 def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity: int | None = None,
-                 persistent: bool = True, keys: bool = True, depth: bool = False) -> Frame:
+                 persistent: bool = True, keys: bool = True, depth: bool = False, params=None,
+                 filter3d: torch.Tensor | None = None) -> Frame:
     """Run the forward rasterizer.  ``cams`` is a C camera array from
     ``binding.make_cameras``; ``opts`` an ``hgs_options``.  With
     ``capacity`` None the entry count is read back (one synchronisation) and
@@ -103,12 +106,19 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
     entries and an overflow is reported in ``frame.overflow``.  With
     ``persistent`` the raster takes tiles longest-list first from a
     persistent grid; ``keys`` False skips the 64-bit sort keys (the raster
-    does not need them); ``depth`` adds the blended depth per pixel."""
+    does not need them); ``depth`` adds the blended depth per pixel;
+    ``params`` (an hgs_params) overrides the parameter planes taken from
+    ``soa`` (which then only gives the device and the gradient layout);
+    ``filter3d`` (float32 [n] on the device) is the Mip-Splatting 3-D
+    filter variance per kernel."""
     dev = soa.device
     nc = len(cams)
     n_rec = n * nc
     stream = _stream()
-    params = B.params_struct(soa, n, soa.shape[1], sh_degree)
+    if params is None:
+        params = B.params_struct(soa, n, soa.shape[1], sh_degree)
+    if filter3d is not None:
+        params.filter3d = filter3d.data_ptr()
     records = _bytes(n_rec * B.HGS_RECORD_BYTES, dev)
     tiles = torch.empty(max(n_rec, 1), dtype=torch.int32, device=dev)
     offsets = torch.empty(max(n_rec, 1), dtype=torch.int64, device=dev)
@@ -137,7 +147,8 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
     B.hgs_render_fwd(records, values, ranges, order, cams, opts, images, T_final, last_idx, n_contrib, ws_r,
                      stream, depth=depth_t)
     return Frame(soa, n, sh_degree, cams, opts, records, tiles, offsets, n_dup, keys_t, values, ranges,
-                 overflow, images, T_final, last_idx, n_contrib, capacity, ws_r, order, depth_t)
+                 overflow, images, T_final, last_idx, n_contrib, capacity, ws_r, order, depth_t, params,
+                 filter3d)
 
 
 def depth_normals(fr: Frame) -> torch.Tensor:
@@ -151,19 +162,29 @@ def depth_normals(fr: Frame) -> torch.Tensor:
 
 
 def backward_pass(fr: Frame, dL_dimages: torch.Tensor, record_grads: torch.Tensor | None = None,
-                  grads: torch.Tensor | None = None):
+                  grads: torch.Tensor | None = None, stats=None):
     """Gradients of every parameter plane (same SoA layout as ``fr.soa``) and
-    the per-record gradients."""
+    the per-record gradients.  ``stats`` = (grad_accum, grad_count,
+    max_radii) runs the two halves of the backward pass separately and
+    accumulates the densification statistics between them."""
     dev = fr.soa.device
     n_rec = fr.n * len(fr.cams)
     if record_grads is None:
         record_grads = torch.empty(max(n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
     if grads is None:
         grads = torch.zeros_like(fr.soa)
-    params = B.params_struct(fr.soa, fr.n, fr.soa.shape[1], fr.sh_degree)
+    params = fr.params if fr.params is not None else B.params_struct(fr.soa, fr.n, fr.soa.shape[1], fr.sh_degree)
     gs = B.grads_struct(grads, fr.soa.shape[1])
-    B.hgs_render_bwd(params, fr.cams, fr.opts, fr.records, fr.values, fr.ranges, fr.tile_order, fr.T_final,
-                     fr.last_idx, dL_dimages, record_grads, gs, fr.ws_render, _stream())
+    if stats is None:
+        B.hgs_render_bwd(params, fr.cams, fr.opts, fr.records, fr.values, fr.ranges, fr.tile_order, fr.T_final,
+                         fr.last_idx, dL_dimages, record_grads, gs, fr.ws_render, _stream())
+    else:
+        accum, count, radii = stats
+        record_grads.zero_()
+        B.hgs_raster_bwd(fr.records, fr.values, fr.ranges, fr.tile_order, fr.cams, fr.opts, fr.T_final,
+                         fr.last_idx, dL_dimages, record_grads, fr.ws_render, _stream())
+        B.hgs_densify_stats(fr.records, record_grads, fr.cams, fr.opts, fr.n, accum, count, radii, _stream())
+        B.hgs_preprocess_bwd(params, fr.cams, fr.opts, fr.records, record_grads, gs, _stream())
     return grads, record_grads
 
 

@@ -217,3 +217,62 @@ def sample_pixels(camera: dict, count: int, seed: int = 11):
     count = min(count, w * h)
     flat = rng.choice(w * h, size=count, replace=False)
     return np.stack([flat % w, flat // w], 1).astype(np.int64)
+
+
+def depth_maps(cameras, seed: int = 7):
+    """Seeded blended-depth and transmittance maps, one [H,W] float32 pair
+    per camera: a tilted wavy surface at depth ~3 seen through a random
+    coverage 1 - T in [0.7, 1], with ~3% empty pixels (T = 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Ds, Ts = [], []
+    for c in cameras:
+        H, W = c["height"], c["width"]
+        yy, xx = np.mgrid[0:H, 0:W]
+        z = 3.0 + 0.01 * xx + 0.004 * yy + 0.05 * np.sin(xx / 7.0) * np.cos(yy / 5.0)
+        T = rng.uniform(0.0, 0.3, (H, W))
+        T[rng.uniform(size=(H, W)) < 0.03] = 1.0
+        Ds.append((z * (1.0 - T)).astype(np.float32))
+        Ts.append(T.astype(np.float32))
+    return Ds, Ts
+
+
+def train_state(n: int, sh_degree: int, extent: float = 2.0, seed: int = 21):
+    """Seeded optimiser state of n half-Gaussians in the raw layout
+    (float32 [planes, n] arrays: means, log-scales, quaternions, normals,
+    opacity logits, SH), activated-space gradients, Adam moments, and
+    densification statistics spread around the 3D-GS thresholds (largest
+    scale around 0.01 * extent, opacities around 0.01, average NDC gradient
+    around 0.0002, screen radii 0..40 px), plus the standard normal draws of
+    two children per kernel ([2, 3, n])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    K = 3 * (sh_degree + 1) ** 2
+    f32 = np.float32
+    raw = dict(
+        means=rng.normal(0.0, extent, (3, n)).astype(f32),
+        scales=(np.log(0.01 * extent) + rng.normal(0.0, 1.0, (3, n))).astype(f32),
+        quats=rng.normal(0.0, 1.0, (4, n)).astype(f32),
+        normals=rng.normal(0.0, 1.0, (3, n)).astype(f32),
+        opac1=(np.log(0.01 / 0.99) + rng.normal(0.0, 2.0, (1, n))).astype(f32),
+        opac2=(np.log(0.01 / 0.99) + rng.normal(0.0, 2.0, (1, n))).astype(f32),
+        sh=rng.normal(0.0, 0.3, (K, n)).astype(f32),
+    )
+    grads = {k: (rng.normal(0.0, 1e-2, v.shape) * (rng.random(v.shape) < 0.9)).astype(f32) for k, v in raw.items()}
+    m = {k: rng.normal(0.0, 1e-3, v.shape).astype(f32) for k, v in raw.items()}
+    v2 = {k: (rng.random(v.shape) * 1e-4).astype(f32) for k, v in raw.items()}
+    count = rng.integers(0, 6, n).astype(np.int32)
+    accum = (count * rng.lognormal(np.log(0.0002), 0.7, n)).astype(f32)
+    radii = np.floor(rng.random(n) * 40.0).astype(f32)
+    samples = rng.normal(0.0, 1.0, (2, 3, n)).astype(f32)
+    return dict(raw=raw, grads=grads, m=m, v=v2, accum=accum, count=count, radii=radii, samples=samples)
+
+
+def with_filter3d(scene: dict, seed: int = 13, scale: float = 0.5) -> dict:
+    """Copy of ``scene`` with a seeded Mip-Splatting 3-D filter variance per
+    kernel: (scale * smallest axis)^2 times a log-uniform factor in
+    [0.1, 10], so that the filter ranges from negligible to dominant."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = dict(scene)
+    smin = np.asarray(scene["scales"], np.float64).min(1)
+    fac = np.exp(rng.uniform(np.log(0.1), np.log(10.0), smin.shape[0]))
+    out["filter3d"] = ((scale * smin) ** 2 * fac).astype(np.float32)
+    return out

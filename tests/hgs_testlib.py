@@ -26,7 +26,7 @@ def ambiguous(margin) -> np.ndarray:
     return (m < BANDS).any(-1)
 
 OPT_KEYS = ("tile", "batch", "lowpass", "kappa", "alpha_min", "alpha_max", "t_min", "fov_clamp", "bg",
-            "full_box", "sort_full_keys")
+            "full_box", "sort_full_keys", "mip2d")
 
 
 def split_opts(kw):
@@ -38,8 +38,10 @@ def split_opts(kw):
 def gpu_forward(scene, cams, capacity=None, persistent=True, **kw):
     gkw, _ = split_opts(kw)
     soa = R.scene_to_soa(scene)
+    f3 = scene.get("filter3d")
+    f3 = None if f3 is None else torch.as_tensor(np.asarray(f3, np.float32)).cuda()
     fr = R.forward_pass(soa, scene["means"].shape[0], scene["sh_degree"], B.make_cameras(cams),
-                        B.default_options(**gkw), capacity=capacity, persistent=persistent)
+                        B.default_options(**gkw), capacity=capacity, persistent=persistent, filter3d=f3)
     torch.cuda.synchronize()
     return fr
 

@@ -465,22 +465,58 @@ def test_blended_depth_matches_oracle():
     assert np.abs(D - Dr)[ok].max() <= 1e-4 * scale
 
 
-def test_depth_normals_match_oracle_on_the_same_depth():
-    """hgs_depth_normals against the oracle's estimate from the same depth
-    and transmittance maps (the GPU's), two cameras of different sizes."""
-    scene, cams = CASES["cfg4_three_views"]
+def test_depth_normals_match_oracle_on_seeded_maps():
+    """hgs_depth_normals against the oracle's estimate on seeded synthetic
+    depth and transmittance maps (a tilted wavy surface with empty pixels),
+    two cameras of different sizes packed one after the other."""
+    _, cams = CASES["cfg4_three_views"]
     cams = cams[:2]
-    fr = R.forward_pass(R.scene_to_soa(scene), scene["means"].shape[0], scene["sh_degree"],
-                        B.make_cameras(cams), B.default_options(), depth=True)
-    nrm = R.depth_normals(fr)
+    Ds, Ts = scenes.depth_maps(cams, seed=7)
+    depth = torch.from_numpy(np.concatenate([d.ravel() for d in Ds])).cuda()
+    T_final = torch.from_numpy(np.concatenate([t.ravel() for t in Ts])).cuda()
+    out = torch.empty(3 * depth.numel(), dtype=torch.float32, device="cuda")
+    B.hgs_depth_normals(depth, T_final, B.make_cameras(cams), out, R._stream())
     torch.cuda.synchronize()
     off = 0
     for c, cam in enumerate(cams):
         H, W = cam["height"], cam["width"]
-        D = fr.per_pixel(fr.depth, c).cpu().numpy()
-        T = fr.per_pixel(fr.T_final, c).cpu().numpy()
-        ref = O.depth_normals(D, T, cam)
-        got = nrm[3 * off:3 * (off + H * W)].view(3, H, W).cpu().numpy()
+        ref = O.depth_normals(Ds[c], Ts[c], cam)
+        got = out[3 * off:3 * (off + H * W)].view(3, H, W).cpu().numpy()
         assert np.abs(got - ref).max() <= 1e-5
-        assert (np.abs(ref).sum(0) > 0).mean() > 0.05
+        assert (np.abs(ref).sum(0) > 0).mean() > 0.5
         off += H * W
+
+
+def test_depth_normals_of_a_render_match_oracle():
+    """End to end: normals from the GPU's depth and transmittance against
+    the oracle's from its own (REC mode), on pixels whose 3x3 neighbourhood
+    holds no ambiguous decision.  The finite differences divide depth errors
+    (~1e-6 relative) by neighbour depth differences, so the bound is loose."""
+    scene, cams = CASES["cfg2_small"]
+    fr = R.forward_pass(R.scene_to_soa(scene), scene["means"].shape[0], scene["sh_degree"],
+                        B.make_cameras(cams), B.default_options(), depth=True)
+    nrm = R.depth_normals(fr)
+    torch.cuda.synchronize()
+    pre = oracle_pre(scene, cams)[0]
+    ref = O.render(pre, "rec")
+    cam = cams[0]
+    H, W = cam["height"], cam["width"]
+    want = O.depth_normals(ref["depth"].numpy(), ref["T_final"].numpy(), cam)
+    got = nrm[:3 * H * W].view(3, H, W).cpu().numpy()
+    amb = ambiguous(ref["margin"])
+    near = amb.copy()
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            near |= np.roll(np.roll(amb, dy, 0), dx, 1)
+    # the expected depth divides by 1 - T: keep pixels with real coverage
+    acc = 1.0 - ref["T_final"].numpy()
+    thin = acc < 0.1
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            near |= np.roll(np.roll(thin, dy, 0), dx, 1)
+    ok = ~near
+    assert ok.mean() > 0.5
+    err = np.abs(got - want).max(0)[ok]
+    print(f"normals: {ok.sum()} pixels, err q50 {np.median(err):.2e} q99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
+    assert np.quantile(err, 0.99) <= 1e-3
+    assert err.max() <= 5e-2

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header():
     assert C.sizeof(B.hgs_camera) == 80
     assert C.sizeof(B.hgs_options) == 48
-    assert C.sizeof(B.hgs_params) == 7 * 8 + 8 + 8 + 8
+    assert C.sizeof(B.hgs_params) == 7 * 8 + 8 + 8 + 8 + 8
     assert C.sizeof(B.hgs_param_grads) == 7 * 8
 
 
@@ -104,3 +104,29 @@ def test_raster_erfc_approximation_error_bound():
     e = np.exp2(p.astype(np.float64))
     approx = np.where(x >= 0, e, 2.0 - e)
     assert np.abs(approx - erfc(x.astype(np.float64))).max() < 1e-7
+
+
+def test_adam_schedule_host_call_matches_oracle():
+    """hgs_adam_schedule is host code: its rates are the oracle's schedule
+    rounded to float32, and it rejects bad arguments."""
+    import numpy as np
+    from oracle import hgs_train_oracle as T
+    for t in (1, 2, 4999, 5000, 12345, 30000, 45000):
+        for ext in (0.5, 3.7):
+            cfg = B.hgs_adam_schedule(t, ext)
+            want = T.learning_rates(t, float(np.float32(ext)))
+            got = dict(means=cfg.lr_means, scales=cfg.lr_scales, quats=cfg.lr_quats, normals=cfg.lr_normals,
+                       opac=cfg.lr_opacity, sh_dc=cfg.lr_sh_dc, sh_rest=cfg.lr_sh_rest)
+            for k, v in want.items():
+                assert got[k] == np.float32(v), (t, ext, k, got[k], v)
+            assert (cfg.beta1, cfg.beta2, cfg.step) == (np.float32(0.9), np.float32(0.999), t)
+            assert cfg.eps == np.float32(1e-15)
+    lib = B.load()
+    c = B.hgs_adam_config()
+    assert lib.hgs_adam_schedule(0, 1.0, 0.003, C.byref(c)) == B.HGS_EINVAL
+    assert lib.hgs_adam_schedule(1, 0.0, 0.003, C.byref(c)) == B.HGS_EINVAL
+    d = B.hgs_densify_default(2.0)
+    assert (d.grad_threshold, d.percent_dense, d.min_opacity) == (np.float32(0.0002), np.float32(0.01),
+                                                                  np.float32(0.01))
+    assert B.hgs_densify_workspace_bytes(1000) > 3 * 4 * 1000 + 3 * 8 * 1000
+    assert B.hgs_densify_workspace_bytes(-1) == 0

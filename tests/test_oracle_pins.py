@@ -642,3 +642,98 @@ def test_depth_normals_of_a_plane_are_its_normal():
     for (y, x) in ((9, 10), (11, 10), (10, 9), (10, 11)):
         assert (n2[:, y, x] == 0).all()
     np.testing.assert_allclose(n2[:, 10, 10], nrm, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Mip-Splatting-HGS filters
+# ---------------------------------------------------------------------------
+def _pre(scene, cam, **kw):
+    with torch.no_grad():
+        return O.preprocess(O.scene_to_torch(scene), O.camera_to_torch(cam), O.options(**kw))
+
+
+def test_filter3d_equals_a_kernel_with_inflated_scales():
+    """Sigma + f I = R diag(s^2 + f) R^T, and the opacity factor
+    sqrt(det Sigma / det(Sigma + f I)) = prod s / sqrt(s^2 + f): the filtered
+    kernel projects exactly like an unfiltered one with those scales and
+    opacities (half factor, valid region and all)."""
+    scene, _ = scenes.make_config(2, n=400)
+    cam = scenes.axis_camera(120, 90, distance=3.0)
+    sf = scenes.with_filter3d(scene, scale=0.8)
+    s = np.asarray(scene["scales"], np.float64)
+    f = np.asarray(sf["filter3d"], np.float64)[:, None]
+    comp = np.prod(s / np.sqrt(s * s + f), 1)
+    sg = dict(scene)
+    sg["scales"] = np.sqrt(s * s + f)
+    sg["opac1"] = np.asarray(scene["opac1"], np.float64) * comp
+    sg["opac2"] = np.asarray(scene["opac2"], np.float64) * comp
+    a, b = _pre(sf, cam), _pre(sg, cam)
+    # the inflated scene goes through float32 rounding of its inputs in
+    # scene_to_torch only if given as float32: it is float64 here
+    np.testing.assert_array_equal(a["valid"].numpy(), b["valid"].numpy())
+    np.testing.assert_array_equal(a["rect"].numpy()[a["valid"].numpy()], b["rect"].numpy()[b["valid"].numpy()])
+    for k in ("mean2d", "conic", "k", "alpha2", "d_o", "colour"):
+        np.testing.assert_allclose(a["rec"][k].numpy(), b["rec"][k].numpy(), rtol=1e-10, atol=1e-13)
+    assert (comp < 0.999).mean() > 0.5          # the filter matters for most kernels
+
+
+def test_filter3d_of_zero_is_no_filter():
+    scene, _ = scenes.make_config(2, n=300)
+    cam = scenes.axis_camera(100, 80, distance=3.0)
+    s0 = dict(scene)
+    s0["filter3d"] = np.zeros(scene["means"].shape[0], np.float32)
+    a, b = _pre(scene, cam), _pre(s0, cam)
+    np.testing.assert_array_equal(a["valid"].numpy(), b["valid"].numpy())
+    for k in ("conic", "k", "alpha2", "d_o"):
+        np.testing.assert_array_equal(a["rec"][k].numpy(), b["rec"][k].numpy())
+
+
+def test_mip2d_compensation_is_the_screen_eigenvalue_ratio():
+    """With the 2-D mip filter the opacities carry prod_i sqrt(l_i / (l_i +
+    lowpass)) over the eigenvalues l_i of the undilated screen covariance
+    (the screen integral of the compensated, filtered kernel equals the
+    unfiltered one)."""
+    scene, _ = scenes.make_config(2, n=300)
+    cam = scenes.axis_camera(100, 80, distance=3.0)
+    lp = 0.1
+    a = _pre(scene, cam, mip2d=True, lowpass=lp)
+    ref = _pre(scene, cam, lowpass=lp)
+    idx = a["idx"].numpy()
+    Shat0 = a["rec"]["Shat"].numpy() - np.float32(lp) * np.eye(2)
+    lam = np.linalg.eigvalsh(Shat0)
+    c2 = np.prod(np.sqrt(np.clip(lam, 0, None) / (lam + np.float32(lp))), 1)
+    opac2 = np.asarray(scene["opac2"], np.float64)[idx]
+    np.testing.assert_allclose(a["rec"]["alpha2"].numpy(), opac2 * c2, rtol=1e-9)
+    # the geometry is the plain low-passed one
+    same = np.intersect1d(idx, ref["idx"].numpy())
+    ia = np.searchsorted(idx, same)
+    ib = np.searchsorted(ref["idx"].numpy(), same)
+    np.testing.assert_array_equal(a["rec"]["conic"].numpy()[ia], ref["rec"]["conic"].numpy()[ib])
+    assert (c2 < 0.99).mean() > 0.1
+
+
+def test_mip_filter3d_hand_cases():
+    """Sampling rate fx / z of the nearest seeing camera: two cameras on the
+    z axis at different distances, a kernel seen by both, one outside the
+    widened image of both (it takes the smallest seen rate), one behind
+    both."""
+    c1 = scenes.axis_camera(100, 100, distance=4.0)      # camera at z = -4
+    c2 = scenes.axis_camera(100, 100, distance=9.0)      # camera at z = -9
+    fx = float(np.float32(c1["fx"]))
+    means = np.array([[0.0, 0.0, 0.0],                   # depth 4 and 9: nu = fx / 4
+                      [0.0, 0.0, 6.0],                   # depth 10 and 15: nu = fx / 10
+                      [50.0, 0.0, 0.0],                  # far off to the side
+                      [0.0, 0.0, -20.0]], np.float32)    # behind both
+    f = O.mip_filter3d(means, [c1, c2], s=0.2, margin=0.15)
+    s = float(np.float32(0.2))
+    nu = np.array([fx / 4.0, fx / 10.0, fx / 10.0, fx / 10.0])
+    np.testing.assert_allclose(f, s / nu ** 2, rtol=1e-12)
+    # the margin: a centre projected 10% outside the image is seen (rate
+    # fx / 4), 20% outside is not (it takes the smallest seen rate, fx / 8)
+    W = 100.0
+    for frac, rate in ((0.10, fx / 4.0), (0.20, fx / 8.0)):
+        X = (-frac * W - float(np.float32(c1["cx"]))) * 4.0 / fx
+        pts = np.array([[X, 0.0, 0.0], [0.0, 0.0, 4.0]], np.float32)    # the second at depth 8
+        g = O.mip_filter3d(pts, [c1], s=0.2, margin=0.15)
+        np.testing.assert_allclose(g, [s / rate ** 2, s / (fx / 8.0) ** 2], rtol=1e-6)
+    assert not O.mip_filter3d(np.array([[0.0, 0.0, -20.0]], np.float32), [c1]).any()
