@@ -841,29 +841,41 @@ __global__ __launch_bounds__(64) void place_offsets_kernel(
 // The entries of one item, staged in LDS.  Each wavefront takes
 // kEmitPerWave consecutive pairs (records in depth order).  Pass 1 counts
 // per wavefront how many of its records cover each tile of the band; a scan
-// across the wavefronts turns the counts into per-wavefront cursors
-// (relative to the tile's run, 16 bits each, two wavefronts per LDS word),
-// and a scan over the tiles lays the item's runs (one per tile, in tile
-// order) out in the staging area.  Pass 2 walks every wavefront's records
-// one after another (covered tiles across the lanes) and takes each entry's
+// across the wavefronts turns the counts into per-wavefront cursors, and a
+// scan over the tiles lays the item's runs (one per tile, in tile order)
+// out in the staging area.  Pass 2 walks every wavefront's records one
+// after another (covered tiles across the lanes) and takes each entry's
 // slot with an LDS fetch-and-add, so a tile's slots follow record order.
 // Each run is then copied to its place in the tile's list in one contiguous
 // burst.  An item with more entries than the staging area holds writes its
 // entries straight to their final positions instead.
+//
+// Bands of up to kEmitWideTiles tiles keep a 32-bit cursor per (wavefront,
+// tile), counted with a difference array (two LDS increments per record
+// row, lanes = records) and holding absolute slots.  Wider bands (one tile
+// row of a very wide image) pack two wavefronts' 16-bit cursors, relative
+// to the run, per word, and count entry by entry.
 constexpr int kEmitWaves = 8;
 constexpr int kEmitThreads = kEmitWaves * 64;
 constexpr int kEmitPerWave = kBlockPairs / kEmitWaves;
 static_assert(kEmitPerWave == 64, "one pair per lane in the decode");
 static_assert(kBlockPairs < 65536, "16-bit cursors");
+constexpr int kEmitWideTiles = 512;
 constexpr size_t kEmitLdsBytes = 65536 - 256;  // dynamic part; the static s_wsum sits beside it
 
+// LDS words of the cursor area per tile, and the fixed part in bytes.
+inline bool emit_packed(int band_tiles) { return band_tiles > kEmitWideTiles; }
 inline size_t emit_fixed_lds(int band_tiles) {
-  return (size_t)(kEmitWaves / 2 + 2) * (size_t)band_tiles * sizeof(uint32_t);
+  const size_t cur = emit_packed(band_tiles) ? (size_t)(kEmitWaves / 2) * band_tiles
+                                             : (size_t)kEmitWaves * (band_tiles + 1);
+  return (cur + 2 * (size_t)band_tiles + 1) * sizeof(uint32_t);
 }
 
 // Entry e of a record's band part -> its local tile (rows of width W
-// starting at local tile `base`, band row pitch tx).
-__device__ __forceinline__ int entry_tile(int e, int W, float inv_w, int base, int tx) {
+// starting at local tile `base`, band row pitch tx).  n <= 2 W (at most two
+// rows, the common case) needs no division.
+__device__ __forceinline__ int entry_tile(int e, int W, int n, float inv_w, int base, int tx) {
+  if (n <= 2 * W) return base + (e >= W ? tx - W : 0) + e;
   int row = (int)((float)e * inv_w);
   int col = e - row * W;
   if (col < 0) { --row; col += W; }
@@ -871,6 +883,7 @@ __device__ __forceinline__ int entry_tile(int e, int W, float inv_w, int base, i
   return base + row * tx + col;
 }
 
+template <bool PACKED>
 __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
     const uint4* __restrict__ desc, const uint32_t* __restrict__ pval, const uint32_t* __restrict__ brange,
     const uint32_t* __restrict__ item_band, const uint64_t* __restrict__ item0, const uint64_t* __restrict__ n_items,
@@ -878,10 +891,14 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
     const uint64_t* __restrict__ n_dup, int64_t capacity, int32_t* __restrict__ overflow,
     uint32_t* __restrict__ vals) {
   extern __shared__ uint32_t lds[];
-  uint32_t* s_cur = lds;                                      // [kEmitWaves / 2][band_tiles], 2 x 16 bits
-  uint32_t* s_start = s_cur + (kEmitWaves / 2) * band_tiles;  // [band_tiles] run start in the staging area
-  uint32_t* s_off = s_start + band_tiles;                     // [band_tiles] run start in the tile's list
-  uint32_t* s_stage = s_off + band_tiles;                     // [stage_cap]
+  // cursor area: PACKED [kEmitWaves / 2][band_tiles] (2 x 16 bits), else
+  // [kEmitWaves][band_tiles + 1]
+  constexpr int kCurRows = PACKED ? kEmitWaves / 2 : kEmitWaves;
+  const int pitch = PACKED ? band_tiles : band_tiles + 1;
+  uint32_t* s_cur = lds;
+  uint32_t* s_start = s_cur + kCurRows * pitch;     // [band_tiles + 1] run start in the staging area
+  uint32_t* s_off = s_start + band_tiles + 1;       // [band_tiles] run start in the tile's list
+  uint32_t* s_stage = s_off + band_tiles;           // [stage_cap]
   __shared__ uint32_t s_wsum[kEmitWaves];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const bool over = *n_dup > (uint64_t)capacity;
@@ -893,18 +910,18 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
   const uint32_t k = item_band[item];
   const Band B = band_of(cp, k);
   const int nt = B.n;
-  for (int i = tid; i < (kEmitWaves / 2) * band_tiles; i += kEmitThreads) s_cur[i] = 0u;
+  for (int i = tid; i < kCurRows * pitch; i += kEmitThreads) s_cur[i] = 0u;
   const uint32_t* src = offsets + item * (uint64_t)band_tiles;
   for (int i = tid; i < nt; i += kEmitThreads) s_off[i] = src[i];
   // this wavefront's pairs, one per lane: record, width, first local tile,
-  // entries in the band
+  // rows in the band, entries in the band
   const uint64_t p0 = brange[2 * (uint64_t)k] + (item - item0[k]) * kBlockPairs;
   const uint64_t pe = brange[2 * (uint64_t)k + 1];
   const uint64_t w0 = p0 + (uint64_t)wv * kEmitPerWave;
   const uint64_t w1 = w0 + kEmitPerWave < pe ? w0 + kEmitPerWave : pe;
   const int cnt = w1 > w0 ? (int)(w1 - w0) : 0;
   uint32_t dR = 0, dW = 1;
-  int dbase = 0, dn = 0;
+  int dbase = 0, dn = 0, drows = 0;
   if (lane < cnt) {
     const uint4 d = desc[pval[w0 + lane]];
     const int tx0 = (int)(d.y & 0xffffu), ty0 = (int)(d.z & 0xffffu), ty1 = (int)(d.z >> 16);
@@ -912,25 +929,51 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
     dR = d.x;
     dW = d.y >> 16;
     dbase = (ya - B.r0) * B.tx + tx0;
-    dn = (int)dW * (yb - ya + 1);
+    drows = yb - ya + 1;
+    dn = (int)dW * drows;
   }
-  uint32_t* cur = s_cur + (wv >> 1) * band_tiles;
-  const int half = (wv & 1) * 16;
+  uint32_t* cur = s_cur + (PACKED ? (wv >> 1) : wv) * pitch;
+  const int half = PACKED ? (wv & 1) * 16 : 0;
   const uint32_t inc = 1u << half;
   __syncthreads();
   // pass 1: this wavefront's count per tile
-  for (int l = 0; l < cnt; ++l) {
-    const int W = __builtin_amdgcn_readlane((int)dW, l);
-    const int base = __builtin_amdgcn_readlane(dbase, l);
-    const int n = __builtin_amdgcn_readlane(dn, l);
-    const float inv_w = __builtin_amdgcn_rcpf((float)W);
-    for (int q = 0; q < n; q += 64) {
-      const int e = q + lane;
-      const int t = entry_tile(e, W, inv_w, base, B.tx);
-      if (e < n) atomicAdd(&cur[t], inc);
+  if constexpr (PACKED) {
+    for (int l = 0; l < cnt; ++l) {
+      const int W = __builtin_amdgcn_readlane((int)dW, l);
+      const int base = __builtin_amdgcn_readlane(dbase, l);
+      const int n = __builtin_amdgcn_readlane(dn, l);
+      const float inv_w = __builtin_amdgcn_rcpf((float)W);
+      for (int q = 0; q < n; q += 64) {
+        const int e = q + lane;
+        const int t = entry_tile(e, W, n, inv_w, base, B.tx);
+        if (e < n) atomicAdd(&cur[t], inc);
+      }
+    }
+  } else {
+    // difference array over the band's linear tile index: +1 at a row's
+    // first tile, -1 after its last (modular arithmetic; the prefix sums
+    // are the counts)
+    for (int r = 0; r < drows; ++r) {
+      const int a = dbase + r * B.tx;
+      atomicAdd(&cur[a], 1u);
+      atomicSub(&cur[a + (int)dW], 1u);
     }
   }
   __syncthreads();
+  if constexpr (!PACKED) {
+    // each wavefront's prefix sum over its own difference array
+    const int chunk = (nt + 63) / 64;
+    const int c0 = lane * chunk, c1 = c0 + chunk < nt ? c0 + chunk : nt;
+    uint32_t run = 0;
+    for (int i = c0; i < c1; ++i) {
+      run += cur[i];
+      cur[i] = run;
+    }
+    uint32_t tot;
+    const uint32_t ex = wave_excl_scan_u32(run, lane, &tot);
+    for (int i = c0; i < c1; ++i) cur[i] += ex;
+    __syncthreads();
+  }
   // per tile: counts -> offsets across the wavefronts (relative to the
   // run), the run length; then the runs laid out in tile order
   const int per = (nt + kEmitThreads - 1) / kEmitThreads;
@@ -938,12 +981,21 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
   uint32_t mine = 0;
   for (int t = t0; t < t1; ++t) {
     uint32_t run = 0;
+    if constexpr (PACKED) {
 #pragma unroll
-    for (int p = 0; p < kEmitWaves / 2; ++p) {
-      const uint32_t c = s_cur[p * band_tiles + t];
-      const uint32_t lo = run, hi = run + (c & 0xffffu);
-      s_cur[p * band_tiles + t] = lo | (hi << 16);
-      run = hi + (c >> 16);
+      for (int p = 0; p < kEmitWaves / 2; ++p) {
+        const uint32_t c = s_cur[p * pitch + t];
+        const uint32_t lo = run, hi = run + (c & 0xffffu);
+        s_cur[p * pitch + t] = lo | (hi << 16);
+        run = hi + (c >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < kEmitWaves; ++w) {
+        const uint32_t c = s_cur[w * pitch + t];
+        s_cur[w * pitch + t] = run;
+        run += c;
+      }
     }
     s_start[t] = run;
     mine += run;
@@ -964,8 +1016,15 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
   for (int t = t0; t < t1; ++t) {
     const uint32_t len = s_start[t];
     s_start[t] = at;
+    if constexpr (!PACKED) {
+      // absolute slots: in the staging area, or in the tile's list
+      const uint32_t base = staged ? at : s_off[t];
+#pragma unroll
+      for (int w = 0; w < kEmitWaves; ++w) s_cur[w * pitch + t] += base;
+    }
     at += len;
   }
+  if (tid == 0) s_start[nt] = total;
   __syncthreads();
   // pass 2: slots in record order per tile
   uint32_t* dst = staged ? s_stage : vals;
@@ -978,24 +1037,25 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
     const float inv_w = __builtin_amdgcn_rcpf((float)W);
     for (int q = 0; q < n; q += 64) {
       const int e = q + lane;
-      const int t = entry_tile(e, W, inv_w, base, B.tx);
+      const int t = entry_tile(e, W, n, inv_w, base, B.tx);
       if (e < n) {
-        const uint32_t rel = (atomicAdd(&cur[t], inc) >> half) & 0xffffu;
-        dst[run_base[t] + rel] = R;
+        if constexpr (PACKED) {
+          const uint32_t rel = (atomicAdd(&cur[t], inc) >> half) & 0xffffu;
+          dst[run_base[t] + rel] = R;
+        } else {
+          dst[atomicAdd(&cur[t], 1u)] = R;
+        }
       }
     }
   }
   if (!staged) continue;
   __syncthreads();
-  // copy out: staging slot i belongs to the last tile whose run starts at
-  // or before i (empty runs share their start with the next run)
-  for (uint32_t i = tid; i < total; i += kEmitThreads) {
-    int lo = 0, hi = nt - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_start[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    vals[s_off[lo] + (i - s_start[lo])] = s_stage[i];
+  // copy out, one tile run per wavefront step: contiguous in the staging
+  // area and in the tile's list
+  for (int t = wv; t < nt; t += kEmitWaves) {
+    const uint32_t a = s_start[t], e = s_start[t + 1];
+    const uint32_t o = s_off[t];
+    for (uint32_t i = a + lane; i < e; i += 64) vals[o + (i - a)] = s_stage[i];
   }
   }
 }
@@ -1243,10 +1303,16 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     const size_t emit_fixed = emit_fixed_lds(g.band_tiles);
     const int stage_cap = emit_fixed < kEmitLdsBytes ? (int)((kEmitLdsBytes - emit_fixed) / sizeof(uint32_t)) : 0;
     const size_t emit_lds = emit_fixed + (size_t)stage_cap * sizeof(uint32_t);
-    hipLaunchKernelGGL(place_emit_kernel, dim3(items), dim3(kEmitThreads), emit_lds, s, (const uint4*)w.desc,
-                       pval, (const uint32_t*)w.brange, (const uint32_t*)w.item_band, (const uint64_t*)w.item0,
-                       (const uint64_t*)n_items, cp, g.band_tiles, stage_cap, (const uint32_t*)w.counts, n_dup,
-                       capacity, overflow, vals);
+    if (emit_packed(g.band_tiles))
+      hipLaunchKernelGGL(place_emit_kernel<true>, dim3(items), dim3(kEmitThreads), emit_lds, s,
+                         (const uint4*)w.desc, pval, (const uint32_t*)w.brange, (const uint32_t*)w.item_band,
+                         (const uint64_t*)w.item0, (const uint64_t*)n_items, cp, g.band_tiles, stage_cap,
+                         (const uint32_t*)w.counts, n_dup, capacity, overflow, vals);
+    else
+      hipLaunchKernelGGL(place_emit_kernel<false>, dim3(items), dim3(kEmitThreads), emit_lds, s,
+                         (const uint4*)w.desc, pval, (const uint32_t*)w.brange, (const uint32_t*)w.item_band,
+                         (const uint64_t*)w.item0, (const uint64_t*)n_items, cp, g.band_tiles, stage_cap,
+                         (const uint32_t*)w.counts, n_dup, capacity, overflow, vals);
     if (keys)
       hipLaunchKernelGGL(keys_from_ranges_kernel, dim3(nt > 0 ? (unsigned)nt : 1u), dim3(64), 0, s,
                          (const uint32_t*)ranges, (const uint32_t*)vals, rec, nt, keys);

@@ -98,7 +98,7 @@ def _bytes(n: int, device) -> torch.Tensor:
 
 def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity: int | None = None,
                  persistent: bool = True, keys: bool = True, depth: bool = False, params=None,
-                 filter3d: torch.Tensor | None = None) -> Frame:
+                 filter3d: torch.Tensor | None = None, render: bool = True) -> Frame:
     """Run the forward rasterizer.  ``cams`` is a C camera array from
     ``binding.make_cameras``; ``opts`` an ``hgs_options``.  With
     ``capacity`` None the entry count is read back (one synchronisation) and
@@ -110,7 +110,8 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
     ``params`` (an hgs_params) overrides the parameter planes taken from
     ``soa`` (which then only gives the device and the gradient layout);
     ``filter3d`` (float32 [n] on the device) is the Mip-Splatting 3-D
-    filter variance per kernel."""
+    filter variance per kernel; ``render`` False stops after the sort (the
+    per-pixel outputs are left unwritten)."""
     dev = soa.device
     nc = len(cams)
     n_rec = n * nc
@@ -144,8 +145,9 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
     n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
     depth_t = torch.empty(npix, dtype=torch.float32, device=dev) if depth else None
     ws_r = _bytes(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), dev)
-    B.hgs_render_fwd(records, values, ranges, order, cams, opts, images, T_final, last_idx, n_contrib, ws_r,
-                     stream, depth=depth_t)
+    if render:
+        B.hgs_render_fwd(records, values, ranges, order, cams, opts, images, T_final, last_idx, n_contrib, ws_r,
+                         stream, depth=depth_t)
     return Frame(soa, n, sh_degree, cams, opts, records, tiles, offsets, n_dup, keys_t, values, ranges,
                  overflow, images, T_final, last_idx, n_contrib, capacity, ws_r, order, depth_t, params,
                  filter3d)

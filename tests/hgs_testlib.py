@@ -35,13 +35,14 @@ def split_opts(kw):
     return gpu, O.options(**orc)
 
 
-def gpu_forward(scene, cams, capacity=None, persistent=True, **kw):
+def gpu_forward(scene, cams, capacity=None, persistent=True, render=True, **kw):
     gkw, _ = split_opts(kw)
     soa = R.scene_to_soa(scene)
     f3 = scene.get("filter3d")
     f3 = None if f3 is None else torch.as_tensor(np.asarray(f3, np.float32)).cuda()
     fr = R.forward_pass(soa, scene["means"].shape[0], scene["sh_degree"], B.make_cameras(cams),
-                        B.default_options(**gkw), capacity=capacity, persistent=persistent, filter3d=f3)
+                        B.default_options(**gkw), capacity=capacity, persistent=persistent, filter3d=f3,
+                        render=render)
     torch.cuda.synchronize()
     return fr
 

@@ -444,6 +444,23 @@ def test_placement_equals_full_key_sort_at_4k_tile8():
     np.testing.assert_array_equal(u32(a.tile_order), u32(b.tile_order))
 
 
+def test_placement_of_a_very_wide_image_matches_oracle():
+    """A 4200 x 40 image at 8-pixel tiles: 525 tiles per row, a band wider
+    than the 32-bit cursor layout takes (packed 16-bit cursors, entry-wise
+    counting), sorted lists and ranges equal to the oracle's."""
+    scene, _ = scenes.make_config(2, n=3000)
+    cam = scenes.pinhole(4200, 40, np.eye(3), (0.0, 0.0, 3.0), hfov_deg=120.0)
+    print("[case] wide image 4200x40 tile 8", flush=True)
+    fr = gpu_forward(scene, [cam], tile=8)
+    pres = oracle_pre(scene, [cam], tile=8)
+    bs = O.bin_sort(pres)
+    keys, vals, ranges = sorted_entries(fr)
+    assert int(fr.overflow.item()) == 0
+    assert vals.size == bs["vals"].size > 0
+    np.testing.assert_array_equal(vals, bs["vals"])
+    np.testing.assert_array_equal(ranges, bs["ranges"])
+
+
 def test_blended_depth_matches_oracle():
     """The optional depth output of hgs_render_fwd against the oracle's
     blended depth (REC mode), relative to the depth scale, on the pixels
