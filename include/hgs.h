@@ -211,8 +211,11 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
  *   ranges         device, uint32 [tiles_total][2] (out); a tile without
  *                  entries gets [0, 0)
  *   tile_order     device, uint32 [tiles_total] (out), may be NULL: the tile
- *                  ids by decreasing number of entries (ties by id), the
- *                  order in which the persistent raster takes tiles
+ *                  ids, longest lists first, the order in which the
+ *                  persistent raster takes tiles: ascending key
+ *                  255 - min(255, 16 m + f), m = floor(log2(n + 1)) and f
+ *                  the four bits of n + 1 below its leading one (n = the
+ *                  tile's entries), ties by tile id
  *   overflow       device, int32 [1] (out): 0, or 1 when *n_dup > capacity;
  *                  then no entry is written and every range is empty
  *   workspace      device, hgs_workspace_bytes(HGS_WS_BIN_SORT, ...) bytes

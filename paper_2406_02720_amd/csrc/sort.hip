@@ -479,12 +479,24 @@ __global__ __launch_bounds__(kBlock) void ranges_kernel(const K* __restrict__ ke
 // Processing order of the tiles, longest list first: 16-bit key
 // 0xffff - min(length, 0xffff), value = tile id, and the histograms of its
 // two digits.
+// Tile order key: the number of entries on a log scale with 4 fractional
+// bits (16 buckets per doubling, computed in integers), longest first:
+// 255 - min(255, 16 msb(n + 1) + next four bits).  Lists of 2^16 - 1
+// entries and more share the first bucket.
+__device__ __forceinline__ uint32_t order_key(uint32_t len) {
+  const uint32_t v = len + 1u;                 // >= 1
+  const int msb = 31 - __clz((int)v);
+  const uint32_t frac = (uint32_t)(((uint64_t)v << (32 - msb)) >> 28) & 15u;
+  const uint32_t b = (uint32_t)msb * 16u + frac;
+  return 255u - (b < 255u ? b : 255u);
+}
+
 __global__ __launch_bounds__(kBlock) void order_keys_kernel(const uint32_t* __restrict__ ranges,
                                                             int64_t n_tiles, uint32_t* __restrict__ keys,
                                                             uint32_t* __restrict__ ids,
                                                             uint32_t* __restrict__ hist) {
-  __shared__ uint32_t s_h[2 * kRadix];
-  for (int i = threadIdx.x; i < 2 * kRadix; i += kBlock) s_h[i] = 0u;
+  __shared__ uint32_t s_h[kRadix];
+  for (int i = threadIdx.x; i < kRadix; i += kBlock) s_h[i] = 0u;
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n_tiles; base += stride) {
@@ -492,16 +504,14 @@ __global__ __launch_bounds__(kBlock) void order_keys_kernel(const uint32_t* __re
     const bool ok = t < n_tiles;
     uint32_t k = 0;
     if (ok) {
-      const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-      k = 0xffffu - (len < 0xffffu ? len : 0xffffu);
+      k = order_key(ranges[2 * t + 1] - ranges[2 * t]);
       keys[t] = k;
       ids[t] = (uint32_t)t;
     }
-    wave_hist_add(s_h, k & 0xffu, ok);
-    wave_hist_add(s_h + kRadix, (k >> 8) & 0xffu, ok);
+    wave_hist_add(s_h, k, ok);
   }
   __syncthreads();
-  flush_hist(s_h, 2 * kRadix, hist);
+  flush_hist(s_h, kRadix, hist);
 }
 
 // Optional 64-bit keys of the placed entries: one wavefront per tile writes
@@ -642,14 +652,23 @@ __global__ __launch_bounds__(kBlock) void place_desc_kernel(const Record* __rest
 }
 
 // (band, slot) pairs in slot order, with the histograms of the band digits.
+// Band-count histogram in LDS: bands up to this many take the difference
+// array below, more bands the per-pair digit increments.
+constexpr int kPairBandsLds = 4096;
+
 __global__ __launch_bounds__(kBlock) void place_pairs_kernel(const uint4* __restrict__ desc,
                                                              const uint32_t* __restrict__ nbands,
                                                              const uint64_t* __restrict__ poff, int64_t n_rec,
-                                                             int64_t pairs_max, CamPack cp, uint32_t* __restrict__ pkey,
-                                                             uint32_t* __restrict__ pval, uint32_t* __restrict__ hist,
-                                                             int hist_passes) {
+                                                             int64_t pairs_max, CamPack cp, int64_t n_bands,
+                                                             uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval,
+                                                             uint32_t* __restrict__ hist, int hist_passes) {
   __shared__ uint32_t s_h[kMaxPasses * kRadix];
+  __shared__ uint32_t s_bd[kPairBandsLds + 1];   // +1 at a record's first band, -1 after its last
+  __shared__ uint32_t s_part[kBlock / 64];
+  const bool by_band = n_bands <= kPairBandsLds;
   for (int i = threadIdx.x; i < hist_passes * kRadix; i += kBlock) s_h[i] = 0u;
+  if (by_band)
+    for (int i = threadIdx.x; i <= (int)n_bands; i += kBlock) s_bd[i] = 0u;
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n_rec; base += stride) {
@@ -667,8 +686,20 @@ __global__ __launch_bounds__(kBlock) void place_pairs_kernel(const uint4* __rest
         o = poff[j];
       }
     }
-    // the wavefront walks the pairs of its lanes' records together, so the
-    // digit histograms see every pair once
+    if (by_band) {
+      if (nb) {
+        atomicAdd(&s_bd[kb0], 1u);
+        atomicSub(&s_bd[kb0 + nb], 1u);
+      }
+      const bool fits = o + nb <= (uint64_t)pairs_max;  // past the bound only on overflow
+      for (uint32_t b = 0; b < nb && fits; ++b) {
+        pkey[o + b] = kb0 + b;
+        pval[o + b] = (uint32_t)j;
+      }
+      continue;
+    }
+    // many bands: the wavefront walks the pairs of its lanes' records
+    // together, so the digit histograms see every pair once
     uint32_t most = nb;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
@@ -676,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void place_pairs_kernel(const uint4* __rest
       most = t > most ? t : most;
     }
     for (uint32_t b = 0; b < most; ++b) {
-      const bool ok = b < nb && o + b < (uint64_t)pairs_max;  // past the bound only on overflow
+      const bool ok = b < nb && o + b < (uint64_t)pairs_max;
       const uint32_t k = kb0 + b;
       if (ok) {
         pkey[o + b] = k;
@@ -686,6 +717,28 @@ __global__ __launch_bounds__(kBlock) void place_pairs_kernel(const uint4* __rest
     }
   }
   __syncthreads();
+  if (by_band) {
+    // band counts = prefix sums of the difference array; each band adds
+    // its count to its digits' bins
+    const int nbd = (int)n_bands;
+    const int chunk = (nbd + kBlock - 1) / kBlock;
+    const int c0 = threadIdx.x * chunk, c1 = c0 + chunk < nbd ? c0 + chunk : nbd;
+    uint32_t run = 0;
+    for (int i = c0; i < c1; ++i) run += s_bd[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t wtot;
+    const uint32_t wex = wave_excl_scan_u32(run, lane, &wtot);
+    if (lane == 0) s_part[wv] = wtot;
+    __syncthreads();
+    uint32_t acc = wex;
+    for (int w = 0; w < wv; ++w) acc += s_part[w];
+    for (int i = c0; i < c1; ++i) {
+      acc += s_bd[i];
+      if (acc)
+        for (int p = 0; p < hist_passes; ++p) atomicAdd(&s_h[p * kRadix + ((i >> (8 * p)) & 0xff)], acc);
+    }
+    __syncthreads();
+  }
   flush_hist(s_h, hist_passes * kRadix, hist);
 }
 
@@ -1030,10 +1083,10 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
   uint32_t* dst = staged ? s_stage : vals;
   const uint32_t* run_base = staged ? s_start : s_off;
   for (int l = 0; l < cnt; ++l) {
+    const int n = __builtin_amdgcn_readlane(dn, l);
     const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)dR, l);
     const int W = __builtin_amdgcn_readlane((int)dW, l);
     const int base = __builtin_amdgcn_readlane(dbase, l);
-    const int n = __builtin_amdgcn_readlane(dn, l);
     const float inv_w = __builtin_amdgcn_rcpf((float)W);
     for (int q = 0; q < n; q += 64) {
       const int e = q + lane;
@@ -1260,7 +1313,7 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     const int bpasses = (g.band_bits + 7) / 8;
     hipLaunchKernelGGL(place_pairs_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s,
                        (const uint4*)w.desc, (const uint32_t*)w.nbands, (const uint64_t*)w.poff, n_rec,
-                       g.pairs_max, cp, w.pkey[0], w.pval[0], hist_ent, bpasses);
+                       g.pairs_max, cp, g.n_bands, w.pkey[0], w.pval[0], hist_ent, bpasses);
     if (bpasses > 0) {
       hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, bpasses);
       onesweep_passes<uint32_t, kSmallItems>(w.pkey, w.pval, n_pairs, g.pairs_max, 0, bpasses, base_ent, w,
@@ -1321,12 +1374,12 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
   if (tile_order) {
     const int64_t nt = (int64_t)cp.tiles_total;
     uint32_t* ob[2] = {w.okeys[0], w.okeys[1]};
-    uint32_t* ov[2] = {tile_order, w.oalt};  // two passes: the order lands in tile_order
+    uint32_t* ov[2] = {w.oalt, tile_order};  // one pass: the order lands in tile_order
     hipLaunchKernelGGL(order_keys_kernel, dim3(grid_for(nt, kBlock, 1024)), dim3(kBlock), 0, s, ranges, nt,
                        ob[0], ov[0], hist_rec + 4 * kRadix);
     hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec + 4 * kRadix,
-                       base_rec + 4 * kRadix, 2);
-    onesweep_passes<uint32_t, kSmallItems>(ob, ov, nullptr, nt, 0, 2, base_rec + 4 * kRadix, w, w.tickets + 4,
+                       base_rec + 4 * kRadix, 1);
+    onesweep_passes<uint32_t, kSmallItems>(ob, ov, nullptr, nt, 0, 1, base_rec + 4 * kRadix, w, w.tickets + 4,
                                            lb, s);
   }
   return hipGetLastError();

@@ -163,7 +163,15 @@ def test_tile_order_is_longest_list_first():
     r = u32(fr.ranges).reshape(-1, 2).astype(np.int64)
     lengths = r[:, 1] - r[:, 0]
     assert sorted(order.tolist()) == list(range(lengths.size))
-    np.testing.assert_array_equal(order, np.lexsort((np.arange(lengths.size), -lengths)))
+    # log-scale buckets of the list length, 16 per doubling, longest first
+    v = (lengths + 1).astype(np.uint64)
+    msb = np.floor(np.log2(v.astype(np.float64))).astype(np.int64)
+    frac = ((v << (32 - msb).astype(np.uint64)) >> np.uint64(28)).astype(np.int64) & 15
+    key = 255 - np.minimum(255, 16 * msb + frac)
+    np.testing.assert_array_equal(order, np.lexsort((np.arange(lengths.size), key)))
+    # a later tile is never longer than an earlier one by more than one bucket
+    lo = (lengths[order] + 1).astype(np.float64)
+    assert np.all(lo[1:] < np.maximum.accumulate(lo)[:-1] * (17 / 16) + 1e-9)
 
 
 def test_persistent_backward_equals_per_tile_backward():
