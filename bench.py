@@ -76,13 +76,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=32)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cpu-pixels", type=int, default=1024, help="pixels of the oracle CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage timings to stderr")
     ap.add_argument("--full-keys", action="store_true", help="sort the 64-bit keys over all bits")
-    ap.add_argument("--per-tile", action="store_true", help="one raster workgroup per tile (no persistent grid)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="persistent raster grid taking tiles longest list first (default: one workgroup per "
+                         "tile, in tile order, which keeps neighbouring tiles' records together in the caches)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES, 5 times (counter calibration)")
     ap.add_argument("--multiview", action="store_true",
@@ -167,7 +169,7 @@ def main():
     keys = torch.empty(cap, dtype=torch.int64, device=dev) if args.full_keys else None
     values = torch.empty(cap, dtype=torch.int32, device=dev)
     ranges = torch.empty(2 * tiles_total, dtype=torch.int32, device=dev)
-    order = None if args.per_tile else torch.empty(tiles_total, dtype=torch.int32, device=dev)
+    order = torch.empty(tiles_total, dtype=torch.int32, device=dev) if args.persistent else None
     overflow = torch.zeros(1, dtype=torch.int32, device=dev)
     ws_sort = buf(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, ca, opts, cap))
     images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
@@ -284,8 +286,9 @@ def main():
     roofline = {k: v for k, v in roof[dominant].items() if k not in ("ms", "bytes", "flops")}
     roofline["kernel"] = dominant
     kname = {"render_fwd": "render_fwd", "raster_bwd": "render_bwd", "preprocess_bwd": "preprocess_bwd"}[dominant]
-    if dominant in ("render_fwd", "raster_bwd") and not args.per_tile:
-        kname += f"_persistent_kernel<{args.tile},{args.batch // 64}>"
+    if dominant in ("render_fwd", "raster_bwd"):
+        kname += f"_persistent_kernel<{args.tile},{args.batch // 64}>" if args.persistent else \
+            f"_kernel<{args.tile},{args.batch // 64}>"
     roofline["traffic"] = measured_traffic(kname)
 
     if args.stages:
@@ -322,7 +325,7 @@ def main():
         "config": {"workload": WORKLOADS.get(args.config, str(args.config)), "n_kernels": n,
                    "views": len(cams), "pixels": W, "tile": args.tile, "batch": args.batch,
                    "entries": n_dup, "sort": "full_keys" if args.full_keys else "placement",
-                   "raster": "per_tile" if args.per_tile else "persistent"},
+                   "raster": "persistent" if args.persistent else "per_tile"},
         "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
         "fwd_bwd_over_fwd": round((fwd_ms + bwd_ms) / fwd_ms, 3),
         "stage_ms": {k: round(float(v), 4) for k, v in st.items()},

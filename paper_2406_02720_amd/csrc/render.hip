@@ -323,11 +323,12 @@ __device__ __forceinline__ void fwd_block(
   }
 }
 
-// Next work item of a persistent wavefront: (tile of rank w in `order`, sub-block).
-__device__ __forceinline__ uint32_t next_work(uint32_t* counter, int lane) {
-  uint32_t w = 0;
-  if (lane == 0) w = atomicAdd(counter, 1u);
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int)w);
+// Next tile rank of a persistent workgroup (all its wavefronts see it).
+__device__ __forceinline__ uint32_t next_tile(uint32_t* counter, uint32_t* s_w) {
+  __syncthreads();   // every wavefront has read the previous rank
+  if (threadIdx.x == 0) *s_w = atomicAdd(counter, 1u);
+  __syncthreads();
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)*s_w);
 }
 
 template <int T, int IPL, bool DEPTH>
@@ -340,21 +341,21 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
                            threadIdx.x >> 6, threadIdx.x & 63);
 }
 
-// Persistent form: one wavefront per workgroup, a grid sized to the chip;
-// every wavefront takes work items (tile rank, sub-block) from a counter,
-// tiles in `order` (longest list first) so that long tiles do not start last.
+// Persistent form: workgroups of one tile's wavefronts (they share the
+// tile's records through the CU's scalar cache), a grid sized to the chip;
+// every workgroup takes tiles from a counter in `order` (longest list
+// first) so that long tiles do not start last.
 template <int T, int IPL, bool DEPTH>
-__global__ __launch_bounds__(64) void render_fwd_persistent_kernel(
+__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_persistent_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
     float* __restrict__ img, float* __restrict__ T_final, int32_t* __restrict__ last_idx,
     int32_t* __restrict__ n_contrib, float* __restrict__ depth, uint32_t* __restrict__ counter) {
-  constexpr uint32_t WAVES = Geometry<T>::WAVES;
-  const uint32_t n_work = cp.tiles_total * WAVES;
-  const int lane = threadIdx.x & 63;
-  for (uint32_t w = next_work(counter, lane); w < n_work; w = next_work(counter, lane))
-    fwd_block<T, IPL, DEPTH>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, depth,
-                             order[w / WAVES], (int)(w % WAVES), lane);
+  __shared__ uint32_t s_w;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t w = next_tile(counter, &s_w); w < cp.tiles_total; w = next_tile(counter, &s_w))
+    fwd_block<T, IPL, DEPTH>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, depth, order[w], wave,
+                             lane);
 }
 
 // One wavefront's block of pixels, back to front.  Same masks as the
@@ -523,17 +524,16 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
 }
 
 template <int T, int IPL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void render_bwd_persistent_kernel(
+__global__ __launch_bounds__(64 * Geometry<T>::WAVES) __attribute__((amdgpu_waves_per_eu(6))) void
+render_bwd_persistent_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
     const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,
     const float* __restrict__ dL_dimg, float* __restrict__ rgrad, uint32_t* __restrict__ counter) {
-  constexpr uint32_t WAVES = Geometry<T>::WAVES;
-  const uint32_t n_work = cp.tiles_total * WAVES;
-  const int lane = threadIdx.x & 63;
-  for (uint32_t w = next_work(counter, lane); w < n_work; w = next_work(counter, lane))
-    bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, order[w / WAVES],
-                      (int)(w % WAVES), lane);
+  __shared__ uint32_t s_w;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t w = next_tile(counter, &s_w); w < cp.tiles_total; w = next_tile(counter, &s_w))
+    bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, order[w], wave, lane);
 }
 
 __global__ void clear_counter_kernel(uint32_t* __restrict__ p) { *p = 0u; }
@@ -544,15 +544,15 @@ __global__ void zero_f32_kernel(float* __restrict__ p, int64_t n) {
   for (int64_t i = t; i < n; i += stride) p[i] = 0.0f;
 }
 
-// Workgroups of the persistent grid: as many one-wavefront workgroups as
+// Workgroups of the persistent grid: as many workgroups of `threads` as
 // the chip keeps resident, never more than there are work items.
 template <typename F>
-unsigned persistent_grid(F kernel, uint32_t n_work) {
+unsigned persistent_grid(F kernel, uint32_t n_work, int threads) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
     per_cu = 8;
   const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
   return (unsigned)(g < n_work ? g : (n_work > 0 ? n_work : 1));
@@ -565,10 +565,11 @@ hipError_t fwd_launch_d(const Record* rec, const uint32_t* vals, const uint32_t*
   if (order) {
     uint32_t* counter = static_cast<uint32_t*>(ws);
     hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-    const uint32_t n_work = cp.tiles_total * Geometry<T>::WAVES;
+    constexpr int threads = 64 * Geometry<T>::WAVES;
     hipLaunchKernelGGL((render_fwd_persistent_kernel<T, B / 64, DEPTH>),
-                       dim3(persistent_grid(render_fwd_persistent_kernel<T, B / 64, DEPTH>, n_work)), dim3(64), 0,
-                       s, rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, counter);
+                       dim3(persistent_grid(render_fwd_persistent_kernel<T, B / 64, DEPTH>, cp.tiles_total,
+                                            threads)),
+                       dim3(threads), 0, s, rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, counter);
   } else {
     hipLaunchKernelGGL((render_fwd_kernel<T, B / 64, DEPTH>), dim3(cp.tiles_total),
                        dim3(64 * Geometry<T>::WAVES), 0, s, rec, vals, ranges, cp, o, img, Tf, li, nc, depth);
@@ -591,10 +592,10 @@ hipError_t bwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* r
   if (order) {
     uint32_t* counter = static_cast<uint32_t*>(ws) + 1;
     hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-    const uint32_t n_work = cp.tiles_total * Geometry<T>::WAVES;
+    constexpr int threads = 64 * Geometry<T>::WAVES;
     hipLaunchKernelGGL((render_bwd_persistent_kernel<T, B / 64>),
-                       dim3(persistent_grid(render_bwd_persistent_kernel<T, B / 64>, n_work)), dim3(64), 0,
-                       s, rec, vals, ranges, order, cp, o, Tf, li, dL, rg, counter);
+                       dim3(persistent_grid(render_bwd_persistent_kernel<T, B / 64>, cp.tiles_total, threads)),
+                       dim3(threads), 0, s, rec, vals, ranges, order, cp, o, Tf, li, dL, rg, counter);
   } else {
     hipLaunchKernelGGL((render_bwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
                        0, s, rec, vals, ranges, cp, o, Tf, li, dL, rg);
