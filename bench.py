@@ -38,7 +38,7 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hbm_traffic_1M_1080p.txt")
 TRAFFIC_SOURCES = ("include/hgs.h", "paper_2406_02720_amd/csrc/hgs_internal.h",
                    "paper_2406_02720_amd/csrc/geometry.h", "paper_2406_02720_amd/csrc/preprocess.hip",
                    "paper_2406_02720_amd/csrc/sort.hip", "paper_2406_02720_amd/csrc/render.hip",
-                   "paper_2406_02720_amd/build.py")
+                   "paper_2406_02720_amd/csrc/train.hip", "paper_2406_02720_amd/build.py")
 
 
 def sources_digest() -> str:
