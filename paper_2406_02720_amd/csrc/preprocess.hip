@@ -257,6 +257,26 @@ __global__ __launch_bounds__(kScanBlock) void scan_partials_kernel(uint64_t* __r
   if (threadIdx.x == 0) *total = run;
 }
 
+// Small inputs: the whole scan in one workgroup (one launch instead of
+// three).
+constexpr int64_t kScanSmall = 8192;
+
+__global__ __launch_bounds__(kScanBlock) void scan_small_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                                uint64_t* __restrict__ out,
+                                                                uint64_t* __restrict__ total) {
+  __shared__ uint64_t lds[kScanBlock / 64];
+  uint64_t run = 0;
+  for (int64_t base = 0; base < n; base += kScanBlock) {
+    const int64_t idx = base + threadIdx.x;
+    const uint64_t x = idx < n ? (uint64_t)in[idx] : 0ull;
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan(x, &tot, lds);
+    if (idx < n) out[idx] = run + ex;
+    run += tot;
+  }
+  if (threadIdx.x == 0) *total = run;
+}
+
 __global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const uint32_t* __restrict__ in,
                                                                 int64_t n,
                                                                 const uint64_t* __restrict__ partial,
@@ -565,6 +585,10 @@ size_t scan_workspace_bytes(int64_t n) {
 
 hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint64_t* total,
                        void* ws, hipStream_t s) {
+  if (n <= kScanSmall) {
+    hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kScanBlock), 0, s, tiles, n, offsets, total);
+    return hipGetLastError();
+  }
   const int64_t blocks = (n + kScanTile - 1) / kScanTile;
   uint64_t* partial = (uint64_t*)ws;
   if (blocks > 0)

@@ -765,14 +765,24 @@ __global__ __launch_bounds__(kBlock) void place_band_items_kernel(const uint32_t
   nitems[k] = (len + kBlockPairs - 1) / kBlockPairs;
 }
 
-// item -> band for the items of every band (items of band k start at item0[k]).
+// item -> band for the items of every band (band k owns items
+// [item0[k], item0[k] + nitems[k]), ascending): one thread per item, a
+// binary search for the first band whose items end past it (bands without
+// items never qualify).
 __global__ __launch_bounds__(kBlock) void place_item_bands_kernel(const uint32_t* __restrict__ nitems,
                                                                   const uint64_t* __restrict__ item0,
+                                                                  const uint64_t* __restrict__ n_items,
                                                                   int64_t n_bands, uint32_t* __restrict__ item_band) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n_bands) return;
-  const uint64_t a = item0[k];
-  for (uint32_t i = 0; i < nitems[k]; ++i) item_band[a + i] = (uint32_t)k;
+  const uint64_t items = *n_items;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < items; i += stride) {
+    int64_t lo = 0, hi = n_bands - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (item0[mid] + nitems[mid] > i) hi = mid; else lo = mid + 1;
+    }
+    item_band[i] = (uint32_t)lo;
+  }
 }
 
 // counts[item][t] for the tiles t of the item's band: how many of the
@@ -1329,8 +1339,9 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        (const uint32_t*)w.brange, g.n_bands, w.nitems);
     e = launch_scan(w.nitems, g.n_bands, w.item0, n_items, w.scan_ws, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(place_item_bands_kernel, dim3(grid_for(g.n_bands, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
-                       (const uint32_t*)w.nitems, (const uint64_t*)w.item0, g.n_bands, w.item_band);
+    hipLaunchKernelGGL(place_item_bands_kernel, dim3(grid_for(g.items_max, kBlock, 1024)), dim3(kBlock), 0, s,
+                       (const uint32_t*)w.nitems, (const uint64_t*)w.item0, (const uint64_t*)n_items, g.n_bands,
+                       w.item_band);
     // 3. counts[item][tile], tile totals, their scan, per-item offsets, ranges
     const size_t lds = (size_t)(g.band_tiles + 1) * sizeof(uint32_t);
     const unsigned items = (unsigned)(g.items_max < kItemGrid ? g.items_max : kItemGrid);
