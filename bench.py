@@ -163,7 +163,7 @@ def main():
     gstruct = B.grads_struct(grads, n)
     records = buf(n_rec * 64)
     tiles = torch.empty(n_rec, dtype=torch.int32, device=dev)
-    offsets = torch.empty(n_rec, dtype=torch.int64, device=dev)
+    offsets = torch.empty(n_rec, dtype=torch.int64, device=dev) if args.full_keys else None
     ndup = torch.zeros(1, dtype=torch.int64, device=dev)
     ws_pre = buf(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, ca, opts))
     keys = torch.empty(cap, dtype=torch.int64, device=dev) if args.full_keys else None

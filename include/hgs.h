@@ -180,7 +180,9 @@ int64_t hgs_pixels_total(const hgs_camera* cams, int32_t n_cams);
  *   records        device, [n_cams * n] records of HGS_RECORD_BYTES (out)
  *   tiles_touched  device, uint32 [n_cams * n], 0 for culled records (out)
  *   offsets        device, uint64 [n_cams * n], exclusive prefix sum of
- *                  tiles_touched (out)
+ *                  tiles_touched (out); may be NULL (then only n_dup is
+ *                  computed): hgs_bin_sort needs it only with
+ *                  HGS_FLAG_SORT_FULL_KEYS
  *   n_dup          device, uint64 [1], sum of tiles_touched (out)
  *   workspace      device, hgs_workspace_bytes(HGS_WS_PREPROCESS, ...) bytes
  * Errors: HGS_EINVAL for null pointers, n < 0, stride < n, sh_degree not in
@@ -201,7 +203,8 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
  * their scans, then cursors that hand out each tile's positions in record
  * order); HGS_FLAG_SORT_FULL_KEYS duplicates the 64-bit keys and radix-sorts
  * them over all bits.  Both give the same entries, ranges and order.
- *   records, tiles_touched, offsets, n_dup   from hgs_preprocess (device)
+ *   records, tiles_touched, offsets, n_dup   from hgs_preprocess (device);
+ *                  offsets may be NULL unless HGS_FLAG_SORT_FULL_KEYS is set
  *   n_rec          n_cams * n
  *   keys, values   device, `capacity` entries each (out: sorted entries in
  *                  the first *n_dup positions); keys may be NULL unless

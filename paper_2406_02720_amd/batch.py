@@ -50,7 +50,8 @@ class BatchedRasterizer:
         self.params = B.params_struct(soa, n, soa.shape[1], sh_degree)
         self.records = _bytes(self.n_rec * B.HGS_RECORD_BYTES, dev)
         self.tiles = torch.empty(max(self.n_rec, 1), dtype=torch.int32, device=dev)
-        self.offsets = torch.empty(max(self.n_rec, 1), dtype=torch.int64, device=dev)
+        self.offsets = (torch.empty(max(self.n_rec, 1), dtype=torch.int64, device=dev)
+                        if self.opts.flags & B.HGS_FLAG_SORT_FULL_KEYS else None)
         self.n_dup = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_pre = _bytes(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, self.n_rec, self.cams, self.opts), dev)
         self.ranges = torch.empty(max(2 * self.tiles_total, 1), dtype=torch.int32, device=dev)

@@ -189,7 +189,7 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
   hgs::CamPack cp;
   if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
   const int64_t n_rec = p.n * n_cams;
-  if (!n_dup || (n_rec > 0 && (!records || !tiles_touched || !offsets)))
+  if (!n_dup || (n_rec > 0 && (!records || !tiles_touched)))
     return fail(HGS_EINVAL, "an output pointer is null");
   if (!workspace || workspace_bytes < hgs::scan_workspace_bytes(n_rec))
     return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", hgs::scan_workspace_bytes(n_rec));
@@ -213,7 +213,7 @@ int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint6
   if (n_rec < 0 || n_rec % n_cams != 0) return fail(HGS_EINVAL, "n_rec must be n_cams * n");
   if (capacity < 0 || capacity >= (int64_t)UINT32_MAX) return fail(HGS_EINVAL, "capacity out of range");
   const bool full_keys = (opts->flags & HGS_FLAG_SORT_FULL_KEYS) != 0;
-  if (!n_dup || !ranges || !overflow || (n_rec > 0 && (!records || !tiles_touched || !offsets)) ||
+  if (!n_dup || !ranges || !overflow || (n_rec > 0 && (!records || !tiles_touched || (full_keys && !offsets))) ||
       (capacity > 0 && (!values || (full_keys && !keys))))
     return fail(HGS_EINVAL, "a pointer is null");
   const size_t need = hgs::sort_workspace_bytes(n_rec, capacity, cp, full_keys);

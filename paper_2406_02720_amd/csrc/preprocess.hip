@@ -585,7 +585,7 @@ size_t scan_workspace_bytes(int64_t n) {
 
 hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint64_t* total,
                        void* ws, hipStream_t s) {
-  if (n <= kScanSmall) {
+  if (n <= kScanSmall && offsets) {
     hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kScanBlock), 0, s, tiles, n, offsets, total);
     return hipGetLastError();
   }
@@ -595,7 +595,7 @@ hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)blocks), dim3(kScanBlock), 0, s, tiles,
                        n, partial);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, partial, blocks, total);
-  if (blocks > 0)
+  if (blocks > 0 && offsets)   // no offsets wanted: the total alone
     hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)blocks), dim3(kScanBlock), 0, s, tiles, n,
                        partial, offsets);
   return hipGetLastError();

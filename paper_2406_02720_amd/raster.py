@@ -122,14 +122,15 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
         params.filter3d = filter3d.data_ptr()
     records = _bytes(n_rec * B.HGS_RECORD_BYTES, dev)
     tiles = torch.empty(max(n_rec, 1), dtype=torch.int32, device=dev)
-    offsets = torch.empty(max(n_rec, 1), dtype=torch.int64, device=dev)
+    full = bool(opts.flags & B.HGS_FLAG_SORT_FULL_KEYS)
+    # per-record entry offsets: only the full-key sort reads them
+    offsets = torch.empty(max(n_rec, 1), dtype=torch.int64, device=dev) if full else None
     n_dup = torch.zeros(1, dtype=torch.int64, device=dev)
     ws = _bytes(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, cams, opts), dev)
     B.hgs_preprocess(params, cams, opts, records, tiles, offsets, n_dup, ws, stream)
     if capacity is None:
         capacity = int(n_dup.item())
     tiles_total = B.hgs_tiles_total(cams, opts)
-    full = bool(opts.flags & B.HGS_FLAG_SORT_FULL_KEYS)
     keys_t = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev) if (keys or full) else None
     values = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
     ranges = torch.empty(max(2 * tiles_total, 1), dtype=torch.int32, device=dev)
