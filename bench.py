@@ -179,7 +179,6 @@ def main():
     ws_r = buf(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts))
     rgrad = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
     dL = torch.empty(3 * npix, dtype=torch.float32, device=dev)
-    inv_numel = 1.0 / float(3 * npix)
 
     stage_names = ["preprocess", "bin_sort", "render_fwd", "loss_grad", "raster_bwd", "preprocess_bwd"]
 
@@ -196,9 +195,7 @@ def main():
         B.hgs_render_fwd(records, values, ranges, order, ca, opts, images, T_final, last_idx, n_contrib, ws_r,
                          stream)
         mark(3)
-        torch.sub(images, target, out=dL)
-        torch.sign(dL, out=dL)
-        dL.mul_(inv_numel)
+        B.hgs_l1_loss_grad(images, target, dL, stream)
         mark(4)
         # record gradients start cleared (hgs_preprocess_bwd clears them after use)
         B.hgs_raster_bwd(records, values, ranges, order, ca, opts, T_final, last_idx, dL, rgrad, ws_r, stream)
@@ -406,6 +403,7 @@ def multiview(args):
     import torch
 
     from paper_2406_02720_amd import batch as BT
+    from paper_2406_02720_amd import binding as B
     from paper_2406_02720_amd import raster as R
     from paper_2406_02720_amd import scenes
 
@@ -440,9 +438,7 @@ def multiview(args):
 
     def view_loss(t):
         def fn(images, dL):
-            torch.sub(images, t, out=dL)
-            torch.sign(dL, out=dL)
-            dL.mul_(inv)
+            B.hgs_l1_loss_grad(images, t, dL, torch.cuda.current_stream().cuda_stream, scale=inv)
         return fn
 
     views = [BT.BatchedRasterizer(soa, n, deg, [c], tile=tile, batch=batch) for c in cams]

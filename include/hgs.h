@@ -336,6 +336,16 @@ int hgs_mip_filter3d(const float* means, int64_t n, int64_t stride, const hgs_ca
  * pointers; n kernels, plane p of a field at ptr + p * stride.
  * ------------------------------------------------------------------------ */
 
+/* The photometric L1 term of the 3D-GS loss the paper trains with: the
+ * gradient of L = scale * sum |images - target| with respect to the
+ * images, dL_dimages[i] = scale * sign(images[i] - target[i]) (0 where
+ * equal), over n floats (packed images of any number of cameras); scale =
+ * 1/n gives the mean, 1/N one view's share of a mean over N values.  loss
+ * may be NULL; otherwise L is ADDED to *loss (device float, float atomics:
+ * clear it first).  HGS_EINVAL for n < 0 or a null array. */
+int hgs_l1_loss_grad(const float* images, const float* target, int64_t n, float scale, float* dL_dimages,
+                     float* loss, hipStream_t stream);
+
 /* Adam step constants.  lr_*: learning rate per group; beta1, beta2, eps;
  * step: the step number t >= 1 (bias corrections 1 - beta^t). */
 typedef struct hgs_adam_config {

@@ -146,13 +146,11 @@ class BatchedRasterizer:
 
 
 def l1_loss_grad(target):
-    """dL/dimages of the mean L1 loss against ``target`` (packed like images)."""
-    inv = 1.0 / float(target.numel())
+    """dL/dimages of the mean L1 loss against ``target`` (packed like
+    images), by the library's hgs_l1_loss_grad on the current stream."""
 
     def fn(images, dL):
-        torch.sub(images, target, out=dL)
-        torch.sign(dL, out=dL)
-        dL.mul_(inv)
+        B.hgs_l1_loss_grad(images, target, dL, torch.cuda.current_stream().cuda_stream)
     return fn
 
 

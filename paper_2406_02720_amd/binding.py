@@ -25,7 +25,7 @@ HGS_WS_PREPROCESS, HGS_WS_BIN_SORT, HGS_WS_RENDER = 0, 1, 2
 EXPORTS = ("hgs_default_options", "hgs_workspace_bytes", "hgs_tiles_total", "hgs_pixels_total",
            "hgs_preprocess", "hgs_bin_sort", "hgs_render_fwd", "hgs_render_bwd",
            "hgs_raster_bwd", "hgs_preprocess_bwd", "hgs_depth_normals", "hgs_mip_filter3d",
-           "hgs_adam_schedule", "hgs_adam_step",
+           "hgs_l1_loss_grad", "hgs_adam_schedule", "hgs_adam_step",
            "hgs_activate", "hgs_densify_stats", "hgs_densify_default", "hgs_densify_workspace_bytes",
            "hgs_densify", "hgs_reset_opacity", "hgs_strerror", "hgs_last_error")
 
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
     lib.hgs_preprocess_bwd.restype = C.c_int
     lib.hgs_mip_filter3d.argtypes = [vp, i64, i64, P(hgs_camera), i32, C.c_float, C.c_float, vp, vp, vp]
     lib.hgs_mip_filter3d.restype = C.c_int
+    lib.hgs_l1_loss_grad.argtypes = [vp, vp, i64, C.c_float, vp, vp, vp]
+    lib.hgs_l1_loss_grad.restype = C.c_int
     PG = P(hgs_param_grads)
     lib.hgs_adam_schedule.argtypes = [i32, C.c_float, C.c_float, P(hgs_adam_config)]
     lib.hgs_adam_schedule.restype = C.c_int
@@ -264,6 +266,12 @@ def hgs_preprocess_bwd(params, cams, opts, records, record_grads, grads, stream)
 def hgs_mip_filter3d(means, n, stride, cams, s, margin, filter3d, ws, stream):
     check(load().hgs_mip_filter3d(_ptr(means), n, stride, cams, len(cams), s, margin, _ptr(filter3d), _ptr(ws),
                                   stream))
+
+
+def hgs_l1_loss_grad(images, target, dL, stream, loss=None, scale=None):
+    n = images.numel()
+    s = 1.0 / max(n, 1) if scale is None else float(scale)
+    check(load().hgs_l1_loss_grad(_ptr(images), _ptr(target), n, s, _ptr(dL), _ptr(loss), stream))
 
 
 def hgs_adam_schedule(step: int, extent: float, normal_lr: float = 0.003) -> hgs_adam_config:

@@ -343,6 +343,16 @@ int hgs_mip_filter3d(const float* means, int64_t n, int64_t stride, const hgs_ca
   return HGS_OK;
 }
 
+int hgs_l1_loss_grad(const float* images, const float* target, int64_t n, float scale, float* dL_dimages,
+                     float* loss, hipStream_t stream) {
+  if (n < 0) return fail(HGS_EINVAL, "n must be >= 0");
+  if (n == 0) return HGS_OK;
+  if (!images || !target || !dL_dimages) return fail(HGS_EINVAL, "a pointer is null");
+  const hipError_t h = hgs::launch_l1_grad(images, target, n, scale, dL_dimages, loss, stream);
+  if (h != hipSuccess) return hip_fail(h, "l1 gradient launch");
+  return HGS_OK;
+}
+
 int hgs_adam_schedule(int32_t step, float extent, float normal_lr, hgs_adam_config* cfg) {
   if (!cfg) return fail(HGS_EINVAL, "cfg is null");
   if (step < 1) return fail(HGS_EINVAL, "step must be >= 1");

@@ -165,6 +165,8 @@ hipError_t launch_reset_opacity(const Grads& raw, const Grads& m, const Grads& v
                                 float cap, hipStream_t s);
 hipError_t launch_densify_stats(const Record* rec, const float* rgrad, const CamPack& cp, int64_t n, double kappa,
                                 float* accum, int32_t* count, float* max_radii, hipStream_t s);
+hipError_t launch_l1_grad(const float* img, const float* tgt, int64_t n, float scale, float* dL, float* loss,
+                          hipStream_t s);
 size_t densify_workspace_bytes(int64_t n);
 hipError_t launch_densify(const Grads& raw, const Grads& m, const Grads& v, int64_t n, int64_t stride,
                           int sh_degree, const DensifyPlan& dp, const float* accum, const int32_t* count,

@@ -286,6 +286,32 @@ __global__ __launch_bounds__(kBlock) void densify_write_kernel(
   }
 }
 
+// Gradient of scale * sum |img - target| with respect to the images:
+// scale * sign(img - target), and optionally the loss itself (block sums,
+// one float atomic per block).
+__global__ __launch_bounds__(kBlock) void l1_grad_kernel(const float* __restrict__ img,
+                                                         const float* __restrict__ tgt, int64_t n, float inv_n,
+                                                         float* __restrict__ dL, float* __restrict__ loss) {
+  __shared__ float s_sum[kBlock / 64];
+  float acc = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const float d = img[i] - tgt[i];
+    dL[i] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
+    acc += fabsf(d);
+  }
+  if (!loss) return;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < kBlock / 64; ++w) t += s_sum[w];
+    atomicAdd(loss, t * inv_n);
+  }
+}
+
 PlaneSets make_sets(const Grads& raw, const float* const* grad, const Grads& m, const Grads& v, const Grads& act) {
   PlaneSets ps{};
   float* const r[7] = {raw.means, raw.scales, raw.quats, raw.normals, raw.opac1, raw.opac2, raw.sh};
@@ -340,6 +366,14 @@ hipError_t launch_densify_stats(const Record* rec, const float* rgrad, const Cam
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(densify_stats_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, rec, rgrad, cp, n,
                      kappa, accum, count, max_radii);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_grad(const float* img, const float* tgt, int64_t n, float scale, float* dL, float* loss,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = blocks_for(n, 4 * kBlock) < 4096u ? blocks_for(n, 4 * kBlock) : 4096u;
+  hipLaunchKernelGGL(l1_grad_kernel, dim3(grid), dim3(kBlock), 0, s, img, tgt, n, scale, dL, loss);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@ import pytest
 import torch
 
 from paper_2406_02720_amd import batch as BT
+from paper_2406_02720_amd import binding as B
 from paper_2406_02720_amd import raster as R
 from paper_2406_02720_amd import scenes
 
@@ -95,9 +96,7 @@ def test_batched_views_equal_a_per_view_loop():
         t = target[off:off + npx]
 
         def lf(images, dL, t=t):
-            torch.sub(images, t, out=dL)
-            torch.sign(dL, out=dL)
-            dL.mul_(inv)
+            B.hgs_l1_loss_grad(images, t, dL, torch.cuda.current_stream().cuda_stream, scale=inv)
         v = BT.BatchedRasterizer(soa, n, deg, [cam])
         v.step(lf)
         torch.cuda.synchronize()

@@ -270,3 +270,23 @@ def test_train_state_steps_reduce_the_loss_and_densify():
     fr = R.forward_pass(state.raw, state.n, deg, cb, opts, params=state.params())
     torch.cuda.synchronize()
     assert torch.isfinite(fr.images).all()
+
+
+@pytest.mark.parametrize("n", [1, 1000, 3 * 97 * 61])
+def test_l1_loss_gradient_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    img = rng.random(n).astype(np.float32)
+    tgt = rng.random(n).astype(np.float32)
+    tgt[::7] = img[::7]                                   # equal values: zero gradient
+    it, tt = torch.from_numpy(img).cuda(), torch.from_numpy(tgt).cuda()
+    dL = torch.full((n,), 9.0, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    B.hgs_l1_loss_grad(it, tt, dL, torch.cuda.current_stream().cuda_stream, loss=loss)
+    torch.cuda.synchronize()
+    d = img.astype(np.float64) - tgt.astype(np.float64)
+    np.testing.assert_array_equal(dL.cpu().numpy(), (np.sign(d) * np.float32(1.0 / n)).astype(np.float32))
+    assert abs(float(loss.item()) - np.abs(d).mean()) <= 1e-5 * max(np.abs(d).mean(), 1e-30)
+    # a view's share of a larger mean
+    B.hgs_l1_loss_grad(it, tt, dL, torch.cuda.current_stream().cuda_stream, scale=0.25)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dL.cpu().numpy(), (np.sign(d) * 0.25).astype(np.float32))
