@@ -12,13 +12,18 @@
  *
  * Pipeline (each call only enqueues work on `stream`; nothing blocks):
  *   hgs_preprocess  projection, half factor, valid region, SH colour, depth,
- *                   tiles touched and their exclusive scan
+ *                   tiles touched, their total (and exclusive scan)
  *   hgs_bin_sort    one (tile | depth, record) entry per covered tile in
  *                   key order (depth sort of the records, then placement
  *                   by counting), per-tile ranges
  *   hgs_render_fwd  per-pixel front-to-back blending
  *   hgs_render_bwd  per-pixel back-to-front replay, per-record gradients,
  *                   chain rule to every kernel parameter
+ * Around it: blended depth (an hgs_render_fwd output) and depth-derived
+ * normals (hgs_depth_normals); the training step after the backward pass
+ * (hgs_l1_loss_grad, hgs_adam_step with hgs_adam_schedule, hgs_activate,
+ * hgs_densify_stats, hgs_densify, hgs_reset_opacity); the Mip-Splatting-HGS
+ * filters (hgs_params.filter3d from hgs_mip_filter3d, HGS_FLAG_MIP_2D).
  *
  * Conventions (the paper leaves them open):
  *   - camera axes x right, y down, z forward; pixel (i, j) has its centre at

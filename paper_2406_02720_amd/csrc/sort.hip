@@ -5,30 +5,31 @@
 // (depth, id) order.
 //
 // Default path ("placement").  Every entry of a record carries that
-// record's depth, so the depth order is established once, on the N records:
+// record's depth, so the depth order is established once, on the records:
 //
 //   1. depth keys of the records (+ their digit histograms), four one-sweep
-//      passes over the records -> record ids in (depth, id) order;
-//   2. the ordered records are cut into blocks of RB consecutive records and
-//      the tiles into bands of kBand consecutive tile ids.  For each (block,
-//      band) a wavefront counts how many of the block's records cover each
-//      tile of the band (two LDS increments per rect row into a difference
-//      array, then a prefix sum) -> counts[block][tile];
-//   3. per tile: total over blocks, exclusive scan over tiles -> the tile's
-//      first entry (its range), and per block the running offset, i.e. where
-//      the block's first entry for that tile goes;
-//   4. for each (block, band) a wavefront loads those offsets into LDS as
-//      cursors and walks the block's records in order; a record's covered
-//      tiles (one per lane) take their cursor's position and advance it.
-//      Records are walked one after another, so each tile's positions are
-//      handed out in (depth, id) order: the result is exactly the sorted
-//      entry list, and no entry key is ever written or sorted.
+//      passes -> record slots in (depth, id) order;
+//   2. per slot the record's tile rectangle and the bands it meets (a band:
+//      whole tile rows of one camera, >= kBandTiles tiles); one (band, slot)
+//      pair per band met, radix-sorted by band (stable, so each band's slots
+//      stay in depth order); each band's pairs are cut into items of
+//      kBlockPairs;
+//   3. per item, how many of its records cover each tile of the band (LDS
+//      difference arrays) -> counts[item][tile]; per tile the total over the
+//      items and its exclusive scan over tiles (the tile's range), and per
+//      item the position of its first entry of each tile;
+//   4. per item a workgroup places the entries: per-wavefront counts,
+//      cursors from scans across the wavefronts, each wavefront walks its
+//      records in order and takes each covered tile's next slot, so a tile's
+//      slots follow (depth, id) order; the slots live in an LDS staging area
+//      whose per-tile runs are then copied out in contiguous bursts.
 //
-// The entries cost one 4-byte write each (their record id) instead of a
-// duplication and ceil(tile bits / 8) sorting passes over 8-byte pairs.
-// With HGS_FLAG_SORT_FULL_KEYS the entries are instead duplicated with full
-// 64-bit keys in record order and sorted over all 32 + tile bits, the
-// literal form of the method's sort; both paths produce the same order.
+// The result is exactly the sorted entry list, at one 4-byte write per entry
+// (its record id) instead of a duplication and ceil(tile bits / 8) sorting
+// passes over 8-byte pairs.  With HGS_FLAG_SORT_FULL_KEYS the entries are
+// instead duplicated with full 64-bit keys in record order and sorted over
+// all 32 + tile bits, the literal form of the method's sort; both paths
+// produce the same order.
 //
 // One-sweep pass (Onesweep, Adinets & Merrill 2022): a block takes a
 // partition ticket (forward progress: earlier partitions belong to blocks
@@ -39,8 +40,10 @@
 // equal digits.  Histograms use the same ballot match so that a wavefront
 // adds each distinct digit once.
 //
-// The device-side entry count decides all work; launch grids are sized by
-// the caller's capacity and surplus blocks exit at once.
+// The device-side counts decide all work; grids are sized from bounds (the
+// caller's capacity, the pair bound) and the kernels whose true work can be
+// much smaller loop over it from a bounded grid (one-sweep partitions by
+// ticket, placement items by stride).
 
 #include "hgs_internal.h"
 
@@ -56,9 +59,11 @@ template <typename K>
 struct SweepItems {
   static constexpr int value = sizeof(K) == 4 ? 32 : 16;
 };
-// the record and tile-order sorts (a few million keys at most) use 2048-key
-// partitions so that their passes still spread over every CU
-constexpr int kSmallItems = 8;
+// the record, pair and tile-order sorts (a few million keys at most) use
+// 4096-key partitions: a million records make 245 of them, about one per
+// CU, and the look-back chains stay short (2048-key partitions measured
+// 25 us slower over the five passes of a step, 1024-key ones slower still)
+constexpr int kSmallItems = 16;
 constexpr int kPartMinEntries = kBlock * 16;          // smallest entry partition
 constexpr int kPartMinSmall = kBlock * kSmallItems;   // record / tile-order partition
 // Digit histograms are accumulated in kHistCopies replicas (block b adds to
