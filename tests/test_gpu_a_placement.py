@@ -41,3 +41,42 @@ def test_sorted_lists_match_oracle_without_raster(name, tile):
     np.testing.assert_array_equal(vals, bs["vals"])
     np.testing.assert_array_equal(keys, bs["keys"])
     np.testing.assert_array_equal(ranges, bs["ranges"])
+
+
+def _check(scene, cams, tile):
+    fr = gpu_forward(scene, cams, tile=tile, render=False)
+    pres = oracle_pre(scene, cams, tile=tile)
+    bs = O.bin_sort(pres)
+    keys, vals, ranges = sorted_entries(fr)
+    assert int(fr.overflow.item()) == 0
+    assert vals.size == bs["vals"].size
+    np.testing.assert_array_equal(vals, bs["vals"])
+    np.testing.assert_array_equal(keys, bs["keys"])
+    np.testing.assert_array_equal(ranges, bs["ranges"])
+    return vals.size
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_all_equal_depths_order_by_record_id(tile):
+    """Every kernel at the same camera depth: each list is in record id
+    order (the tie rule), across two cameras at the same distance."""
+    scene, _ = scenes.make_config(2, n=5000)
+    scene = dict(scene)
+    m = np.asarray(scene["means"], np.float32).copy()
+    m[:, 2] = np.float32(0.0)
+    scene["means"] = m
+    cams = [scenes.pinhole(160, 120, np.eye(3), (0.0, 0.0, 3.0)),
+            scenes.pinhole(96, 64, np.eye(3), (0.1, 0.0, 3.0))]
+    assert _check(scene, cams, tile) > 1000
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_single_tile_image_and_a_single_entry(tile):
+    scene, _ = scenes.make_config(2, n=3000)
+    cams = [scenes.pinhole(8, 8, np.eye(3), (0.0, 0.0, 3.0))]
+    assert _check(scene, cams, tile) > 0
+    one = scenes.subset(scene, np.array([0]))
+    one = dict(one)
+    one["means"] = np.zeros((1, 3), np.float32)
+    one["scales"] = np.full((1, 3), 0.002, np.float32)
+    assert _check(one, [scenes.pinhole(8, 8, np.eye(3), (0.0, 0.0, 3.0))], tile) == 1

@@ -545,3 +545,20 @@ def test_depth_normals_of_a_render_match_oracle():
     print(f"normals: {ok.sum()} pixels, err q50 {np.median(err):.2e} q99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
     assert np.quantile(err, 0.99) <= 1e-3
     assert err.max() <= 5e-2
+
+
+def test_white_kernels_on_black_image_is_one_minus_transmittance():
+    """All colours 1 and a black background: each channel is the total
+    blending weight, 1 - T_final (an identity of front-to-back
+    compositing)."""
+    scene, cams = CASES["cfg4_three_views"]
+    scene = dict(scene)
+    sh = np.zeros_like(np.asarray(scene["sh"], np.float32))
+    sh[:, 0, :] = np.float32(0.5 / 0.28209479177387814)     # 0.5 + Y00 c = 1
+    scene["sh"] = sh
+    fr = gpu_forward(scene, cams)
+    for c in range(len(cams)):
+        img = fr.image(c).cpu().numpy().astype(np.float64)
+        T = fr.per_pixel(fr.T_final, c).cpu().numpy().astype(np.float64)
+        assert np.abs(img - (1.0 - T)[None]).max() <= 1e-5
+        assert (T < 1.0).mean() > 0.2 and np.all((T >= 0.0) & (T <= 1.0))
