@@ -466,38 +466,43 @@ __device__ __forceinline__ void bwd_block(
           m &= lanes(!(a < amin));
           if (m == 0ull) continue;
           any = true;
-          const bool on = in_mask(m);
-          const float inv1ma = __builtin_amdgcn_rcpf(1.0f - a);  // 1 - a >= 1 - alpha_max
-          const float Tb = Tr[j] * inv1ma;
-          const float wcol = on ? a * Tb : 0.0f;
-          gs[9] += wcol * dL0[j];
-          gs[10] += wcol * dL1[j];
-          gs[11] += wcol * dL2[j];
-          // acc: colour of the entries behind this one (already replayed)
-          float dLda = ((r.r - acc0[j]) * dL0[j] + (r.g - acc1[j]) * dL1[j] + (r.b - acc2[j]) * dL2[j]) * Tb;
-          dLda = fmaf(inv1ma, tbg[j], dLda);
-          acc0[j] = on ? a * r.r + (1.0f - a) * acc0[j] : acc0[j];
-          acc1[j] = on ? a * r.g + (1.0f - a) * acc1[j] : acc1[j];
-          acc2[j] = on ? a * r.b + (1.0f - a) * acc2[j] : acc2[j];
-          Tr[j] = on ? Tb : Tr[j];
-          // no gradient through the alpha_max clamp
-          const float dHG = in_mask(m & lanes(!(HG > amax))) ? dLda : 0.0f;
-          const float dG = dHG * (r.alpha2 + r.d_o * I);
-          gs[7] += dHG * G;
-          gs[8] += dHG * I * G;
-          float du = 0.0f;
-          if (u.split) {
-            const float w = fmaf(r.ky, dy, col.kxdx);
-            du = dHG * r.d_o * G * kTwoOverSqrtPi * __builtin_amdgcn_exp2f(-kLog2e * w * w);
+          {
+            // gradient arithmetic only (every decision is taken above): the
+            // compiler may fuse multiply-adds here
+#pragma clang fp contract(fast)
+            const bool on = in_mask(m);
+            const float inv1ma = __builtin_amdgcn_rcpf(1.0f - a);  // 1 - a >= 1 - alpha_max
+            const float Tb = Tr[j] * inv1ma;
+            const float wcol = on ? a * Tb : 0.0f;
+            gs[9] += wcol * dL0[j];
+            gs[10] += wcol * dL1[j];
+            gs[11] += wcol * dL2[j];
+            // acc: colour of the entries behind this one (already replayed)
+            float dLda = ((r.r - acc0[j]) * dL0[j] + (r.g - acc1[j]) * dL1[j] + (r.b - acc2[j]) * dL2[j]) * Tb;
+            dLda = fmaf(inv1ma, tbg[j], dLda);
+            acc0[j] = on ? a * r.r + (1.0f - a) * acc0[j] : acc0[j];
+            acc1[j] = on ? a * r.g + (1.0f - a) * acc1[j] : acc1[j];
+            acc2[j] = on ? a * r.b + (1.0f - a) * acc2[j] : acc2[j];
+            Tr[j] = on ? Tb : Tr[j];
+            // no gradient through the alpha_max clamp
+            const float dHG = in_mask(m & lanes(!(HG > amax))) ? dLda : 0.0f;
+            const float dG = dHG * (r.alpha2 + r.d_o * I);
+            gs[7] += dHG * G;
+            gs[8] += dHG * I * G;
+            float du = 0.0f;
+            if (u.split) {
+              const float w = fmaf(r.ky, dy, col.kxdx);
+              du = dHG * r.d_o * G * kTwoOverSqrtPi * __builtin_amdgcn_exp2f(-kLog2e * w * w);
+            }
+            gs[5] += du * col.dx;
+            gs[6] += du * dy;
+            const float GG = dG * G;
+            gs[0] += GG * (col.qadx + r.qb * dy) - du * r.kx;
+            gs[1] += GG * (col.qbdx + r.qc * dy) - du * r.ky;
+            gs[2] += -0.5f * GG * col.dx * col.dx;
+            gs[3] += -GG * col.dx * dy;
+            gs[4] += -0.5f * GG * dy * dy;
           }
-          gs[5] += du * col.dx;
-          gs[6] += du * dy;
-          const float GG = dG * G;
-          gs[0] += GG * (col.qadx + r.qb * dy) - du * r.kx;
-          gs[1] += GG * (col.qbdx + r.qc * dy) - du * r.ky;
-          gs[2] += -0.5f * GG * col.dx * col.dx;
-          gs[3] += -GG * col.dx * dy;
-          gs[4] += -0.5f * GG * dy * dy;
         }
         if (!any) continue;
         float tot[3];

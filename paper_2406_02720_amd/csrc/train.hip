@@ -226,9 +226,14 @@ __device__ inline void rotation(float w, float x, float y, float z, float R[9]) 
 }
 
 // Writes the kept kernels, the clones and the children at their scanned
-// positions: [kept | clones | first children | second children].  New
-// kernels get zero moments; a child's centre is mean + R (scale * z), its
-// log-scales the parent's minus log(0.8 * 2).
+// positions: [kept | clones | first children | second children].  A thread
+// owns one kernel and a group of kWriteGroup planes (grid y is the group):
+// the flags and destinations are read once per group, the group's loads are
+// all issued before its stores, and every plane is read and written in
+// coalesced runs.  New kernels get zero moments; a child's centre is
+// mean + R (scale * z), its log-scales the parent's minus log(0.8 * 2).
+constexpr int kWriteGroup = 8;
+
 __global__ __launch_bounds__(kBlock) void densify_write_kernel(
     PlaneSets in, PlaneSets out, int64_t n, int64_t stride, int64_t stride_out, int planes, float shrink,
     const float* __restrict__ samples, const uint32_t* __restrict__ f_keep, const uint32_t* __restrict__ f_clone,
@@ -237,51 +242,79 @@ __global__ __launch_bounds__(kBlock) void densify_write_kernel(
     int64_t* __restrict__ n_out, int32_t* __restrict__ overflow) {
   const uint64_t nk = totals[0], nc = totals[1], nh = totals[2];
   const uint64_t total = nk + nc + 2 * nh;
+  const int p0 = (int)blockIdx.y * kWriteGroup;
+  const int np = planes - p0 < kWriteGroup ? planes - p0 : kWriteGroup;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i == 0) {
+  if (blockIdx.y == 0 && i == 0) {
     *n_out = (int64_t)total;
     *overflow = total > (uint64_t)capacity ? 1 : 0;
   }
   if (i >= n || total > (uint64_t)capacity) return;
   const bool keep = f_keep[i] != 0u, clone = f_clone[i] != 0u, child = f_child[i] != 0u;
   if (!keep && !clone && !child) return;
-  int64_t dst[4];
-  int nd = 0;
-  if (keep) dst[nd++] = (int64_t)o_keep[i];
-  if (clone) dst[nd++] = (int64_t)(nk + o_clone[i]);
-  const int first_child = nd;
-  if (child) {
-    dst[nd++] = (int64_t)(nk + nc + o_child[i]);
-    dst[nd++] = (int64_t)(nk + nc + nh + o_child[i]);
-  }
-  for (int p = 0; p < planes; ++p) {
-    int field, sub;
-    plane_of(p, &field, &sub);
-    const float x = in.raw[field][(int64_t)sub * stride + i];
-    const float mm = in.m[field][(int64_t)sub * stride + i];
-    const float vv = in.v[field][(int64_t)sub * stride + i];
-    for (int d = 0; d < nd; ++d) {
-      const int64_t o = (int64_t)sub * stride_out + dst[d];
-      const bool fresh = d > 0 || !keep;
-      out.raw[field][o] = (field == 1 && d >= first_child && child) ? x - shrink : x;
-      out.m[field][o] = fresh ? 0.0f : mm;
-      out.v[field][o] = fresh ? 0.0f : vv;
+  const int64_t dk = keep ? (int64_t)o_keep[i] : 0;
+  const int64_t dc = clone ? (int64_t)(nk + o_clone[i]) : 0;
+  const int64_t d0 = child ? (int64_t)(nk + nc + o_child[i]) : 0;
+  const int64_t d1 = d0 + (int64_t)nh;
+
+  float x[kWriteGroup], mm[kWriteGroup], vv[kWriteGroup];
+#pragma unroll
+  for (int k = 0; k < kWriteGroup; ++k) {
+    x[k] = mm[k] = vv[k] = 0.0f;
+    if (k < np) {
+      int field, sub;
+      plane_of(p0 + k, &field, &sub);
+      const int64_t io = (int64_t)sub * stride + i;
+      x[k] = in.raw[field][io];
+      if (keep) {
+        mm[k] = in.m[field][io];
+        vv[k] = in.v[field][io];
+      }
     }
   }
-  if (child) {
+  // the children's centre offsets R (scale * z); the means are planes 0..2,
+  // so only group 0 needs them
+  float dmu[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+  if (child && p0 == 0) {
     float R[9];
     rotation(in.raw[2][i], in.raw[2][stride + i], in.raw[2][2 * stride + i], in.raw[2][3 * stride + i], R);
-    float s[3], mu[3];
-    for (int a = 0; a < 3; ++a) {
-      s[a] = expf(in.raw[1][(int64_t)a * stride + i]);
-      mu[a] = in.raw[0][(int64_t)a * stride + i];
-    }
+    float sz[3];
     for (int c = 0; c < 2; ++c) {
-      float z[3];
-      for (int a = 0; a < 3; ++a) z[a] = samples[((int64_t)c * 3 + a) * n + i] * s[a];
-      const int64_t o = dst[first_child + c];
       for (int a = 0; a < 3; ++a)
-        out.raw[0][(int64_t)a * stride_out + o] = mu[a] + (R[3 * a] * z[0] + R[3 * a + 1] * z[1] + R[3 * a + 2] * z[2]);
+        sz[a] = samples[((int64_t)c * 3 + a) * n + i] * expf(in.raw[1][(int64_t)a * stride + i]);
+      for (int a = 0; a < 3; ++a) dmu[c][a] = R[3 * a] * sz[0] + R[3 * a + 1] * sz[1] + R[3 * a + 2] * sz[2];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kWriteGroup; ++k) {
+    if (k >= np) break;
+    int field, sub;
+    plane_of(p0 + k, &field, &sub);
+    const int64_t po = (int64_t)sub * stride_out;
+    if (keep) {
+      out.raw[field][po + dk] = x[k];
+      out.m[field][po + dk] = mm[k];
+      out.v[field][po + dk] = vv[k];
+    }
+    if (clone) {
+      out.raw[field][po + dc] = x[k];
+      out.m[field][po + dc] = 0.0f;
+      out.v[field][po + dc] = 0.0f;
+    }
+    if (child) {
+      float y0 = x[k], y1 = x[k];
+      if (field == 1) {
+        y0 = y1 = x[k] - shrink;
+      } else if (field == 0) {          // then p0 == 0 and sub == k
+        y0 = x[k] + dmu[0][k < 3 ? k : 0];
+        y1 = x[k] + dmu[1][k < 3 ? k : 0];
+      }
+      out.raw[field][po + d0] = y0;
+      out.m[field][po + d0] = 0.0f;
+      out.v[field][po + d0] = 0.0f;
+      out.raw[field][po + d1] = y1;
+      out.m[field][po + d1] = 0.0f;
+      out.v[field][po + d1] = 0.0f;
     }
   }
 }
@@ -408,9 +441,10 @@ hipError_t launch_densify(const Grads& raw, const Grads& m, const Grads& v, int6
     const hipError_t e = launch_scan(f[k], n, o[k], totals + k, scan_ws, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(densify_write_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, in, out, n, stride,
-                     stride_out, planes_of(sh_degree), dp.shrink, samples, f[0], f[1], f[2], o[0], o[1], o[2],
-                     totals, capacity, n_out, overflow);
+  const int planes = planes_of(sh_degree);
+  hipLaunchKernelGGL(densify_write_kernel, dim3(blocks_for(n, kBlock), (planes + kWriteGroup - 1) / kWriteGroup),
+                     dim3(kBlock), 0, s, in, out, n, stride, stride_out, planes, dp.shrink, samples, f[0], f[1], f[2],
+                     o[0], o[1], o[2], totals, capacity, n_out, overflow);
   return hipGetLastError();
 }
 
