@@ -98,6 +98,28 @@ def parse():
     return ap.parse_args()
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Read + write GB/s of a plain device-to-device copy (torch's copy of a
+    resident float32 buffer): the measured reference beside the 8 TB/s
+    specification for the HBM-bound stages."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def copy_probe(nbytes: int):
     """A plain device-to-device copy of known size: the reference for scaling
     the HBM byte counters of the rasterizer's kernels."""
@@ -262,13 +284,15 @@ def main():
     flops_fwd = pairs * F_EVAL + blended * F_BLEND
     flops_bwd = pairs * F_EVAL + blended * (F_BLEND + F_GRAD)
     roof = {}
+    copy_gbs = copy_bandwidth()
 
     def add(name, bound, amount):
         ms = float(st[name])
         if bound == "hbm":
             a = amount / (ms * 1e-3) / 1e9
             roof[name] = dict(bound="hbm", achieved=round(a, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                              frac=round(a / HBM_PEAK_GBS, 4), bytes=int(amount), ms=round(ms, 4))
+                              frac=round(a / HBM_PEAK_GBS, 4), frac_of_copy=round(a / copy_gbs, 4),
+                              bytes=int(amount), ms=round(ms, 4))
         else:
             a = amount / (ms * 1e-3) / 1e12
             roof[name] = dict(bound="alu", achieved=round(a, 2), peak=FP32_VECTOR_PEAK_TF, unit="TFLOP/s",
@@ -328,6 +352,7 @@ def main():
         "stage_ms": {k: round(float(v), 4) for k, v in st.items()},
         "roofline": roofline,
         "roofline_stages": roof,
+        "copy_GBps": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "multiview": multi,
     }
