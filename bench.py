@@ -25,6 +25,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector (256 CU x 2.4 GHz)
+# the same without packed FP32 (disabled in this build): one wave64 FP32
+# instruction per SIMD every 4 cycles, 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
+FP32_UNPACKED_PEAK_TF = 78.6
 
 WORKLOADS = {
     3: "1M half-Gaussians, 1920x1080, SH deg 3, fwd+bwd (shell+box mixture)",
@@ -296,7 +299,9 @@ def main():
         else:
             a = amount / (ms * 1e-3) / 1e12
             roof[name] = dict(bound="alu", achieved=round(a, 2), peak=FP32_VECTOR_PEAK_TF, unit="TFLOP/s",
-                              frac=round(a / FP32_VECTOR_PEAK_TF, 4), flops=float(amount), ms=round(ms, 4))
+                              frac=round(a / FP32_VECTOR_PEAK_TF, 4),
+                              frac_of_unpacked=round(a / FP32_UNPACKED_PEAK_TF, 4),
+                              flops=float(amount), ms=round(ms, 4))
     add("preprocess", "hbm", bytes_pre)
     add("bin_sort", "hbm", bytes_sort)
     add("render_fwd", "alu", flops_fwd)
