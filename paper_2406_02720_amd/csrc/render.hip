@@ -38,7 +38,7 @@ constexpr float kTwoOverSqrtPi = 1.12837916709551257390f;
 // clamped (erfc(3.9) = 3.5e-8).  erfc(-z) = 2 - erfc(z).  No reciprocal,
 // one exp2, ten fma; branch-free, result in [0, 2].
 __device__ __forceinline__ float erfc_fast(float x) {
-  const float z = fminf(fabsf(x), 3.9f);
+  const float z = __builtin_amdgcn_fmed3f(fabsf(x), 0.0f, 3.9f);   // min(|x|, 3.9), one instruction
   float p = -1.3359800732359872e-06f;
   p = fmaf(p, z, 2.5692050257930532e-05f);
   p = fmaf(p, z, -0.00021396989177446812f);
@@ -55,6 +55,13 @@ __device__ __forceinline__ float erfc_fast(float x) {
 }
 
 constexpr float kLog2e = 1.44269504088896340736f;
+
+// min(amax, HG) for HG >= 0 (alpha2 >= 0, alpha2 + d_o I lies between the two
+// opacities, G >= 0): the median of (HG, 0, amax) is the same value, in one
+// instruction instead of a canonicalising max and a min.
+__device__ __forceinline__ float clamp_alpha(float hg, float amax) {
+  return __builtin_amdgcn_fmed3f(hg, 0.0f, amax);
+}
 
 // Per-record values that do not depend on the lane (computed once per
 // wavefront): a bound below which no pair of the record can reach alpha_min
@@ -196,6 +203,18 @@ __device__ __forceinline__ int wave_max(int v) {
 // Uniform over the wavefront (the compiler cannot always prove it).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// A wave-uniform value copied once into a vector register, so that the
+// per-strip instructions that also read a scalar operand (one scalar source
+// per vector instruction) take it without a copy at every use.
+__device__ __forceinline__ float in_vgpr(float v) {
+  asm("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ int in_vgpr(int v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 // One wavefront's block of pixels (sub-block `wave` of `tile`), front to back.
 // Per record, everything that does not depend on the lane is decided once
 // for the wavefront on lane masks (rect against each strip, pixels still
@@ -264,6 +283,8 @@ __device__ __forceinline__ void fwd_block(
         const uint64_t cols = lanes(px >= x0) & lanes(px <= x1);
         if (cols == 0ull) continue;
         const int32_t pos = (int32_t)(base + k * 64 + l);
+        const int32_t posv = in_vgpr(pos);
+        const float a2v = in_vgpr(r.alpha2);
         const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
         bool ended = false;
@@ -281,7 +302,7 @@ __device__ __forceinline__ void fwd_block(
           m &= lanes(!(G * u.hb < amin));
           if (m == 0ull) continue;
           const float I = half_factor(r, u, col, dy, m, e39);
-          const float a = fminf(amax, fmaf(r.d_o, I, r.alpha2) * G);
+          const float a = clamp_alpha(fmaf(r.d_o, I, a2v) * G, amax);
           m &= lanes(!(a < amin));
           if (m == 0ull) continue;
           const float Tn = Tr[j] * (1.0f - a);
@@ -294,7 +315,7 @@ __device__ __forceinline__ void fwd_block(
           if constexpr (DEPTH) Dz[j] = fmaf(__uint_as_float(r.depth), w, Dz[j]);
           Tr[j] = take ? Tn : Tr[j];
           cnt[j] += take ? 1 : 0;
-          last[j] = take ? pos : last[j];
+          last[j] = take ? posv : last[j];
           open[j] &= ~stop;
           ended |= stop != 0ull;
         }
@@ -440,6 +461,8 @@ __device__ __forceinline__ void bwd_block(
         const uint64_t cols = lanes(px >= x0) & lanes(px <= x1);
         if (cols == 0ull) continue;
         const int32_t pos = hi - (k * 64 + l);
+        const float a2v = in_vgpr(r.alpha2);
+        const float cdu = r.d_o * kTwoOverSqrtPi;   // d(d_o I)/du = d_o 2/sqrt(pi) exp(-u^2)
         const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
         float gs[HGS_RECORD_GRAD_FLOATS];
@@ -461,8 +484,8 @@ __device__ __forceinline__ void bwd_block(
           m &= lanes(!(G * u.hb < amin));
           if (m == 0ull) continue;
           const float I = half_factor(r, u, col, dy, m, e39);
-          const float HG = fmaf(r.d_o, I, r.alpha2) * G;
-          const float a = fminf(amax, HG);
+          const float HG = fmaf(r.d_o, I, a2v) * G;
+          const float a = clamp_alpha(HG, amax);
           m &= lanes(!(a < amin));
           if (m == 0ull) continue;
           any = true;
@@ -486,19 +509,20 @@ __device__ __forceinline__ void bwd_block(
             Tr[j] = on ? Tb : Tr[j];
             // no gradient through the alpha_max clamp
             const float dHG = in_mask(m & lanes(!(HG > amax))) ? dLda : 0.0f;
-            const float dG = dHG * (r.alpha2 + r.d_o * I);
-            gs[7] += dHG * G;
-            gs[8] += dHG * I * G;
+            const float dG = dHG * (a2v + r.d_o * I);
+            const float dHGG = dHG * G;
+            gs[7] += dHGG;
+            gs[8] += dHGG * I;
             float du = 0.0f;
             if (u.split) {
               const float w = fmaf(r.ky, dy, col.kxdx);
-              du = dHG * r.d_o * G * kTwoOverSqrtPi * __builtin_amdgcn_exp2f(-kLog2e * w * w);
+              du = (dHGG * cdu) * __builtin_amdgcn_exp2f(-kLog2e * w * w);
             }
             gs[5] += du * col.dx;
             gs[6] += du * dy;
             const float GG = dG * G;
-            gs[0] += GG * (col.qadx + r.qb * dy) - du * r.kx;
-            gs[1] += GG * (col.qbdx + r.qc * dy) - du * r.ky;
+            gs[0] = fmaf(-du, r.kx, fmaf(GG, col.qadx + r.qb * dy, gs[0]));
+            gs[1] = fmaf(-du, r.ky, fmaf(GG, col.qbdx + r.qc * dy, gs[1]));
             gs[2] += -0.5f * GG * col.dx * col.dx;
             gs[3] += -GG * col.dx * dy;
             gs[4] += -0.5f * GG * dy * dy;
