@@ -344,6 +344,36 @@ __device__ __forceinline__ void fwd_block(
   }
 }
 
+// Tile of launch slot b in the per-tile backward grid, placed for the eight
+// XCDs (each with its own L2).  Workgroups go to the XCDs in turn, so slots
+// x + 32 m + 8 j (j < 4) all run on XCD x; they take positions
+// 4 (x + 8 m) + j of the tiles in block order (each camera's tiles by 2x2
+// blocks: block rows of two tile rows, blocks left to right, row-major inside
+// a block; a last odd row or column gives narrower blocks).  The tiles of a
+// block, which share most of their records, are thus read through one L2,
+// and consecutive blocks still spread over all XCDs.  Slots from 32 (n / 32)
+// on take their own position.  Both steps are bijections of [0, n).
+__device__ __forceinline__ uint32_t xcd_block_tile(uint32_t b, const CamPack& cp) {
+  const uint32_t full = cp.tiles_total / 32u * 32u;
+  const uint32_t p = b < full ? 4u * ((b % 8u) + 8u * (b / 32u)) + (b / 8u) % 4u : b;
+  const int c = cam_of_tile(cp, p);
+  const CamDev& cam = cp.cam[c];
+  const uint32_t tx = (uint32_t)cam.tiles_x, ty = (uint32_t)cam.tiles_y;
+  const uint32_t lp = p - cam.tile_off;
+  const uint32_t br = lp / (2u * tx), pr = lp - br * 2u * tx;   // block row, position in it
+  const uint32_t h = ty - 2u * br < 2u ? ty - 2u * br : 2u;      // its height (1 or 2)
+  const uint32_t bc = pr / (2u * h), in = pr - bc * 2u * h;      // block, position in it
+  uint32_t col, row;
+  if (2u * bc + 1u < tx) {           // two columns wide
+    col = 2u * bc + in % 2u;
+    row = 2u * br + in / 2u;
+  } else {                           // the last, one-column block
+    col = 2u * bc;
+    row = 2u * br + in;
+  }
+  return cam.tile_off + row * tx + col;
+}
+
 // Next tile rank of a persistent workgroup (all its wavefronts see it).
 __device__ __forceinline__ uint32_t next_tile(uint32_t* counter, uint32_t* s_w) {
   __syncthreads();   // every wavefront has read the previous rank
@@ -548,7 +578,7 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
     const uint32_t* __restrict__ ranges, CamPack cp, Opts o, const float* __restrict__ T_final,
     const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimg,
     float* __restrict__ rgrad) {
-  bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, blockIdx.x,
+  bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, xcd_block_tile(blockIdx.x, cp),
                     threadIdx.x >> 6, threadIdx.x & 63);
 }
 

@@ -174,19 +174,27 @@ def test_tile_order_is_longest_list_first():
     assert np.all(lo[1:] < np.maximum.accumulate(lo)[:-1] * (17 / 16) + 1e-9)
 
 
-def test_persistent_backward_equals_per_tile_backward():
+@pytest.mark.parametrize("tile", [16, 32, 8])
+def test_persistent_backward_equals_per_tile_backward(tile):
+    """Three views with odd tile counts (13x10, 9x6, 10x7 tiles at 16; 7x5,
+    5x3, 5x4 at 32): the per-tile backward grid, whose launch slots take the
+    tiles in XCD-grouped 2x2 block order, covers every tile once, like the
+    persistent one."""
     scene, cams = CASES["cfg4_three_views"]
-    a = gpu_forward(scene, cams, persistent=True)
-    b = gpu_forward(scene, cams, persistent=False)
+    a = gpu_forward(scene, cams, persistent=True, tile=tile)
+    b = gpu_forward(scene, cams, persistent=False, tile=tile)
     dl = torch.randn(a.images.numel(), device="cuda")
     ga, _ = R.backward_pass(a, dl)
     gb, _ = R.backward_pass(b, dl)
     torch.cuda.synchronize()
     # same per-entry sums; only the order of the float atomics differs
     # between the two schedules, so compare each parameter plane by norm
+    # (float32 sums of many signed terms per kernel: at 8-pixel tiles a
+    # kernel takes several times more atomics, and the scale planes, whose
+    # terms cancel, differ by ~1e-5 of their norm)
     diff = (ga - gb).norm(dim=1)
     scale = ga.norm(dim=1).clamp_min(1e-30)
-    assert float((diff / scale).max()) <= 1e-5
+    assert float((diff / scale).max()) <= 1e-4
 
 
 def test_flipped_normals_swap_halves():
