@@ -8,9 +8,10 @@
 // wavefront needs the same record at the same time, so the list is walked
 // with wave-uniform indices: a round fetches `batch` entry ids with one
 // vector load per lane, then each id is broadcast with v_readlane and its
-// 64-byte record is loaded as uniform (scalar) data, one entry ahead of its
-// use.  No LDS staging and no workgroup barriers: each wavefront stops as
-// soon as all of its pixels are done.
+// 64-byte record is loaded as uniform (scalar) data: the rect's columns
+// first, the rest only when they meet the wavefront's block.  No LDS
+// staging and no workgroup barriers: each wavefront stops as soon as all of
+// its pixels are done.
 //
 // Backward: each lane replays its pixels back to front from the last blended
 // entry, dividing the transmittance back out, and sums its pixels'
