@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector (256 CU x 2.4 GHz)
-# the same without packed FP32 (disabled in this build): one wave64 FP32
+# the same without packed FP32 (compiled with packed-fp32-ops off): one wave64 FP32
 # instruction per SIMD every 4 cycles, 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
 FP32_UNPACKED_PEAK_TF = 78.6
 
@@ -148,7 +148,7 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
               "(views would shard across GPUs with one gradient all-reduce; not built).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
