@@ -11,6 +11,7 @@ spherical harmonics, brute-force per-pixel lists, and central differences of
 the forward for the gradient.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -737,3 +738,23 @@ def test_mip_filter3d_hand_cases():
         g = O.mip_filter3d(pts, [c1], s=0.2, margin=0.15)
         np.testing.assert_allclose(g, [s / rate ** 2, s / (fx / 8.0) ** 2], rtol=1e-6)
     assert not O.mip_filter3d(np.array([[0.0, 0.0, -20.0]], np.float32), [c1]).any()
+
+
+def test_oracle_reproduces_golden_fixture():
+    """tests/golden/cfg1_oracle.json (written by tests/golden/make_golden.py
+    from the oracle alone) still matches what the oracle computes: a
+    regression guard on the oracle, not a pin to the paper (the paper prints
+    no worked example)."""
+    import importlib.util
+    import json
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(here, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    want = json.load(open(os.path.join(here, "cfg1_oracle.json")))
+    got = mg.compute()
+    for k in ("entries", "list_lengths", "pixels", "n_contrib"):
+        assert got[k] == want[k], k
+    for k in ("values", "T_final", "margin"):
+        np.testing.assert_allclose(np.asarray(got[k], np.float64), np.asarray(want[k], np.float64),
+                                   rtol=1e-12, atol=1e-15, err_msg=k)
