@@ -118,12 +118,18 @@ __device__ __forceinline__ void flush_hist(const uint32_t* s_h, int words, uint3
 }
 
 // ---------------------------------------------------------------------------
+// Clears the digit histograms and pass tickets, and (placement path) the
+// band ranges and tile totals, which are only written later in the call.
 __global__ __launch_bounds__(kBlock) void sort_init_kernel(uint32_t* __restrict__ hist,
-                                                           uint32_t* __restrict__ tickets) {
+                                                           uint32_t* __restrict__ tickets,
+                                                           uint32_t* __restrict__ brange, int64_t n_brange,
+                                                           uint32_t* __restrict__ totals, int64_t n_totals) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = t; i < (int64_t)kHistCopies * kHistWords; i += stride) hist[i] = 0u;
   for (int64_t i = t; i < 2 * kMaxPasses; i += stride) tickets[i] = 0u;
+  for (int64_t i = t; i < n_brange; i += stride) brange[i] = 0u;
+  for (int64_t i = t; i < n_totals; i += stride) totals[i] = 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void zero_u64_kernel(uint64_t* __restrict__ p, int64_t n) {
@@ -1276,8 +1282,11 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
   uint32_t* base_rec = w.bases;
   uint32_t* base_ent = w.bases + kMaxPasses * kRadix;
   int lb = 0;  // look-back buffer in use
-  hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(kHistCopies * kHistWords, kBlock, 4096)), dim3(kBlock),
-                     0, s, w.hist, w.tickets);
+  const int64_t n_brange = full_keys ? 0 : 2 * (int64_t)w.geom.n_bands;
+  const int64_t n_totals = full_keys ? 0 : (int64_t)cp.tiles_total;
+  const int64_t n_init = kHistCopies * kHistWords > n_totals ? kHistCopies * kHistWords : n_totals;
+  hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(n_init, kBlock, 4096)), dim3(kBlock), 0, s, w.hist,
+                     w.tickets, w.brange, n_brange, w.totals, n_totals);
   const unsigned dup_grid = grid_for((capacity + kChunk - 1) / kChunk, kWaves, 1 << 30);
 
   if (full_keys) {
@@ -1336,8 +1345,6 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     }
     const uint32_t* pkey = w.pkey[bpasses & 1];
     const uint32_t* pval = w.pval[bpasses & 1];
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(2 * g.n_bands, kBlock, 4096)), dim3(kBlock), 0, s,
-                       w.brange, 2 * g.n_bands, 0u);
     hipLaunchKernelGGL(place_band_ranges_kernel, dim3(grid_for(g.pairs_max, kBlock, 8192)), dim3(kBlock), 0, s,
                        pkey, (const uint64_t*)n_pairs, g.pairs_max, w.brange);
     hipLaunchKernelGGL(place_band_items_kernel, dim3(grid_for(g.n_bands, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
@@ -1358,7 +1365,6 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     const int64_t items_band = (n_per_cam + kBlockPairs - 1) / kBlockPairs;
     const int groups = (int)((items_band + kItemGroup - 1) / kItemGroup > 0 ? (items_band + kItemGroup - 1) / kItemGroup : 1);
     const unsigned scan_grid = (unsigned)(g.n_bands * chunks * groups);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nt, kBlock, 4096)), dim3(kBlock), 0, s, w.totals, nt, 0u);
     hipLaunchKernelGGL(place_group_sums_kernel, dim3(scan_grid), dim3(64), 0, s, (const uint32_t*)w.counts,
                        (const uint32_t*)w.nitems, (const uint64_t*)w.item0, cp, g.band_tiles, g.n_bands, chunks,
                        groups, w.gsum, w.totals);
