@@ -434,6 +434,27 @@ def test_non_finite_and_degenerate_parameters_are_culled_or_defined():
     assert f[3, 2] == 0.0 and f[3, 3] == 0.0
 
 
+def test_maximum_camera_count_matches_oracle():
+    """HGS_MAX_CAMERAS (32) views of uneven small sizes in one call: records,
+    sorted lists (global tile ids across all 32 views) and every pixel
+    against the oracle; one camera more is rejected."""
+    scene, cams = scenes.make_config(4, n=2000, n_cams=B.HGS_MAX_CAMERAS)
+    sizes = [(33 + 7 * (c % 5), 21 + 5 * (c % 7)) for c in range(len(cams))]
+    cams = [scenes.pinhole(w, h, c["R"], c["t"]) for c, (w, h) in zip(cams, sizes)]
+    print(f"[case] {len(cams)} cameras", flush=True)
+    fr = gpu_forward(scene, cams, tile=16)
+    pres = oracle_pre(scene, cams, tile=16)
+    _check_records(scene, cams, fr, pres)
+    bs = O.bin_sort(pres)
+    _, vals, ranges = sorted_entries(fr)
+    np.testing.assert_array_equal(vals, bs["vals"])
+    np.testing.assert_array_equal(ranges, bs["ranges"])
+    _check_render(scene, cams, fr, pres)
+    with pytest.raises(B.HGSError) as e:
+        gpu_forward(scene, cams + cams[:1], tile=16)
+    assert e.value.code == B.HGS_EINVAL
+
+
 def test_invalid_arguments_return_einval():
     scene, cams = scenes.make_config(1, n=10)
     with pytest.raises(B.HGSError) as e:
