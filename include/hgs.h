@@ -413,7 +413,11 @@ typedef struct hgs_densify_config {
                                 with the screen rule)                        */
 } hgs_densify_config;
 
+/* Fills cfg with the bracketed defaults above and the given extent (host
+ * only; a null cfg is ignored). */
 void hgs_densify_default(float extent, hgs_densify_config* cfg);
+/* Device workspace bytes hgs_densify needs for n input kernels (flags,
+ * their scans and the scan partials); 0 for n < 0.  Host only. */
 size_t hgs_densify_workspace_bytes(int64_t n);
 
 /* Clone, split and prune (3D-GS densification with the half-Gaussian
