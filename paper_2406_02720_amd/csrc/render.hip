@@ -89,8 +89,13 @@ __device__ __forceinline__ RecordU record_uniform(const Record& r, int x0, int y
 
 // Per-record values that a lane's pixels share (they lie in one column).
 // fpx = px + 1/2 is the pixel centre; fpx - x0 is exact in float.
+// p2 = log2(e) power is a quadratic in the row offset dy with per-column
+// coefficients, p2 = p2a + p2b dy + p2c dy^2 (p2a = -log2(e)/2 qa dx^2,
+// p2b = -log2(e) qb dx, p2c = -log2(e)/2 qc once per record), so a strip
+// evaluates it in two multiply-adds.
 struct Column {
   float dx, qadx, qbdx, kxdx;
+  float p2a, p2b;
 };
 
 __device__ __forceinline__ Column column_of(const Record& r, const RecordU& u, float fpx) {
@@ -99,6 +104,8 @@ __device__ __forceinline__ Column column_of(const Record& r, const RecordU& u, f
   c.qadx = r.qa * c.dx;
   c.qbdx = r.qb * c.dx;
   c.kxdx = r.kx * c.dx;
+  c.p2a = r.qa * ((c.dx * c.dx) * (-0.5f * kLog2e));
+  c.p2b = r.qb * (c.dx * -kLog2e);
   return c;
 }
 
@@ -108,8 +115,8 @@ __device__ __forceinline__ Column column_of(const Record& r, const RecordU& u, f
 // a mask; forward and backward evaluate the same expressions, so they take
 // identical decisions.
 //   1. rect: pixel centre in the record's rect (column and row masks).
-//   2. power = -q / 2 of the dilated conic, p2 = log2(e) power (so that
-//      G = exp2(p2)); power <= 0 and p2 >= p2_min.  A pair below p2_min has
+//   2. p2 = log2(e) power, power = -q / 2 of the dilated conic (so that
+//      G = exp2(p2)); p2 <= 0 and p2 >= p2_min.  A pair below p2_min has
 //      G * hb < alpha_min for the rounded G too (the 2^-10 margin covers the
 //      exp2 and log2 rounding), so it cannot reach alpha_min: the skip is
 //      exact.
@@ -120,9 +127,8 @@ __device__ __forceinline__ Column column_of(const Record& r, const RecordU& u, f
 __device__ __forceinline__ uint64_t lanes(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ __forceinline__ bool in_mask(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
-__device__ __forceinline__ float gauss_power(const Record& r, const Column& c, float dy) {
-  const float quad = fmaf(c.qadx, c.dx, (r.qc * dy) * dy);
-  return fmaf(-0.5f, quad, -(c.qbdx * dy));
+__device__ __forceinline__ float gauss_p2(const Column& c, float p2c, float dy) {
+  return fmaf(fmaf(p2c, dy, c.p2b), dy, c.p2a);
 }
 
 // I = erfc(x), x = -(k . offset).  When every lane of mask m has |x| >= 3.9
@@ -288,6 +294,7 @@ __device__ __forceinline__ void fwd_block(
         const float a2v = in_vgpr(r.alpha2);
         const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
+        const float p2c = r.qc * (-0.5f * kLog2e);
         bool ended = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
@@ -295,9 +302,8 @@ __device__ __forceinline__ void fwd_block(
           uint64_t m = open[j] & cols & lanes(fpy > u.y0f) & lanes(fpy < u.y1p);
           if (m == 0ull) continue;
           const float dy = (fpy - u.y0f) - r.my;
-          const float power = gauss_power(r, col, dy);
-          const float p2 = power * kLog2e;
-          m &= lanes(!(power > 0.0f)) & lanes(!(p2 < u.p2_min));
+          const float p2 = gauss_p2(col, p2c, dy);
+          m &= lanes(!(p2 > 0.0f)) & lanes(!(p2 < u.p2_min));
           if (m == 0ull) continue;
           const float G = __builtin_amdgcn_exp2f(p2);
           m &= lanes(!(G * u.hb < amin));
@@ -496,6 +502,7 @@ __device__ __forceinline__ void bwd_block(
         const float cdu = r.d_o * kTwoOverSqrtPi;   // d(d_o I)/du = d_o 2/sqrt(pi) exp(-u^2)
         const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
+        const float p2c = r.qc * (-0.5f * kLog2e);
         float gs[HGS_RECORD_GRAD_FLOATS];
 #pragma unroll
         for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q) gs[q] = 0.0f;
@@ -507,9 +514,8 @@ __device__ __forceinline__ void bwd_block(
           uint64_t m = cols & lanes(fpy > u.y0f) & lanes(fpy < u.y1p) & lanes(pos <= last[j]);
           if (m == 0ull) continue;
           const float dy = (fpy - u.y0f) - r.my;
-          const float power = gauss_power(r, col, dy);
-          const float p2 = power * kLog2e;
-          m &= lanes(!(power > 0.0f)) & lanes(!(p2 < u.p2_min));
+          const float p2 = gauss_p2(col, p2c, dy);
+          m &= lanes(!(p2 > 0.0f)) & lanes(!(p2 < u.p2_min));
           if (m == 0ull) continue;
           const float G = __builtin_amdgcn_exp2f(p2);
           m &= lanes(!(G * u.hb < amin));
