@@ -167,29 +167,32 @@ def sh_basis(d: torch.Tensor, degree: int) -> torch.Tensor:
 
 def splitting_covariance(Sigma_w: torch.Tensor, n_hat: torch.Tensor) -> torch.Tensor:
     """Alg. 1 (Supp. B.1): covariance of the flattened ellipsoid that stands
-    for the splitting plane.  The in-plane block is the Schur complement of
-    the covariance expressed in the plane basis (v1, v2, n), and the normal
-    variance is one hundredth of the smaller in-plane variance."""
-    nx, ny, nz = n_hat.unbind(-1)
-    special = (nx == 0) & (ny == 0)
+    for the splitting plane.  Within the plane it is the Gaussian's planar
+    cross-section: the covariance of the offset conditioned on a zero plane
+    value, S0 = Sigma - (Sigma n)(Sigma n)^T / (n^T Sigma n), which in Alg. 1's
+    plane basis (v1, v2, n) is the Schur complement (a', b', c') with a zero
+    row and column for n.  Along n it gets the thickness variance
+    min(a', c') / 100, a' and c' being S0's variances along v1 and v2:
+    S = S0 + (min(a', c') / 100) n n^T."""
+    Sn = (Sigma_w @ n_hat.unsqueeze(-1)).squeeze(-1)
+    v = (n_hat * Sn).sum(-1)
+    S0 = Sigma_w - Sn.unsqueeze(-1) * Sn.unsqueeze(-2) / v[..., None, None]
+    # the plane axes of Alg. 1: v1 = (ny, -nx, 0) / |.|, v2 = n x v1 / |.|;
+    # (e1, e2) for a normal along z
+    nx, ny, _ = n_hat.unbind(-1)
+    special = ((nx == 0) & (ny == 0)).unsqueeze(-1)
     e1 = torch.tensor([1.0, 0.0, 0.0], dtype=F64).expand_as(n_hat)
     e2 = torch.tensor([0.0, 1.0, 0.0], dtype=F64).expand_as(n_hat)
     v1 = torch.stack([ny, -nx, torch.zeros_like(nx)], -1)
-    v1n = torch.linalg.norm(v1, dim=-1, keepdim=True)
-    v1 = torch.where(special.unsqueeze(-1), e1, v1 / torch.where(v1n == 0, torch.ones_like(v1n), v1n))
+    v1 = torch.where(special, e1, v1 / torch.where(special, torch.ones_like(v1), torch.linalg.norm(v1, dim=-1,
+                                                                                                    keepdim=True)))
     v2 = torch.linalg.cross(n_hat, v1)
-    v2n = torch.linalg.norm(v2, dim=-1, keepdim=True)
-    v2 = torch.where(special.unsqueeze(-1), e2, v2 / torch.where(v2n == 0, torch.ones_like(v2n), v2n))
-    B = torch.stack([v1, v2, n_hat], -1)                      # columns
-    C = B.transpose(-1, -2) @ Sigma_w @ B
-    a_ = C[..., 0, 0] - C[..., 0, 2] ** 2 / C[..., 2, 2]
-    b_ = C[..., 0, 1] - C[..., 0, 2] * C[..., 1, 2] / C[..., 2, 2]
-    c_ = C[..., 1, 1] - C[..., 1, 2] ** 2 / C[..., 2, 2]
-    z = torch.zeros_like(a_)
-    S = torch.stack([torch.stack([a_, b_, z], -1),
-                     torch.stack([b_, c_, z], -1),
-                     torch.stack([z, z, torch.minimum(a_, c_) / 100.0], -1)], -2)
-    return B @ S @ B.transpose(-1, -2)
+    v2 = torch.where(special, e2, v2 / torch.where(special, torch.ones_like(v2), torch.linalg.norm(v2, dim=-1,
+                                                                                                    keepdim=True)))
+    a_ = (v1 * (S0 @ v1.unsqueeze(-1)).squeeze(-1)).sum(-1)
+    c_ = (v2 * (S0 @ v2.unsqueeze(-1)).squeeze(-1)).sum(-1)
+    thick = torch.minimum(a_, c_) / 100.0
+    return S0 + thick[..., None, None] * n_hat.unsqueeze(-1) * n_hat.unsqueeze(-2)
 
 
 def _geometry(sc: dict, cam: dict, o: dict, idx: torch.Tensor) -> dict:

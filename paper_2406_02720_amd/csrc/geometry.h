@@ -207,10 +207,24 @@ __device__ __forceinline__ void kernel_geo(const float* mu, const float* s, cons
 }
 
 // Alg. 1 (Supp. B.1): covariance of the flattened ellipsoid standing for the
-// splitting plane.  Plane basis (v1, v2, n); the in-plane block is the Schur
-// complement of the covariance in that basis; the normal variance is
-// min(a', c') / 100.
+// splitting plane.  In the plane it is the Gaussian's planar cross-section,
+// the covariance conditioned on a zero plane value,
+// S0 = Sigma - (Sigma n)(Sigma n)^T / (n^T Sigma n) -- in Alg. 1's basis
+// (v1, v2, n) the Schur complement with a zero row and column for n; along n
+// it gets the variance min(a', c') / 100, where a' and c' are S0's variances
+// along v1 and v2.  Sigma n and n^T Sigma n are the kernel's Sn and v.
 __device__ __forceinline__ Sym3 splitting_cov(const KernelGeo& k) {
+  const double iv = 1.0 / k.v;
+  const double* Sn = k.Sn;
+  Sym3 S;
+  S.xx = k.Sw.xx - Sn[0] * Sn[0] * iv;
+  S.xy = k.Sw.xy - Sn[0] * Sn[1] * iv;
+  S.xz = k.Sw.xz - Sn[0] * Sn[2] * iv;
+  S.yy = k.Sw.yy - Sn[1] * Sn[1] * iv;
+  S.yz = k.Sw.yz - Sn[1] * Sn[2] * iv;
+  S.zz = k.Sw.zz - Sn[2] * Sn[2] * iv;
+  // Alg. 1's plane axes: v1 = (ny, -nx, 0) / |.|, v2 = n x v1 / |.|, and
+  // (e1, e2) for a normal along z
   const double nx = k.nh[0], ny = k.nh[1], nz = k.nh[2];
   double v1[3], v2[3];
   if (nx == 0.0 && ny == 0.0) {
@@ -225,27 +239,13 @@ __device__ __forceinline__ Sym3 splitting_cov(const KernelGeo& k) {
     const double i2 = 1.0 / sqrt(c0 * c0 + c1 * c1 + c2 * c2);
     v2[0] = c0 * i2; v2[1] = c1 * i2; v2[2] = c2 * i2;
   }
-  // covariance in the basis (v1, v2, n)
-  const double C00 = sym_form(k.Sw, v1, v1), C01 = sym_form(k.Sw, v1, v2);
-  const double C02 = sym_form(k.Sw, v1, k.nh), C11 = sym_form(k.Sw, v2, v2);
-  const double C12 = sym_form(k.Sw, v2, k.nh), C22 = sym_form(k.Sw, k.nh, k.nh);
-  const double i22 = 1.0 / C22;
-  const double ap = C00 - C02 * C02 * i22;
-  const double bp = C01 - C02 * C12 * i22;
-  const double cp = C11 - C12 * C12 * i22;
-  const double dp = fmin(ap, cp) * 0.01;
-  // back to world: S = ap v1 v1^T + bp (v1 v2^T + v2 v1^T) + cp v2 v2^T + dp n n^T
-  Sym3 S;
-  const double* nh = k.nh;
-#define HGS_SPLIT_ENTRY(i, j) \
-  (ap * v1[i] * v1[j] + bp * (v1[i] * v2[j] + v2[i] * v1[j]) + cp * v2[i] * v2[j] + dp * nh[i] * nh[j])
-  S.xx = HGS_SPLIT_ENTRY(0, 0);
-  S.xy = HGS_SPLIT_ENTRY(0, 1);
-  S.xz = HGS_SPLIT_ENTRY(0, 2);
-  S.yy = HGS_SPLIT_ENTRY(1, 1);
-  S.yz = HGS_SPLIT_ENTRY(1, 2);
-  S.zz = HGS_SPLIT_ENTRY(2, 2);
-#undef HGS_SPLIT_ENTRY
+  const double t = fmin(sym_form(S, v1, v1), sym_form(S, v2, v2)) / 100.0;
+  S.xx += t * nx * nx;
+  S.xy += t * nx * ny;
+  S.xz += t * nx * nz;
+  S.yy += t * ny * ny;
+  S.yz += t * ny * nz;
+  S.zz += t * nz * nz;
   return S;
 }
 
