@@ -83,8 +83,9 @@ extern "C" {
                                     covariance (Mip-Splatting-HGS, Sec. 4)   */
 
 /* Pinhole camera.  R is the world->camera rotation (row-major 3x3), t the
- * translation (x_cam = R x_world + t).  fx, fy, cx, cy in pixels.  Kernels
- * with camera z <= znear are culled. */
+ * translation (x_cam = R x_world + t).  fx, fy, cx, cy in pixels (fx, fy
+ * positive and finite).  Kernels with camera z <= znear are culled; znear
+ * must be positive and finite (HGS_EINVAL otherwise). */
 typedef struct hgs_camera {
   float R[9];
   float t[3];
@@ -141,8 +142,10 @@ typedef struct hgs_param_grads {
 } hgs_param_grads;
 
 /* Rasterizer options; hgs_default_options() fills the defaults given in
- * brackets.  tile: tile edge in pixels, 8, 16 or 32 [16].  batch: records
- * staged in on-chip memory per round, 128, 256 or 512 [256].  Outputs do not
+ * brackets.  tile: tile edge in pixels, 8, 16 or 32 [16].  batch: how many
+ * entry ids of its tile list a raster wavefront fetches per round (batch / 64
+ * per lane, one vector load each; the records themselves are read as
+ * wave-uniform loads, not staged), 128, 256 or 512 [256].  Outputs do not
  * depend on tile or batch. */
 typedef struct hgs_options {
   int32_t tile;

@@ -58,8 +58,13 @@ int make_pack(const hgs_camera* cams, int32_t n_cams, const hgs_options* o, hgs:
     const hgs_camera& s = cams[c];
     if (s.width < 1 || s.height < 1 || s.width > HGS_MAX_IMAGE_SIDE || s.height > HGS_MAX_IMAGE_SIDE)
       return fail(HGS_EINVAL, "camera %d: image size %dx%d out of range", c, s.width, s.height);
-    if (!(s.fx > 0.0f) || !(s.fy > 0.0f))
-      return fail(HGS_EINVAL, "camera %d: focal lengths must be positive", c);
+    if (!(s.fx > 0.0f) || !(s.fy > 0.0f) || !isfinite(s.fx) || !isfinite(s.fy))
+      return fail(HGS_EINVAL, "camera %d: focal lengths must be positive and finite", c);
+    // a near plane at or behind the camera would let kernels with camera z
+    // in (znear, 0] through, projected mirrored and sorted after every
+    // positive depth
+    if (!(s.znear > 0.0f) || !isfinite(s.znear))
+      return fail(HGS_EINVAL, "camera %d: znear must be positive and finite (got %g)", c, (double)s.znear);
     hgs::CamDev& d = cp->cam[c];
     memcpy(d.R, s.R, sizeof(d.R));
     memcpy(d.t, s.t, sizeof(d.t));

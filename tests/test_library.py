@@ -75,6 +75,27 @@ def test_host_side_validation_and_sizes():
     assert lib.hgs_strerror(B.HGS_ECAPACITY) == b"buffer too small"
 
 
+@pytest.mark.skipif(not os.path.exists(B.LIB_PATH), reason="libhgs.so not built")
+def test_near_plane_must_be_positive_and_finite():
+    """A near plane at or behind the camera (or not a number) is rejected:
+    with znear < 0, kernels with camera z in (znear, 0) would pass the cull,
+    project mirrored, and their negative depth bits would sort after every
+    positive depth."""
+    o = B.default_options()
+    _, cams = scenes.make_config(1, n=10)
+    assert B.hgs_tiles_total(B.make_cameras(cams), o) == 64
+    lib = B.load()
+    p = B.hgs_params()
+    p.n, p.stride, p.sh_degree = 0, 0, 0
+    for zn in (0.0, -0.5, float("nan"), float("inf")):
+        bad = [dict(cams[0], znear=np.float32(zn))]
+        ca = B.make_cameras(bad)
+        assert B.hgs_tiles_total(ca, o) == -1, zn
+        assert B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, 10, ca, o, 100) == 0
+        rc = lib.hgs_preprocess(C.byref(p), ca, 1, C.byref(o), None, None, None, None, None, 0, None)
+        assert rc == B.HGS_EINVAL and b"znear" in lib.hgs_last_error(), zn
+
+
 def test_autotune_shape_class_is_stable():
     from paper_2406_02720_amd import batch
     _, cams = scenes.make_config(4, n=10, n_cams=3)
