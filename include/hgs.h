@@ -202,6 +202,23 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
                    uint64_t* offsets, uint64_t* n_dup, void* workspace, size_t workspace_bytes,
                    hipStream_t stream);
 
+/* hgs_preprocess for callers that cannot allocate device memory at all (code
+ * under HIP graph capture that must not add allocations, tight serving loops,
+ * harnesses that forbid hipMalloc): the same computation and outputs, with no
+ * workspace argument.  The entry-count scan keeps its partial sums in a
+ * device array inside the library (256 KiB per device, held from the first
+ * call on that device until the process ends), which limits n_cams * n to
+ * HGS_NOALLOC_MAX_RECORDS; larger calls return HGS_ECAPACITY before any work
+ * is enqueued.  Uses the array of the current device: `stream` must belong to
+ * it.  Every call on a device shares that device's array, so calls that
+ * overlap on one device (other streams, other threads) race: serialise them.
+ * Calls no hipMalloc, hipFree or allocating library routine.  Errors as
+ * hgs_preprocess, plus HGS_EHIP if the array's address cannot be obtained. */
+#define HGS_NOALLOC_MAX_RECORDS 134217728ll
+int hgs_preprocess_noalloc(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
+                           const hgs_options* opts, void* records, uint32_t* tiles_touched,
+                           uint64_t* offsets, uint64_t* n_dup, hipStream_t stream);
+
 /* The tile lists of the tile-based rasterizer (Sec. 3.1, built as in 3D-GS):
  * one (tile, record) entry per tile of every record's tile rectangle, in the
  * order of the key (global tile << 32 | fp32 depth bits), ties by record id,

@@ -21,9 +21,10 @@ HGS_FLAG_FULL_BOX = 1
 HGS_FLAG_SORT_FULL_KEYS = 2
 HGS_FLAG_MIP_2D = 4
 HGS_WS_PREPROCESS, HGS_WS_BIN_SORT, HGS_WS_RENDER = 0, 1, 2
+HGS_NOALLOC_MAX_RECORDS = 134217728
 
 EXPORTS = ("hgs_default_options", "hgs_workspace_bytes", "hgs_tiles_total", "hgs_pixels_total",
-           "hgs_preprocess", "hgs_bin_sort", "hgs_render_fwd", "hgs_render_bwd",
+           "hgs_preprocess", "hgs_preprocess_noalloc", "hgs_bin_sort", "hgs_render_fwd", "hgs_render_bwd",
            "hgs_raster_bwd", "hgs_preprocess_bwd", "hgs_depth_normals", "hgs_mip_filter3d",
            "hgs_l1_loss_grad", "hgs_adam_schedule", "hgs_adam_step",
            "hgs_activate", "hgs_densify_stats", "hgs_densify_default", "hgs_densify_workspace_bytes",
@@ -99,6 +100,9 @@ def load(path: str = LIB_PATH):
     lib.hgs_preprocess.argtypes = [P(hgs_params), P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp,
                                    vp, sz, vp]
     lib.hgs_preprocess.restype = C.c_int
+    lib.hgs_preprocess_noalloc.argtypes = [P(hgs_params), P(hgs_camera), i32, P(hgs_options), vp, vp, vp, vp,
+                                           vp]
+    lib.hgs_preprocess_noalloc.restype = C.c_int
     lib.hgs_bin_sort.argtypes = [vp, vp, vp, vp, i64, P(hgs_camera), i32, P(hgs_options), vp, vp, i64,
                                  vp, vp, vp, vp, sz, vp]
     lib.hgs_bin_sort.restype = C.c_int
@@ -222,6 +226,11 @@ def hgs_pixels_total(cams) -> int:
 def hgs_preprocess(params, cams, opts, records, tiles, offsets, n_dup, ws, stream):
     check(load().hgs_preprocess(C.byref(params), cams, len(cams), C.byref(opts), _ptr(records), _ptr(tiles),
                                 _ptr(offsets), _ptr(n_dup), _ptr(ws), ws.numel() * ws.element_size(), stream))
+
+
+def hgs_preprocess_noalloc(params, cams, opts, records, tiles, offsets, n_dup, stream):
+    check(load().hgs_preprocess_noalloc(C.byref(params), cams, len(cams), C.byref(opts), _ptr(records),
+                                        _ptr(tiles), _ptr(offsets), _ptr(n_dup), stream))
 
 
 def hgs_bin_sort(records, tiles, offsets, n_dup, n_rec, cams, opts, keys, values, capacity, ranges,

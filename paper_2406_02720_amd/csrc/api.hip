@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "hgs_internal.h"
 
 namespace {
@@ -133,6 +135,78 @@ int check_sizes(int64_t n, int64_t stride, int32_t sh_degree) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Device scratch of hgs_preprocess_noalloc: the entry-count scan's per-block
+// partial sums (one uint64 per 4096 records), for callers that cannot
+// allocate.  Each device holds its own copy of the array for the life of the
+// process.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address on the current device comes from
+// hipGetSymbolAddress, taken once per device and kept in g_scratch.  The
+// partials are overwritten by every call (nothing needs clearing), so two
+// calls in flight on one device at the same time race on them.
+constexpr size_t kNoAllocScratchBytes = 256 * 1024;
+constexpr int64_t kNoAllocMaxRecords =
+    (int64_t)(kNoAllocScratchBytes / sizeof(uint64_t)) * hgs::kScanRecordsPerPartial;
+static_assert(kNoAllocMaxRecords == HGS_NOALLOC_MAX_RECORDS, "hgs.h states the no-alloc limit");
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t h = hipGetDevice(&dev);
+  if (h != hipSuccess) return hip_fail(h, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(HGS_EINVAL, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    h = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (h != hipSuccess) return hip_fail(h, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(HGS_EHIP, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return HGS_OK;
+}
+
+// hgs_preprocess with the caller's workspace, or (no_alloc) the scratch array.
+int preprocess_impl(const hgs_params* params, const hgs_camera* cams, int32_t n_cams, const hgs_options* opts,
+                    void* records, uint32_t* tiles_touched, uint64_t* offsets, uint64_t* n_dup, void* workspace,
+                    size_t workspace_bytes, bool no_alloc, hipStream_t stream) {
+  int e;
+  if ((e = check_opts(opts)) != HGS_OK) return e;
+  hgs::Params p;
+  if ((e = make_params(params, &p)) != HGS_OK) return e;
+  hgs::CamPack cp;
+  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
+  const int64_t n_rec = p.n * n_cams;
+  if (!n_dup || (n_rec > 0 && (!records || !tiles_touched)))
+    return fail(HGS_EINVAL, "an output pointer is null");
+  const size_t need = hgs::scan_workspace_bytes(n_rec);
+  if (no_alloc) {
+    if (need > kNoAllocScratchBytes)
+      return fail(HGS_ECAPACITY, "n_cams * n = %lld records exceed the no-alloc limit of %lld",
+                  (long long)n_rec, (long long)kNoAllocMaxRecords);
+    if ((e = scratch_address(&workspace)) != HGS_OK) return e;
+    workspace_bytes = kNoAllocScratchBytes;
+  }
+  if (!workspace || workspace_bytes < need)
+    return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", need);
+  const hgs::Opts o = hgs::to_opts(*opts);
+  hipError_t h = hgs::launch_preprocess(p, cp, o, (hgs::Record*)records, tiles_touched, stream);
+  if (h != hipSuccess) return hip_fail(h, "preprocess launch");
+  h = hgs::launch_scan(tiles_touched, n_rec, offsets, n_dup, workspace, stream);
+  if (h != hipSuccess) return hip_fail(h, "scan launch");
+  return HGS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void hgs_default_options(hgs_options* o) {
@@ -187,23 +261,15 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
                    const hgs_options* opts, void* records, uint32_t* tiles_touched,
                    uint64_t* offsets, uint64_t* n_dup, void* workspace, size_t workspace_bytes,
                    hipStream_t stream) {
-  int e;
-  if ((e = check_opts(opts)) != HGS_OK) return e;
-  hgs::Params p;
-  if ((e = make_params(params, &p)) != HGS_OK) return e;
-  hgs::CamPack cp;
-  if ((e = make_pack(cams, n_cams, opts, &cp)) != HGS_OK) return e;
-  const int64_t n_rec = p.n * n_cams;
-  if (!n_dup || (n_rec > 0 && (!records || !tiles_touched)))
-    return fail(HGS_EINVAL, "an output pointer is null");
-  if (!workspace || workspace_bytes < hgs::scan_workspace_bytes(n_rec))
-    return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", hgs::scan_workspace_bytes(n_rec));
-  const hgs::Opts o = hgs::to_opts(*opts);
-  hipError_t h = hgs::launch_preprocess(p, cp, o, (hgs::Record*)records, tiles_touched, stream);
-  if (h != hipSuccess) return hip_fail(h, "preprocess launch");
-  h = hgs::launch_scan(tiles_touched, n_rec, offsets, n_dup, workspace, stream);
-  if (h != hipSuccess) return hip_fail(h, "scan launch");
-  return HGS_OK;
+  return preprocess_impl(params, cams, n_cams, opts, records, tiles_touched, offsets, n_dup, workspace,
+                         workspace_bytes, false, stream);
+}
+
+int hgs_preprocess_noalloc(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
+                           const hgs_options* opts, void* records, uint32_t* tiles_touched,
+                           uint64_t* offsets, uint64_t* n_dup, hipStream_t stream) {
+  return preprocess_impl(params, cams, n_cams, opts, records, tiles_touched, offsets, n_dup, nullptr, 0, true,
+                         stream);
 }
 
 int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint64_t* offsets,

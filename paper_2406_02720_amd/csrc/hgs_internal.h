@@ -129,6 +129,8 @@ __device__ inline int cam_of_tile(const CamPack& cp, uint32_t tile) {
 // ---------------------------------------------------------------------------
 hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, Record* rec,
                              uint32_t* tiles, hipStream_t s);
+// records per uint64 partial sum of the entry-count scan (its workspace)
+constexpr int64_t kScanRecordsPerPartial = 4096;
 size_t scan_workspace_bytes(int64_t n);
 hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint64_t* total,
                        void* ws, hipStream_t s);

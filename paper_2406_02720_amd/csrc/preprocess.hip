@@ -196,6 +196,7 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;
+static_assert(kScanTile == kScanRecordsPerPartial, "scan workspace: one partial per kScanTile records");
 
 __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
   const int lane = threadIdx.x & 63;

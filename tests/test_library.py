@@ -151,3 +151,24 @@ def test_adam_schedule_host_call_matches_oracle():
                                                                   np.float32(0.01))
     assert B.hgs_densify_workspace_bytes(1000) > 3 * 4 * 1000 + 3 * 8 * 1000
     assert B.hgs_densify_workspace_bytes(-1) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(B.LIB_PATH), reason="libhgs.so not built")
+def test_noalloc_preprocess_rejects_more_records_than_its_array_holds():
+    """hgs_preprocess_noalloc returns HGS_ECAPACITY for more records than its
+    device array serves, before it touches the GPU (the pointers below are
+    never dereferenced)."""
+    lib = B.load()
+    o = B.default_options()
+    _, cams = scenes.make_config(1, n=10)
+    ca = B.make_cameras(cams * 3)
+    p = B.hgs_params()
+    fake = 1 << 40
+    p.means = p.scales = p.quats = p.normals = p.opac1 = p.opac2 = p.sh = fake
+    p.n = B.HGS_NOALLOC_MAX_RECORDS // 3 + 1          # three views: one record over the limit
+    p.stride, p.sh_degree = p.n, 0
+    rc = lib.hgs_preprocess_noalloc(C.byref(p), ca, 3, C.byref(o), fake, fake, None, fake, None)
+    assert rc == B.HGS_ECAPACITY and b"no-alloc limit" in lib.hgs_last_error()
+    # null outputs are still EINVAL
+    rc = lib.hgs_preprocess_noalloc(C.byref(p), ca, 3, C.byref(o), None, None, None, fake, None)
+    assert rc == B.HGS_EINVAL
