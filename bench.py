@@ -90,14 +90,20 @@ def parse():
                          "tile, in tile order, which keeps neighbouring tiles' records together in the caches)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES, 5 times (counter calibration)")
-    ap.add_argument("--multiview", action="store_true",
-                    help="add the multi-view comparison (batched graph step against a per-view loop)")
+    ap.add_argument("--no-multiview", action="store_true",
+                    help="skip the multi-view comparison (batched graph step against a per-view loop, autotuned)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the efficient-rasterizer ablation, the equal-opacity run and the stress workload")
+    ap.add_argument("--no-stress", action="store_true", help="skip the 3M-kernel 8 x 4K stress workload")
     ap.add_argument("--multiview-steps", type=int, default=10)
     ap.add_argument("--train", action="store_true",
                     help="add the training step after the backward pass (Adam, densification statistics, "
                          "densify) on the same 1M kernels")
-    ap.add_argument("--autotune", metavar="JSON", default=None,
-                    help="autotune tile size and batch depth for the multi-view workload, caching in JSON")
+    ap.add_argument("--no-autograd", action="store_true",
+                    help="skip timing the torch.autograd path (Rasterizer forward + torch L1 loss + backward)")
+    ap.add_argument("--autotune", metavar="JSON", default="",
+                    help="autotune cache for the multi-view workload (JSON; default: tune every run, no cache)")
+    ap.add_argument("--no-autotune", action="store_true", help="multi-view at --tile / --batch, not autotuned")
     return ap.parse_args()
 
 
@@ -142,6 +148,210 @@ def copy_probe(nbytes: int):
                       "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
 
 
+class PipelineStep:
+    """One fwd + bwd step of the rasterizer over fixed buffers: hgs_preprocess,
+    hgs_bin_sort, hgs_render_fwd, the L1 loss gradient against a seeded
+    target, hgs_raster_bwd, hgs_preprocess_bwd, all on the current stream.
+    Inputs are resident on the device; the entry buffers are sized by one
+    untimed forward pass of this fixed scene."""
+
+    STAGES = ["preprocess", "bin_sort", "render_fwd", "loss_grad", "raster_bwd", "preprocess_bwd"]
+
+    def __init__(self, scene, cams, tile, batch, persistent, full_keys, dev, flags=0):
+        import torch
+
+        from paper_2406_02720_amd import binding as B
+        from paper_2406_02720_amd import raster as R
+        from paper_2406_02720_amd import scenes
+
+        self.B, self.torch = B, torch
+        n = scene["means"].shape[0]
+        deg = scene["sh_degree"]
+        self.n, self.deg, self.cameras = n, deg, cams
+        self.soa = R.scene_to_soa(scene, dev)
+        self.cams = ca = B.make_cameras(cams)
+        self.opts = opts = B.default_options(tile=tile, batch=batch, sort_full_keys=full_keys)
+        self.opts.flags |= flags
+        self.target = torch.cat([torch.as_tensor(t).reshape(-1) for t in scenes.target_image(cams, seed=102)]).to(dev)
+        # sizing pass (not timed): entry count of this fixed scene
+        fr = R.forward_pass(self.soa, n, deg, ca, opts, keys=False, render=False)
+        torch.cuda.synchronize()
+        self.n_dup = cap = int(fr.n_dup.item())
+        del fr
+        self.n_rec = n_rec = n * len(cams)
+        self.tiles_total = tiles_total = B.hgs_tiles_total(ca, opts)
+        npix = B.hgs_pixels_total(ca)
+
+        def buf(nbytes):
+            return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
+
+        self.params = B.params_struct(self.soa, n, n, deg)
+        self.grads = torch.zeros_like(self.soa)
+        self.gstruct = B.grads_struct(self.grads, n)
+        self.records = buf(n_rec * 64)
+        self.tiles = torch.empty(n_rec, dtype=torch.int32, device=dev)
+        self.offsets = torch.empty(n_rec, dtype=torch.int64, device=dev) if full_keys else None
+        self.ndup = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ws_pre = buf(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, ca, opts))
+        self.keys = torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if full_keys else None
+        self.values = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        self.cap = cap
+        self.ranges = torch.empty(2 * tiles_total, dtype=torch.int32, device=dev)
+        self.order = torch.empty(tiles_total, dtype=torch.int32, device=dev) if persistent else None
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws_sort = buf(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, ca, opts, cap))
+        self.images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+        self.T_final = torch.empty(npix, dtype=torch.float32, device=dev)
+        self.last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
+        self.n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+        self.ws_r = buf(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts))
+        self.rgrad = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
+        self.dL = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+        self.pixels = sum(c["width"] * c["height"] for c in cams)
+
+    def step(self, ev=None):
+        B = self.B
+        stream = self.torch.cuda.current_stream().cuda_stream
+        ca, opts = self.cams, self.opts
+
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        B.hgs_preprocess(self.params, ca, opts, self.records, self.tiles, self.offsets, self.ndup, self.ws_pre,
+                         stream)
+        mark(1)
+        B.hgs_bin_sort(self.records, self.tiles, self.offsets, self.ndup, self.n_rec, ca, opts, self.keys,
+                       self.values, self.cap, self.ranges, self.order, self.overflow, self.ws_sort, stream)
+        mark(2)
+        B.hgs_render_fwd(self.records, self.values, self.ranges, self.order, ca, opts, self.images, self.T_final,
+                         self.last_idx, self.n_contrib, self.ws_r, stream)
+        mark(3)
+        B.hgs_l1_loss_grad(self.images, self.target, self.dL, stream)
+        mark(4)
+        # record gradients start cleared (hgs_preprocess_bwd clears them after use)
+        B.hgs_raster_bwd(self.records, self.values, self.ranges, self.order, ca, opts, self.T_final,
+                         self.last_idx, self.dL, self.rgrad, self.ws_r, stream)
+        mark(5)
+        B.hgs_preprocess_bwd(self.params, ca, opts, self.records, self.rgrad, self.gstruct, stream)
+        mark(6)
+
+    def time(self, steps, warmup):
+        """(ms per whole step, {stage: ms}): whole steps back to back with
+        nothing else in the stream, then a separate run with events between
+        the stage calls."""
+        import numpy as np
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        assert int(self.overflow.item()) == 0
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            self.step()
+        t1.record()
+        torch.cuda.synchronize()
+        ms_step = t0.elapsed_time(t1) / steps
+        ns = len(self.STAGES)
+        stage_ms = np.zeros(ns)
+        for _ in range(steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)]
+            self.step(ev)
+            torch.cuda.synchronize()
+            for i in range(ns):
+                stage_ms[i] += ev[i].elapsed_time(ev[i + 1])
+        stage_ms /= steps
+        return ms_step, {k: float(v) for k, v in zip(self.STAGES, stage_ms)}
+
+    def pair_counts(self):
+        """Pairs the raster must evaluate (for every pixel, the entries of its
+        tile list up to its last blended one) and blended pairs."""
+        torch = self.torch
+        pairs = int((self.last_idx.to(torch.int64) + 1).sum().item())
+        blended = int(self.n_contrib.to(torch.int64).sum().item())
+        return pairs, blended
+
+    def summary(self, steps, warmup):
+        ms, st = self.time(steps, warmup)
+        fwd = st["preprocess"] + st["bin_sort"] + st["render_fwd"]
+        bwd = st["raster_bwd"] + st["preprocess_bwd"]
+        return {"entries": self.n_dup, "ms_per_step": round(ms, 4),
+                "Mpix_s": round(self.pixels / (ms * 1e-3) / 1e6, 2),
+                "fwd_bwd_over_fwd": round((fwd + bwd) / fwd, 3),
+                "stage_ms": {k: round(v, 4) for k, v in st.items()}}
+
+
+def extra_workloads(args, dev):
+    """The other measurements the method's workloads call for, each a
+    PipelineStep on its own scene (freed before the next):
+      - efficient_rasterizer: the 1M-kernel 1080p scene with one half of
+        half the kernels transparent, with the half-aware valid region
+        against both halves splatted with the full box (the paper's
+        rendering-speed ablation of its efficient rasterizer);
+      - equal_opacities: the headline scene with alpha2 := alpha1 (standard
+        Gaussians: the raster skips the half factor);
+      - stress: 3M kernels (5 % large splats) over 8 views at 3840x2160 in one
+        batched call per stage (persistent raster), per-stage times, and the
+        same through the autograd Rasterizer."""
+    import torch
+
+    from paper_2406_02720_amd import binding as B
+    from paper_2406_02720_amd import raster as R
+    from paper_2406_02720_amd import scenes
+
+    out = {}
+    scene, cams = scenes.make_config(3)
+    clear = scenes.with_transparent_halves(scene)
+    half = PipelineStep(clear, cams, args.tile, args.batch, args.persistent, False, dev)
+    a = half.summary(args.steps, args.warmup)
+    del half
+    full = PipelineStep(clear, cams, args.tile, args.batch, args.persistent, False, dev, flags=B.HGS_FLAG_FULL_BOX)
+    b = full.summary(args.steps, args.warmup)
+    del full
+    out["efficient_rasterizer"] = {
+        "workload": "1M half-Gaussians, 1920x1080, half of the kernels with one transparent half",
+        "half_aware": a, "full_box": b,
+        "speedup": round(b["ms_per_step"] / a["ms_per_step"], 3),
+        "entries_ratio": round(b["entries"] / max(a["entries"], 1), 3)}
+    eq = PipelineStep(scenes.with_equal_opacities(scene), cams, args.tile, args.batch, args.persistent, False, dev)
+    out["equal_opacities"] = dict(workload="1M Gaussians (alpha2 = alpha1), 1920x1080",
+                                  **eq.summary(args.steps, args.warmup))
+    del eq, scene, clear
+    torch.cuda.empty_cache()
+    if not args.no_stress:
+        scene, cams = scenes.make_config(5)
+        st = PipelineStep(scene, cams, args.tile, args.batch, True, False, dev)
+        k = max(3, args.steps // 4)
+        r = st.summary(k, 2)
+        planes = st.soa.clone().requires_grad_(True)
+        target = st.target
+        del st
+        torch.cuda.empty_cache()
+        rast = R.Rasterizer(cams, scene["sh_degree"], tile=args.tile, batch=args.batch, persistent=True)
+
+        def auto_step():
+            planes.grad = None
+            loss = (rast(planes) - target).abs().mean()
+            loss.backward()
+
+        auto_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            auto_step()
+        e1.record()
+        torch.cuda.synchronize()
+        r["autograd_ms_per_step"] = round(e0.elapsed_time(e1) / k, 4)
+        out["stress"] = dict(workload="3M half-Gaussians (5% large splats), 8 views of 3840x2160, persistent raster",
+                             views=len(cams), pixels=sum(c["width"] * c["height"] for c in cams), steps=k, **r)
+        del planes, rast, scene
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -164,97 +374,13 @@ def main():
     scene, cams = scenes.make_config(args.config)
     n = scene["means"].shape[0]
     deg = scene["sh_degree"]
-    soa = R.scene_to_soa(scene, dev)
-    ca = B.make_cameras(cams)
-    opts = B.default_options(tile=args.tile, batch=args.batch, sort_full_keys=args.full_keys)
-    targets = scenes.target_image(cams, seed=102)
-    target = torch.cat([torch.as_tensor(t).reshape(-1) for t in targets]).to(dev)
-
-    # sizing pass (not timed): entry count of this fixed scene
-    fr = R.forward_pass(soa, n, deg, ca, opts)
-    torch.cuda.synchronize()
-    n_dup = int(fr.n_dup.item())
-    cap = n_dup
-    n_rec = n * len(cams)
-    tiles_total = B.hgs_tiles_total(ca, opts)
-    npix = B.hgs_pixels_total(ca)
-    stream = torch.cuda.current_stream().cuda_stream
-
-    def buf(nbytes):
-        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
-
-    params = B.params_struct(soa, n, n, deg)
-    grads = torch.zeros_like(soa)
-    gstruct = B.grads_struct(grads, n)
-    records = buf(n_rec * 64)
-    tiles = torch.empty(n_rec, dtype=torch.int32, device=dev)
-    offsets = torch.empty(n_rec, dtype=torch.int64, device=dev) if args.full_keys else None
-    ndup = torch.zeros(1, dtype=torch.int64, device=dev)
-    ws_pre = buf(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, ca, opts))
-    keys = torch.empty(cap, dtype=torch.int64, device=dev) if args.full_keys else None
-    values = torch.empty(cap, dtype=torch.int32, device=dev)
-    ranges = torch.empty(2 * tiles_total, dtype=torch.int32, device=dev)
-    order = torch.empty(tiles_total, dtype=torch.int32, device=dev) if args.persistent else None
-    overflow = torch.zeros(1, dtype=torch.int32, device=dev)
-    ws_sort = buf(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, ca, opts, cap))
-    images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
-    T_final = torch.empty(npix, dtype=torch.float32, device=dev)
-    last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
-    n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
-    ws_r = buf(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts))
-    rgrad = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
-    dL = torch.empty(3 * npix, dtype=torch.float32, device=dev)
-
-    stage_names = ["preprocess", "bin_sort", "render_fwd", "loss_grad", "raster_bwd", "preprocess_bwd"]
-
-    def step(ev=None):
-        def mark(i):
-            if ev is not None:
-                ev[i].record()
-        mark(0)
-        B.hgs_preprocess(params, ca, opts, records, tiles, offsets, ndup, ws_pre, stream)
-        mark(1)
-        B.hgs_bin_sort(records, tiles, offsets, ndup, n_rec, ca, opts, keys, values, cap, ranges, order,
-                       overflow, ws_sort, stream)
-        mark(2)
-        B.hgs_render_fwd(records, values, ranges, order, ca, opts, images, T_final, last_idx, n_contrib, ws_r,
-                         stream)
-        mark(3)
-        B.hgs_l1_loss_grad(images, target, dL, stream)
-        mark(4)
-        # record gradients start cleared (hgs_preprocess_bwd clears them after use)
-        B.hgs_raster_bwd(records, values, ranges, order, ca, opts, T_final, last_idx, dL, rgrad, ws_r, stream)
-        mark(5)
-        B.hgs_preprocess_bwd(params, ca, opts, records, rgrad, gstruct, stream)
-        mark(6)
-
+    run = PipelineStep(scene, cams, args.tile, args.batch, args.persistent, args.full_keys, dev)
+    soa, target, ca, opts = run.soa, run.target, run.cams, run.opts
+    n_dup, n_rec, tiles_total = run.n_dup, run.n_rec, run.tiles_total
+    ms_step, st = run.time(args.steps, args.warmup)
+    stage_names = PipelineStep.STAGES
+    pairs, blended = run.pair_counts()
     ns = len(stage_names)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    assert int(overflow.item()) == 0
-
-    # whole-step timing, nothing else in the stream
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    ms_step = t0.elapsed_time(t1) / args.steps
-
-    # per-stage timing (separate run, events between the stage calls)
-    stage_ms = np.zeros(ns)
-    for _ in range(args.steps):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)]
-        step(ev)
-        torch.cuda.synchronize()
-        for i in range(ns):
-            stage_ms[i] += ev[i].elapsed_time(ev[i + 1])
-    stage_ms /= args.steps
-    st = dict(zip(stage_names, stage_ms))
 
     fwd_ms = st["preprocess"] + st["bin_sort"] + st["render_fwd"]
     bwd_ms = st["raster_bwd"] + st["preprocess_bwd"]
@@ -262,10 +388,6 @@ def main():
     value = W / (ms_step * 1e-3) / 1e6
 
     # ---- algorithmic work per stage
-    # pairs the raster must evaluate: for every pixel, the entries of its
-    # tile list up to its last blended one; blended pairs: n_contrib
-    pairs = int((last_idx.to(torch.int64) + 1).sum().item())
-    blended = int(n_contrib.to(torch.int64).sum().item())
     sh_floats = 3 * (deg + 1) ** 2
     param_bytes = 4 * (15 + sh_floats)
     tb = max(0, math.ceil(math.log2(max(tiles_total, 1))))
@@ -324,12 +446,16 @@ def main():
               file=sys.stderr)
         print(json.dumps(roof), file=sys.stderr)
 
-    multi = None
-    if args.multiview:
-        multi = multiview(args)
+    auto = None
+    if not args.no_autograd:
+        auto = autograd_bench(args, soa, deg, cams, target, ms_step)
     train = None
     if args.train:
-        train = train_bench(args, n, deg, records, rgrad, ca, opts, cams)
+        train = train_bench(args, n, deg, run.records, run.rgrad, ca, opts, cams)
+    del run, soa, target
+    torch.cuda.empty_cache()
+    multi = None if args.no_multiview else multiview(args)
+    extra = None if args.no_extra else extra_workloads(args, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -359,11 +485,48 @@ def main():
         "roofline_stages": roof,
         "copy_GBps": round(copy_gbs, 1),
         "cpu_baseline": cpu,
+        "autograd": auto,
         "multiview": multi,
+        "workloads": extra,
     }
     if train is not None:
         out["train"] = train
     print(json.dumps(out), flush=True)
+
+
+def autograd_bench(args, soa, deg, cams, target, ms_step):
+    """The same fwd + bwd through torch.autograd, as a training loop calls
+    it: a Rasterizer over the parameter planes (requires_grad), the L1 loss
+    written with torch operations, loss.backward().  Includes the
+    Rasterizer's end-of-forward overflow check (one small read-back) and
+    torch's loss kernels."""
+    import torch
+
+    from paper_2406_02720_amd import raster as R
+
+    planes = soa.clone().requires_grad_(True)
+    rast = R.Rasterizer(cams, deg, tile=args.tile, batch=args.batch, persistent=args.persistent)
+
+    def step():
+        planes.grad = None
+        img = rast(planes)
+        loss = (img - target).abs().mean()
+        loss.backward()
+
+    for _ in range(max(args.warmup, 2)):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    del planes
+    return {"ms_per_step": round(ms, 4), "over_native_step": round(ms / ms_step, 3),
+            "overflow_reruns": rast.overflows, "entry_capacity": rast.capacity,
+            "what": "Rasterizer(planes) + torch L1 loss + loss.backward(), same workload and launch configuration"}
 
 
 def train_bench(args, n, deg, records, rgrad, ca, opts, cams):
@@ -426,10 +589,12 @@ def train_bench(args, n, deg, records, rgrad, ca, opts, cams):
 
 def multiview(args):
     """500k half-Gaussians, SH degree 3, 16 orbit views of uneven size: the
-    whole fwd + loss + bwd step over all views as one HIP-graph replay
-    (persistent raster, one launch per stage) against a loop over the views
-    (one call chain per view, gradients summed over views), both eager and
-    with one captured graph per view.  Returns the timings and the ratio."""
+    whole fwd + loss + bwd step over all views as one HIP-graph replay (one
+    launch per stage, in the launch configuration the autotuner picks)
+    against a loop over the views (one call chain per view, gradients summed
+    over views), both eager and with one captured graph per view, in either
+    raster schedule (the faster is the baseline).  Returns the timings and
+    the ratios."""
     import torch
 
     from paper_2406_02720_amd import batch as BT
@@ -445,12 +610,15 @@ def multiview(args):
     tgt = [torch.as_tensor(t).reshape(-1).to(dev) for t in scenes.target_image(cams, seed=102)]
     target = torch.cat(tgt)
     W = sum(c["width"] * c["height"] for c in cams)
-    tile, batch, tuned = args.tile, args.batch, None
-    if args.autotune:
-        tile, batch, tuned = BT.autotune(soa, n, deg, cams, target, cache_path=args.autotune)
+    tile, batch, persistent, tuned, tune_s = args.tile, args.batch, True, None, None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tile, batch, persistent, tuned = BT.autotune(soa, n, deg, cams, target, cache_path=args.autotune or None)
+        tune_s = time.perf_counter() - t0
+        tuned = {k: round(v, 4) for k, v in tuned.items()}
     K = args.multiview_steps
 
-    br = BT.BatchedRasterizer(soa, n, deg, cams, tile=tile, batch=batch)
+    br = BT.BatchedRasterizer(soa, n, deg, cams, tile=tile, batch=batch, persistent=persistent)
     loss = BT.l1_loss_grad(target)
     br.capture(loss)
     assert not br.replay()
@@ -471,38 +639,47 @@ def multiview(args):
             B.hgs_l1_loss_grad(images, t, dL, torch.cuda.current_stream().cuda_stream, scale=inv)
         return fn
 
-    views = [BT.BatchedRasterizer(soa, n, deg, [c], tile=tile, batch=batch) for c in cams]
     losses = [view_loss(t) for t in tgt]
     total = torch.zeros_like(soa)
-
-    def loop_eager():
-        total.zero_()
-        for v, lf in zip(views, losses):
-            v.step(lf)
-            total.add_(v.grads)
-
-    ms_loop = BT.time_steps(loop_eager, K, 3)
-    img_loop = torch.cat([v.images for v in views])
-    img_diff = float((img_loop - img_batched).abs().max().item())
+    loop = {}
+    img_diff = grad_diff = 0.0
     gscale = float(grads_batched.abs().max().item())
-    grad_diff = float((total - grads_batched).abs().max().item()) / max(gscale, 1e-30)
-    for v, lf in zip(views, losses):
-        v.capture(lf)
+    # the loop in both raster schedules at the tuned tile size and batch
+    # depth; the faster one is the baseline
+    for sched in (True, False):
+        views = [BT.BatchedRasterizer(soa, n, deg, [c], tile=tile, batch=batch, persistent=sched) for c in cams]
 
-    def loop_graph():
-        total.zero_()
-        for v in views:
-            v.graph.replay()
-            total.add_(v.grads)
+        def loop_eager():
+            total.zero_()
+            for v, lf in zip(views, losses):
+                v.step(lf)
+                total.add_(v.grads)
 
-    ms_loop_graph = BT.time_steps(loop_graph, K, 3)
-    del views
-    torch.cuda.empty_cache()
+        ms_eager = BT.time_steps(loop_eager, K, 3)
+        img_loop = torch.cat([v.images for v in views])
+        img_diff = max(img_diff, float((img_loop - img_batched).abs().max().item()))
+        grad_diff = max(grad_diff, float((total - grads_batched).abs().max().item()) / max(gscale, 1e-30))
+        for v, lf in zip(views, losses):
+            v.capture(lf)
+
+        def loop_graph():
+            total.zero_()
+            for v in views:
+                v.graph.replay()
+                total.add_(v.grads)
+
+        ms_graph = BT.time_steps(loop_graph, K, 3)
+        loop["persistent" if sched else "per_tile"] = {"eager_ms": round(ms_eager, 4), "graph_ms": round(ms_graph, 4)}
+        del views, img_loop
+        torch.cuda.empty_cache()
+    ms_loop = min(v["eager_ms"] for v in loop.values())
+    ms_loop_graph = min(v["graph_ms"] for v in loop.values())
     return {
         "workload": "500k half-Gaussians, SH deg 3, 16 orbit views {640x480,1024x768,1297x840,1600x1064}",
-        "pixels": W, "tile": tile, "batch": batch, "autotune_ms": tuned,
+        "pixels": W, "tile": tile, "batch": batch, "raster": "persistent" if persistent else "per_tile",
+        "autotune_ms": tuned, "autotune_s": None if tune_s is None else round(tune_s, 2),
         "batched_graph_ms": round(ms_batched, 4), "batched_eager_ms": round(ms_batched_eager, 4),
-        "loop_eager_ms": round(ms_loop, 4), "loop_graph_ms": round(ms_loop_graph, 4),
+        "loop_eager_ms": round(ms_loop, 4), "loop_graph_ms": round(ms_loop_graph, 4), "loop_by_schedule": loop,
         "batched_Mpix_s": round(W / (ms_batched * 1e-3) / 1e6, 2),
         "speedup_vs_loop_eager": round(ms_loop / ms_batched, 3),
         "speedup_vs_loop_graph": round(ms_loop_graph / ms_batched, 3),

@@ -433,7 +433,11 @@ def _composite(recs: dict, cand: torch.Tensor, px: torch.Tensor, py: torch.Tenso
     depth-sorted records).  Returns colour [P,3], T_final [P], count [P],
     last position [P] (index into cand, -1 if none) and, per pixel, the
     smallest relative distance of each kind of decision to its threshold
-    [P,3]: alpha vs alpha_min, transmittance vs t_min, power vs 0."""
+    [P,5]: alpha vs alpha_min, transmittance vs t_min, power vs 0 (relative
+    to the sum of the absolute terms of the quadratic form), then the alpha
+    and transmittance distances again divided by those terms (for the
+    transmittance: by the running sum of alpha / (1 - alpha) times the terms
+    of the blended pairs)."""
     r = recs["rect"][cand]
     inside = ((px[:, None] >= r[None, :, 0]) & (px[:, None] <= r[None, :, 1]) &
               (py[:, None] >= r[None, :, 2]) & (py[:, None] <= r[None, :, 3]))
@@ -464,10 +468,20 @@ def _composite(recs: dict, cand: torch.Tensor, px: torch.Tensor, py: torch.Tenso
         rel_t = torch.where(contrib & before_or_at, (T_after - o["t_min"]).abs() / o["t_min"], inf)
         terms = 0.5 * (a_.abs() * dx * dx + c_.abs() * dy * dy) + cross.abs()
         rel_p = torch.where(inside, power.abs() / torch.clamp(terms, min=1e-300), inf)
+        # the same distances per unit of the error scale of a float32
+        # evaluation: the exponent's rounding error grows with the size of
+        # the terms of its quadratic form (they cancel to |power| when the
+        # offset is large and the kernel thin), and a relative error of alpha
+        # enters the transmittance weighted by alpha / (1 - alpha)
+        rel_a_terms = torch.where(evaluated, (alpha - o["alpha_min"]).abs() / (o["alpha_min"] * terms), inf)
+        scale_t = torch.cumsum(torch.where(contrib, a_c / (1.0 - a_c) * terms, torch.zeros_like(a_c)), dim=1)
+        rel_t_terms = torch.where(contrib & before_or_at, (T_after - o["t_min"]).abs() /
+                                  (o["t_min"] * torch.clamp(scale_t, min=1e-300)), inf)
         if cand.numel():
-            margin = torch.stack([rel_a.min(1).values, rel_t.min(1).values, rel_p.min(1).values], 1)
+            margin = torch.stack([rel_a.min(1).values, rel_t.min(1).values, rel_p.min(1).values,
+                                  rel_a_terms.min(1).values, rel_t_terms.min(1).values], 1)
         else:
-            margin = torch.full((px.shape[0], 3), math.inf, dtype=F64)
+            margin = torch.full((px.shape[0], 5), math.inf, dtype=F64)
         count = blend.sum(1)
         pos = torch.arange(cand.numel()).expand_as(blend)
         last = torch.where(blend, pos, torch.full_like(pos, -1)).max(1).values \

@@ -1,7 +1,7 @@
 """Multi-view training step of the half-Gaussian rasterizer: all views in one
 call per stage, the persistent tile scheduler, HIP-graph capture of the whole
-forward + loss + backward step, and an autotuner for tile size and batch
-depth.
+forward + loss + backward step, and an autotuner for the tile size, the
+raster schedule and the batch depth.
 
 Every view shares one preprocess launch (parameters read once), one sort (one
 global tile numbering) and one raster launch per direction.  A captured step
@@ -174,6 +174,7 @@ def time_steps(run, steps=10, warmup=3):
 # ---------------------------------------------------------------------------
 TILES = (8, 16, 32)
 BATCHES = (128, 256, 512)
+SCHEDULES = (True, False)      # persistent longest-first grid, one workgroup per tile
 
 
 def shape_class(n, cameras):
@@ -183,11 +184,19 @@ def shape_class(n, cameras):
     return f"n{2 ** round(math.log2(max(n, 1)))}_p{2 ** round(math.log2(max(pix, 1)))}_v{len(cameras)}"
 
 
+def _config_name(tile, batch, persistent):
+    return f"{tile}x{batch}{'p' if persistent else 'g'}"
+
+
 def autotune(soa, n, sh_degree, cameras, target, cache_path=None, steps=5, warmup=2, tiles=TILES,
-             batches=BATCHES):
-    """Time the graph-captured step for every (tile, batch) and return the
-    fastest as (tile, batch, {config: ms}); results are cached per shape
-    class in ``cache_path`` (JSON)."""
+             batches=BATCHES, schedules=SCHEDULES):
+    """Time the graph-captured step and pick the fastest launch
+    configuration: first every (tile size, raster schedule) at the default
+    batch depth, then every batch depth at the best of those (the batch depth
+    -- entry ids a raster wavefront fetches per round -- matters least).
+    Returns (tile, batch, persistent, {config: ms}), config names
+    "<tile>x<batch>p" (persistent grid) or "...g" (one workgroup per tile);
+    results are cached per shape class in ``cache_path`` (JSON)."""
     key = shape_class(n, cameras)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -195,19 +204,24 @@ def autotune(soa, n, sh_degree, cameras, target, cache_path=None, steps=5, warmu
             cache = json.load(f)
         if key in cache:
             e = cache[key]
-            return e["tile"], e["batch"], e["ms"]
+            return e["tile"], e["batch"], e["persistent"], e["ms"]
     loss = l1_loss_grad(target)
     ms = {}
-    for t in tiles:
-        for b in batches:
-            br = BatchedRasterizer(soa, n, sh_degree, cameras, tile=t, batch=b)
+
+    def run(t, b, p):
+        name = _config_name(t, b, p)
+        if name not in ms:
+            br = BatchedRasterizer(soa, n, sh_degree, cameras, tile=t, batch=b, persistent=p)
             br.capture(loss)
-            ms[f"{t}x{b}"] = time_steps(lambda: br.graph.replay(), steps, warmup)
+            ms[name] = time_steps(lambda: br.graph.replay(), steps, warmup)
             del br
-    best = min(ms, key=ms.get)
-    t, b = (int(x) for x in best.split("x"))
+        return ms[name]
+
+    b0 = 256 if 256 in batches else batches[0]
+    t, p = min(((t, p) for t in tiles for p in schedules), key=lambda tp: run(tp[0], b0, tp[1]))
+    b = min(batches, key=lambda bb: run(t, bb, p))
     if cache_path:
-        cache[key] = {"tile": t, "batch": b, "ms": ms}
+        cache[key] = {"tile": t, "batch": b, "persistent": p, "ms": ms}
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
-    return t, b, ms
+    return t, b, p, ms

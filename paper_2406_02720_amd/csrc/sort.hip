@@ -145,23 +145,44 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* __restrict__
 }
 
 // Sum of the replicas and exclusive scan of each pass's 256 digit counts
-// (one block, thread = digit); `hist` points at the passes of replica 0,
-// `bases` receives the scans.
-__global__ __launch_bounds__(kRadix) void hist_scan_kernel(const uint32_t* __restrict__ hist,
-                                                           uint32_t* __restrict__ bases, int passes) {
-  __shared__ uint32_t s[kRadix];
+// (one block of kHistScanThreads: each digit's replicas are summed by four
+// threads, 32 replicas each, then one thread per digit scans); `hist` points
+// at the passes of replica 0, `bases` receives the scans.
+constexpr int kHistScanThreads = 4 * kRadix;
+static_assert(kHistCopies % 4 == 0, "four threads per digit");
+
+__global__ __launch_bounds__(kHistScanThreads) void hist_scan_kernel(const uint32_t* __restrict__ hist,
+                                                                     uint32_t* __restrict__ bases, int passes) {
+  __shared__ uint32_t s_part[4][kRadix];
+  __shared__ uint32_t s_wave[kRadix / 64];
+  const int t = threadIdx.x, d = t & (kRadix - 1), q = t >> 8;
+  constexpr int kPer = kHistCopies / 4;
   for (int p = 0; p < passes; ++p) {
+    const uint32_t* h = hist + (size_t)q * kPer * kHistWords + p * kRadix + d;
     uint32_t v = 0;
-    for (int c = 0; c < kHistCopies; ++c) v += hist[c * kHistWords + p * kRadix + threadIdx.x];
-    s[threadIdx.x] = v;
+#pragma unroll 16
+    for (int c = 0; c < kPer; ++c) v += h[(size_t)c * kHistWords];
+    s_part[q][d] = v;
     __syncthreads();
-    for (int off = 1; off < kRadix; off <<= 1) {
-      const uint32_t add = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
-      __syncthreads();
-      s[threadIdx.x] += add;
-      __syncthreads();
+    // threads below kRadix (whole wavefronts) own a digit each
+    const int lane = t & 63, wv = t >> 6;
+    uint32_t x = 0, inc = 0;
+    if (t < kRadix) {
+      x = s_part[0][d] + s_part[1][d] + s_part[2][d] + s_part[3][d];
+      inc = x;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+      }
+      if (lane == 63) s_wave[wv] = inc;
     }
-    bases[p * kRadix + threadIdx.x] = s[threadIdx.x] - v;
+    __syncthreads();
+    if (t < kRadix) {
+      uint32_t pre = 0;
+      for (int w = 0; w < wv; ++w) pre += s_wave[w];
+      bases[p * kRadix + d] = pre + inc - x;
+    }
     __syncthreads();
   }
 }
@@ -1307,7 +1328,7 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     hipLaunchKernelGGL(duplicate_kernel<true>, dim3(dup_grid), dim3(kBlock), 0, s, rec, nullptr, tiles,
                        offsets, (const uint32_t*)w.chunk_start, n_dup, n_rec, n_per_cam, cp, (void*)kb[0],
                        vb[0], capacity, overflow, hist_ent + 4 * kRadix, 32, passes - 4);
-    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, passes);
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kHistScanThreads), 0, s, hist_ent, base_ent, passes);
     onesweep_passes<uint64_t, SweepItems<uint64_t>::value>(kb, vb, n_dup, capacity, 0, passes, base_ent, w,
                                                            w.tickets + kMaxPasses, lb, s);
     const int64_t nr = 2 * (int64_t)cp.tiles_total;
@@ -1319,7 +1340,7 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     // 1. records in (depth, id) order
     hipLaunchKernelGGL(depth_keys_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s, rec,
                        tiles, n_rec, w.rkeys[0], w.rids[0], hist_rec);
-    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec, base_rec, 4);
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kHistScanThreads), 0, s, hist_rec, base_rec, 4);
     if (n_rec > 0)
       onesweep_passes<uint32_t, kSmallItems>(w.rkeys, w.rids, nullptr, n_rec, 0, 4, base_rec, w, w.tickets,
                                              lb, s);
@@ -1339,7 +1360,7 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                        (const uint4*)w.desc, (const uint32_t*)w.nbands, (const uint64_t*)w.poff, n_rec,
                        g.pairs_max, cp, g.n_bands, w.pkey[0], w.pval[0], hist_ent, bpasses);
     if (bpasses > 0) {
-      hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_ent, base_ent, bpasses);
+      hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kHistScanThreads), 0, s, hist_ent, base_ent, bpasses);
       onesweep_passes<uint32_t, kSmallItems>(w.pkey, w.pval, n_pairs, g.pairs_max, 0, bpasses, base_ent, w,
                                              w.tickets + kMaxPasses, lb, s);
     }
@@ -1399,7 +1420,7 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     uint32_t* ov[2] = {w.oalt, tile_order};  // one pass: the order lands in tile_order
     hipLaunchKernelGGL(order_keys_kernel, dim3(grid_for(nt, kBlock, 1024)), dim3(kBlock), 0, s, ranges, nt,
                        ob[0], ov[0], hist_rec + 4 * kRadix);
-    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kRadix), 0, s, hist_rec + 4 * kRadix,
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kHistScanThreads), 0, s, hist_rec + 4 * kRadix,
                        base_rec + 4 * kRadix, 1);
     onesweep_passes<uint32_t, kSmallItems>(ob, ov, nullptr, nt, 0, 1, base_rec + 4 * kRadix, w, w.tickets + 4,
                                            lb, s);

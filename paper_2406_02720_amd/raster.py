@@ -9,6 +9,7 @@ Backward: hgs_render_bwd.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -191,40 +192,172 @@ def backward_pass(fr: Frame, dL_dimages: torch.Tensor, record_grads: torch.Tenso
     return grads, record_grads
 
 
-class HGSRasterize(torch.autograd.Function):
-    """Differentiable half-Gaussian rasterization of one or more views.
+class Rasterizer:
+    """Differentiable rasterization of fixed cameras with fixed options, the
+    parameters given as one float32 structure-of-arrays tensor of planes
+    ([means 3 | scales 3 | quats 4 | normals 3 | opac1 | opac2 | sh 3(D+1)^2]
+    x N, activated values; see ``soa_from_natural``).  Its gradient comes
+    back in the same layout, so no repacking happens on either pass.
 
-    Inputs are natural-layout CUDA tensors (activated values); returns the
-    packed images of all cameras (camera c's [3,H,W] image follows those of
-    cameras 0..c-1)."""
+    A call enqueues preprocess, sort and raster back to back: the sort runs
+    in capacity mode, with entry buffers sized from earlier calls with
+    ``headroom``.  The entry count is copied to pinned host memory right after
+    the preprocess, and the host waits for that copy only once sort and
+    raster are already queued behind it, so the device never idles for the
+    check; if the entries did not fit, the entry buffers grow and the sort and
+    raster are queued again.  Workspaces and the per-record gradient buffer
+    are kept between calls (every call leaves the latter cleared); the
+    per-call outputs and the state saved for the backward pass come from
+    torch's caching allocator (no device allocation after the first call of
+    a size)."""
+
+    def __init__(self, cameras, sh_degree: int, tile: int = 32, persistent: bool | None = None,
+                 headroom: float = 1.25, **options):
+        self.cameras = list(cameras)
+        self.cams = B.make_cameras(self.cameras)
+        self.opts = B.default_options(tile=tile, **options)
+        self.sh_degree = int(sh_degree)
+        # one view: one workgroup per tile in tile order (neighbouring tiles
+        # share records in the caches); several views: the persistent grid
+        self.persistent = len(self.cameras) > 1 if persistent is None else bool(persistent)
+        self.headroom = float(headroom)
+        self.capacity = 0
+        self._ws = {}
+        self._rgrad = None
+        self._count = None
+        self.tiles_total = B.hgs_tiles_total(self.cams, self.opts)
+        self.npix = B.hgs_pixels_total(self.cams)
+        self.overflows = 0          # re-runs after an entry overflow (for tests and logs)
+
+    def _workspace(self, which: str, nbytes: int, dev) -> torch.Tensor:
+        t = self._ws.get(which)
+        if t is None or t.numel() < nbytes or t.device != dev:
+            t = _bytes(nbytes, dev)
+            self._ws[which] = t
+        return t
+
+    def record_grads(self, n_rec: int, dev) -> torch.Tensor:
+        """The per-record gradient buffer, cleared (hgs_preprocess_bwd clears
+        it after every use, in stream order)."""
+        need = max(n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS
+        if self._rgrad is None or self._rgrad.numel() < need or self._rgrad.device != dev:
+            self._rgrad = torch.zeros(need, dtype=torch.float32, device=dev)
+        return self._rgrad
+
+    def forward_frame(self, planes: torch.Tensor) -> Frame:
+        n = planes.shape[1]
+        dev = planes.device
+        cams, opts = self.cams, self.opts
+        n_rec = n * len(self.cameras)
+        stream = _stream()
+        params = B.params_struct(planes, n, planes.shape[1], self.sh_degree)
+        records = _bytes(n_rec * B.HGS_RECORD_BYTES, dev)
+        tiles = torch.empty(max(n_rec, 1), dtype=torch.int32, device=dev)
+        n_dup = torch.empty(1, dtype=torch.int64, device=dev)
+        overflow = torch.empty(1, dtype=torch.int32, device=dev)
+        ws_pre = self._workspace("pre", B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, cams, opts), dev)
+        B.hgs_preprocess(params, cams, opts, records, tiles, None, n_dup, ws_pre, stream)
+        if self._count is None:
+            self._count = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        self._count.copy_(n_dup, non_blocking=True)
+        copied = torch.cuda.Event()
+        copied.record()
+        if self.capacity == 0:      # first call: size the entry buffers from this scene
+            copied.synchronize()
+            self.capacity = max(1, int(math.ceil(int(self._count.item()) * self.headroom)))
+        ranges = torch.empty(max(2 * self.tiles_total, 1), dtype=torch.int32, device=dev)
+        order = torch.empty(max(self.tiles_total, 1), dtype=torch.int32, device=dev) if self.persistent else None
+        images = torch.empty(3 * self.npix, dtype=torch.float32, device=dev)
+        T_final = torch.empty(self.npix, dtype=torch.float32, device=dev)
+        last_idx = torch.empty(self.npix, dtype=torch.int32, device=dev)
+        n_contrib = torch.empty(self.npix, dtype=torch.int32, device=dev)
+        ws_r = self._workspace("render", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), dev)
+        while True:
+            values = torch.empty(self.capacity, dtype=torch.int32, device=dev)
+            ws_sort = self._workspace("sort", B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, cams, opts,
+                                                                    self.capacity), dev)
+            B.hgs_bin_sort(records, tiles, None, n_dup, n_rec, cams, opts, None, values, self.capacity, ranges,
+                           order, overflow, ws_sort, stream)
+            B.hgs_render_fwd(records, values, ranges, order, cams, opts, images, T_final, last_idx, n_contrib,
+                             ws_r, stream)
+            copied.synchronize()        # the entry count, long before the raster ends
+            entries = int(self._count.item())
+            if entries <= self.capacity:
+                break
+            self.overflows += 1
+            self.capacity = int(math.ceil(entries * self.headroom))
+        return Frame(planes, n, self.sh_degree, cams, opts, records, tiles, None, n_dup, None, values, ranges,
+                     overflow, images, T_final, last_idx, n_contrib, self.capacity, ws_r, order, None, params)
+
+    def backward_frame(self, fr: Frame, d_images: torch.Tensor) -> torch.Tensor:
+        """Parameter gradients (plane layout) of a frame from this rasterizer."""
+        grads = torch.empty_like(fr.soa)      # hgs_preprocess_bwd overwrites every plane
+        rgrad = self.record_grads(fr.n * len(self.cameras), fr.soa.device)
+        st = _stream()
+        B.hgs_raster_bwd(fr.records, fr.values, fr.ranges, fr.tile_order, fr.cams, fr.opts, fr.T_final,
+                         fr.last_idx, d_images, rgrad, fr.ws_render, st)
+        B.hgs_preprocess_bwd(fr.params, fr.cams, fr.opts, fr.records, rgrad, B.grads_struct(grads, fr.soa.shape[1]),
+                             st)
+        return grads
+
+    def __call__(self, planes: torch.Tensor) -> torch.Tensor:
+        """Packed images of all cameras (camera c's [3,H,W] image follows
+        those of cameras 0..c-1), differentiable with respect to planes."""
+        return _RasterizePlanes.apply(planes, self)
+
+    def images(self, packed: torch.Tensor) -> list:
+        """[3,H,W] views of the packed images, one per camera."""
+        out, off = [], 0
+        for c in self.cameras:
+            w, h = int(c["width"]), int(c["height"])
+            out.append(packed[3 * off:3 * off + 3 * w * h].view(3, h, w))
+            off += w * h
+        return out
+
+
+class _RasterizePlanes(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, planes, rasterizer):
+        fr = rasterizer.forward_frame(planes.detach())
+        ctx.fr, ctx.rast = fr, rasterizer
+        return fr.images
 
     @staticmethod
-    def forward(ctx, means, scales, quats, normals, opac1, opac2, sh, cams, opts):
+    def backward(ctx, d_images):
+        grads = ctx.rast.backward_frame(ctx.fr, d_images.contiguous().to(torch.float32))
+        ctx.fr = None
+        return grads, None
+
+
+class HGSRasterize(torch.autograd.Function):
+    """Differentiable half-Gaussian rasterization of one or more views from
+    natural-layout CUDA tensors (activated values): packs them into planes
+    (one copy per call) and runs a ``Rasterizer``; the gradients are
+    unpacked back.  Training loops that keep their parameters as planes call
+    a ``Rasterizer`` directly and skip both copies."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, normals, opac1, opac2, sh, rasterizer):
         K = sh.shape[1]
-        deg = int(round(K ** 0.5)) - 1
         soa = soa_from_natural(means.detach(), scales.detach(), quats.detach(), normals.detach(),
                                opac1.detach(), opac2.detach(), sh.detach())
-        fr = forward_pass(soa, means.shape[0], deg, cams, opts)
-        ctx.fr = fr
+        fr = rasterizer.forward_frame(soa)
+        ctx.fr, ctx.rast = fr, rasterizer
         ctx.K = K
         return fr.images
 
     @staticmethod
     def backward(ctx, d_images):
-        grads, _ = backward_pass(ctx.fr, d_images.contiguous().to(torch.float32))
+        grads = ctx.rast.backward_frame(ctx.fr, d_images.contiguous().to(torch.float32))
+        ctx.fr = None
         m, s, q, nrm, o1, o2, sh = natural_from_soa(grads, ctx.K)
-        return m, s, q, nrm, o1, o2, sh, None, None
+        return m, s, q, nrm, o1, o2, sh, None
 
 
 def rasterize(means, scales, quats, normals, opac1, opac2, sh, cameras, **options):
     """Render ``cameras`` (list of camera dicts); returns a list of [3,H,W]
     images, differentiable with respect to every parameter."""
-    cams = B.make_cameras(cameras)
-    opts = B.default_options(**options)
-    packed = HGSRasterize.apply(means, scales, quats, normals, opac1, opac2, sh, cams, opts)
-    out, off = [], 0
-    for c in cameras:
-        w, h = int(c["width"]), int(c["height"])
-        out.append(packed[3 * off:3 * off + 3 * w * h].view(3, h, w))
-        off += w * h
-    return out
+    K = sh.shape[1]
+    rast = Rasterizer(cameras, int(round(K ** 0.5)) - 1, **options)
+    packed = HGSRasterize.apply(means, scales, quats, normals, opac1, opac2, sh, rast)
+    return rast.images(packed)

@@ -219,6 +219,23 @@ def sample_pixels(camera: dict, count: int, seed: int = 11):
     return np.stack([flat % w, flat // w], 1).astype(np.int64)
 
 
+def sample_pixel_blocks(camera: dict, blocks: int, side: int = 8, seed: int = 11):
+    """Seeded pixels of `blocks` distinct side x side squares of one camera
+    (squares on a grid of that pitch, clipped at the image border), each
+    square's pixels consecutive: a sample whose consecutive pixels share
+    their neighbourhood."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w, h = camera["width"], camera["height"]
+    gx, gy = (w + side - 1) // side, (h + side - 1) // side
+    picks = rng.choice(gx * gy, size=min(blocks, gx * gy), replace=False)
+    out = []
+    for b in picks:
+        x0, y0 = (b % gx) * side, (b // gx) * side
+        yy, xx = np.meshgrid(np.arange(y0, min(y0 + side, h)), np.arange(x0, min(x0 + side, w)), indexing="ij")
+        out.append(np.stack([xx.ravel(), yy.ravel()], 1))
+    return np.concatenate(out).astype(np.int64)
+
+
 def depth_maps(cameras, seed: int = 7):
     """Seeded blended-depth and transmittance maps, one [H,W] float32 pair
     per camera: a tilted wavy surface at depth ~3 seen through a random

@@ -68,13 +68,15 @@ def test_autotune_returns_a_valid_config_and_caches(tmp_path):
     scene, cams = _scene(n=2000, n_cams=2)
     soa = R.scene_to_soa(scene)
     path = tmp_path / "tune.json"
-    t, b, ms = BT.autotune(soa, 2000, scene["sh_degree"], cams, _target(cams), cache_path=str(path),
-                           steps=2, warmup=1, tiles=(8, 16), batches=(128, 256))
-    assert (t, b) in {(8, 128), (8, 256), (16, 128), (16, 256)}
-    assert ms[f"{t}x{b}"] == min(ms.values())
+    t, b, p, ms = BT.autotune(soa, 2000, scene["sh_degree"], cams, _target(cams), cache_path=str(path),
+                              steps=2, warmup=1, tiles=(8, 16), batches=(128, 256))
+    # (tile, schedule) at batch 256 first, then the other batch at the best
+    assert (t, b) in {(8, 128), (8, 256), (16, 128), (16, 256)} and p in (True, False)
+    assert len(ms) == 5
+    assert ms[f"{t}x{b}{'p' if p else 'g'}"] == min(ms.values())
     cache = json.loads(path.read_text())
     assert BT.shape_class(2000, cams) in cache
-    assert BT.autotune(soa, 2000, scene["sh_degree"], cams, None, cache_path=str(path))[:2] == (t, b)
+    assert BT.autotune(soa, 2000, scene["sh_degree"], cams, None, cache_path=str(path))[:3] == (t, b, p)
 
 
 def test_batched_views_equal_a_per_view_loop():

@@ -19,7 +19,8 @@ from paper_2406_02720_amd import binding as B
 from paper_2406_02720_amd import raster as R
 from paper_2406_02720_amd import scenes
 
-from hgs_testlib import ambiguous, gpu_forward, oracle_pre, records_np, sorted_entries, split_opts, u32
+from hgs_testlib import (ambiguous, check_gradients, gpu_forward, kernel_terms, oracle_pre, records_np,
+                         sorted_entries, split_opts, u32)
 
 pytestmark = pytest.mark.gpu
 
@@ -115,7 +116,8 @@ def _check_render(scene, cams, fr, pres, mode="rec"):
         tstart = starts[toff + ys * ((cam["width"] + T - 1) // T) + xs]
         last_id = np.where(last >= 0, vals[np.maximum(tstart + last, 0)].astype(np.int64) - c * n, -1)
         np.testing.assert_array_equal(last_id[ok], ref["last_id"].numpy()[ok])
-    assert flagged_total <= 0.02 * pix_total, (flagged_total, pix_total)
+    print(f"[flagged] {flagged_total}/{pix_total} = {flagged_total / max(pix_total, 1):.4%}", flush=True)
+    assert flagged_total < 0.01 * pix_total, (flagged_total, pix_total)
     return flagged_total, pix_total
 
 
@@ -240,7 +242,7 @@ def test_gpu_matches_golden_fixture():
     img = fr.image(0).cpu().numpy()[:, pix[:, 1], pix[:, 0]].T
     cnt = fr.per_pixel(fr.n_contrib, 0).cpu().numpy()[pix[:, 1], pix[:, 0]]
     ok = ~ambiguous(np.asarray(want["margin"]))
-    assert ok.mean() > 0.9
+    assert ok.mean() > 0.99
     assert np.abs(img - np.asarray(want["values"]))[ok].max() <= 1e-4
     np.testing.assert_array_equal(cnt[ok], np.asarray(want["n_contrib"])[ok])
 
@@ -296,13 +298,7 @@ def _grad_case(scene, cams, seed=5, **kw):
     ref = O.render_grad(scene, cams, dls, o)
     K = scene["sh"].shape[1]
     got = dict(zip(O.PARAM_KEYS, [t.cpu().numpy() for t in R.natural_from_soa(grads, K)]))
-    for k in O.PARAM_KEYS:
-        g, r = got[k].astype(np.float64).reshape(ref[k].shape), ref[k]
-        rel_l2 = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
-        assert rel_l2 <= 1e-3, (k, rel_l2)
-        tol = 1e-3 * np.abs(r) + 1e-5 * np.abs(r).max()
-        bad = np.abs(g - r) > tol
-        assert bad.mean() <= 1e-3, (k, bad.sum(), np.abs(g - r).max())
+    check_gradients(got, ref)
 
 
 def test_gradients_match_oracle_small():
@@ -378,6 +374,41 @@ def test_autograd_function_matches_backward_pass():
     ref = R.natural_from_soa(grads, scene["sh"].shape[1])
     for k, r in zip(("means", "scales", "quats", "normals", "opac1", "opac2", "sh"), ref):
         assert torch.allclose(t[k].grad, r.reshape(t[k].shape), rtol=1e-5, atol=1e-9), k
+
+
+def test_rasterizer_planes_match_the_pipeline_and_rerun_on_overflow():
+    """The autograd Rasterizer over a structure-of-arrays parameter tensor:
+    images bit-identical to the stage-by-stage pipeline, gradients (returned
+    in the same plane layout) equal to backward_pass up to the order of the
+    float atomics; a call whose entries overflow the capacity kept from the
+    previous call grows it and runs the sort and raster again."""
+    scene, cams = CASES["cfg4_three_views"]
+    n, K = scene["means"].shape[0], scene["sh"].shape[1]
+    soa = R.scene_to_soa(scene)
+    planes = soa.clone().requires_grad_(True)
+    rast = R.Rasterizer(cams, scene["sh_degree"], tile=16)
+    img = rast(planes)
+    fr = gpu_forward(scene, cams, tile=16)
+    assert torch.equal(img.detach(), fr.images)
+    dl = torch.randn_like(img)
+    img.backward(dl)
+    g_ref, _ = R.backward_pass(fr, dl)
+    torch.cuda.synchronize()
+
+    def same_grads(g):   # per plane, up to the float-atomic order
+        return float(((g - g_ref).norm(dim=1) / g_ref.norm(dim=1).clamp_min(1e-30)).max()) <= 1e-5
+
+    assert same_grads(planes.grad)
+    assert rast.overflows == 0
+    # a scene with more entries than the capacity sized on the first call
+    rast.capacity = max(1, int(fr.n_dup.item()) // 3)
+    planes.grad = None
+    img2 = rast(planes)
+    assert rast.overflows == 1 and rast.capacity >= int(fr.n_dup.item())
+    assert torch.equal(img2.detach(), fr.images)
+    img2.backward(dl)
+    torch.cuda.synchronize()
+    assert same_grads(planes.grad)
 
 
 # ---------------------------------------------------------------------------
@@ -505,7 +536,8 @@ def test_full_size_1080p_one_million_sampled(tile, persistent):
     img = fr.image(0).cpu().numpy()[:, pix[:, 1], pix[:, 0]].T
     cnt = fr.per_pixel(fr.n_contrib, 0).cpu().numpy()[pix[:, 1], pix[:, 0]]
     ok = ~ambiguous(ref["margin"])
-    assert ok.mean() > 0.9
+    print(f"[flagged-full] {int((~ok).sum())}/{ok.size}", flush=True)
+    assert ok.mean() > 0.99
     assert np.abs(img - ref["values"].numpy())[ok].max() <= 1e-4
     np.testing.assert_array_equal(cnt[ok], ref["n_contrib"].numpy()[ok])
 
@@ -524,7 +556,8 @@ def test_full_size_1080p_gradients_sampled():
     pre = oracle_pre(scene, cams, tile=32)[0]
     pix = scenes.sample_pixels(cam, 512, seed=21)
     amb = ambiguous(O.render(pre, "e2e", pixels=pix)["margin"])
-    assert amb.mean() < 0.05
+    print(f"[flagged-full-grad] {int(amb.sum())}/{amb.size}", flush=True)
+    assert amb.mean() < 0.01
     w = np.random.default_rng(4).normal(size=(pix.shape[0], 3))
     w[amb] = 0.0
     dl = np.zeros((3, cam["height"], cam["width"]), np.float32)
@@ -534,13 +567,7 @@ def test_full_size_1080p_gradients_sampled():
     ref = O.render_grad(scene, [cam], [w], O.options(tile=32), pixels=[pix])
     K = scene["sh"].shape[1]
     got = dict(zip(O.PARAM_KEYS, [t.cpu().numpy() for t in R.natural_from_soa(grads, K)]))
-    for k in O.PARAM_KEYS:
-        g, r = got[k].astype(np.float64).reshape(ref[k].shape), ref[k]
-        assert np.abs(r).max() > 0, k
-        rel_l2 = np.linalg.norm(g - r) / np.linalg.norm(r)
-        assert rel_l2 <= 1e-3, (k, rel_l2)
-        tol = 1e-3 * np.abs(r) + 1e-5 * np.abs(r).max()
-        assert (np.abs(g - r) > tol).mean() <= 1e-4, (k, np.abs(g - r).max())
+    check_gradients(got, ref, terms=kernel_terms(pre, pix), label="-1080p")
 
 
 @pytest.mark.slow
