@@ -205,9 +205,9 @@ int hgs_preprocess(const hgs_params* params, const hgs_camera* cams, int32_t n_c
 /* hgs_preprocess for callers that cannot allocate device memory at all (code
  * under HIP graph capture that must not add allocations, tight serving loops,
  * harnesses that forbid hipMalloc): the same computation and outputs, with no
- * workspace argument.  The entry-count scan keeps its partial sums in a
- * device array inside the library (256 KiB per device, held from the first
- * call on that device until the process ends), which limits n_cams * n to
+ * workspace argument.  The entry count keeps its partial sums in a device
+ * array inside the library (4 MiB per device, held from the first call on
+ * that device until the process ends), which limits n_cams * n to
  * HGS_NOALLOC_MAX_RECORDS; larger calls return HGS_ECAPACITY before any work
  * is enqueued.  Uses the array of the current device: `stream` must belong to
  * it.  Every call on a device shares that device's array, so calls that

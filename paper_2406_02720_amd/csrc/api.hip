@@ -138,17 +138,17 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 namespace {
 
 // ---------------------------------------------------------------------------
-// Device scratch of hgs_preprocess_noalloc: the entry-count scan's per-block
-// partial sums (one uint64 per 4096 records), for callers that cannot
-// allocate.  Each device holds its own copy of the array for the life of the
+// Device scratch of hgs_preprocess_noalloc: the partial sums of the entry
+// count (one uint64 per 256 kernels, or per 4096 records with offsets), for
+// callers that cannot allocate.  Each device holds its own copy of the array for the life of the
 // process.  In host code `scratch` names a host-side stand-in, not device
 // memory: its device address on the current device comes from
 // hipGetSymbolAddress, taken once per device and kept in g_scratch.  The
 // partials are overwritten by every call (nothing needs clearing), so two
 // calls in flight on one device at the same time race on them.
-constexpr size_t kNoAllocScratchBytes = 256 * 1024;
+constexpr size_t kNoAllocScratchBytes = 4 * 1024 * 1024;
 constexpr int64_t kNoAllocMaxRecords =
-    (int64_t)(kNoAllocScratchBytes / sizeof(uint64_t)) * hgs::kScanRecordsPerPartial;
+    (int64_t)(kNoAllocScratchBytes / sizeof(uint64_t)) * hgs::kPreprocessRecordsPerPartial;
 static_assert(kNoAllocMaxRecords == HGS_NOALLOC_MAX_RECORDS, "hgs.h states the no-alloc limit");
 static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
 
@@ -187,7 +187,7 @@ int preprocess_impl(const hgs_params* params, const hgs_camera* cams, int32_t n_
   const int64_t n_rec = p.n * n_cams;
   if (!n_dup || (n_rec > 0 && (!records || !tiles_touched)))
     return fail(HGS_EINVAL, "an output pointer is null");
-  const size_t need = hgs::scan_workspace_bytes(n_rec);
+  const size_t need = hgs::preprocess_workspace_bytes(n_rec);
   if (no_alloc) {
     if (need > kNoAllocScratchBytes)
       return fail(HGS_ECAPACITY, "n_cams * n = %lld records exceed the no-alloc limit of %lld",
@@ -198,10 +198,9 @@ int preprocess_impl(const hgs_params* params, const hgs_camera* cams, int32_t n_
   if (!workspace || workspace_bytes < need)
     return fail(HGS_ECAPACITY, "workspace too small: need %zu bytes", need);
   const hgs::Opts o = hgs::to_opts(*opts);
-  hipError_t h = hgs::launch_preprocess(p, cp, o, (hgs::Record*)records, tiles_touched, stream);
+  const hipError_t h = hgs::launch_preprocess(p, cp, o, (hgs::Record*)records, tiles_touched, offsets, n_dup,
+                                              workspace, stream);
   if (h != hipSuccess) return hip_fail(h, "preprocess launch");
-  h = hgs::launch_scan(tiles_touched, n_rec, offsets, n_dup, workspace, stream);
-  if (h != hipSuccess) return hip_fail(h, "scan launch");
   return HGS_OK;
 }
 
@@ -242,7 +241,7 @@ size_t hgs_workspace_bytes(int32_t which, int64_t n_rec, const hgs_camera* cams,
   if (n_rec < 0) return 0;
   switch (which) {
     case HGS_WS_PREPROCESS:
-      return hgs::scan_workspace_bytes(n_rec);
+      return hgs::preprocess_workspace_bytes(n_rec);
     case HGS_WS_BIN_SORT: {
       if (check_opts(opts) != HGS_OK || capacity < 0) return 0;
       hgs::CamPack cp;

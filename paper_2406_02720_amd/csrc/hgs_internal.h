@@ -127,11 +127,17 @@ __device__ inline int cam_of_tile(const CamPack& cp, uint32_t tile) {
 // ---------------------------------------------------------------------------
 // host-side launch helpers (defined in the .hip files)
 // ---------------------------------------------------------------------------
+// projection of every (camera, kernel) pair, then the entry total (and, with
+// offsets, the exclusive scan of the tiles touched)
 hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, Record* rec,
-                             uint32_t* tiles, hipStream_t s);
-// records per uint64 partial sum of the entry-count scan (its workspace)
+                             uint32_t* tiles, uint64_t* offsets, uint64_t* total, void* ws, hipStream_t s);
+// records per uint64 partial sum of the entry-count scan, and kernels per
+// partial of the projection's own total (the preprocess workspace holds
+// whichever is larger)
 constexpr int64_t kScanRecordsPerPartial = 4096;
+constexpr int64_t kPreprocessRecordsPerPartial = 256;
 size_t scan_workspace_bytes(int64_t n);
+size_t preprocess_workspace_bytes(int64_t n_rec);
 hipError_t launch_scan(const uint32_t* tiles, int64_t n, uint64_t* offsets, uint64_t* total,
                        void* ws, hipStream_t s);
 int tile_bits(uint32_t tiles_total);

@@ -16,6 +16,7 @@ namespace hgs {
 namespace {
 
 constexpr int kPreBlock = 256;
+static_assert(kPreBlock == kPreprocessRecordsPerPartial, "preprocess workspace: one partial per kPreBlock kernels");
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 
@@ -80,13 +81,13 @@ __device__ __forceinline__ int clamp_floor(double x, int hi) {
   return v > hi ? hi : v;
 }
 
+// The records of kernel i for every camera; returns the sum of their tiles.
 template <int D>
-__global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack cp, Opts o,
-                                                               Record* __restrict__ rec,
-                                                               uint32_t* __restrict__ tiles_out) {
+__device__ __forceinline__ uint64_t preprocess_one(const Params& p, const CamPack& cp, const Opts& o,
+                                                   Record* __restrict__ rec, uint32_t* __restrict__ tiles_out,
+                                                   int64_t i) {
   constexpr int K = (D + 1) * (D + 1);
-  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
-  if (i >= p.n) return;
+  uint64_t tiles_sum = 0;
   const int64_t S = p.stride;
   float mu[3], s[3], q[4], nrm[3];
   for (int c = 0; c < 3; ++c) {
@@ -187,6 +188,33 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
     const int64_t ri = (int64_t)c * p.n + i;
     rec[ri] = r;
     tiles_out[ri] = tiles;
+    tiles_sum += tiles;
+  }
+  return tiles_sum;
+}
+
+// One thread per kernel.  With block_tiles, each workgroup also stores the
+// sum of its records' tiles (the entry total is then the sum of these
+// partials: no second pass over tiles_out).
+template <int D>
+__global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack cp, Opts o,
+                                                               Record* __restrict__ rec,
+                                                               uint32_t* __restrict__ tiles_out,
+                                                               uint64_t* __restrict__ block_tiles) {
+  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  uint64_t mine = 0;
+  if (i < p.n) mine = preprocess_one<D>(p, cp, o, rec, tiles_out, i);
+  if (!block_tiles) return;
+  __shared__ uint64_t s_w[kPreBlock / 64];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, 64);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kPreBlock / 64; ++w) t += s_w[w];
+    block_tiles[blockIdx.x] = t;
   }
 }
 
@@ -567,16 +595,33 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
 }  // namespace
 
 hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, Record* rec,
-                             uint32_t* tiles, hipStream_t s) {
-  if (p.n == 0) return hipSuccess;
+                             uint32_t* tiles, uint64_t* offsets, uint64_t* total, void* ws, hipStream_t s) {
+  const int64_t n_rec = p.n * cp.n_cams;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
-  switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
-    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
-    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
-    default: hipLaunchKernelGGL(preprocess_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles); break;
+  // the total alone: summed from per-workgroup partials written by the
+  // projection itself; with offsets, the scan over the records
+  uint64_t* partial = offsets ? nullptr : (uint64_t*)ws;
+  if (p.n > 0) {
+    switch (p.sh_degree) {
+      case 0: hipLaunchKernelGGL(preprocess_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial); break;
+      case 1: hipLaunchKernelGGL(preprocess_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial); break;
+      case 2: hipLaunchKernelGGL(preprocess_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial); break;
+      default: hipLaunchKernelGGL(preprocess_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial); break;
+    }
   }
+  if (offsets) return launch_scan(tiles, n_rec, offsets, total, ws, s);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, partial, p.n > 0 ? (int64_t)grid : 0,
+                     total);
   return hipGetLastError();
+}
+
+size_t preprocess_workspace_bytes(int64_t n_rec) {
+  // the scan (with offsets), or one partial per kPreBlock kernels (at most
+  // one per kPreBlock records)
+  const size_t a = scan_workspace_bytes(n_rec);
+  const int64_t blocks = (n_rec + kPreBlock - 1) / kPreBlock;
+  const size_t b = (size_t)(blocks > 0 ? blocks : 1) * sizeof(uint64_t);
+  return a > b ? a : b;
 }
 
 size_t scan_workspace_bytes(int64_t n) {

@@ -445,7 +445,9 @@ __device__ __forceinline__ void bwd_block(
 
   int32_t last[PPL], top_j[PPL];
   float Tr[PPL], dL0[PPL], dL1[PPL], dL2[PPL];
-  float acc0[PPL], acc1[PPL], acc2[PPL], tbg[PPL];
+  // S: the colour of the entries behind the current one (already replayed),
+  // dotted with dL/dcolour -- the only way that colour enters dL/dalpha
+  float S[PPL], tbg[PPL];
   int top = -1;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
@@ -463,7 +465,7 @@ __device__ __forceinline__ void bwd_block(
       dL2[j] = g[2 * plane + pix];
     }
     Tr[j] = Tf;
-    acc0[j] = acc1[j] = acc2[j] = 0.0f;
+    S[j] = 0.0f;
     // the background seen through the final transmittance: its share of
     // dL/dalpha is -T_final / (1 - alpha) * (bg . dL)
     tbg[j] = -Tf * (o.bg[0] * dL0[j] + o.bg[1] * dL1[j] + o.bg[2] * dL2[j]);
@@ -503,9 +505,11 @@ __device__ __forceinline__ void bwd_block(
         const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
         const Column col = column_of(r, u, fpx);
         const float p2c = r.qc * (-0.5f * kLog2e);
-        float gs[HGS_RECORD_GRAD_FLOATS];
-#pragma unroll
-        for (int q = 0; q < HGS_RECORD_GRAD_FLOATS; ++q) gs[q] = 0.0f;
+        // per-lane sums over the lane's pixels: the centre, conic and
+        // half-factor gradients are linear in them (the lane's pixels share
+        // the column offset dx), so they are formed once per entry below
+        float sGG = 0.0f, sT = 0.0f, sT2 = 0.0f, sDu = 0.0f, sDuDy = 0.0f;   // sums of GG, GG dy, GG dy^2, du, du dy
+        float g7 = 0.0f, g8 = 0.0f, g9 = 0.0f, g10 = 0.0f, g11 = 0.0f;
         bool any = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
@@ -521,7 +525,8 @@ __device__ __forceinline__ void bwd_block(
           m &= lanes(!(G * u.hb < amin));
           if (m == 0ull) continue;
           const float I = half_factor(r, u, col, dy, m, e39);
-          const float HG = fmaf(r.d_o, I, a2v) * G;
+          const float hgf = fmaf(r.d_o, I, a2v);
+          const float HG = hgf * G;
           const float a = clamp_alpha(HG, amax);
           m &= lanes(!(a < amin));
           if (m == 0ull) continue;
@@ -533,39 +538,54 @@ __device__ __forceinline__ void bwd_block(
             const bool on = in_mask(m);
             const float inv1ma = __builtin_amdgcn_rcpf(1.0f - a);  // 1 - a >= 1 - alpha_max
             const float Tb = Tr[j] * inv1ma;
-            const float wcol = on ? a * Tb : 0.0f;
-            gs[9] += wcol * dL0[j];
-            gs[10] += wcol * dL1[j];
-            gs[11] += wcol * dL2[j];
-            // acc: colour of the entries behind this one (already replayed)
-            float dLda = ((r.r - acc0[j]) * dL0[j] + (r.g - acc1[j]) * dL1[j] + (r.b - acc2[j]) * dL2[j]) * Tb;
-            dLda = fmaf(inv1ma, tbg[j], dLda);
-            acc0[j] = on ? a * r.r + (1.0f - a) * acc0[j] : acc0[j];
-            acc1[j] = on ? a * r.g + (1.0f - a) * acc1[j] : acc1[j];
-            acc2[j] = on ? a * r.b + (1.0f - a) * acc2[j] : acc2[j];
+            const float aon = on ? a : 0.0f;
+            const float wcol = aon * Tb;
+            g9 += wcol * dL0[j];
+            g10 += wcol * dL1[j];
+            g11 += wcol * dL2[j];
+            // dL/dalpha = T (c - A) . dL - T_final / (1 - alpha) bg . dL,
+            // A the colour behind: (c . dL - S) T
+            const float cdl = r.r * dL0[j] + r.g * dL1[j] + r.b * dL2[j];
+            const float dcs = cdl - S[j];
+            const float dLda = dcs * Tb + inv1ma * tbg[j];
+            S[j] = fmaf(aon, dcs, S[j]);
             Tr[j] = on ? Tb : Tr[j];
             // no gradient through the alpha_max clamp
             const float dHG = in_mask(m & lanes(!(HG > amax))) ? dLda : 0.0f;
-            const float dG = dHG * (a2v + r.d_o * I);
             const float dHGG = dHG * G;
-            gs[7] += dHGG;
-            gs[8] += dHGG * I;
+            g7 += dHGG;
+            g8 += dHGG * I;
             float du = 0.0f;
             if (u.split) {
               const float w = fmaf(r.ky, dy, col.kxdx);
               du = (dHGG * cdu) * __builtin_amdgcn_exp2f(-kLog2e * w * w);
             }
-            gs[5] += du * col.dx;
-            gs[6] += du * dy;
-            const float GG = dG * G;
-            gs[0] = fmaf(-du, r.kx, fmaf(GG, col.qadx + r.qb * dy, gs[0]));
-            gs[1] = fmaf(-du, r.ky, fmaf(GG, col.qbdx + r.qc * dy, gs[1]));
-            gs[2] += -0.5f * GG * col.dx * col.dx;
-            gs[3] += -GG * col.dx * dy;
-            gs[4] += -0.5f * GG * dy * dy;
+            sDu += du;
+            sDuDy += du * dy;
+            const float GG = dHG * hgf * G;   // dL/dG times G
+            const float t = GG * dy;
+            sGG += GG;
+            sT += t;
+            sT2 += t * dy;
           }
         }
         if (!any) continue;
+        float gs[HGS_RECORD_GRAD_FLOATS];
+        {
+#pragma clang fp contract(fast)
+          gs[0] = col.qadx * sGG + r.qb * sT - r.kx * sDu;
+          gs[1] = col.qbdx * sGG + r.qc * sT - r.ky * sDu;
+          gs[2] = -0.5f * col.dx * col.dx * sGG;
+          gs[3] = -col.dx * sT;
+          gs[4] = -0.5f * sT2;
+          gs[5] = col.dx * sDu;
+          gs[6] = sDuDy;
+          gs[7] = g7;
+          gs[8] = g8;
+          gs[9] = g9;
+          gs[10] = g10;
+          gs[11] = g11;
+        }
         float tot[3];
         wave_reduce12(gs, lane, tot);
         if (lane < 4) {
