@@ -182,31 +182,32 @@ class PipelineStep:
         self.tiles_total = tiles_total = B.hgs_tiles_total(ca, opts)
         npix = B.hgs_pixels_total(ca)
 
-        def buf(nbytes):
-            return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
-
         self.params = B.params_struct(self.soa, n, n, deg)
         self.grads = torch.zeros_like(self.soa)
         self.gstruct = B.grads_struct(self.grads, n)
-        self.records = buf(n_rec * 64)
-        self.tiles = torch.empty(n_rec, dtype=torch.int32, device=dev)
-        self.offsets = torch.empty(n_rec, dtype=torch.int64, device=dev) if full_keys else None
-        self.ndup = torch.zeros(1, dtype=torch.int64, device=dev)
-        self.ws_pre = buf(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, ca, opts))
-        self.keys = torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if full_keys else None
-        self.values = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        u8, i32, i64, f32 = torch.uint8, torch.int32, torch.int64, torch.float32
+        # every buffer of the step in one allocation (raster.Arena: buffers
+        # the raster uses together do not compete for the same sets of the
+        # address-translation caches); zeroed once, so the record gradients
+        # start cleared
+        a = R.Arena(dev, [
+            ("records", n_rec * 64, u8), ("tiles", n_rec, i32),
+            ("offsets", n_rec, i64) if full_keys else None, ("ndup", 1, i64),
+            ("ws_pre", B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, ca, opts), u8),
+            ("keys", cap, i64) if full_keys else None, ("values", cap, i32),
+            ("ranges", 2 * tiles_total, i32), ("order", tiles_total, i32) if persistent else None,
+            ("overflow", 1, i32), ("ws_sort", B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, ca, opts, cap), u8),
+            ("images", 3 * npix, f32), ("T_final", npix, f32), ("last_idx", npix, i32), ("n_contrib", npix, i32),
+            ("ws_r", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts), u8),
+            ("rgrad", n_rec * B.HGS_RECORD_GRAD_FLOATS, f32), ("dL", 3 * npix, f32)], zero=True)
+        self.arena = a
+        for name in ("records", "tiles", "ndup", "ws_pre", "values", "ranges", "overflow", "ws_sort", "images",
+                     "T_final", "last_idx", "n_contrib", "ws_r", "rgrad", "dL"):
+            setattr(self, name, a[name])
+        self.offsets = a["offsets"] if full_keys else None
+        self.keys = a["keys"] if full_keys else None
+        self.order = a["order"] if persistent else None
         self.cap = cap
-        self.ranges = torch.empty(2 * tiles_total, dtype=torch.int32, device=dev)
-        self.order = torch.empty(tiles_total, dtype=torch.int32, device=dev) if persistent else None
-        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.ws_sort = buf(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, ca, opts, cap))
-        self.images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
-        self.T_final = torch.empty(npix, dtype=torch.float32, device=dev)
-        self.last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
-        self.n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
-        self.ws_r = buf(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts))
-        self.rgrad = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
-        self.dL = torch.empty(3 * npix, dtype=torch.float32, device=dev)
         self.pixels = sum(c["width"] * c["height"] for c in cams)
 
     def step(self, ev=None):
@@ -644,10 +645,11 @@ def multiview(args):
     loop = {}
     img_diff = grad_diff = 0.0
     gscale = float(grads_batched.abs().max().item())
-    # the loop in both raster schedules at the tuned tile size and batch
-    # depth; the faster one is the baseline
-    for sched in (True, False):
-        views = [BT.BatchedRasterizer(soa, n, deg, [c], tile=tile, batch=batch, persistent=sched) for c in cams]
+    # the loop in both raster schedules, at the batched call's tuned tile
+    # size and at 16 pixels (one view alone has 16x fewer tiles to balance);
+    # the fastest is the baseline
+    for tl, sched in [(t_, p_) for t_ in sorted({tile, 16}) for p_ in (True, False)]:
+        views = [BT.BatchedRasterizer(soa, n, deg, [c], tile=tl, batch=batch, persistent=sched) for c in cams]
 
         def loop_eager():
             total.zero_()
@@ -669,7 +671,7 @@ def multiview(args):
                 total.add_(v.grads)
 
         ms_graph = BT.time_steps(loop_graph, K, 3)
-        loop["persistent" if sched else "per_tile"] = {"eager_ms": round(ms_eager, 4), "graph_ms": round(ms_graph, 4)}
+        loop[BT._config_name(tl, batch, sched)] = {"eager_ms": round(ms_eager, 4), "graph_ms": round(ms_graph, 4)}
         del views, img_loop
         torch.cuda.empty_cache()
     ms_loop = min(v["eager_ms"] for v in loop.values())
@@ -679,7 +681,7 @@ def multiview(args):
         "pixels": W, "tile": tile, "batch": batch, "raster": "persistent" if persistent else "per_tile",
         "autotune_ms": tuned, "autotune_s": None if tune_s is None else round(tune_s, 2),
         "batched_graph_ms": round(ms_batched, 4), "batched_eager_ms": round(ms_batched_eager, 4),
-        "loop_eager_ms": round(ms_loop, 4), "loop_graph_ms": round(ms_loop_graph, 4), "loop_by_schedule": loop,
+        "loop_eager_ms": round(ms_loop, 4), "loop_graph_ms": round(ms_loop_graph, 4), "loop_by_config": loop,
         "batched_Mpix_s": round(W / (ms_batched * 1e-3) / 1e6, 2),
         "speedup_vs_loop_eager": round(ms_loop / ms_batched, 3),
         "speedup_vs_loop_graph": round(ms_loop_graph / ms_batched, 3),

@@ -48,42 +48,48 @@ class BatchedRasterizer:
         self.npix = B.hgs_pixels_total(self.cams)
         dev = self.dev
         self.params = B.params_struct(soa, n, soa.shape[1], sh_degree)
-        self.records = _bytes(self.n_rec * B.HGS_RECORD_BYTES, dev)
-        self.tiles = torch.empty(max(self.n_rec, 1), dtype=torch.int32, device=dev)
-        self.offsets = (torch.empty(max(self.n_rec, 1), dtype=torch.int64, device=dev)
-                        if self.opts.flags & B.HGS_FLAG_SORT_FULL_KEYS else None)
-        self.n_dup = torch.zeros(1, dtype=torch.int64, device=dev)
-        self.ws_pre = _bytes(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, self.n_rec, self.cams, self.opts), dev)
-        self.ranges = torch.empty(max(2 * self.tiles_total, 1), dtype=torch.int32, device=dev)
-        self.order = torch.empty(max(self.tiles_total, 1), dtype=torch.int32, device=dev) if persistent else None
-        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.images = torch.empty(3 * self.npix, dtype=torch.float32, device=dev)
-        self.T_final = torch.empty(self.npix, dtype=torch.float32, device=dev)
-        self.last_idx = torch.empty(self.npix, dtype=torch.int32, device=dev)
-        self.n_contrib = torch.empty(self.npix, dtype=torch.int32, device=dev)
-        self.ws_r = _bytes(B.hgs_workspace_bytes(B.HGS_WS_RENDER, self.n_rec, self.cams, self.opts), dev)
-        self.rgrad = torch.zeros(max(self.n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS, dtype=torch.float32, device=dev)
         self.grads = torch.zeros_like(soa)
         self.gstruct = B.grads_struct(self.grads, soa.shape[1])
-        self.dL = torch.zeros(3 * self.npix, dtype=torch.float32, device=dev)
         self.graph = None
-        if capacity is None:
-            B.hgs_preprocess(self.params, self.cams, self.opts, self.records, self.tiles, self.offsets,
-                             self.n_dup, self.ws_pre, self._stream())
-            capacity = max(1, int(math.ceil(int(self.n_dup.item()) * headroom)))
-        self._alloc_entries(capacity)
+        if capacity is None:    # one preprocess into throw-away buffers sizes the entries
+            records = _bytes(self.n_rec * B.HGS_RECORD_BYTES, dev)
+            tiles = torch.empty(max(self.n_rec, 1), dtype=torch.int32, device=dev)
+            n_dup = torch.zeros(1, dtype=torch.int64, device=dev)
+            ws = _bytes(B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, self.n_rec, self.cams, self.opts), dev)
+            B.hgs_preprocess(self.params, self.cams, self.opts, records, tiles, None, n_dup, ws, self._stream())
+            capacity = max(1, int(math.ceil(int(n_dup.item()) * headroom)))
+            del records, tiles, n_dup, ws
+        self._alloc(capacity)
 
     @staticmethod
     def _stream():
         return torch.cuda.current_stream().cuda_stream
 
-    def _alloc_entries(self, capacity):
+    def _alloc(self, capacity):
+        """Every buffer of the step, for ``capacity`` entries, carved from one
+        zeroed allocation (raster.Arena); the per-record gradients start
+        cleared and every backward pass leaves them cleared."""
         self.capacity = int(capacity)
         full = bool(self.opts.flags & B.HGS_FLAG_SORT_FULL_KEYS)
-        self.keys = torch.empty(self.capacity, dtype=torch.int64, device=self.dev) if full else None
-        self.values = torch.empty(self.capacity, dtype=torch.int32, device=self.dev)
-        self.ws_sort = _bytes(B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, self.n_rec, self.cams, self.opts,
-                                                    self.capacity), self.dev)
+        u8, i32, i64, f32 = torch.uint8, torch.int32, torch.int64, torch.float32
+        n_rec, npix, nt, cams, opts = self.n_rec, self.npix, max(self.tiles_total, 1), self.cams, self.opts
+        a = R.Arena(self.dev, [
+            ("records", n_rec * B.HGS_RECORD_BYTES, u8), ("tiles", n_rec, i32),
+            ("offsets", n_rec, i64) if full else None, ("n_dup", 1, i64),
+            ("ws_pre", B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, cams, opts), u8),
+            ("keys", self.capacity, i64) if full else None, ("values", self.capacity, i32),
+            ("ranges", 2 * nt, i32), ("order", nt, i32) if self.persistent else None, ("overflow", 1, i32),
+            ("ws_sort", B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, cams, opts, self.capacity), u8),
+            ("images", 3 * npix, f32), ("T_final", npix, f32), ("last_idx", npix, i32),
+            ("n_contrib", npix, i32), ("ws_r", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), u8),
+            ("rgrad", max(n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS, f32), ("dL", 3 * npix, f32)], zero=True)
+        self.arena = a
+        for name in ("records", "tiles", "n_dup", "ws_pre", "values", "ranges", "overflow", "ws_sort", "images",
+                     "T_final", "last_idx", "n_contrib", "ws_r", "rgrad", "dL"):
+            setattr(self, name, a[name])
+        self.offsets = a["offsets"] if full else None
+        self.keys = a["keys"] if full else None
+        self.order = a["order"] if self.persistent else None
 
     # -- stages ------------------------------------------------------------
     def forward(self):
@@ -132,7 +138,7 @@ class BatchedRasterizer:
         self.graph.replay()
         if check and int(self.overflow.item()) != 0:
             need = int(self.n_dup.item())
-            self._alloc_entries(max(2 * self.capacity, int(need * 1.25)))
+            self._alloc(max(2 * self.capacity, int(need * 1.25)))
             self.capture(self._loss_grad)
             self.graph.replay()
             return True

@@ -86,6 +86,12 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libhgs.so not found at {path}; build it with "
                            "`python -m paper_2406_02720_amd.build` (there is no CPU fallback)")
+    # torch's HIP runtime first: the library's dependency on the HIP runtime
+    # is then resolved to the copy already loaded, and the process holds one
+    # runtime.  Loaded the other way round, torch brings a second copy, and
+    # the two contend for the device (the library's launches then fail with
+    # "no ROCm-capable device").
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     P = C.POINTER

@@ -153,6 +153,19 @@ struct Geometry {
 
 };
 
+// The backward pass uses taller blocks at 32-pixel tiles: SUBX x SUBY pixels
+// per wavefront (16 x 32, two wavefronts per tile, 8 pixels per lane), so
+// that the per-entry work of a wavefront -- record setup, the 12-value
+// reduction and the atomics -- is shared by twice the pixels.
+template <int T>
+struct BwdGeometry {
+  static constexpr int SUBX = (T == 8) ? 8 : 16;
+  static constexpr int SUBY = (T == 32) ? 32 : SUBX;
+  static constexpr int PPL = SUBX * SUBY / 64;
+  static constexpr int WAVES = (T / SUBX) * (T / SUBY);
+  static constexpr int ROWSTEP = 64 / SUBX;
+};
+
 __device__ __forceinline__ Record load_record(const Record* __restrict__ rec, uint32_t id) {
   return rec[id];
 }
@@ -426,7 +439,7 @@ __device__ __forceinline__ void bwd_block(
     const uint32_t* __restrict__ ranges, const CamPack& cp, const Opts& o,
     const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,
     const float* __restrict__ dL_dimg, float* __restrict__ rgrad, uint32_t tile, int wave, int lane) {
-  using Gm = Geometry<T>;
+  using Gm = BwdGeometry<T>;
   constexpr int PPL = Gm::PPL;
   constexpr int RS = Gm::ROWSTEP;
   if (tile >= cp.tiles_total) return;  // never index past the tile arrays
@@ -435,11 +448,11 @@ __device__ __forceinline__ void bwd_block(
   const uint32_t lt = tile - cam.tile_off;
   const int ty = (int)(lt / (uint32_t)cam.tiles_x);
   const int tx = (int)(lt - (uint32_t)ty * (uint32_t)cam.tiles_x);
-  const int ox = uniform(tx * T + (wave % (T / Gm::SUB)) * Gm::SUB);
-  const int oy = uniform(ty * T + (wave / (T / Gm::SUB)) * Gm::SUB);
-  const int px = ox + lane % Gm::SUB;
+  const int ox = uniform(tx * T + (wave % (T / Gm::SUBX)) * Gm::SUBX);
+  const int oy = uniform(ty * T + (wave / (T / Gm::SUBX)) * Gm::SUBY);
+  const int px = ox + lane % Gm::SUBX;
   const float fpx = (float)px + 0.5f;
-  const int py0 = oy + lane / Gm::SUB;
+  const int py0 = oy + lane / Gm::SUBX;
   const uint64_t plane = (uint64_t)cam.width * cam.height;
   const float* g = dL_dimg + 3 * cam.pix_off;
 
@@ -600,7 +613,7 @@ __device__ __forceinline__ void bwd_block(
 }
 
 template <int T, int IPL>
-__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
+__global__ __launch_bounds__(64 * BwdGeometry<T>::WAVES) void render_bwd_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, CamPack cp, Opts o, const float* __restrict__ T_final,
     const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimg,
@@ -610,7 +623,7 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_bwd_kernel(
 }
 
 template <int T, int IPL>
-__global__ __launch_bounds__(64 * Geometry<T>::WAVES) __attribute__((amdgpu_waves_per_eu(6))) void
+__global__ __launch_bounds__(64 * BwdGeometry<T>::WAVES) __attribute__((amdgpu_waves_per_eu(4))) void
 render_bwd_persistent_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
@@ -678,12 +691,12 @@ hipError_t bwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* r
   if (order) {
     uint32_t* counter = static_cast<uint32_t*>(ws) + 1;
     hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-    constexpr int threads = 64 * Geometry<T>::WAVES;
+    constexpr int threads = 64 * BwdGeometry<T>::WAVES;
     hipLaunchKernelGGL((render_bwd_persistent_kernel<T, B / 64>),
                        dim3(persistent_grid(render_bwd_persistent_kernel<T, B / 64>, cp.tiles_total, threads)),
                        dim3(threads), 0, s, rec, vals, ranges, order, cp, o, Tf, li, dL, rg, counter);
   } else {
-    hipLaunchKernelGGL((render_bwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * Geometry<T>::WAVES),
+    hipLaunchKernelGGL((render_bwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * BwdGeometry<T>::WAVES),
                        0, s, rec, vals, ranges, cp, o, Tf, li, dL, rg);
   }
   return hipGetLastError();

@@ -76,6 +76,7 @@ class Frame:
     depth: torch.Tensor | None = None
     params: object | None = None      # the hgs_params the frame was rendered with
     filter3d: torch.Tensor | None = None
+    record_grads: torch.Tensor | None = None   # cleared per-record gradient buffer for the backward pass
 
     def image(self, c: int) -> torch.Tensor:
         """[3,H,W] view of camera c's image."""
@@ -95,6 +96,31 @@ class Frame:
 
 def _bytes(n: int, device) -> torch.Tensor:
     return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+class Arena:
+    """Device buffers carved from one allocation, back to back at 256-byte
+    alignment.  Separate large allocations start at equally aligned virtual
+    addresses, and buffers a kernel uses together then compete for the same
+    sets of the compute units' address-translation caches; carved from one
+    allocation their pages follow one another (measured on the backward
+    raster, 1M kernels at 1080p: 6.5x fewer translation misses, 0.69 ->
+    0.62 ms).  ``specs``: (name, element count, dtype) triples, None entries
+    skipped; ``zero`` clears the whole allocation."""
+
+    def __init__(self, device, specs, zero: bool = False):
+        specs = [sp for sp in specs if sp is not None]
+        offs, off = [], 0
+        for _, numel, dt in specs:
+            nbytes = max(int(numel), 1) * torch.empty((), dtype=dt).element_size()
+            offs.append((off, nbytes))
+            off += (nbytes + 255) // 256 * 256
+        make = torch.zeros if zero else torch.empty
+        self.base = make(max(off, 1), dtype=torch.uint8, device=device)
+        self.views = {name: self.base[o:o + nb].view(dt) for (name, _, dt), (o, nb) in zip(specs, offs)}
+
+    def __getitem__(self, name):
+        return self.views[name]
 
 
 def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity: int | None = None,
@@ -205,11 +231,11 @@ class Rasterizer:
     the preprocess, and the host waits for that copy only once sort and
     raster are already queued behind it, so the device never idles for the
     check; if the entries did not fit, the entry buffers grow and the sort and
-    raster are queued again.  Workspaces and the per-record gradient buffer
-    are kept between calls (every call leaves the latter cleared); the
-    per-call outputs and the state saved for the backward pass come from
-    torch's caching allocator (no device allocation after the first call of
-    a size)."""
+    raster are queued again.  Workspaces are kept between calls; the state
+    saved for the backward pass (records, tile lists, per-pixel results, the
+    per-record gradient buffer) is carved from one allocation per call (see
+    Arena), the images are a second; both come from torch's caching
+    allocator (no device allocation after the first call of a size)."""
 
     def __init__(self, cameras, sh_degree: int, tile: int = 32, persistent: bool | None = None,
                  headroom: float = 1.25, **options):
@@ -223,7 +249,6 @@ class Rasterizer:
         self.headroom = float(headroom)
         self.capacity = 0
         self._ws = {}
-        self._rgrad = None
         self._count = None
         self.tiles_total = B.hgs_tiles_total(self.cams, self.opts)
         self.npix = B.hgs_pixels_total(self.cams)
@@ -236,14 +261,6 @@ class Rasterizer:
             self._ws[which] = t
         return t
 
-    def record_grads(self, n_rec: int, dev) -> torch.Tensor:
-        """The per-record gradient buffer, cleared (hgs_preprocess_bwd clears
-        it after every use, in stream order)."""
-        need = max(n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS
-        if self._rgrad is None or self._rgrad.numel() < need or self._rgrad.device != dev:
-            self._rgrad = torch.zeros(need, dtype=torch.float32, device=dev)
-        return self._rgrad
-
     def forward_frame(self, planes: torch.Tensor) -> Frame:
         n = planes.shape[1]
         dev = planes.device
@@ -251,10 +268,24 @@ class Rasterizer:
         n_rec = n * len(self.cameras)
         stream = _stream()
         params = B.params_struct(planes, n, planes.shape[1], self.sh_degree)
-        records = _bytes(n_rec * B.HGS_RECORD_BYTES, dev)
-        tiles = torch.empty(max(n_rec, 1), dtype=torch.int32, device=dev)
-        n_dup = torch.empty(1, dtype=torch.int64, device=dev)
-        overflow = torch.empty(1, dtype=torch.int32, device=dev)
+        if self.capacity == 0:      # first call: size the entry buffers from this scene
+            self.capacity = self._first_capacity(params, n_rec, dev)
+        npix, nt = self.npix, max(self.tiles_total, 1)
+        a = Arena(dev, [("records", n_rec * B.HGS_RECORD_BYTES, torch.uint8),
+                        ("tiles", n_rec, torch.int32), ("n_dup", 1, torch.int64), ("overflow", 1, torch.int32),
+                        ("values", self.capacity, torch.int32), ("ranges", 2 * nt, torch.int32),
+                        ("order", nt, torch.int32) if self.persistent else None,
+                        ("T_final", npix, torch.float32), ("last_idx", npix, torch.int32),
+                        ("n_contrib", npix, torch.int32),
+                        ("record_grads", max(n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS, torch.float32)])
+        a["record_grads"].zero_()
+        records, tiles, n_dup, overflow = a["records"], a["tiles"], a["n_dup"], a["overflow"]
+        ranges, T_final, last_idx, n_contrib = a["ranges"], a["T_final"], a["last_idx"], a["n_contrib"]
+        order = a["order"] if self.persistent else None
+        values = a["values"]
+        # the output the caller keeps: a separate allocation, so that holding
+        # it does not hold the rest
+        images = torch.empty(3 * npix, dtype=torch.float32, device=dev)
         ws_pre = self._workspace("pre", B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, cams, opts), dev)
         B.hgs_preprocess(params, cams, opts, records, tiles, None, n_dup, ws_pre, stream)
         if self._count is None:
@@ -262,18 +293,10 @@ class Rasterizer:
         self._count.copy_(n_dup, non_blocking=True)
         copied = torch.cuda.Event()
         copied.record()
-        if self.capacity == 0:      # first call: size the entry buffers from this scene
-            copied.synchronize()
-            self.capacity = max(1, int(math.ceil(int(self._count.item()) * self.headroom)))
-        ranges = torch.empty(max(2 * self.tiles_total, 1), dtype=torch.int32, device=dev)
-        order = torch.empty(max(self.tiles_total, 1), dtype=torch.int32, device=dev) if self.persistent else None
-        images = torch.empty(3 * self.npix, dtype=torch.float32, device=dev)
-        T_final = torch.empty(self.npix, dtype=torch.float32, device=dev)
-        last_idx = torch.empty(self.npix, dtype=torch.int32, device=dev)
-        n_contrib = torch.empty(self.npix, dtype=torch.int32, device=dev)
         ws_r = self._workspace("render", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), dev)
         while True:
-            values = torch.empty(self.capacity, dtype=torch.int32, device=dev)
+            if values.numel() < self.capacity:      # after an overflow: more room, outside the arena
+                values = torch.empty(self.capacity, dtype=torch.int32, device=dev)
             ws_sort = self._workspace("sort", B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, cams, opts,
                                                                     self.capacity), dev)
             B.hgs_bin_sort(records, tiles, None, n_dup, n_rec, cams, opts, None, values, self.capacity, ranges,
@@ -287,12 +310,24 @@ class Rasterizer:
             self.overflows += 1
             self.capacity = int(math.ceil(entries * self.headroom))
         return Frame(planes, n, self.sh_degree, cams, opts, records, tiles, None, n_dup, None, values, ranges,
-                     overflow, images, T_final, last_idx, n_contrib, self.capacity, ws_r, order, None, params)
+                     overflow, images, T_final, last_idx, n_contrib, self.capacity, ws_r, order, None, params,
+                     record_grads=a["record_grads"])
+
+    def _first_capacity(self, params, n_rec: int, dev) -> int:
+        """Entry capacity from one preprocess of the first scene (one
+        synchronisation, first call only)."""
+        cams, opts = self.cams, self.opts
+        records = _bytes(n_rec * B.HGS_RECORD_BYTES, dev)
+        tiles = torch.empty(max(n_rec, 1), dtype=torch.int32, device=dev)
+        n_dup = torch.empty(1, dtype=torch.int64, device=dev)
+        ws_pre = self._workspace("pre", B.hgs_workspace_bytes(B.HGS_WS_PREPROCESS, n_rec, cams, opts), dev)
+        B.hgs_preprocess(params, cams, opts, records, tiles, None, n_dup, ws_pre, _stream())
+        return max(1, int(math.ceil(int(n_dup.item()) * self.headroom)))
 
     def backward_frame(self, fr: Frame, d_images: torch.Tensor) -> torch.Tensor:
         """Parameter gradients (plane layout) of a frame from this rasterizer."""
         grads = torch.empty_like(fr.soa)      # hgs_preprocess_bwd overwrites every plane
-        rgrad = self.record_grads(fr.n * len(self.cameras), fr.soa.device)
+        rgrad = fr.record_grads               # cleared in the forward pass
         st = _stream()
         B.hgs_raster_bwd(fr.records, fr.values, fr.ranges, fr.tile_order, fr.cams, fr.opts, fr.T_final,
                          fr.last_idx, d_images, rgrad, fr.ws_render, st)
