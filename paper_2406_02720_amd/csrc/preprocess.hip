@@ -82,13 +82,22 @@ __device__ __forceinline__ int clamp_floor(double x, int hi) {
 }
 
 // The records of kernel i for every camera; returns the sum of their tiles.
-template <int D>
+// ONE: a single camera.  Its SH coefficients are then loaded before the
+// kernel geometry, so that their loads are in flight while the FP64 geometry
+// runs (with several cameras they are read per camera, from cache, after it:
+// held across the camera loop they would double the register footprint).
+template <int D, bool ONE>
 __device__ __forceinline__ uint64_t preprocess_one(const Params& p, const CamPack& cp, const Opts& o,
                                                    Record* __restrict__ rec, uint32_t* __restrict__ tiles_out,
                                                    int64_t i) {
   constexpr int K = (D + 1) * (D + 1);
   uint64_t tiles_sum = 0;
   const int64_t S = p.stride;
+  float shv[ONE ? 3 * K : 1];
+  if (ONE) {
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) shv[j] = p.sh[j * S + i];
+  }
   float mu[3], s[3], q[4], nrm[3];
   for (int c = 0; c < 3; ++c) {
     mu[c] = p.means[c * S + i];
@@ -112,7 +121,8 @@ __device__ __forceinline__ uint64_t preprocess_one(const Params& p, const CamPac
   if (!(o.flags & HGS_FLAG_FULL_BOX) && !kg.nzero) Ss = splitting_cov(kg);
   const int tsh = cp.tile_shift;
 
-  for (int c = 0; c < cp.n_cams; ++c) {
+  const int n_cams = ONE ? 1 : cp.n_cams;
+  for (int c = 0; c < n_cams; ++c) {
     const CamDev& cam = cp.cam[c];
     Record r;
     uint32_t tiles = 0;
@@ -132,9 +142,15 @@ __device__ __forceinline__ uint64_t preprocess_one(const Params& p, const CamPac
       sh_eval<D>(dx, dy, dz, Y);
 #pragma unroll
       for (int kk = 0; kk < K; ++kk) {
-        col0 += Y[kk] * (double)p.sh[(kk * 3 + 0) * S + i];
-        col1 += Y[kk] * (double)p.sh[(kk * 3 + 1) * S + i];
-        col2 += Y[kk] * (double)p.sh[(kk * 3 + 2) * S + i];
+        if (ONE) {
+          col0 += Y[kk] * (double)shv[kk * 3 + 0];
+          col1 += Y[kk] * (double)shv[kk * 3 + 1];
+          col2 += Y[kk] * (double)shv[kk * 3 + 2];
+        } else {
+          col0 += Y[kk] * (double)p.sh[(kk * 3 + 0) * S + i];
+          col1 += Y[kk] * (double)p.sh[(kk * 3 + 1) * S + i];
+          col2 += Y[kk] * (double)p.sh[(kk * 3 + 2) * S + i];
+        }
       }
       col0 = fmax(col0 + 0.5, 0.0);
       col1 = fmax(col1 + 0.5, 0.0);
@@ -196,14 +212,14 @@ __device__ __forceinline__ uint64_t preprocess_one(const Params& p, const CamPac
 // One thread per kernel.  With block_tiles, each workgroup also stores the
 // sum of its records' tiles (the entry total is then the sum of these
 // partials: no second pass over tiles_out).
-template <int D>
+template <int D, bool ONE>
 __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack cp, Opts o,
                                                                Record* __restrict__ rec,
                                                                uint32_t* __restrict__ tiles_out,
                                                                uint64_t* __restrict__ block_tiles) {
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   uint64_t mine = 0;
-  if (i < p.n) mine = preprocess_one<D>(p, cp, o, rec, tiles_out, i);
+  if (i < p.n) mine = preprocess_one<D, ONE>(p, cp, o, rec, tiles_out, i);
   if (!block_tiles) return;
   __shared__ uint64_t s_w[kPreBlock / 64];
 #pragma unroll
@@ -337,7 +353,7 @@ __device__ __forceinline__ void add_sym_outer(Sym3& S, const double* u, const do
   S.yz += w * 0.5 * (u[1] * v[2] + u[2] * v[1]);
 }
 
-template <int D>
+template <int D, bool ONE>
 __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     Params p, CamPack cp, Opts o, const Record* __restrict__ rec,
     float* __restrict__ rgrad, Grads G) {
@@ -345,61 +361,27 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   if (i >= p.n) return;
   const int64_t S = p.stride;
-  float mu[3], s[3], q[4], nrm[3];
-  for (int c = 0; c < 3; ++c) {
-    mu[c] = p.means[c * S + i];
-    s[c] = p.scales[c * S + i];
-    nrm[c] = p.normals[c * S + i];
-  }
-  for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
-
-  const double f3 = p.filter3d ? (double)p.filter3d[i] : 0.0;
-  KernelGeo kg;
-  kernel_geo(mu, s, q, nrm, kg, (isfinite(f3) && f3 >= 0.0) ? f3 : 0.0);
-  const double a1 = (double)p.opac1[i], a2 = (double)p.opac2[i];
-  double g_c3 = 0.0;   // dL / d comp3
-
+  // a single camera: no loops (their registers are then scheduled as one
+  // straight-line body)
+  const int n_cams = ONE ? 1 : cp.n_cams;
   double g_mu[3] = {0.0, 0.0, 0.0};
-  Sym3 g_Sw = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  double g_nh[3] = {0.0, 0.0, 0.0};
-  double g_a1 = 0.0, g_a2 = 0.0;
-  float g_sh[3 * K];
+
+  // ---- colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - o) / |mu - o|,
+  // over all cameras first: the SH coefficients, basis values and their
+  // gradients are dead before the geometry below starts
+  {
+    const double mu0 = (double)p.means[i], mu1 = (double)p.means[S + i], mu2 = (double)p.means[2 * S + i];
+    float g_sh[3 * K];
 #pragma unroll
-  for (int j = 0; j < 3 * K; ++j) g_sh[j] = 0.0f;
-
-  for (int c = 0; c < cp.n_cams; ++c) {
-    const int64_t ri = (int64_t)c * p.n + i;
-    if (rec[ri].tiles == 0) continue;  // culled: no gradient, nothing to clear
-    float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS;
-    float4* gr4 = reinterpret_cast<float4*>(gr);
-    const float4 r0 = gr4[0], r1 = gr4[1], r2 = gr4[2];
-    gr4[0] = gr4[1] = gr4[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // leave the buffer cleared
-    const double gmx = r0.x, gmy = r0.y;
-    const double gqa = r0.z, gqb = r0.w, gqc = r1.x;
-    const double gkx = r1.y, gky = r1.z;
-    const double galpha2 = r1.w, gdo = r2.x;
-    const double gcol[3] = {r2.y, r2.z, r2.w};
-
-    const CamDev& cam = cp.cam[c];
-    ViewGeo vg;
-    view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
-
-    // alpha2 = comp a2 and (alpha1 - alpha2) / 2 = comp (a1 - a2) / 2, with
-    // comp = comp3 c2 (Mip-Splatting compensations; 1 without filters)
-    const bool mip2 = (o.flags & HGS_FLAG_MIP_2D) != 0;
-    const double c2 = mip2 ? (vg.det0 > 0.0 ? sqrt(vg.det0 / vg.det) : 0.0) : 1.0;
-    const double comp = kg.comp3 * c2;
-    g_a2 += comp * (galpha2 - 0.5 * gdo);
-    g_a1 += comp * 0.5 * gdo;
-    const double gcomp = galpha2 * a2 + 0.5 * gdo * (a1 - a2);
-    g_c3 += gcomp * c2;
-    const double g_c2 = gcomp * kg.comp3;
-
-    // ---- colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - o) / |mu - o|
-    {
+    for (int j = 0; j < 3 * K; ++j) g_sh[j] = 0.0f;
+    for (int c = 0; c < n_cams; ++c) {
+      const int64_t ri = (int64_t)c * p.n + i;
+      if (rec[ri].tiles == 0) continue;  // culled: no gradient
+      const float4 r2 = reinterpret_cast<const float4*>(rgrad + ri * HGS_RECORD_GRAD_FLOATS)[2];
+      const double gcol[3] = {r2.y, r2.z, r2.w};
       double oc[3];
-      camera_centre(cam, oc);
-      const double dv0 = kg.mu[0] - oc[0], dv1 = kg.mu[1] - oc[1], dv2 = kg.mu[2] - oc[2];
+      camera_centre(cp.cam[c], oc);
+      const double dv0 = mu0 - oc[0], dv1 = mu1 - oc[1], dv2 = mu2 - oc[2];
       const double dl = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
       const double il = 1.0 / dl;
       const double d0 = dv0 * il, d1 = dv1 * il, d2 = dv2 * il;
@@ -431,6 +413,55 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
       g_mu[1] += (gd1 - d1 * dot) * il;
       g_mu[2] += (gd2 - d2 * dot) * il;
     }
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = g_sh[j];
+  }
+
+  float mu[3], s[3], q[4], nrm[3];
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = p.means[c * S + i];
+    s[c] = p.scales[c * S + i];
+    nrm[c] = p.normals[c * S + i];
+  }
+  for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
+
+  const double f3 = p.filter3d ? (double)p.filter3d[i] : 0.0;
+  KernelGeo kg;
+  kernel_geo(mu, s, q, nrm, kg, (isfinite(f3) && f3 >= 0.0) ? f3 : 0.0);
+  const double a1 = (double)p.opac1[i], a2 = (double)p.opac2[i];
+  double g_c3 = 0.0;   // dL / d comp3
+
+  Sym3 g_Sw = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double g_nh[3] = {0.0, 0.0, 0.0};
+  double g_a1 = 0.0, g_a2 = 0.0;
+
+  for (int c = 0; c < n_cams; ++c) {
+    const int64_t ri = (int64_t)c * p.n + i;
+    if (rec[ri].tiles == 0) continue;  // culled: no gradient, nothing to clear
+    float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS;
+    float4* gr4 = reinterpret_cast<float4*>(gr);
+    const float4 r0 = gr4[0], r1 = gr4[1];
+    const float gdo_f = gr[8];
+    gr4[0] = gr4[1] = gr4[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // leave the buffer cleared
+    const double gmx = r0.x, gmy = r0.y;
+    const double gqa = r0.z, gqb = r0.w, gqc = r1.x;
+    const double gkx = r1.y, gky = r1.z;
+    const double galpha2 = r1.w, gdo = gdo_f;
+
+    const CamDev& cam = cp.cam[c];
+    ViewGeo vg;
+    view_geo(kg, cam, (double)o.lowpass, (double)o.fov_clamp, vg);
+
+    // alpha2 = comp a2 and (alpha1 - alpha2) / 2 = comp (a1 - a2) / 2, with
+    // comp = comp3 c2 (Mip-Splatting compensations; 1 without filters)
+    const bool mip2 = (o.flags & HGS_FLAG_MIP_2D) != 0;
+    const double c2 = mip2 ? (vg.det0 > 0.0 ? sqrt(vg.det0 / vg.det) : 0.0) : 1.0;
+    const double comp = kg.comp3 * c2;
+    g_a2 += comp * (galpha2 - 0.5 * gdo);
+    g_a1 += comp * 0.5 * gdo;
+    const double gcomp = galpha2 * a2 + 0.5 * gdo * (a1 - a2);
+    g_c3 += gcomp * c2;
+    const double g_c2 = gcomp * kg.comp3;
 
     // ---- k = w r, r = (2 s2)^-1/2, w = Q g, s2 = v - g.w (or 1e-12 v)
     double gg0 = 0.0, gg1 = 0.0, gv = 0.0;
@@ -588,8 +619,20 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   for (int c = 0; c < 4; ++c) G.quats[c * S + i] = (float)gq_raw[c];
   G.opac1[i] = (float)g_a1;
   G.opac2[i] = (float)g_a2;
-#pragma unroll
-  for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = g_sh[j];
+}
+
+template <int D>
+void launch_projection(unsigned grid, const Params& p, const CamPack& cp, const Opts& o, Record* rec,
+                       uint32_t* tiles, uint64_t* partial, hipStream_t s) {
+  auto kern = cp.n_cams == 1 ? preprocess_kernel<D, true> : preprocess_kernel<D, false>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial);
+}
+
+template <int D>
+void launch_projection_bwd(unsigned grid, const Params& p, const CamPack& cp, const Opts& o, const Record* rec,
+                           float* rec_grads, const Grads& g, hipStream_t s) {
+  auto kern = cp.n_cams == 1 ? preprocess_bwd_kernel<D, true> : preprocess_bwd_kernel<D, false>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g);
 }
 
 }  // namespace
@@ -603,10 +646,10 @@ hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, 
   uint64_t* partial = offsets ? nullptr : (uint64_t*)ws;
   if (p.n > 0) {
     switch (p.sh_degree) {
-      case 0: hipLaunchKernelGGL(preprocess_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial); break;
-      case 1: hipLaunchKernelGGL(preprocess_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial); break;
-      case 2: hipLaunchKernelGGL(preprocess_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial); break;
-      default: hipLaunchKernelGGL(preprocess_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, tiles, partial); break;
+      case 0: launch_projection<0>(grid, p, cp, o, rec, tiles, partial, s); break;
+      case 1: launch_projection<1>(grid, p, cp, o, rec, tiles, partial, s); break;
+      case 2: launch_projection<2>(grid, p, cp, o, rec, tiles, partial, s); break;
+      default: launch_projection<3>(grid, p, cp, o, rec, tiles, partial, s); break;
     }
   }
   if (offsets) return launch_scan(tiles, n_rec, offsets, total, ws, s);
@@ -712,10 +755,10 @@ hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts&
   if (p.n == 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
   switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(preprocess_bwd_kernel<0>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
-    case 1: hipLaunchKernelGGL(preprocess_bwd_kernel<1>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
-    case 2: hipLaunchKernelGGL(preprocess_bwd_kernel<2>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
-    default: hipLaunchKernelGGL(preprocess_bwd_kernel<3>, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g); break;
+    case 0: launch_projection_bwd<0>(grid, p, cp, o, rec, rec_grads, g, s); break;
+    case 1: launch_projection_bwd<1>(grid, p, cp, o, rec, rec_grads, g, s); break;
+    case 2: launch_projection_bwd<2>(grid, p, cp, o, rec, rec_grads, g, s); break;
+    default: launch_projection_bwd<3>(grid, p, cp, o, rec, rec_grads, g, s); break;
   }
   return hipGetLastError();
 }
