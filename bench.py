@@ -34,6 +34,7 @@ WORKLOADS = {
     2: "100k half-Gaussians, 1280x720, SH deg 3, fwd+bwd",
     1: "1k half-Gaussians, 128x128, SH deg 0, fwd+bwd",
     4: "500k half-Gaussians, 16 views of uneven size, SH deg 3, fwd+bwd",
+    5: "3M half-Gaussians (5% large splats), 8 views of 3840x2160, SH deg 3, fwd+bwd",
 }
 
 
