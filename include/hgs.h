@@ -324,7 +324,10 @@ int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_c
  *
  * hgs_preprocess_bwd: the chain rule from record_grads to every kernel
  * parameter (summed over cameras, grads overwritten); clears record_grads
- * after reading it. */
+ * after reading it.  `records` (those of hgs_preprocess) must be non-null but
+ * are not read: a record whose twelve gradients are all zero -- every culled
+ * record, since hgs_raster_bwd adds only to records in the tile lists --
+ * contributes nothing and is skipped. */
 int hgs_raster_bwd(const void* records, const uint32_t* values, const uint32_t* ranges,
                    const uint32_t* tile_order, const hgs_camera* cams, int32_t n_cams,
                    const hgs_options* opts, const float* T_final, const int32_t* last_idx,

@@ -368,7 +368,7 @@ int hgs_preprocess_bwd(const hgs_params* params, const hgs_camera* cams, int32_t
   const hgs::Opts o = hgs::to_opts(*opts);
   hgs::Grads g{grads->means, grads->scales, grads->quats, grads->normals,
                grads->opac1, grads->opac2,  grads->sh};
-  hipError_t h = hgs::launch_preprocess_bwd(p, cp, o, (const hgs::Record*)records, record_grads, g, stream);
+  hipError_t h = hgs::launch_preprocess_bwd(p, cp, o, record_grads, g, stream);
   if (h != hipSuccess) return hip_fail(h, "preprocess_bwd launch");
   return HGS_OK;
 }

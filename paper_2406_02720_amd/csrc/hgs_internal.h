@@ -181,8 +181,7 @@ hipError_t launch_densify(const Grads& raw, const Grads& m, const Grads& v, int6
                           const float* max_radii, const float* samples, int64_t capacity, int64_t stride_out,
                           const Grads& raw_out, const Grads& m_out, const Grads& v_out, int64_t* n_out,
                           int32_t* overflow, void* ws, hipStream_t s);
-hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o,
-                                 const Record* rec, float* rec_grads, const Grads& g,
-                                 hipStream_t s);
+hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o, float* rec_grads,
+                                 const Grads& g, hipStream_t s);
 
 }  // namespace hgs

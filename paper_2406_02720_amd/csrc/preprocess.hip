@@ -355,8 +355,7 @@ __device__ __forceinline__ void add_sym_outer(Sym3& S, const double* u, const do
 
 template <int D, bool ONE>
 __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
-    Params p, CamPack cp, Opts o, const Record* __restrict__ rec,
-    float* __restrict__ rgrad, Grads G) {
+    Params p, CamPack cp, Opts o, float* __restrict__ rgrad, Grads G) {
   constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   if (i >= p.n) return;
@@ -376,8 +375,10 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     for (int j = 0; j < 3 * K; ++j) g_sh[j] = 0.0f;
     for (int c = 0; c < n_cams; ++c) {
       const int64_t ri = (int64_t)c * p.n + i;
-      if (rec[ri].tiles == 0) continue;  // culled: no gradient
       const float4 r2 = reinterpret_cast<const float4*>(rgrad + ri * HGS_RECORD_GRAD_FLOATS)[2];
+      // no colour gradient (a culled record has none: the raster adds only
+      // to records in the tile lists, into a cleared buffer)
+      if (r2.y == 0.0f && r2.z == 0.0f && r2.w == 0.0f) continue;
       const double gcol[3] = {r2.y, r2.z, r2.w};
       double oc[3];
       camera_centre(cp.cam[c], oc);
@@ -437,11 +438,19 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
 
   for (int c = 0; c < n_cams; ++c) {
     const int64_t ri = (int64_t)c * p.n + i;
-    if (rec[ri].tiles == 0) continue;  // culled: no gradient, nothing to clear
     float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS;
     float4* gr4 = reinterpret_cast<float4*>(gr);
-    const float4 r0 = gr4[0], r1 = gr4[1];
-    const float gdo_f = gr[8];
+    const float4 r0 = gr4[0], r1 = gr4[1], r2 = gr4[2];
+    // all twelve zero (every culled record, and visible ones no pixel
+    // blended): no contribution and nothing to clear.  The records
+    // themselves are not read.
+    const uint32_t nz = (__float_as_uint(r0.x) | __float_as_uint(r0.y) | __float_as_uint(r0.z) |
+                         __float_as_uint(r0.w) | __float_as_uint(r1.x) | __float_as_uint(r1.y) |
+                         __float_as_uint(r1.z) | __float_as_uint(r1.w) | __float_as_uint(r2.x) |
+                         __float_as_uint(r2.y) | __float_as_uint(r2.z) | __float_as_uint(r2.w)) &
+                        0x7fffffffu;
+    if (nz == 0u) continue;
+    const float gdo_f = r2.x;
     gr4[0] = gr4[1] = gr4[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // leave the buffer cleared
     const double gmx = r0.x, gmy = r0.y;
     const double gqa = r0.z, gqb = r0.w, gqc = r1.x;
@@ -629,10 +638,10 @@ void launch_projection(unsigned grid, const Params& p, const CamPack& cp, const 
 }
 
 template <int D>
-void launch_projection_bwd(unsigned grid, const Params& p, const CamPack& cp, const Opts& o, const Record* rec,
-                           float* rec_grads, const Grads& g, hipStream_t s) {
+void launch_projection_bwd(unsigned grid, const Params& p, const CamPack& cp, const Opts& o, float* rec_grads,
+                           const Grads& g, hipStream_t s) {
   auto kern = cp.n_cams == 1 ? preprocess_bwd_kernel<D, true> : preprocess_bwd_kernel<D, false>;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec, rec_grads, g);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kPreBlock), 0, s, p, cp, o, rec_grads, g);
 }
 
 }  // namespace
@@ -749,16 +758,15 @@ hipError_t launch_mip_filter3d(const float* means, int64_t n, int64_t stride, co
   return hipGetLastError();
 }
 
-hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o,
-                                 const Record* rec, float* rec_grads, const Grads& g,
-                                 hipStream_t s) {
+hipError_t launch_preprocess_bwd(const Params& p, const CamPack& cp, const Opts& o, float* rec_grads,
+                                 const Grads& g, hipStream_t s) {
   if (p.n == 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n + kPreBlock - 1) / kPreBlock);
   switch (p.sh_degree) {
-    case 0: launch_projection_bwd<0>(grid, p, cp, o, rec, rec_grads, g, s); break;
-    case 1: launch_projection_bwd<1>(grid, p, cp, o, rec, rec_grads, g, s); break;
-    case 2: launch_projection_bwd<2>(grid, p, cp, o, rec, rec_grads, g, s); break;
-    default: launch_projection_bwd<3>(grid, p, cp, o, rec, rec_grads, g, s); break;
+    case 0: launch_projection_bwd<0>(grid, p, cp, o, rec_grads, g, s); break;
+    case 1: launch_projection_bwd<1>(grid, p, cp, o, rec_grads, g, s); break;
+    case 2: launch_projection_bwd<2>(grid, p, cp, o, rec_grads, g, s); break;
+    default: launch_projection_bwd<3>(grid, p, cp, o, rec_grads, g, s); break;
   }
   return hipGetLastError();
 }
