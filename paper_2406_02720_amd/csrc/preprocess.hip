@@ -302,6 +302,26 @@ __global__ __launch_bounds__(kScanBlock) void scan_partials_kernel(uint64_t* __r
   if (threadIdx.x == 0) *total = run;
 }
 
+// The entry total from the projection's per-workgroup partials: one
+// workgroup, every load issued at once (a scan is not needed here).
+constexpr int kSumThreads = 1024;
+__global__ __launch_bounds__(kSumThreads) void sum_partials_kernel(const uint64_t* __restrict__ partial, int64_t m,
+                                                                   uint64_t* __restrict__ total) {
+  __shared__ uint64_t s_w[kSumThreads / 64];
+  uint64_t x = 0;
+  for (int64_t i = threadIdx.x; i < m; i += kSumThreads) x += partial[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kSumThreads / 64; ++w) t += s_w[w];
+    *total = t;
+  }
+}
+
 // Small inputs: the whole scan in one workgroup (one launch instead of
 // three).
 constexpr int64_t kScanSmall = 8192;
@@ -662,7 +682,7 @@ hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, 
     }
   }
   if (offsets) return launch_scan(tiles, n_rec, offsets, total, ws, s);
-  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, partial, p.n > 0 ? (int64_t)grid : 0,
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kSumThreads), 0, s, partial, p.n > 0 ? (int64_t)grid : 0,
                      total);
   return hipGetLastError();
 }

@@ -191,12 +191,16 @@ __global__ __launch_bounds__(kHistScanThreads) void hist_scan_kernel(const uint3
 // depth-first path
 // ---------------------------------------------------------------------------
 // Depth key of every record (culled records sort last and emit nothing) and
-// the histograms of its four digits.
+// the histograms of its four digits; also each record's tile rectangle in
+// record order (tx0 | w << 16, ty0 | ty1 << 16; w = 0 for a culled record):
+// the depth-order gather of the rectangles then reads this compact array
+// instead of whole records.
 __global__ __launch_bounds__(kBlock) void depth_keys_kernel(const Record* __restrict__ rec,
                                                             const uint32_t* __restrict__ tiles,
                                                             int64_t n_rec, uint32_t* __restrict__ keys,
                                                             uint32_t* __restrict__ ids,
-                                                            uint32_t* __restrict__ hist) {
+                                                            uint32_t* __restrict__ hist,
+                                                            uint2* __restrict__ rects, int sh) {
   __shared__ uint32_t s_h[4 * kRadix];
   for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) s_h[i] = 0u;
   __syncthreads();
@@ -206,9 +210,15 @@ __global__ __launch_bounds__(kBlock) void depth_keys_kernel(const Record* __rest
     const bool ok = i < n_rec;
     uint32_t k = 0xffffffffu;
     if (ok) {
-      k = tiles[i] ? rec[i].depth : 0xffffffffu;
+      const bool vis = tiles[i] != 0u;
+      // the record's last 16 bytes: rect x, rect y, depth bits, tiles
+      const uint4 q = reinterpret_cast<const uint4*>(rec + i)[3];
+      k = vis ? q.z : 0xffffffffu;
       keys[i] = k;
       ids[i] = (uint32_t)i;
+      const uint32_t tx0 = (q.x & 0xffffu) >> sh, tx1 = (q.x >> 16) >> sh;
+      const uint32_t ty0 = (q.y & 0xffffu) >> sh, ty1 = (q.y >> 16) >> sh;
+      rects[i] = vis ? make_uint2(tx0 | ((tx1 - tx0 + 1) << 16), ty0 | (ty1 << 16)) : make_uint2(0u, 0u);
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p) wave_hist_add(s_h + p * kRadix, (k >> (8 * p)) & 0xffu, ok);
@@ -642,14 +652,6 @@ __device__ __forceinline__ void camera_bands(const CamPack& cp, int c, int64_t* 
   *rows = band_rows(cp.cam[c].tiles_x);
 }
 
-// A record's tile rectangle, packed: record id, tx0 | w << 16, ty0 | ty1 << 16,
-// camera.
-__device__ __forceinline__ uint4 tile_desc(const Record& R, int sh, uint32_t r, int cam) {
-  const uint32_t tx0 = (R.xr & 0xffffu) >> sh, tx1 = (R.xr >> 16) >> sh;
-  const uint32_t ty0 = (R.yr & 0xffffu) >> sh, ty1 = (R.yr >> 16) >> sh;
-  return make_uint4(r, tx0 | ((tx1 - tx0 + 1) << 16), ty0 | (ty1 << 16), (uint32_t)cam);
-}
-
 __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t x, int lane, uint32_t* total) {
   uint32_t inc = x;
 #pragma unroll
@@ -661,21 +663,22 @@ __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t x, int lane, uin
   return inc - x;
 }
 
-// Per slot j of the depth order: the record's tile rectangle and the number
-// of bands it meets.
-__global__ __launch_bounds__(kBlock) void place_desc_kernel(const Record* __restrict__ rec,
-                                                            const uint32_t* __restrict__ order,
-                                                            const uint32_t* __restrict__ tiles, int64_t n_rec,
+// Per slot j of the depth order: the record's tile rectangle, packed as
+// record id, tx0 | w << 16, ty0 | ty1 << 16, camera (from the compact
+// rectangles of depth_keys_kernel), and the number of bands it meets.
+__global__ __launch_bounds__(kBlock) void place_desc_kernel(const uint2* __restrict__ rects,
+                                                            const uint32_t* __restrict__ order, int64_t n_rec,
                                                             int64_t n_per_cam, CamPack cp, uint4* __restrict__ desc,
                                                             uint32_t* __restrict__ nbands) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= n_rec) return;
   const uint32_t r = order[j];
+  const uint2 c = rects[r];
   uint32_t nb = 0;
   uint4 d = make_uint4(r, 0u, 0u, 0u);
-  if (tiles[r] != 0u) {
+  if ((c.x >> 16) != 0u) {   // w >= 1: not culled
     const int cam = (int)(r / (uint64_t)n_per_cam);
-    d = tile_desc(rec[r], cp.tile_shift, r, cam);
+    d = make_uint4(r, c.x, c.y, (uint32_t)cam);
     const uint32_t rows = (uint32_t)band_rows(cp.cam[cam].tiles_x);
     nb = (d.z >> 16) / rows - (d.z & 0xffffu) / rows + 1;
   }
@@ -1338,8 +1341,12 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                          0, s, keys, 32, n_dup, capacity, ranges);
   } else {
     // 1. records in (depth, id) order
+    // the compact rectangles live in the pair-offset buffer, which is only
+    // written after their last reader (place_desc_kernel)
+    static_assert(sizeof(uint2) == sizeof(uint64_t), "one rectangle per pair offset");
+    uint2* rects = reinterpret_cast<uint2*>(w.poff);
     hipLaunchKernelGGL(depth_keys_kernel, dim3(grid_for(n_rec, kBlock, 2048)), dim3(kBlock), 0, s, rec,
-                       tiles, n_rec, w.rkeys[0], w.rids[0], hist_rec);
+                       tiles, n_rec, w.rkeys[0], w.rids[0], hist_rec, rects, cp.tile_shift);
     hipLaunchKernelGGL(hist_scan_kernel, dim3(1), dim3(kHistScanThreads), 0, s, hist_rec, base_rec, 4);
     if (n_rec > 0)
       onesweep_passes<uint32_t, kSmallItems>(w.rkeys, w.rids, nullptr, n_rec, 0, 4, base_rec, w, w.tickets,
@@ -1351,8 +1358,8 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
     uint64_t* n_items = w.scalars + 1;
     // 2. tile rectangles in depth order, (band, slot) pairs sorted by band
     //    (stable: slots stay in depth order inside a band)
-    hipLaunchKernelGGL(place_desc_kernel, dim3(grid_for(n_rec, kBlock, 1ll << 31)), dim3(kBlock), 0, s, rec,
-                       order, tiles, n_rec, n_per_cam, cp, w.desc, w.nbands);
+    hipLaunchKernelGGL(place_desc_kernel, dim3(grid_for(n_rec, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
+                       (const uint2*)rects, order, n_rec, n_per_cam, cp, w.desc, w.nbands);
     hipError_t e = launch_scan(w.nbands, n_rec, w.poff, n_pairs, w.scan_ws, s);
     if (e != hipSuccess) return e;
     const int bpasses = (g.band_bits + 7) / 8;
