@@ -267,13 +267,76 @@ class PipelineStep:
         stage_ms /= steps
         return ms_step, {k: float(v) for k, v in zip(self.STAGES, stage_ms)}
 
-    def pair_counts(self):
-        """Pairs the raster must evaluate (for every pixel, the entries of its
-        tile list up to its last blended one) and blended pairs."""
+    def pair_counts(self, chunk: int = 32768):
+        """(pairs, tested, listed, blended): `pairs` are the pixel-entry pairs
+        the raster must evaluate -- for every pixel, the entries of its tile
+        list up to its last blended one whose record's pixel rect contains
+        the pixel (the rect test is the raster's first, per wavefront; pixels
+        outside it are never evaluated); `tested` those of them whose
+        Gaussian exponent passes the bound below which alpha_min cannot be
+        reached (the raster's second test; only these go on to exp, the half
+        factor and Eq. 10); `listed` counts every entry up to the last
+        blended one, rect or not; `blended` the blended pairs.  Counted on
+        the device from the step's own buffers, tile by tile (the exponent
+        in float32 as the raster forms it, so a pair on the bound may
+        count either way)."""
         torch = self.torch
-        pairs = int((self.last_idx.to(torch.int64) + 1).sum().item())
+        listed = int((self.last_idx.to(torch.int64) + 1).sum().item())
         blended = int(self.n_contrib.to(torch.int64).sum().item())
-        return pairs, blended
+        T = int(self.opts.tile)
+        dev = self.last_idx.device
+        rec = self.records.view(torch.int32).view(-1, 16)
+        recf = self.records.view(torch.float32).view(-1, 16)
+        xr, yr = rec[:, 12].to(torch.int64), rec[:, 13].to(torch.int64)
+        log2e = 1.4426950408889634
+        l2amin = math.log2(float(self.opts.alpha_min))
+        tested = 0
+        ranges = self.ranges.view(-1, 2).to(torch.int64)
+        vals = self.values.to(torch.int64)
+        lin = torch.arange(T, device=dev)
+        pairs = 0
+        tile_off = pix_off = 0
+        for cam in self.cameras:
+            W, H = int(cam["width"]), int(cam["height"])
+            tx, ty = (W + T - 1) // T, (H + T - 1) // T
+            nt = tx * ty
+            pad = torch.full((ty * T, tx * T), -1, dtype=torch.int32, device=dev)
+            pad[:H, :W] = self.last_idx[pix_off:pix_off + W * H].view(H, W)
+            lt = pad.view(ty, T, tx, T).permute(0, 2, 1, 3).reshape(nt, T, T)   # [tile][row][col]
+            r = ranges[tile_off:tile_off + nt]
+            cnt = r[:, 1] - r[:, 0]
+            total = int(cnt.sum().item())
+            if total:
+                tid = torch.repeat_interleave(torch.arange(nt, device=dev), cnt)
+                first = torch.cumsum(cnt, 0) - cnt
+                pos = torch.arange(total, device=dev) - first[tid]
+                rid = vals[r[tid, 0] + pos]
+                ox, oy = (tid % tx) * T, (tid // tx) * T
+                x0, x1 = (xr[rid] & 0xffff) - ox, (xr[rid] >> 16) - ox
+                y0, y1 = (yr[rid] & 0xffff) - oy, (yr[rid] >> 16) - oy
+                f = recf[rid]
+                hb = torch.maximum(f[:, 7], f[:, 7] + 2.0 * f[:, 11])
+                p2min = (l2amin - torch.log2(hb)) - 2.0 ** -10
+                linf = lin.to(torch.float32) + 0.5
+                for a in range(0, total, chunk):
+                    b = min(a + chunk, total)
+                    colm = (lin[None, :] >= x0[a:b, None]) & (lin[None, :] <= x1[a:b, None])
+                    rowm = (lin[None, :] >= y0[a:b, None]) & (lin[None, :] <= y1[a:b, None])
+                    live = lt[tid[a:b]] >= pos[a:b, None, None].to(torch.int32)
+                    inr = live & rowm[:, :, None] & colm[:, None, :]
+                    pairs += int(inr.sum().item())
+                    fa = f[a:b]
+                    dx = (linf[None, :] - x0[a:b, None].to(torch.float32)) - fa[:, 0:1]        # [E, col]
+                    dy = (linf[None, :] - y0[a:b, None].to(torch.float32)) - fa[:, 1:2]        # [E, row]
+                    p2a = fa[:, 4:5] * (dx * dx * (-0.5 * log2e))
+                    p2b = fa[:, 5:6] * (dx * -log2e)
+                    p2c = fa[:, 6:7] * (-0.5 * log2e)
+                    p2 = (p2c[:, :, None] * dy[:, :, None] + p2b[:, None, :]) * dy[:, :, None] + p2a[:, None, :]
+                    ok = (p2 <= 0.0) & (p2 >= p2min[a:b, None, None])
+                    tested += int((inr & ok).sum().item())
+            tile_off += nt
+            pix_off += W * H
+        return pairs, tested, listed, blended
 
     def summary(self, steps, warmup):
         ms, st = self.time(steps, warmup)
@@ -381,7 +444,7 @@ def main():
     n_dup, n_rec, tiles_total = run.n_dup, run.n_rec, run.tiles_total
     ms_step, st = run.time(args.steps, args.warmup)
     stage_names = PipelineStep.STAGES
-    pairs, blended = run.pair_counts()
+    pairs, tested, listed, blended = run.pair_counts()
     ns = len(stage_names)
 
     fwd_ms = st["preprocess"] + st["bin_sort"] + st["render_fwd"]
@@ -404,12 +467,14 @@ def main():
         passes = 0
         bytes_sort = n_rec * (16 + 4 * 16 + 16) + 4 * n_dup + 8 * tiles_total
     bytes_pbwd = n * (param_bytes + param_bytes) + n_rec * (48 + 48 + 4)
-    # FP32 operations of one pair, written out (fma = 2): evaluation
-    # (offsets, quadratic form, exp, half factor, Eq. 10 opacity, clamp) and,
-    # for a blended pair, compositing; backward adds the gradient formulas.
-    F_EVAL, F_BLEND, F_GRAD = 42.0, 9.0, 75.0
-    flops_fwd = pairs * F_EVAL + blended * F_BLEND
-    flops_bwd = pairs * F_EVAL + blended * (F_BLEND + F_GRAD)
+    # FP32 operations of one pair, written out (fma = 2): the exponent test
+    # of every pair in a record's rect (row offset, the quadratic in it, two
+    # comparisons), the rest of the evaluation for the pairs past it (exp,
+    # the alpha_min bound, half factor, Eq. 10 opacity, clamp) and, for a
+    # blended pair, compositing; backward adds the gradient formulas.
+    F_TEST, F_EVAL, F_BLEND, F_GRAD = 8.0, 34.0, 9.0, 75.0
+    flops_fwd = pairs * F_TEST + tested * F_EVAL + blended * F_BLEND
+    flops_bwd = pairs * F_TEST + tested * F_EVAL + blended * (F_BLEND + F_GRAD)
     roof = {}
     copy_gbs = copy_bandwidth()
 
@@ -444,8 +509,9 @@ def main():
     if args.stages:
         for name in stage_names:
             print(f"{name:15s} {st[name]:8.3f} ms", file=sys.stderr)
-        print(f"n_dup {n_dup}  entry passes {passes}  pairs {pairs}  blended {blended}  step {ms_step:.3f} ms",
-              file=sys.stderr)
+        print(f"n_dup {n_dup}  entry passes {passes}  pairs {pairs} (tested {tested}, listed {listed})  "
+              f"blended {blended}  "
+              f"step {ms_step:.3f} ms", file=sys.stderr)
         print(json.dumps(roof), file=sys.stderr)
 
     auto = None
@@ -485,6 +551,8 @@ def main():
         "stage_ms": {k: round(float(v), 4) for k, v in st.items()},
         "roofline": roofline,
         "roofline_stages": roof,
+        "work": {"pairs_in_rect": pairs, "pairs_past_exponent_test": tested, "pairs_listed": listed,
+                 "blended": blended},
         "copy_GBps": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "autograd": auto,
