@@ -80,7 +80,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--tile", type=int, default=0,
+                    help="tile edge in pixels (8, 16, 32); 0: raster.default_tile for the workload's views")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cpu-pixels", type=int, default=1024, help="pixels of the oracle CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -171,6 +172,7 @@ class PipelineStep:
         self.n, self.deg, self.cameras = n, deg, cams
         self.soa = R.scene_to_soa(scene, dev)
         self.cams = ca = B.make_cameras(cams)
+        self.tile = tile = tile or R.default_tile(cams)
         self.opts = opts = B.default_options(tile=tile, batch=batch, sort_full_keys=full_keys)
         self.opts.flags |= flags
         self.target = torch.cat([torch.as_tensor(t).reshape(-1) for t in scenes.target_image(cams, seed=102)]).to(dev)
@@ -394,7 +396,7 @@ def extra_workloads(args, dev):
         target = st.target
         del st
         torch.cuda.empty_cache()
-        rast = R.Rasterizer(cams, scene["sh_degree"], tile=args.tile, batch=args.batch, persistent=True)
+        rast = R.Rasterizer(cams, scene["sh_degree"], tile=args.tile or None, batch=args.batch, persistent=True)
 
         def auto_step():
             planes.grad = None
@@ -440,6 +442,7 @@ def main():
     n = scene["means"].shape[0]
     deg = scene["sh_degree"]
     run = PipelineStep(scene, cams, args.tile, args.batch, args.persistent, args.full_keys, dev)
+    tile = run.tile
     soa, target, ca, opts = run.soa, run.target, run.cams, run.opts
     n_dup, n_rec, tiles_total = run.n_dup, run.n_rec, run.tiles_total
     ms_step, st = run.time(args.steps, args.warmup)
@@ -502,8 +505,8 @@ def main():
     roofline["kernel"] = dominant
     kname = {"render_fwd": "render_fwd", "raster_bwd": "render_bwd", "preprocess_bwd": "preprocess_bwd"}[dominant]
     if dominant in ("render_fwd", "raster_bwd"):
-        kname += f"_persistent_kernel<{args.tile},{args.batch // 64}>" if args.persistent else \
-            f"_kernel<{args.tile},{args.batch // 64}>"
+        kname += f"_persistent_kernel<{tile},{args.batch // 64}>" if args.persistent else \
+            f"_kernel<{tile},{args.batch // 64}>"
     roofline["traffic"] = measured_traffic(kname)
 
     if args.stages:
@@ -543,7 +546,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS.get(args.config, str(args.config)), "n_kernels": n,
-                   "views": len(cams), "pixels": W, "tile": args.tile, "batch": args.batch,
+                   "views": len(cams), "pixels": W, "tile": tile, "batch": args.batch,
                    "entries": n_dup, "sort": "full_keys" if args.full_keys else "placement",
                    "raster": "persistent" if args.persistent else "per_tile"},
         "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
@@ -575,7 +578,7 @@ def autograd_bench(args, soa, deg, cams, target, ms_step):
     from paper_2406_02720_amd import raster as R
 
     planes = soa.clone().requires_grad_(True)
-    rast = R.Rasterizer(cams, deg, tile=args.tile, batch=args.batch, persistent=args.persistent)
+    rast = R.Rasterizer(cams, deg, tile=args.tile or None, batch=args.batch, persistent=args.persistent)
 
     def step():
         planes.grad = None
@@ -680,7 +683,7 @@ def multiview(args):
     tgt = [torch.as_tensor(t).reshape(-1).to(dev) for t in scenes.target_image(cams, seed=102)]
     target = torch.cat(tgt)
     W = sum(c["width"] * c["height"] for c in cams)
-    tile, batch, persistent, tuned, tune_s = args.tile, args.batch, True, None, None
+    tile, batch, persistent, tuned, tune_s = args.tile or R.default_tile(cams), args.batch, True, None, None
     if not args.no_autotune:
         t0 = time.perf_counter()
         tile, batch, persistent, tuned = BT.autotune(soa, n, deg, cams, target, cache_path=args.autotune or None)

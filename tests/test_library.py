@@ -172,3 +172,15 @@ def test_noalloc_preprocess_rejects_more_records_than_its_array_holds():
     # null outputs are still EINVAL
     rc = lib.hgs_preprocess_noalloc(C.byref(p), ca, 3, C.byref(o), None, None, None, fake, None)
     assert rc == B.HGS_EINVAL
+
+
+def test_default_tile_keeps_four_workgroups_per_cu():
+    """32-pixel tiles while their count stays at 1024 or more, else 16."""
+    from paper_2406_02720_amd import raster as R
+    cam = lambda w, h: dict(width=w, height=h)  # noqa: E731
+    assert R.default_tile([cam(1920, 1080)]) == 32          # 60 x 34 = 2040 tiles
+    assert R.default_tile([cam(1280, 720)]) == 16           # 40 x 23 = 920
+    assert R.default_tile([cam(1280, 720)] * 2) == 32       # 1840 over two views
+    assert R.default_tile([cam(1024, 1024)]) == 32          # exactly 1024
+    assert R.default_tile([cam(1023, 1024)]) == 32
+    assert R.default_tile([cam(992, 1024)]) == 16           # 31 x 32 = 992
