@@ -959,7 +959,7 @@ constexpr int kEmitPerWave = kBlockPairs / kEmitWaves;
 static_assert(kEmitPerWave == 64, "one pair per lane in the decode");
 static_assert(kBlockPairs < 65536, "16-bit cursors");
 constexpr int kEmitWideTiles = 512;
-constexpr size_t kEmitLdsBytes = 65536 - 256;  // dynamic part; the static s_wsum sits beside it
+constexpr size_t kEmitLdsBytes = 65536 - 512;  // dynamic part; the static s_wsum and s_spare sit beside it
 
 // LDS words of the cursor area per tile, and the fixed part in bytes.
 inline bool emit_packed(int band_tiles) { return band_tiles > kEmitWideTiles; }
@@ -998,6 +998,7 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
   uint32_t* s_off = s_start + band_tiles + 1;       // [band_tiles] run start in the tile's list
   uint32_t* s_stage = s_off + band_tiles;           // [stage_cap]
   __shared__ uint32_t s_wsum[kEmitWaves];
+  __shared__ uint32_t s_spare[64];   // target of the walk's idle lanes
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const bool over = *n_dup > (uint64_t)capacity;
   if (blockIdx.x == 0 && tid == 0) *overflow = over ? 1 : 0;
@@ -1127,7 +1128,7 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
   // pass 2: slots in record order per tile
   uint32_t* dst = staged ? s_stage : vals;
   const uint32_t* run_base = staged ? s_start : s_off;
-  for (int l = 0; l < cnt; ++l) {
+  auto walk_one = [&](int l) {
     const int n = __builtin_amdgcn_readlane(dn, l);
     const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)dR, l);
     const int W = __builtin_amdgcn_readlane((int)dW, l);
@@ -1145,7 +1146,47 @@ __global__ __launch_bounds__(kEmitThreads) void place_emit_kernel(
         }
       }
     }
+  };
+  int l = 0;
+  if constexpr (!PACKED) {
+    // four records at a time while each has at most 64 entries in the
+    // band: their four fetch-and-adds are in flight together instead of one
+    // round trip per record.  A tile that several of them cover still gets
+    // its slots in record order: a wavefront's LDS operations complete in
+    // the order it issues them.
+    constexpr int G = 4;
+    for (; l + G <= cnt; l += G) {
+      int n[G], t[G];
+      uint32_t R[G], slot[G];
+      int nmax = 0;
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        n[k] = __builtin_amdgcn_readlane(dn, l + k);
+        nmax = n[k] > nmax ? n[k] : nmax;
+      }
+      if (nmax > 64) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) walk_one(l + k);
+        continue;
+      }
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        R[k] = (uint32_t)__builtin_amdgcn_readlane((int)dR, l + k);
+        const int W = __builtin_amdgcn_readlane((int)dW, l + k);
+        const int base = __builtin_amdgcn_readlane(dbase, l + k);
+        t[k] = entry_tile(lane, W, n[k], __builtin_amdgcn_rcpf((float)W), base, B.tx);
+      }
+      // every lane issues each fetch-and-add (lanes past a record's entries
+      // on a word of their own), so no branch separates the four and they
+      // are in flight together
+#pragma unroll
+      for (int k = 0; k < G; ++k) slot[k] = atomicAdd(lane < n[k] ? &cur[t[k]] : &s_spare[lane], 1u);
+#pragma unroll
+      for (int k = 0; k < G; ++k)
+        if (lane < n[k]) dst[slot[k]] = R[k];
+    }
   }
+  for (; l < cnt; ++l) walk_one(l);
   if (!staged) continue;
   __syncthreads();
   // copy out, one tile run per wavefront step: contiguous in the staging
