@@ -74,6 +74,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagPrefix = 2ull << 62;
 constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr int kLookWindow = 8;   // look-back flags requested per round trip
 constexpr int kMaxPasses = 8;
 constexpr int kHistWords = 2 * kMaxPasses * kRadix;  // one replica: record + entry passes
 
@@ -468,20 +469,38 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     s_keys[pos] = key[i];
     s_vals[pos] = val[i];
   }
-  // decoupled look-back for digit t
+  // decoupled look-back for digit t, kLookWindow predecessors per round
+  // trip: their flags are requested together, then taken in order until an
+  // inclusive prefix (done), an unpublished one (wait, then read again from
+  // it) or the end of the window (the next window).  Partition 0 always
+  // holds a prefix, and a read below it counts as an empty prefix, so the
+  // walk ends.
   uint64_t excl = 0;
   if (part > 0) {
     int64_t j = (int64_t)part - 1;
     while (true) {
-      const uint64_t w = ld_flag(lookback + (uint64_t)j * kRadix + t);
-      const uint64_t flag = w & ~kValueMask;
-      if (flag == 0) {
-        __builtin_amdgcn_s_sleep(1);
-        continue;
+      uint64_t w[kLookWindow];
+#pragma unroll
+      for (int q = 0; q < kLookWindow; ++q)
+        w[q] = j - q >= 0 ? ld_flag(lookback + (uint64_t)(j - q) * kRadix + t) : kFlagPrefix;
+      int used = kLookWindow;
+      bool done = false;
+#pragma unroll
+      for (int q = 0; q < kLookWindow; ++q) {
+        const uint64_t flag = w[q] & ~kValueMask;
+        if (flag == 0) {
+          used = q;
+          break;
+        }
+        excl += w[q] & kValueMask;
+        if (flag == kFlagPrefix) {
+          done = true;
+          break;
+        }
       }
-      excl += w & kValueMask;
-      if (flag == kFlagPrefix) break;
-      --j;
+      if (done) break;
+      j -= used;
+      if (used != kLookWindow) __builtin_amdgcn_s_sleep(1);
     }
     st_flag(my, kFlagPrefix | (excl + tot));
   }
