@@ -119,24 +119,22 @@ __device__ __forceinline__ void flush_hist(const uint32_t* s_h, int words, uint3
 }
 
 // ---------------------------------------------------------------------------
-// Clears the digit histograms and pass tickets, and (placement path) the
-// band ranges and tile totals, which are only written later in the call.
+// Clears the digit histograms, the pass tickets, the look-back flags of the
+// first one-sweep pass (every pass clears those of the next) and
+// (placement path) the band ranges and tile totals, which are only written
+// later in the call.
 __global__ __launch_bounds__(kBlock) void sort_init_kernel(uint32_t* __restrict__ hist,
                                                            uint32_t* __restrict__ tickets,
+                                                           uint64_t* __restrict__ lookback, int64_t n_lookback,
                                                            uint32_t* __restrict__ brange, int64_t n_brange,
                                                            uint32_t* __restrict__ totals, int64_t n_totals) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = t; i < (int64_t)kHistCopies * kHistWords; i += stride) hist[i] = 0u;
   for (int64_t i = t; i < 2 * kMaxPasses; i += stride) tickets[i] = 0u;
+  for (int64_t i = t; i < n_lookback; i += stride) lookback[i] = 0ull;
   for (int64_t i = t; i < n_brange; i += stride) brange[i] = 0u;
   for (int64_t i = t; i < n_totals; i += stride) totals[i] = 0u;
-}
-
-__global__ __launch_bounds__(kBlock) void zero_u64_kernel(uint64_t* __restrict__ p, int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = t; i < n; i += stride) p[i] = 0ull;
 }
 
 __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -385,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint64_t* __restrict__ n_dev, int64_t capacity, int shift,
     const uint32_t* __restrict__ digit_base, uint64_t* __restrict__ lookback,
-    uint64_t* __restrict__ lookback_next, uint32_t* __restrict__ ticket) {
+    uint64_t* __restrict__ lookback_next, int64_t n_lookback, uint32_t* __restrict__ ticket) {
   constexpr int PART = kBlock * ITEMS;
   __shared__ K s_keys[PART];
   __shared__ uint32_t s_vals[PART];
@@ -398,6 +396,10 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const uint64_t n = entry_count(n_dev, capacity);
   const uint64_t parts = (n + PART - 1) / PART;
+  // the next pass's look-back flags, all of them (whatever its partition
+  // count): this pass does not read them and the previous one is done
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < n_lookback; i += (int64_t)gridDim.x * kBlock)
+    lookback_next[i] = 0ull;
   // persistent: partitions are taken by ticket until none is left (a
   // partition's look-back only waits on lower tickets, held by running
   // workgroups)
@@ -407,7 +409,6 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   __syncthreads();
   const uint32_t part = s_part;
   if (part >= parts) return;
-  lookback_next[(uint64_t)part * kRadix + t] = 0ull;
 
   const uint64_t base = (uint64_t)part * PART;
   const uint64_t wbase = base + (uint64_t)wave * 64 * ITEMS;
@@ -1332,12 +1333,13 @@ void onesweep_passes(K** kb, uint32_t** vb, const uint64_t* n_dev, int64_t cap, 
   const int64_t parts = (cap + PART - 1) / PART > 0 ? (cap + PART - 1) / PART : 1;
   const unsigned grid = (unsigned)(parts < kSweepGrid ? parts : kSweepGrid);
   if (passes <= 0) return;
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_for(parts * kRadix, kBlock, 4096)), dim3(kBlock), 0, s,
-                     w.lookback[lb & 1], parts * kRadix);
+  // look-back flags: sort_init_kernel cleared those of the call's first
+  // pass, each pass clears the next one's
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL((onesweep_kernel<K, ITEMS>), dim3(grid), dim3(kBlock), 0, s, kb[p & 1], vb[p & 1],
                        kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, cap, first_shift + 8 * p,
-                       bases + p * kRadix, w.lookback[lb & 1], w.lookback[(lb + 1) & 1], tickets + p);
+                       bases + p * kRadix, w.lookback[lb & 1], w.lookback[(lb + 1) & 1], w.parts * kRadix,
+                       tickets + p);
     ++lb;
   }
 }
@@ -1368,9 +1370,10 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
   int lb = 0;  // look-back buffer in use
   const int64_t n_brange = full_keys ? 0 : 2 * (int64_t)w.geom.n_bands;
   const int64_t n_totals = full_keys ? 0 : (int64_t)cp.tiles_total;
-  const int64_t n_init = kHistCopies * kHistWords > n_totals ? kHistCopies * kHistWords : n_totals;
+  int64_t n_init = kHistCopies * kHistWords > n_totals ? kHistCopies * kHistWords : n_totals;
+  n_init = n_init > w.parts * kRadix ? n_init : w.parts * kRadix;
   hipLaunchKernelGGL(sort_init_kernel, dim3(grid_for(n_init, kBlock, 4096)), dim3(kBlock), 0, s, w.hist,
-                     w.tickets, w.brange, n_brange, w.totals, n_totals);
+                     w.tickets, w.lookback[0], w.parts * kRadix, w.brange, n_brange, w.totals, n_totals);
   const unsigned dup_grid = grid_for((capacity + kChunk - 1) / kChunk, kWaves, 1 << 30);
 
   if (full_keys) {
