@@ -307,38 +307,39 @@ class PipelineStep:
             lt = pad.view(ty, T, tx, T).permute(0, 2, 1, 3).reshape(nt, T, T)   # [tile][row][col]
             r = ranges[tile_off:tile_off + nt]
             cnt = r[:, 1] - r[:, 0]
-            total = int(cnt.sum().item())
-            if total:
-                tid = torch.repeat_interleave(torch.arange(nt, device=dev), cnt)
-                first = torch.cumsum(cnt, 0) - cnt
-                pos = torch.arange(total, device=dev) - first[tid]
+            ends = torch.cumsum(cnt, 0)
+            first = ends - cnt
+            total = int(ends[-1].item()) if nt else 0
+            linf = lin.to(torch.float32) + 0.5
+            # entries in chunks of the camera's concatenated tile lists (no
+            # array over all of its entries: a 4K view holds ~10^8)
+            for a in range(0, total, chunk):
+                k = torch.arange(a, min(a + chunk, total), device=dev)
+                tid = torch.searchsorted(ends, k, right=True)
+                pos = k - first[tid]
                 rid = vals[r[tid, 0] + pos]
                 ox, oy = (tid % tx) * T, (tid // tx) * T
                 x0, x1 = (xr[rid] & 0xffff) - ox, (xr[rid] >> 16) - ox
                 y0, y1 = (yr[rid] & 0xffff) - oy, (yr[rid] >> 16) - oy
+                colm = (lin[None, :] >= x0[:, None]) & (lin[None, :] <= x1[:, None])
+                rowm = (lin[None, :] >= y0[:, None]) & (lin[None, :] <= y1[:, None])
+                live = lt[tid] >= pos[:, None, None].to(torch.int32)
+                inr = live & rowm[:, :, None] & colm[:, None, :]
+                pairs = pairs + inr.sum()
                 f = recf[rid]
                 hb = torch.maximum(f[:, 7], f[:, 7] + 2.0 * f[:, 11])
                 p2min = (l2amin - torch.log2(hb)) - 2.0 ** -10
-                linf = lin.to(torch.float32) + 0.5
-                for a in range(0, total, chunk):
-                    b = min(a + chunk, total)
-                    colm = (lin[None, :] >= x0[a:b, None]) & (lin[None, :] <= x1[a:b, None])
-                    rowm = (lin[None, :] >= y0[a:b, None]) & (lin[None, :] <= y1[a:b, None])
-                    live = lt[tid[a:b]] >= pos[a:b, None, None].to(torch.int32)
-                    inr = live & rowm[:, :, None] & colm[:, None, :]
-                    pairs += int(inr.sum().item())
-                    fa = f[a:b]
-                    dx = (linf[None, :] - x0[a:b, None].to(torch.float32)) - fa[:, 0:1]        # [E, col]
-                    dy = (linf[None, :] - y0[a:b, None].to(torch.float32)) - fa[:, 1:2]        # [E, row]
-                    p2a = fa[:, 4:5] * (dx * dx * (-0.5 * log2e))
-                    p2b = fa[:, 5:6] * (dx * -log2e)
-                    p2c = fa[:, 6:7] * (-0.5 * log2e)
-                    p2 = (p2c[:, :, None] * dy[:, :, None] + p2b[:, None, :]) * dy[:, :, None] + p2a[:, None, :]
-                    ok = (p2 <= 0.0) & (p2 >= p2min[a:b, None, None])
-                    tested += int((inr & ok).sum().item())
+                dx = (linf[None, :] - x0[:, None].to(torch.float32)) - f[:, 0:1]        # [E, col]
+                dy = (linf[None, :] - y0[:, None].to(torch.float32)) - f[:, 1:2]        # [E, row]
+                p2a = f[:, 4:5] * (dx * dx * (-0.5 * log2e))
+                p2b = f[:, 5:6] * (dx * -log2e)
+                p2c = f[:, 6:7] * (-0.5 * log2e)
+                p2 = (p2c[:, :, None] * dy[:, :, None] + p2b[:, None, :]) * dy[:, :, None] + p2a[:, None, :]
+                ok = (p2 <= 0.0) & (p2 >= p2min[:, None, None])
+                tested = tested + (inr & ok).sum()
             tile_off += nt
             pix_off += W * H
-        return pairs, tested, listed, blended
+        return int(pairs), int(tested), listed, blended
 
     def summary(self, steps, warmup):
         ms, st = self.time(steps, warmup)
