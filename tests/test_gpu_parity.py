@@ -395,8 +395,13 @@ def test_rasterizer_planes_match_the_pipeline_and_rerun_on_overflow():
     g_ref, _ = R.backward_pass(fr, dl)
     torch.cuda.synchronize()
 
-    def same_grads(g):   # per plane, up to the float-atomic order
-        return float(((g - g_ref).norm(dim=1) / g_ref.norm(dim=1).clamp_min(1e-30)).max()) <= 1e-5
+    def same_grads(g):
+        # per plane, up to the order of the float atomics, which differs
+        # between any two runs: repeated runs of this case differ by
+        # 2.5e-7 to 3.8e-6 per plane, dominated by single kernels whose
+        # gradient cancels (one element off by 4e-4 of itself), and once
+        # by more than 1e-5
+        return float(((g - g_ref).norm(dim=1) / g_ref.norm(dim=1).clamp_min(1e-30)).max()) <= 1e-4
 
     assert same_grads(planes.grad)
     assert rast.overflows == 0
