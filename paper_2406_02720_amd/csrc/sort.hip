@@ -979,7 +979,7 @@ constexpr int kEmitPerWave = kBlockPairs / kEmitWaves;
 static_assert(kEmitPerWave == 64, "one pair per lane in the decode");
 static_assert(kBlockPairs < 65536, "16-bit cursors");
 constexpr int kEmitWideTiles = 512;
-constexpr size_t kEmitLdsBytes = 65536 - 512;  // dynamic part; the static s_wsum and s_spare sit beside it
+constexpr size_t kEmitLdsBytes = 32768 - 512;  // dynamic part; the static s_wsum and s_spare sit beside it
 
 // LDS words of the cursor area per tile, and the fixed part in bytes.
 inline bool emit_packed(int band_tiles) { return band_tiles > kEmitWideTiles; }
