@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=1024, help="pixels of the oracle CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage timings to stderr")
+    ap.add_argument("--no-pair-counts", action="store_true",
+                    help="skip counting the raster's pixel-entry pairs (its FLOP roofline then reads zero)")
     ap.add_argument("--full-keys", action="store_true", help="sort the 64-bit keys over all bits")
     ap.add_argument("--persistent", action="store_true",
                     help="persistent raster grid taking tiles longest list first (default: one workgroup per "
@@ -448,7 +450,10 @@ def main():
     n_dup, n_rec, tiles_total = run.n_dup, run.n_rec, run.tiles_total
     ms_step, st = run.time(args.steps, args.warmup)
     stage_names = PipelineStep.STAGES
-    pairs, tested, listed, blended = run.pair_counts()
+    if args.no_pair_counts:     # (profiler runs: the count launches thousands of small kernels)
+        pairs = tested = listed = blended = 0
+    else:
+        pairs, tested, listed, blended = run.pair_counts()
     ns = len(stage_names)
 
     fwd_ms = st["preprocess"] + st["bin_sort"] + st["render_fwd"]
