@@ -20,6 +20,22 @@ static_assert(kPreBlock == kPreprocessRecordsPerPartial, "preprocess workspace: 
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 
+// Element `off4` / 4 of plane `plane` of a parameter field: the plane's
+// start is wave-uniform (scalar registers) and the element's byte offset a
+// 32-bit vector value (n <= INT32_MAX / HGS_MAX_CAMERAS keeps it below
+// 2^31), so each load is one instruction with no 64-bit address arithmetic
+// per lane.
+typedef __attribute__((address_space(1))) char gchar_t;
+typedef __attribute__((address_space(1))) float gfloat_t;
+__device__ __forceinline__ gfloat_t* plane_ptr(const float* field, int64_t plane, int64_t stride, uint32_t off4) {
+  gchar_t* base = (gchar_t*)(field + plane * stride);
+  asm("" : "+s"(base));   // the plane start as an opaque scalar: not folded into per-lane address math
+  return (gfloat_t*)(base + off4);
+}
+__device__ __forceinline__ float plane_at(const float* field, int64_t plane, int64_t stride, uint32_t off4) {
+  return *plane_ptr(field, plane, stride, off4);
+}
+
 // Extents (E-x, E+x, E-y, E+y) of the union of the splatted halves (Sec. 3.4):
 // per direction, a half reaches the full-ellipse tangent extent when the
 // tangent point lies on its side of the plane (sign of g on that axis),
@@ -93,27 +109,28 @@ __device__ __forceinline__ uint64_t preprocess_one(const Params& p, const CamPac
   constexpr int K = (D + 1) * (D + 1);
   uint64_t tiles_sum = 0;
   const int64_t S = p.stride;
+  const uint32_t off4 = (uint32_t)i * 4u;
   float shv[ONE ? 3 * K : 1];
   if (ONE) {
 #pragma unroll
-    for (int j = 0; j < 3 * K; ++j) shv[j] = p.sh[j * S + i];
+    for (int j = 0; j < 3 * K; ++j) shv[j] = plane_at(p.sh, j, S, off4);
   }
   float mu[3], s[3], q[4], nrm[3];
   for (int c = 0; c < 3; ++c) {
-    mu[c] = p.means[c * S + i];
-    s[c] = p.scales[c * S + i];
-    nrm[c] = p.normals[c * S + i];
+    mu[c] = plane_at(p.means, c, S, off4);
+    s[c] = plane_at(p.scales, c, S, off4);
+    nrm[c] = plane_at(p.normals, c, S, off4);
   }
-  for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
-  const float a1 = p.opac1[i];
-  const float a2 = p.opac2[i];
+  for (int c = 0; c < 4; ++c) q[c] = plane_at(p.quats, c, S, off4);
+  const float a1 = plane_at(p.opac1, 0, S, off4);
+  const float a2 = plane_at(p.opac2, 0, S, off4);
   // any non-finite parameter culls the kernel
   bool params_ok = finite((double)a1) && finite((double)a2);
   for (int c = 0; c < 3; ++c)
     params_ok = params_ok && finite((double)mu[c]) && finite((double)s[c]) && finite((double)nrm[c]);
   for (int c = 0; c < 4; ++c) params_ok = params_ok && finite((double)q[c]);
 
-  const double f3 = p.filter3d ? (double)p.filter3d[i] : 0.0;
+  const double f3 = p.filter3d ? (double)plane_at(p.filter3d, 0, S, off4) : 0.0;
   params_ok = params_ok && finite(f3) && f3 >= 0.0;
   KernelGeo kg;
   kernel_geo(mu, s, q, nrm, kg, params_ok ? f3 : 0.0);
@@ -147,9 +164,9 @@ __device__ __forceinline__ uint64_t preprocess_one(const Params& p, const CamPac
           col1 += Y[kk] * (double)shv[kk * 3 + 1];
           col2 += Y[kk] * (double)shv[kk * 3 + 2];
         } else {
-          col0 += Y[kk] * (double)p.sh[(kk * 3 + 0) * S + i];
-          col1 += Y[kk] * (double)p.sh[(kk * 3 + 1) * S + i];
-          col2 += Y[kk] * (double)p.sh[(kk * 3 + 2) * S + i];
+          col0 += Y[kk] * (double)plane_at(p.sh, kk * 3 + 0, S, off4);
+          col1 += Y[kk] * (double)plane_at(p.sh, kk * 3 + 1, S, off4);
+          col2 += Y[kk] * (double)plane_at(p.sh, kk * 3 + 2, S, off4);
         }
       }
       col0 = fmax(col0 + 0.5, 0.0);
