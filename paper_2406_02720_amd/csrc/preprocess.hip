@@ -164,9 +164,11 @@ __device__ __forceinline__ uint64_t preprocess_one(const Params& p, const CamPac
           col1 += Y[kk] * (double)shv[kk * 3 + 1];
           col2 += Y[kk] * (double)shv[kk * 3 + 2];
         } else {
-          col0 += Y[kk] * (double)plane_at(p.sh, kk * 3 + 0, S, off4);
-          col1 += Y[kk] * (double)plane_at(p.sh, kk * 3 + 1, S, off4);
-          col2 += Y[kk] * (double)plane_at(p.sh, kk * 3 + 2, S, off4);
+          // plain indexing: the compiler keeps these loads out of the
+          // camera loop (an opaque plane base would reload them per camera)
+          col0 += Y[kk] * (double)p.sh[(kk * 3 + 0) * S + i];
+          col1 += Y[kk] * (double)p.sh[(kk * 3 + 1) * S + i];
+          col2 += Y[kk] * (double)p.sh[(kk * 3 + 2) * S + i];
         }
       }
       col0 = fmax(col0 + 0.5, 0.0);
