@@ -134,7 +134,7 @@ hipError_t launch_preprocess(const Params& p, const CamPack& cp, const Opts& o, 
 // records per uint64 partial sum of the entry-count scan, and kernels per
 // partial of the projection's own total (the preprocess workspace holds
 // whichever is larger)
-constexpr int64_t kScanRecordsPerPartial = 4096;
+constexpr int64_t kScanRecordsPerPartial = 1024;
 constexpr int64_t kPreprocessRecordsPerPartial = 256;
 size_t scan_workspace_bytes(int64_t n);
 size_t preprocess_workspace_bytes(int64_t n_rec);

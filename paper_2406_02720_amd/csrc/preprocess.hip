@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_kernel(Params p, CamPack
 // exclusive scan of tiles touched (uint32 -> uint64), reduce-then-scan
 // ---------------------------------------------------------------------------
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 16;
+constexpr int kScanItems = 4;    // 1024-item tiles: a million items make ~1000 workgroups
 constexpr int kScanTile = kScanBlock * kScanItems;
 static_assert(kScanTile == kScanRecordsPerPartial, "scan workspace: one partial per kScanTile records");
 
