@@ -203,7 +203,7 @@ class PipelineStep:
             ("ranges", 2 * tiles_total, i32), ("order", tiles_total, i32) if persistent else None,
             ("overflow", 1, i32), ("ws_sort", B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, ca, opts, cap), u8),
             ("images", 3 * npix, f32), ("T_final", npix, f32), ("last_idx", npix, i32), ("n_contrib", npix, i32),
-            ("ws_r", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts), u8),
+            ("ws_r", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, ca, opts, cap), u8),
             ("rgrad", n_rec * B.HGS_RECORD_GRAD_FLOATS, f32), ("dL", 3 * npix, f32)], zero=True)
         self.arena = a
         for name in ("records", "tiles", "ndup", "ws_pre", "values", "ranges", "overflow", "ws_sort", "images",

@@ -166,7 +166,12 @@ void hgs_default_options(hgs_options* opts);
 /* Workspace sizes (bytes) of the calls that take one.  `which` is one of the
  * HGS_WS_* values; n_rec = n_cams * n; capacity = key capacity of
  * hgs_bin_sort.  Returns 0 for invalid arguments.  The hgs_bin_sort
- * workspace must be 256-byte aligned (any hipMalloc result is). */
+ * workspace must be 256-byte aligned (any hipMalloc result is).
+ * HGS_WS_RENDER: 256 bytes, plus room for the strip marks of lists of up to
+ * `capacity` entries (one byte per entry and forward wavefront of a tile:
+ * 4 at 32-pixel tiles, 1 otherwise); capacity 0 gives the 256 bytes without
+ * marks.  Any size from 256 bytes on is valid: marks only make the backward
+ * pass faster (see hgs_raster_bwd). */
 #define HGS_WS_PREPROCESS 0
 #define HGS_WS_BIN_SORT 1
 #define HGS_WS_RENDER 2
@@ -272,7 +277,10 @@ int hgs_bin_sort(const void* records, const uint32_t* tiles_touched, const uint6
  *              camera-space depth of the kernel centres, sum of w_i z_i with
  *              the colour weights w_i (no background term; the depth maps of
  *              Sec. 4, divide by 1 - T_final for the expected depth)
- *   workspace  device, hgs_workspace_bytes(HGS_WS_RENDER, ...) bytes */
+ *   workspace  device, at least hgs_workspace_bytes(HGS_WS_RENDER, ...) bytes
+ *              (capacity 0); with room for the marks of these lists, the
+ *              pass also records, per list position it walks, which pixel
+ *              strips blended that entry, for hgs_raster_bwd */
 int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* ranges,
                    const uint32_t* tile_order, const hgs_camera* cams, int32_t n_cams,
                    const hgs_options* opts, float* images, float* T_final, int32_t* last_idx,
@@ -302,7 +310,8 @@ int hgs_depth_normals(const float* depth, const float* T_final, const hgs_camera
  *   record_grads  device, float [n_cams * n][HGS_RECORD_GRAD_FLOATS] scratch
  *                 (any contents on entry; cleared on return)
  *   grads         device pointers, overwritten
- *   workspace     device, hgs_workspace_bytes(HGS_WS_RENDER, ...) bytes
+ *   workspace     device, the workspace (same pointer and size) given to the
+ *                 hgs_render_fwd call that produced T_final and last_idx
  * params, cams and opts must be those given to hgs_preprocess. */
 int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_cams,
                    const hgs_options* opts, const void* records, const uint32_t* values,
@@ -320,7 +329,12 @@ int hgs_render_bwd(const hgs_params* params, const hgs_camera* cams, int32_t n_c
  * record's 12 gradients to record_grads (device, float
  * [n_cams * n][HGS_RECORD_GRAD_FLOATS]), which the caller must have cleared
  * (hgs_preprocess_bwd leaves it cleared).  n is the kernel count given to
- * hgs_preprocess.
+ * hgs_preprocess.  workspace: the one (same pointer and size) given to the
+ * hgs_render_fwd call over these lists.  Where that call left strip marks,
+ * entries and pixel strips that blended nothing are skipped (they add
+ * nothing to any gradient); the forward pass tags the marks with a key of
+ * the lists, the plane size and the tiling, and a workspace without the
+ * matching tag is replayed in full, with the same gradients.
  *
  * hgs_preprocess_bwd: the chain rule from record_grads to every kernel
  * parameter (summed over cameras, grads overwritten); clears record_grads

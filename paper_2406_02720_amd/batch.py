@@ -81,7 +81,7 @@ class BatchedRasterizer:
             ("ranges", 2 * nt, i32), ("order", nt, i32) if self.persistent else None, ("overflow", 1, i32),
             ("ws_sort", B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, cams, opts, self.capacity), u8),
             ("images", 3 * npix, f32), ("T_final", npix, f32), ("last_idx", npix, i32),
-            ("n_contrib", npix, i32), ("ws_r", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), u8),
+            ("n_contrib", npix, i32), ("ws_r", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts, capacity), u8),
             ("rgrad", max(n_rec, 1) * B.HGS_RECORD_GRAD_FLOATS, f32), ("dL", 3 * npix, f32)], zero=True)
         self.arena = a
         for name in ("records", "tiles", "n_dup", "ws_pre", "values", "ranges", "overflow", "ws_sort", "images",

@@ -250,7 +250,8 @@ size_t hgs_workspace_bytes(int32_t which, int64_t n_rec, const hgs_camera* cams,
                                        (opts->flags & HGS_FLAG_SORT_FULL_KEYS) != 0);
     }
     case HGS_WS_RENDER:
-      return hgs::render_workspace_bytes();
+      if (check_opts(opts) != HGS_OK) return 0;
+      return hgs::render_workspace_bytes(opts->tile, capacity);
     default:
       return 0;
   }
@@ -313,7 +314,8 @@ int hgs_render_fwd(const void* records, const uint32_t* values, const uint32_t* 
     return fail(HGS_ECAPACITY, "workspace too small");
   const hgs::Opts o = hgs::to_opts(*opts);
   hipError_t h = hgs::launch_render_fwd((const hgs::Record*)records, values, ranges, tile_order, cp, o,
-                                        images, T_final, last_idx, n_contrib, depth, workspace, stream);
+                                        images, T_final, last_idx, n_contrib, depth, workspace, workspace_bytes,
+                                        stream);
   if (h != hipSuccess) return hip_fail(h, "render_fwd launch");
   return HGS_OK;
 }
@@ -347,7 +349,8 @@ int hgs_raster_bwd(const void* records, const uint32_t* values, const uint32_t* 
     return fail(HGS_ECAPACITY, "workspace too small");
   const hgs::Opts o = hgs::to_opts(*opts);
   hipError_t h = hgs::launch_render_bwd((const hgs::Record*)records, values, ranges, tile_order, cp, o,
-                                        T_final, last_idx, dL_dimages, record_grads, workspace, stream);
+                                        T_final, last_idx, dL_dimages, record_grads, workspace, workspace_bytes,
+                                        stream);
   if (h != hipSuccess) return hip_fail(h, "raster_bwd launch");
   return HGS_OK;
 }

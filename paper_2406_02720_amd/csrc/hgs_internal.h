@@ -147,20 +147,25 @@ hipError_t launch_bin_sort(const Record* rec, const uint32_t* tiles, const uint6
                            const CamPack& cp, uint64_t* keys, uint32_t* vals, int64_t capacity,
                            uint32_t* ranges, uint32_t* tile_order, int32_t* overflow, void* ws,
                            bool full_keys, hipStream_t s);
+// the fixed head of the render workspace (work counters, mark tag), and the
+// whole workspace with strip-mark planes for lists of up to `capacity`
+// entries (tile: the tile size)
 size_t render_workspace_bytes();
+size_t render_workspace_bytes(int tile, int64_t capacity);
 // tile_order non-null selects the persistent raster (workspace holds its
-// work counters: [0] forward, [1] backward)
+// work counters: [0] forward, [1] backward); the forward pass writes the
+// strip marks that fit in ws_bytes, the backward pass reads them
 hipError_t launch_render_fwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                              const uint32_t* tile_order, const CamPack& cp, const Opts& o,
                              float* img, float* T_final, int32_t* last_idx, int32_t* n_contrib,
-                             float* depth, void* ws, hipStream_t s);
+                             float* depth, void* ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_depth_normals(const float* depth, const float* T_final, const CamPack& cp, uint64_t n_pix,
                                 float* normals, hipStream_t s);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t s);
 hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                              const uint32_t* tile_order, const CamPack& cp, const Opts& o,
                              const float* T_final, const int32_t* last_idx, const float* dL_dimg,
-                             float* rec_grads, void* ws, hipStream_t s);
+                             float* rec_grads, void* ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_mip_filter3d(const float* means, int64_t n, int64_t stride, const CamPack& cp, double s,
                                double margin, float* out, uint32_t* scratch, hipStream_t st);
 int planes_of(int sh_degree);

@@ -166,6 +166,27 @@ struct BwdGeometry {
   static constexpr int ROWSTEP = 64 / SUBX;
 };
 
+// Strip marks.  One byte per tile-list position and forward wavefront: bit
+// j set if some pixel of the wavefront's strip j took that entry.  The
+// backward pass replays exactly the blended pairs -- the same expressions
+// give the same decisions, and a pixel's pairs at or before its last
+// blended entry that pass the tests are the pairs it blended -- so it
+// visits only marked entries, and of those only the marked strips: what it
+// skips would add nothing to any gradient.  The forward pass stores every
+// 64-position round of its walk in which it marked something, so every
+// mark of the pass is in place; other bytes keep what they held, and a
+// stale mark only makes the backward evaluate a strip in full, with the
+// same result.  The backward reads a block's bytes only up to that block's
+// last blended entry.
+constexpr int kMarkKeep = 32;   // rounds of a forward walk whose marks are staged in LDS
+
+struct Marks {
+  uint8_t* base;   // plane f (forward wavefront f of a tile) at base + f * cap; null: no marks
+  uint64_t cap;    // positions per plane: a tile is marked iff its list ends at or before cap
+  uint64_t* tag;   // the forward pass stores `key` here; the backward trusts the planes iff it matches
+  uint64_t key;
+};
+
 __device__ __forceinline__ Record load_record(const Record* __restrict__ rec, uint32_t id) {
   return rec[id];
 }
@@ -245,7 +266,7 @@ __device__ __forceinline__ void fwd_block(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const CamPack& cp, const Opts& o, float* __restrict__ img,
     float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib,
-    float* __restrict__ depth, uint32_t tile, int wave, int lane) {
+    float* __restrict__ depth, const Marks& mk, uint32_t tile, int wave, int lane) {
   using Gm = Geometry<T>;
   constexpr int PPL = Gm::PPL;
   constexpr int RS = Gm::ROWSTEP;
@@ -275,6 +296,20 @@ __device__ __forceinline__ void fwd_block(
   // list holds at most one entry per record)
   const uint32_t* __restrict__ lst = vals + ranges[2 * tile];
   const int64_t len = (int64_t)ranges[2 * tile + 1] - (int64_t)ranges[2 * tile];
+  // this wavefront's mark plane, from the tile's list start (none when the
+  // list ends beyond the planes)
+  uint8_t* __restrict__ marks = nullptr;
+  if (mk.base != nullptr && (uint64_t)ranges[2 * tile + 1] <= mk.cap)
+    marks = mk.base + (uint64_t)wave * mk.cap + ranges[2 * tile];
+  // the marks of the walk's first kMarkKeep rounds wait in LDS until the
+  // walk ends (a walk is a few rounds: pixels end at T_min soon after their
+  // last blended entries); rounds past those are marked in full (0xff: the
+  // backward evaluates every strip there, with the same result).  Stored
+  // round by round they would stall the walk: the entry loop waits for
+  // every vector memory operation in flight, stores included.
+  __shared__ uint8_t s_marks[Gm::WAVES][kMarkKeep * 64];
+  uint8_t* s_mk = s_marks[wave];
+  int walked = 0;   // rounds walked
   const float amin = o.alpha_min, amax = o.alpha_max, tmin = o.t_min;
   const float l2amin = __builtin_amdgcn_logf(amin);
   const float e39 = erfc_fast(3.9f);
@@ -295,6 +330,7 @@ __device__ __forceinline__ void fwd_block(
       const int lim = (int)nb - k * 64;
       if (lim <= 0 || any_open == 0ull) break;
       const int cntk = lim < 64 ? lim : 64;
+      uint32_t mark = 0u;   // lane l: the strips that took entry l of this round
       for (int l = 0; l < cntk && any_open != 0ull; ++l) {
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
@@ -303,6 +339,7 @@ __device__ __forceinline__ void fwd_block(
         const uint64_t cols = lanes(px >= x0) & lanes(px <= x1);
         if (cols == 0ull) continue;
         const int32_t pos = (int32_t)(base + k * 64 + l);
+        uint32_t strips = 0u;
         const int32_t posv = in_vgpr(pos);
         const float a2v = in_vgpr(r.alpha2);
         const RecordU u = record_uniform(r, x0, y0, y1, l2amin);
@@ -325,6 +362,7 @@ __device__ __forceinline__ void fwd_block(
           const float a = clamp_alpha(fmaf(r.d_o, I, a2v) * G, amax);
           m &= lanes(!(a < amin));
           if (m == 0ull) continue;
+          strips |= 1u << j;   // a superset of the strips that blend it (a stopping pixel does not)
           const float Tn = Tr[j] * (1.0f - a);
           const uint64_t stop = m & lanes(Tn < tmin);
           const bool take = in_mask(m & ~stop);
@@ -339,12 +377,24 @@ __device__ __forceinline__ void fwd_block(
           open[j] &= ~stop;
           ended |= stop != 0ull;
         }
+        if (marks) mark = lane == l ? strips : mark;
         if (ended) {
           any_open = 0ull;
 #pragma unroll
           for (int j = 0; j < PPL; ++j) any_open |= open[j];
         }
       }
+      if (marks) {
+        const int r = (int)(base >> 6) + k;
+        walked = r + 1;
+        if (r < kMarkKeep) s_mk[r * 64 + lane] = (uint8_t)mark;
+      }
+    }
+  }
+  if (marks) {
+    for (int r = 0; r < walked; ++r) {
+      const int64_t p = (int64_t)r * 64 + lane;
+      if (p < len) marks[p] = r < kMarkKeep ? s_mk[r * 64 + lane] : (uint8_t)0xffu;
     }
   }
   const uint64_t plane = (uint64_t)cam.width * cam.height;
@@ -402,13 +452,23 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* counter, uint32_t* s_w) 
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)*s_w);
 }
 
+// Eight wavefronts per SIMD (at most 64 VGPRs) where the kernel needs
+// barely more: the walk is latency-bound and loses more with one wavefront
+// fewer than with the two registers it then spills.  Instantiations that
+// would spill more (the depth output, 512-entry rounds) are left alone; the
+// persistent form keeps six (at most 80 VGPRs, no spill).
 template <int T, int IPL, bool DEPTH>
-__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
+constexpr int kFwdMinWaves = (!DEPTH && IPL <= 4) ? 8 : 1;
+
+template <int T, int IPL, bool DEPTH>
+__global__ __launch_bounds__(64 * Geometry<T>::WAVES) __attribute__((amdgpu_waves_per_eu(kFwdMinWaves<T, IPL, DEPTH>))) void
+render_fwd_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, CamPack cp, Opts o, float* __restrict__ img,
     float* __restrict__ T_final, int32_t* __restrict__ last_idx, int32_t* __restrict__ n_contrib,
-    float* __restrict__ depth) {
-  fwd_block<T, IPL, DEPTH>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, depth, blockIdx.x,
+    float* __restrict__ depth, Marks mk) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *mk.tag = mk.key;
+  fwd_block<T, IPL, DEPTH>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, depth, mk, blockIdx.x,
                            threadIdx.x >> 6, threadIdx.x & 63);
 }
 
@@ -417,16 +477,18 @@ __global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_kernel(
 // every workgroup takes tiles from a counter in `order` (longest list
 // first) so that long tiles do not start last.
 template <int T, int IPL, bool DEPTH>
-__global__ __launch_bounds__(64 * Geometry<T>::WAVES) void render_fwd_persistent_kernel(
+__global__ __launch_bounds__(64 * Geometry<T>::WAVES) __attribute__((amdgpu_waves_per_eu(kFwdMinWaves<T, IPL, DEPTH> == 8 ? 6 : 1))) void
+render_fwd_persistent_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
     float* __restrict__ img, float* __restrict__ T_final, int32_t* __restrict__ last_idx,
-    int32_t* __restrict__ n_contrib, float* __restrict__ depth, uint32_t* __restrict__ counter) {
+    int32_t* __restrict__ n_contrib, float* __restrict__ depth, Marks mk, uint32_t* __restrict__ counter) {
   __shared__ uint32_t s_w;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *mk.tag = mk.key;
   for (uint32_t w = next_tile(counter, &s_w); w < cp.tiles_total; w = next_tile(counter, &s_w))
-    fwd_block<T, IPL, DEPTH>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, depth, order[w], wave,
-                             lane);
+    fwd_block<T, IPL, DEPTH>(rec, vals, ranges, cp, o, img, T_final, last_idx, n_contrib, depth, mk, order[w],
+                             wave, lane);
 }
 
 // One wavefront's block of pixels, back to front.  Same masks as the
@@ -438,10 +500,17 @@ __device__ __forceinline__ void bwd_block(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const CamPack& cp, const Opts& o,
     const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,
-    const float* __restrict__ dL_dimg, float* __restrict__ rgrad, uint32_t tile, int wave, int lane) {
+    const float* __restrict__ dL_dimg, float* __restrict__ rgrad, const Marks& mk, bool marked,
+    uint32_t tile, int wave, int lane) {
   using Gm = BwdGeometry<T>;
+  using Gf = Geometry<T>;
   constexpr int PPL = Gm::PPL;
   constexpr int RS = Gm::ROWSTEP;
+  // the block is SPLIT forward blocks stacked vertically, each of FPPL strips
+  constexpr int SPLIT = Gm::SUBY / Gf::SUB;
+  constexpr int FPPL = Gf::PPL;
+  static_assert(Gm::SUBX == Gf::SUB && RS == Gf::ROWSTEP && PPL == SPLIT * FPPL,
+                "backward strips are the forward blocks' strips");
   if (tile >= cp.tiles_total) return;  // never index past the tile arrays
   const int c = cam_of_tile(cp, tile);
   const CamDev& cam = cp.cam[c];
@@ -490,22 +559,45 @@ __device__ __forceinline__ void bwd_block(
   const float amin = o.alpha_min, amax = o.alpha_max;
   const float l2amin = __builtin_amdgcn_logf(amin);
   const float e39 = erfc_fast(3.9f);
+  // the mark planes of the forward blocks, each read up to that block's
+  // last blended entry
+  marked = marked && (uint64_t)ranges[2 * tile + 1] <= mk.cap;
+  const uint8_t* mplane[SPLIT];
+  int32_t mtop[SPLIT];
+#pragma unroll
+  for (int q = 0; q < SPLIT; ++q) {
+    const int fw = ((wave / (T / Gm::SUBX)) * SPLIT + q) * (T / Gf::SUB) + wave % (T / Gm::SUBX);
+    mplane[q] = marked ? mk.base + (uint64_t)fw * mk.cap + ranges[2 * tile] : nullptr;
+    mtop[q] = -1;
+#pragma unroll
+    for (int j = q * FPPL; j < (q + 1) * FPPL; ++j) mtop[q] = top_j[j] > mtop[q] ? top_j[j] : mtop[q];
+  }
 
   // list indices top, top-1, ..., 0 in rounds of 64 * IPL
   for (int32_t hi = top; hi >= 0; hi -= 64 * IPL) {
-    uint32_t ids[IPL];
+    uint32_t ids[IPL], sm[IPL];   // entry ids and their strip marks (all strips when unmarked)
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       const int32_t p = hi - (k * 64 + lane);
       ids[k] = p >= 0 ? lst[p] : 0u;
+      sm[k] = 0u;
+      if (p >= 0) {
+        if (marked) {
+#pragma unroll
+          for (int q = 0; q < SPLIT; ++q)
+            if (p <= mtop[q]) sm[k] |= (uint32_t)mplane[q][p] << (q * FPPL);
+        } else {
+          sm[k] = (1u << PPL) - 1u;
+        }
+      }
     }
-    const int32_t nb = (hi + 1) < 64 * IPL ? (hi + 1) : 64 * IPL;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-      const int lim = nb - k * 64;
-      if (lim <= 0) break;
-      const int cntk = lim < 64 ? lim : 64;
-      for (int l = 0; l < cntk; ++l) {
+      if (hi - k * 64 < 0) break;
+      // the marked entries of the round, in list order back to front
+      for (uint64_t todo = lanes(sm[k] != 0u); todo != 0ull; todo &= todo - 1ull) {
+        const int l = (int)__builtin_ctzll(todo);
+        const uint32_t strips = (uint32_t)__builtin_amdgcn_readlane((int)sm[k], l);
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
@@ -526,7 +618,7 @@ __device__ __forceinline__ void bwd_block(
         bool any = false;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          if (pos > top_j[j]) continue;
+          if (pos > top_j[j] || ((strips >> j) & 1u) == 0u) continue;
           const float fpy = (float)(py0 + j * RS) + 0.5f;
           uint64_t m = cols & lanes(fpy > u.y0f) & lanes(fpy < u.y1p) & lanes(pos <= last[j]);
           if (m == 0ull) continue;
@@ -617,9 +709,10 @@ __global__ __launch_bounds__(64 * BwdGeometry<T>::WAVES) void render_bwd_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, CamPack cp, Opts o, const float* __restrict__ T_final,
     const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimg,
-    float* __restrict__ rgrad) {
-  bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, xcd_block_tile(blockIdx.x, cp),
-                    threadIdx.x >> 6, threadIdx.x & 63);
+    float* __restrict__ rgrad, Marks mk) {
+  const bool marked = mk.base != nullptr && *mk.tag == mk.key;
+  bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, mk, marked,
+                    xcd_block_tile(blockIdx.x, cp), threadIdx.x >> 6, threadIdx.x & 63);
 }
 
 template <int T, int IPL>
@@ -628,11 +721,13 @@ render_bwd_persistent_kernel(
     const Record* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, CamPack cp, Opts o,
     const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,
-    const float* __restrict__ dL_dimg, float* __restrict__ rgrad, uint32_t* __restrict__ counter) {
+    const float* __restrict__ dL_dimg, float* __restrict__ rgrad, Marks mk, uint32_t* __restrict__ counter) {
   __shared__ uint32_t s_w;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool marked = mk.base != nullptr && *mk.tag == mk.key;
   for (uint32_t w = next_tile(counter, &s_w); w < cp.tiles_total; w = next_tile(counter, &s_w))
-    bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, order[w], wave, lane);
+    bwd_block<T, IPL>(rec, vals, ranges, cp, o, T_final, last_idx, dL_dimg, rgrad, mk, marked, order[w], wave,
+                      lane);
 }
 
 __global__ void clear_counter_kernel(uint32_t* __restrict__ p) { *p = 0u; }
@@ -660,7 +755,7 @@ unsigned persistent_grid(F kernel, uint32_t n_work, int threads) {
 template <int T, int B, bool DEPTH>
 hipError_t fwd_launch_d(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                         const uint32_t* order, const CamPack& cp, const Opts& o, float* img, float* Tf,
-                        int32_t* li, int32_t* nc, float* depth, void* ws, hipStream_t s) {
+                        int32_t* li, int32_t* nc, float* depth, void* ws, const Marks& mk, hipStream_t s) {
   if (order) {
     uint32_t* counter = static_cast<uint32_t*>(ws);
     hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
@@ -668,10 +763,10 @@ hipError_t fwd_launch_d(const Record* rec, const uint32_t* vals, const uint32_t*
     hipLaunchKernelGGL((render_fwd_persistent_kernel<T, B / 64, DEPTH>),
                        dim3(persistent_grid(render_fwd_persistent_kernel<T, B / 64, DEPTH>, cp.tiles_total,
                                             threads)),
-                       dim3(threads), 0, s, rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, counter);
+                       dim3(threads), 0, s, rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, mk, counter);
   } else {
     hipLaunchKernelGGL((render_fwd_kernel<T, B / 64, DEPTH>), dim3(cp.tiles_total),
-                       dim3(64 * Geometry<T>::WAVES), 0, s, rec, vals, ranges, cp, o, img, Tf, li, nc, depth);
+                       dim3(64 * Geometry<T>::WAVES), 0, s, rec, vals, ranges, cp, o, img, Tf, li, nc, depth, mk);
   }
   return hipGetLastError();
 }
@@ -679,27 +774,56 @@ hipError_t fwd_launch_d(const Record* rec, const uint32_t* vals, const uint32_t*
 template <int T, int B>
 hipError_t fwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                       const uint32_t* order, const CamPack& cp, const Opts& o, float* img, float* Tf,
-                      int32_t* li, int32_t* nc, float* depth, void* ws, hipStream_t s) {
-  return depth ? fwd_launch_d<T, B, true>(rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, ws, s)
-               : fwd_launch_d<T, B, false>(rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, ws, s);
+                      int32_t* li, int32_t* nc, float* depth, void* ws, const Marks& mk, hipStream_t s) {
+  return depth ? fwd_launch_d<T, B, true>(rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, ws, mk, s)
+               : fwd_launch_d<T, B, false>(rec, vals, ranges, order, cp, o, img, Tf, li, nc, depth, ws, mk, s);
 }
 
 template <int T, int B>
 hipError_t bwd_launch(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                       const uint32_t* order, const CamPack& cp, const Opts& o, const float* Tf,
-                      const int32_t* li, const float* dL, float* rg, void* ws, hipStream_t s) {
+                      const int32_t* li, const float* dL, float* rg, void* ws, const Marks& mk, hipStream_t s) {
   if (order) {
     uint32_t* counter = static_cast<uint32_t*>(ws) + 1;
     hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
     constexpr int threads = 64 * BwdGeometry<T>::WAVES;
     hipLaunchKernelGGL((render_bwd_persistent_kernel<T, B / 64>),
                        dim3(persistent_grid(render_bwd_persistent_kernel<T, B / 64>, cp.tiles_total, threads)),
-                       dim3(threads), 0, s, rec, vals, ranges, order, cp, o, Tf, li, dL, rg, counter);
+                       dim3(threads), 0, s, rec, vals, ranges, order, cp, o, Tf, li, dL, rg, mk, counter);
   } else {
     hipLaunchKernelGGL((render_bwd_kernel<T, B / 64>), dim3(cp.tiles_total), dim3(64 * BwdGeometry<T>::WAVES),
-                       0, s, rec, vals, ranges, cp, o, Tf, li, dL, rg);
+                       0, s, rec, vals, ranges, cp, o, Tf, li, dL, rg, mk);
   }
   return hipGetLastError();
+}
+
+// Render workspace: [0, 256) the persistent rasters' work counters (u32 [0]
+// forward, [1] backward) and at byte 64 the mark tag; from 256 on, the mark
+// planes (one per forward wavefront of a tile, `cap` bytes each).
+constexpr size_t kRenderWsHead = 256;
+constexpr size_t kMarkTagOffset = 64;
+
+int mark_planes(int tile) { return tile == 32 ? Geometry<32>::WAVES : (tile == 16 ? Geometry<16>::WAVES : Geometry<8>::WAVES); }
+
+// The planes a workspace of ws_bytes holds, and the key that ties them to
+// these lists: the forward pass stores it, the backward compares it, so a
+// backward given another workspace (or one of another size) than its
+// forward pass ignores the planes instead of trusting stale marks.
+Marks make_marks(const uint32_t* vals, const uint32_t* ranges, const CamPack& cp, const Opts& o, void* ws,
+                 size_t ws_bytes) {
+  Marks mk;
+  const uint64_t planes = (uint64_t)mark_planes(o.tile);
+  mk.cap = ws_bytes > kRenderWsHead ? (uint64_t)(ws_bytes - kRenderWsHead) / planes : 0u;
+  mk.base = mk.cap > 0 ? static_cast<uint8_t*>(ws) + kRenderWsHead : nullptr;
+  mk.tag = reinterpret_cast<uint64_t*>(static_cast<char*>(ws) + kMarkTagOffset);
+  // splitmix64 over the list buffers, the plane size and the tiling
+  uint64_t z = (uint64_t)(uintptr_t)vals ^ ((uint64_t)(uintptr_t)ranges << 1) ^ (mk.cap * 0x9e3779b97f4a7c15ull) ^
+               ((uint64_t)cp.tiles_total << 40) ^ ((uint64_t)o.tile << 56) ^ 0x6867735f6d61726bull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  mk.key = z != 0u ? z : 1u;
+  return mk;
 }
 
 // Normals estimated from the accumulated depth (see launch_depth_normals).
@@ -756,14 +880,21 @@ __global__ __launch_bounds__(256) void depth_normals_kernel(const float* __restr
 
 }  // namespace
 
-size_t render_workspace_bytes() { return 256; }
+size_t render_workspace_bytes() { return kRenderWsHead; }
+
+size_t render_workspace_bytes(int tile, int64_t capacity) {
+  if (capacity <= 0) return kRenderWsHead;
+  const uint64_t planes = (uint64_t)(mark_planes(tile) * capacity);
+  return kRenderWsHead + (size_t)((planes + 255u) / 256u * 256u);
+}
 
 hipError_t launch_render_fwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                              const uint32_t* tile_order, const CamPack& cp, const Opts& o,
                              float* img, float* T_final, int32_t* last_idx, int32_t* n_contrib,
-                             float* depth, void* ws, hipStream_t s) {
+                             float* depth, void* ws, size_t ws_bytes, hipStream_t s) {
   if (cp.tiles_total == 0) return hipSuccess;
-#define ARGS (rec, vals, ranges, tile_order, cp, o, img, T_final, last_idx, n_contrib, depth, ws, s)
+  const Marks mk = make_marks(vals, ranges, cp, o, ws, ws_bytes);
+#define ARGS (rec, vals, ranges, tile_order, cp, o, img, T_final, last_idx, n_contrib, depth, ws, mk, s)
   HGS_DISPATCH(8, 128, fwd_launch) ARGS;
   HGS_DISPATCH(8, 256, fwd_launch) ARGS;
   HGS_DISPATCH(8, 512, fwd_launch) ARGS;
@@ -788,9 +919,10 @@ hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t s) {
 hipError_t launch_render_bwd(const Record* rec, const uint32_t* vals, const uint32_t* ranges,
                              const uint32_t* tile_order, const CamPack& cp, const Opts& o,
                              const float* T_final, const int32_t* last_idx, const float* dL_dimg,
-                             float* rec_grads, void* ws, hipStream_t s) {
+                             float* rec_grads, void* ws, size_t ws_bytes, hipStream_t s) {
   if (cp.tiles_total == 0) return hipSuccess;
-#define ARGS (rec, vals, ranges, tile_order, cp, o, T_final, last_idx, dL_dimg, rec_grads, ws, s)
+  const Marks mk = make_marks(vals, ranges, cp, o, ws, ws_bytes);
+#define ARGS (rec, vals, ranges, tile_order, cp, o, T_final, last_idx, dL_dimg, rec_grads, ws, mk, s)
   HGS_DISPATCH(8, 128, bwd_launch) ARGS;
   HGS_DISPATCH(8, 256, bwd_launch) ARGS;
   HGS_DISPATCH(8, 512, bwd_launch) ARGS;

@@ -185,7 +185,7 @@ def forward_pass(soa: torch.Tensor, n: int, sh_degree: int, cams, opts, capacity
     last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
     n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
     depth_t = torch.empty(npix, dtype=torch.float32, device=dev) if depth else None
-    ws_r = _bytes(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), dev)
+    ws_r = _bytes(B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts, capacity), dev)
     if render:
         B.hgs_render_fwd(records, values, ranges, order, cams, opts, images, T_final, last_idx, n_contrib, ws_r,
                          stream, depth=depth_t)
@@ -306,12 +306,13 @@ class Rasterizer:
         self._count.copy_(n_dup, non_blocking=True)
         copied = torch.cuda.Event()
         copied.record()
-        ws_r = self._workspace("render", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts), dev)
         while True:
             if values.numel() < self.capacity:      # after an overflow: more room, outside the arena
                 values = torch.empty(self.capacity, dtype=torch.int32, device=dev)
             ws_sort = self._workspace("sort", B.hgs_workspace_bytes(B.HGS_WS_BIN_SORT, n_rec, cams, opts,
                                                                     self.capacity), dev)
+            ws_r = self._workspace("render", B.hgs_workspace_bytes(B.HGS_WS_RENDER, n_rec, cams, opts,
+                                                                   self.capacity), dev)
             B.hgs_bin_sort(records, tiles, None, n_dup, n_rec, cams, opts, None, values, self.capacity, ranges,
                            order, overflow, ws_sort, stream)
             B.hgs_render_fwd(records, values, ranges, order, cams, opts, images, T_final, last_idx, n_contrib,

@@ -224,6 +224,45 @@ def test_per_tile_backward_covers_every_tile_once(name, tile):
     assert int(((ga - gb).abs() > tol).sum()) == 0
 
 
+@pytest.mark.parametrize("name,tile,persistent", [("cfg4_three_views", 32, False), ("cfg4_three_views", 32, True),
+                                                  ("cfg4_three_views", 16, False), ("cfg4_three_views", 8, True),
+                                                  ("cfg3_small", 32, False)])
+def test_backward_strip_marks_skip_nothing(name, tile, persistent):
+    """hgs_raster_bwd skips entries and pixel strips that the forward pass
+    marked as blending nothing; replayed in full (a workspace without marks,
+    or marks whose tag does not match) it gives the same record gradients:
+    with dL/dimage = 1 the colour sums (non-negative terms, only the atomic
+    order differs) within a few ulps record by record, with a seeded dL/dimage
+    all twelve within 1e-4 of each record's gradient norm."""
+    scene, cams = CASES[name]
+    fr = gpu_forward(scene, cams, persistent=persistent, tile=tile)
+    assert fr.ws_render.numel() > 256            # room for the marks
+    st = torch.cuda.current_stream().cuda_stream
+    bare = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    untagged = fr.ws_render.clone()
+    untagged[64:72] = 0
+    n_rec = fr.n * len(fr.cams)
+    for dl in (torch.ones(fr.images.numel(), device="cuda"),
+               torch.randn(fr.images.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(5))):
+        out = []
+        for ws in (fr.ws_render, bare, untagged):
+            rg = torch.zeros(n_rec * B.HGS_RECORD_GRAD_FLOATS, device="cuda")
+            B.hgs_raster_bwd(fr.records, fr.values, fr.ranges, fr.tile_order, fr.cams, fr.opts, fr.T_final,
+                             fr.last_idx, dl, rg, ws, st)
+            out.append(rg.view(n_rec, B.HGS_RECORD_GRAD_FLOATS))
+        torch.cuda.synchronize()
+        marked = out[0]
+        assert float(marked.abs().max()) > 0
+        for full in out[1:]:
+            if bool((dl == 1).all()):
+                a, b = marked[:, 9:12], full[:, 9:12]
+                tol = 1e-4 * b.abs() + 1e-7 * float(b.abs().max())
+            else:
+                a, b = marked, full
+                tol = 1e-4 * b.norm(dim=1, keepdim=True) + 1e-7 * float(b.abs().max())
+            assert int(((a - b).abs() > tol).sum()) == 0
+
+
 def test_gpu_matches_golden_fixture():
     """The stored oracle fixture of the 1000-kernel 128x128 workload
     (tests/golden/cfg1_oracle.json, 16-pixel tiles): every tile's list length
@@ -414,6 +453,30 @@ def test_rasterizer_planes_match_the_pipeline_and_rerun_on_overflow():
     img2.backward(dl)
     torch.cuda.synchronize()
     assert same_grads(planes.grad)
+
+
+@pytest.mark.parametrize("tile", [32, 16])
+def test_backward_after_a_forward_of_other_lists(tile):
+    """The strip marks of an earlier forward pass over other lists stay in
+    the workspace wherever the current pass marked nothing; the backward of
+    the current pass still equals a fresh forward + backward of its scene
+    (a stale mark only costs a full evaluation of a strip)."""
+    scene, cams = CASES["cfg4_three_views"]
+    other = dict(scene, means=(scene["means"] + np.random.default_rng(3).normal(
+        scale=0.05, size=scene["means"].shape)).astype(np.float32))
+    rast = R.Rasterizer(cams, scene["sh_degree"], tile=tile)
+    with torch.no_grad():
+        rast(R.scene_to_soa(other))
+    planes = R.scene_to_soa(scene).clone().requires_grad_(True)
+    img = rast(planes)
+    dl = torch.randn(img.shape, device="cuda", generator=torch.Generator("cuda").manual_seed(8))
+    img.backward(dl)
+    fr = gpu_forward(scene, cams, tile=tile)
+    assert torch.equal(img.detach(), fr.images)
+    g_ref, _ = R.backward_pass(fr, dl)
+    torch.cuda.synchronize()
+    rel = (planes.grad - g_ref).norm(dim=1) / g_ref.norm(dim=1).clamp_min(1e-30)
+    assert float(rel.max()) <= 1e-4
 
 
 # ---------------------------------------------------------------------------
