@@ -76,6 +76,22 @@ def test_host_side_validation_and_sizes():
 
 
 @pytest.mark.skipif(not os.path.exists(B.LIB_PATH), reason="libhgs.so not built")
+def test_render_workspace_holds_the_strip_marks():
+    """The render workspace is 256 bytes of head plus one strip-mark byte
+    per entry of the capacity and forward wavefront of a tile (four at
+    32-pixel tiles, one at 16 and 8), rounded up to 256 bytes; capacity 0
+    gives the head alone (a valid workspace, without marks)."""
+    _, cams = scenes.make_config(1)
+    ca = B.make_cameras(cams)
+    for tile, planes in ((32, 4), (16, 1), (8, 1)):
+        o = B.default_options(tile=tile)
+        assert B.hgs_workspace_bytes(B.HGS_WS_RENDER, 100, ca, o, 0) == 256
+        for cap in (1, 1000, 123457):
+            want = 256 + (planes * cap + 255) // 256 * 256
+            assert B.hgs_workspace_bytes(B.HGS_WS_RENDER, 100, ca, o, cap) == want
+    assert B.hgs_workspace_bytes(B.HGS_WS_RENDER, 100, ca, B.default_options(tile=12), 1000) == 0
+
+
 def test_near_plane_must_be_positive_and_finite():
     """A near plane at or behind the camera (or not a number) is rejected:
     with znear < 0, kernels with camera z in (znear, 0) would pass the cull,
