@@ -594,6 +594,11 @@ __device__ __forceinline__ void bwd_block(
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       if (hi - k * 64 < 0) break;
+      // the round's ids are waited for here, once: the entry loop issues
+      // float atomics, and a load still pending at its head would make
+      // every entry wait for all memory operations in flight, the previous
+      // entry's atomics included
+      asm volatile("" ::"v"(ids[k]));
       // the marked entries of the round, in list order back to front
       for (uint64_t todo = lanes(sm[k] != 0u); todo != 0ull; todo &= todo - 1ull) {
         const int l = (int)__builtin_ctzll(todo);
