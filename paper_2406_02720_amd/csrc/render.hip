@@ -8,9 +8,8 @@
 // wavefront needs the same record at the same time, so the list is walked
 // with wave-uniform indices: a round fetches `batch` entry ids with one
 // vector load per lane, then each id is broadcast with v_readlane and its
-// 64-byte record is loaded as uniform (scalar) data: the rect's columns
-// first, the rest only when they meet the wavefront's block.  No LDS
-// staging and no workgroup barriers: each wavefront stops as soon as all of
+// 64-byte record is loaded as uniform (scalar) data, whole, in one
+// request.  No workgroup barriers: each wavefront stops as soon as all of
 // its pixels are done.
 //
 // Backward: each lane replays its pixels back to front from the last blended
@@ -334,6 +333,11 @@ __device__ __forceinline__ void fwd_block(
       for (int l = 0; l < cntk && any_open != 0ull; ++l) {
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
+        // the whole record in one request: nearly every listed entry meets
+        // the block's columns, so loading the rect first and the rest only
+        // after the column test costs a second round trip almost always
+        asm volatile("" ::"s"(r.mx), "s"(r.my), "s"(r.kx), "s"(r.ky), "s"(r.qa), "s"(r.qb), "s"(r.qc),
+                     "s"(r.alpha2), "s"(r.r), "s"(r.g), "s"(r.b), "s"(r.d_o), "s"(r.xr), "s"(r.yr));
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
         const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
         const uint64_t cols = lanes(px >= x0) & lanes(px <= x1);
@@ -605,6 +609,11 @@ __device__ __forceinline__ void bwd_block(
         const uint32_t strips = (uint32_t)__builtin_amdgcn_readlane((int)sm[k], l);
         const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)ids[k], l);
         const Record r = load_record(rec, id);
+        // the whole record in one request: nearly every listed entry meets
+        // the block's columns, so loading the rect first and the rest only
+        // after the column test costs a second round trip almost always
+        asm volatile("" ::"s"(r.mx), "s"(r.my), "s"(r.kx), "s"(r.ky), "s"(r.qa), "s"(r.qb), "s"(r.qc),
+                     "s"(r.alpha2), "s"(r.r), "s"(r.g), "s"(r.b), "s"(r.d_o), "s"(r.xr), "s"(r.yr));
         const int x0 = (int)(r.xr & 0xffffu), x1 = (int)(r.xr >> 16);
         const int y0 = (int)(r.yr & 0xffffu), y1 = (int)(r.yr >> 16);
         const uint64_t cols = lanes(px >= x0) & lanes(px <= x1);
