@@ -236,6 +236,27 @@ def test_backward_strip_marks_skip_nothing(name, tile, persistent):
     all twelve within 1e-4 of each record's gradient norm."""
     scene, cams = CASES[name]
     fr = gpu_forward(scene, cams, persistent=persistent, tile=tile)
+    _marked_backward_equals_full_replay(fr)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_backward_strip_marks_past_the_staged_rounds(persistent):
+    """A forward walk longer than the rounds whose marks are staged in LDS
+    (2048 list positions) marks the rest in full: 4000 faint kernels that all
+    cover a 64x64 view keep its pixels open past position 2048, and the
+    backward still equals a full replay."""
+    scene, _ = scenes.make_config(1, n=4000)
+    n = scene["means"].shape[0]
+    scene = dict(scene, scales=np.full((n, 3), 2.0, np.float32),
+                 opac1=np.full(n, 0.007, np.float32), opac2=np.full(n, 0.005, np.float32))
+    cam = scenes.axis_camera(64, 64)
+    fr = gpu_forward(scene, [cam], persistent=persistent, tile=32)
+    torch.cuda.synchronize()
+    assert int(fr.last_idx.max()) >= 2048
+    _marked_backward_equals_full_replay(fr)
+
+
+def _marked_backward_equals_full_replay(fr):
     assert fr.ws_render.numel() > 256            # room for the marks
     st = torch.cuda.current_stream().cuda_stream
     bare = torch.zeros(256, dtype=torch.uint8, device="cuda")
