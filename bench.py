@@ -480,10 +480,12 @@ def main():
     # of every pair in a record's rect (row offset, the quadratic in it, two
     # comparisons), the rest of the evaluation for the pairs past it (exp,
     # the alpha_min bound, half factor, Eq. 10 opacity, clamp) and, for a
-    # blended pair, compositing; backward adds the gradient formulas.
+    # blended pair, compositing.  The backward must replay only the blended
+    # pairs (which pairs blended is known from the forward pass), each in
+    # full, and adds the gradient formulas.
     F_TEST, F_EVAL, F_BLEND, F_GRAD = 8.0, 34.0, 9.0, 75.0
     flops_fwd = pairs * F_TEST + tested * F_EVAL + blended * F_BLEND
-    flops_bwd = pairs * F_TEST + tested * F_EVAL + blended * (F_BLEND + F_GRAD)
+    flops_bwd = blended * (F_TEST + F_EVAL + F_BLEND + F_GRAD)
     roof = {}
     copy_gbs = copy_bandwidth()
 
