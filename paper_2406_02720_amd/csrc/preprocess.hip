@@ -403,6 +403,27 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
   // straight-line body)
   const int n_cams = ONE ? 1 : cp.n_cams;
   double g_mu[3] = {0.0, 0.0, 0.0};
+  // every input the geometry below reads is requested here, before the SH
+  // gradients are stored: the vector memory counter orders loads and
+  // stores, so a load issued after those 48 stores would wait for them
+  // (0.126 -> 0.089 ms on one 1080p view of 1M kernels).  With one camera
+  // that includes the record's twelve gradients.
+  float4 rg1[3] = {};
+  if (ONE) {
+    const float4* g4 = reinterpret_cast<const float4*>(rgrad + i * HGS_RECORD_GRAD_FLOATS);
+    rg1[0] = g4[0];
+    rg1[1] = g4[1];
+    rg1[2] = g4[2];
+  }
+  float mu[3], s[3], q[4], nrm[3];
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = p.means[c * S + i];
+    s[c] = p.scales[c * S + i];
+    nrm[c] = p.normals[c * S + i];
+  }
+  for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
+  const float a1f = p.opac1[i], a2f = p.opac2[i];
+  const float f3f = p.filter3d ? p.filter3d[i] : 0.0f;
 
   // ---- colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - o) / |mu - o|,
   // over all cameras first: the SH coefficients, basis values and their
@@ -414,7 +435,7 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     for (int j = 0; j < 3 * K; ++j) g_sh[j] = 0.0f;
     for (int c = 0; c < n_cams; ++c) {
       const int64_t ri = (int64_t)c * p.n + i;
-      const float4 r2 = reinterpret_cast<const float4*>(rgrad + ri * HGS_RECORD_GRAD_FLOATS)[2];
+      const float4 r2 = ONE ? rg1[2] : reinterpret_cast<const float4*>(rgrad + ri * HGS_RECORD_GRAD_FLOATS)[2];
       // no colour gradient (a culled record has none: the raster adds only
       // to records in the tile lists, into a cleared buffer)
       if (r2.y == 0.0f && r2.z == 0.0f && r2.w == 0.0f) continue;
@@ -457,18 +478,10 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     for (int j = 0; j < 3 * K; ++j) G.sh[j * S + i] = g_sh[j];
   }
 
-  float mu[3], s[3], q[4], nrm[3];
-  for (int c = 0; c < 3; ++c) {
-    mu[c] = p.means[c * S + i];
-    s[c] = p.scales[c * S + i];
-    nrm[c] = p.normals[c * S + i];
-  }
-  for (int c = 0; c < 4; ++c) q[c] = p.quats[c * S + i];
-
-  const double f3 = p.filter3d ? (double)p.filter3d[i] : 0.0;
+  const double f3 = (double)f3f;
   KernelGeo kg;
   kernel_geo(mu, s, q, nrm, kg, (isfinite(f3) && f3 >= 0.0) ? f3 : 0.0);
-  const double a1 = (double)p.opac1[i], a2 = (double)p.opac2[i];
+  const double a1 = (double)a1f, a2 = (double)a2f;
   double g_c3 = 0.0;   // dL / d comp3
 
   Sym3 g_Sw = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -479,7 +492,7 @@ __global__ __launch_bounds__(kPreBlock) void preprocess_bwd_kernel(
     const int64_t ri = (int64_t)c * p.n + i;
     float* gr = rgrad + ri * HGS_RECORD_GRAD_FLOATS;
     float4* gr4 = reinterpret_cast<float4*>(gr);
-    const float4 r0 = gr4[0], r1 = gr4[1], r2 = gr4[2];
+    const float4 r0 = ONE ? rg1[0] : gr4[0], r1 = ONE ? rg1[1] : gr4[1], r2 = ONE ? rg1[2] : gr4[2];
     // all twelve zero (every culled record, and visible ones no pixel
     // blended): no contribution and nothing to clear.  The records
     // themselves are not read.
