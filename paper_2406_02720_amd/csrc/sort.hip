@@ -156,12 +156,24 @@ __global__ __launch_bounds__(kHistScanThreads) void hist_scan_kernel(const uint3
   __shared__ uint32_t s_wave[kRadix / 64];
   const int t = threadIdx.x, d = t & (kRadix - 1), q = t >> 8;
   constexpr int kPer = kHistCopies / 4;
-  for (int p = 0; p < passes; ++p) {
-    const uint32_t* h = hist + (size_t)q * kPer * kHistWords + p * kRadix + d;
+  // every pass's histograms are read before the first base is stored: the
+  // vector memory counter orders loads and stores, so a pass's loads issued
+  // after the previous pass's stores would wait for them
+  uint32_t vp[kMaxPasses];
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; ++p) {
     uint32_t v = 0;
+    if (p < passes) {
+      const uint32_t* h = hist + (size_t)q * kPer * kHistWords + p * kRadix + d;
 #pragma unroll 16
-    for (int c = 0; c < kPer; ++c) v += h[(size_t)c * kHistWords];
-    s_part[q][d] = v;
+      for (int c = 0; c < kPer; ++c) v += h[(size_t)c * kHistWords];
+    }
+    vp[p] = v;
+  }
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; ++p) {
+    if (p >= passes) break;
+    s_part[q][d] = vp[p];
     __syncthreads();
     // threads below kRadix (whole wavefronts) own a digit each
     const int lane = t & 63, wv = t >> 6;
@@ -396,10 +408,6 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const uint64_t n = entry_count(n_dev, capacity);
   const uint64_t parts = (n + PART - 1) / PART;
-  // the next pass's look-back flags, all of them (whatever its partition
-  // count): this pass does not read them and the previous one is done
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < n_lookback; i += (int64_t)gridDim.x * kBlock)
-    lookback_next[i] = 0ull;
   // persistent: partitions are taken by ticket until none is left (a
   // partition's look-back only waits on lower tickets, held by running
   // workgroups)
@@ -408,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   for (int i = t; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0u;
   __syncthreads();
   const uint32_t part = s_part;
-  if (part >= parts) return;
+  if (part >= parts) break;
 
   const uint64_t base = (uint64_t)part * PART;
   const uint64_t wbase = base + (uint64_t)wave * 64 * ITEMS;
@@ -521,6 +529,12 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
   }
   __syncthreads();
   }
+  // the next pass's look-back flags, all of them (whatever its partition
+  // count): this pass does not read them and the previous one is done.
+  // Cleared last: stores issued before the partitions' loads would make
+  // those loads wait for them (the vector memory counter orders both).
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < n_lookback; i += (int64_t)gridDim.x * kBlock)
+    lookback_next[i] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
