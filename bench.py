@@ -215,7 +215,7 @@ class PipelineStep:
         self.cap = cap
         self.pixels = sum(c["width"] * c["height"] for c in cams)
 
-    def step(self, ev=None):
+    def step(self, ev=None, upto=None):
         B = self.B
         stream = self.torch.cuda.current_stream().cuda_stream
         ca, opts = self.cams, self.opts
@@ -239,8 +239,25 @@ class PipelineStep:
         B.hgs_raster_bwd(self.records, self.values, self.ranges, self.order, ca, opts, self.T_final,
                          self.last_idx, self.dL, self.rgrad, self.ws_r, stream)
         mark(5)
+        if upto == "raster_bwd":
+            return
         B.hgs_preprocess_bwd(self.params, ca, opts, self.records, self.rgrad, self.gstruct, stream)
         mark(6)
+
+    def nonzero_gradients(self):
+        """(records, kernels) with a nonzero record gradient in one step: the
+        backward preprocess reads the parameters, and clears the record
+        gradients, of these only.  One untimed step, looked at before its
+        backward preprocess (which then runs and clears them)."""
+        torch = self.torch
+        self.step(upto="raster_bwd")
+        nz = (self.rgrad.view(self.n_rec, -1) != 0).any(1)
+        records = int(nz.sum().item())
+        kernels = int(nz.view(len(self.cameras), self.n).any(0).sum().item())
+        self.B.hgs_preprocess_bwd(self.params, self.cams, self.opts, self.records, self.rgrad, self.gstruct,
+                                  torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        return records, kernels
 
     def time(self, steps, warmup):
         """(ms per whole step, {stage: ms}): whole steps back to back with
@@ -475,7 +492,13 @@ def main():
         # read once (16 B), 4 B written per entry, the ranges (8 B per tile)
         passes = 0
         bytes_sort = n_rec * (16 + 4 * 16 + 16) + 4 * n_dup + 8 * tiles_total
-    bytes_pbwd = n * (param_bytes + param_bytes) + n_rec * (48 + 48 + 4)
+    # backward preprocess: every kernel's parameter gradients written, every
+    # record's 48 B of gradients and every kernel's 15 geometry parameters
+    # read; the SH coefficients read, and the record gradients cleared, only
+    # where some record gradient is nonzero (the kernel skips the rest:
+    # culled records and those no pixel blended)
+    nz_rec, nz_kernels = run.nonzero_gradients()
+    bytes_pbwd = (n * param_bytes + n_rec * 48 + n * 4 * 15 + nz_kernels * 4 * sh_floats + nz_rec * 48)
     # FP32 operations of one pair, written out (fma = 2): the exponent test
     # of every pair in a record's rect (row offset, the quadratic in it, two
     # comparisons), the rest of the evaluation for the pairs past it (exp,
@@ -563,7 +586,7 @@ def main():
         "roofline": roofline,
         "roofline_stages": roof,
         "work": {"pairs_in_rect": pairs, "pairs_past_exponent_test": tested, "pairs_listed": listed,
-                 "blended": blended},
+                 "blended": blended, "records_with_gradient": nz_rec, "kernels_with_gradient": nz_kernels},
         "copy_GBps": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "autograd": auto,

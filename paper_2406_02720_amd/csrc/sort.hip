@@ -949,24 +949,33 @@ __global__ __launch_bounds__(64) void place_offsets_kernel(
   if (t >= B.n) return;
   const bool over = *n_dup > (uint64_t)capacity;
   const uint64_t tg = B.lo + (uint64_t)t;
+  // every load before the first store: the vector memory counter orders
+  // loads and stores, so a load behind a store would wait for it (and the
+  // group's counts read and overwritten one by one would wait item by item)
   const uint32_t a = (uint32_t)starts[tg];
+  const uint32_t tot = g == 0 ? totals[tg] : 0u;
+  const uint32_t ni = nitems[k];
+  const uint64_t row0 = item0[k];
+  const uint32_t i0 = (uint32_t)g * kItemGroup;
+  const bool mine = !over && i0 < ni;
+  const uint32_t i1 = i0 + kItemGroup < ni ? i0 + kItemGroup : ni;
+  uint32_t* c = counts + row0 * (uint64_t)band_tiles + t;
+  uint32_t run = a;
+  uint32_t v[kItemGroup];
+  if (mine) {
+    for (uint32_t gi = 0; gi < i0; gi += kItemGroup) run += gsum[(row0 + gi) * (uint64_t)band_tiles + t];
+#pragma unroll
+    for (int j = 0; j < kItemGroup; ++j) v[j] = i0 + j < i1 ? c[(uint64_t)(i0 + j) * band_tiles] : 0u;
+  }
   if (g == 0) {
-    const uint32_t tot = totals[tg];
     ranges[2 * tg] = (tot && !over) ? a : 0u;
     ranges[2 * tg + 1] = (tot && !over) ? a + tot : 0u;
   }
-  const uint32_t ni = nitems[k];
-  const uint32_t i0 = (uint32_t)g * kItemGroup;
-  if (over || i0 >= ni) return;
-  const uint32_t i1 = i0 + kItemGroup < ni ? i0 + kItemGroup : ni;
-  const uint64_t row0 = item0[k];
-  uint32_t run = a;
-  for (uint32_t gi = 0; gi < i0; gi += kItemGroup) run += gsum[(row0 + gi) * (uint64_t)band_tiles + t];
-  uint32_t* c = counts + row0 * (uint64_t)band_tiles + t;
-  for (uint32_t i = i0; i < i1; ++i) {
-    const uint32_t v = c[(uint64_t)i * band_tiles];
-    c[(uint64_t)i * band_tiles] = run;
-    run += v;
+  if (!mine) return;
+#pragma unroll
+  for (int j = 0; j < kItemGroup; ++j) {
+    if (i0 + j < i1) c[(uint64_t)(i0 + j) * band_tiles] = run;
+    run += v[j];
   }
 }
 
