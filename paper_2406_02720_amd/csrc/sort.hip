@@ -388,7 +388,11 @@ __global__ __launch_bounds__(kBlock) void depth_hist_weighted_kernel(const Recor
 }
 
 // ---------------------------------------------------------------------------
-constexpr int64_t kSweepGrid = 2048;   // persistent one-sweep workgroups (a few per CU)
+// Persistent one-sweep workgroups: as many as the chip holds at once (about
+// 39 KB of LDS each: four per CU).  More only queue behind the resident ones
+// and, when the partitions are fewer than the grid (the pair pass is sized
+// for its largest count), take an empty ticket after those are done.
+constexpr int64_t kSweepGrid = 1024;
 
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void onesweep_kernel(
